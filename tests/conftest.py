@@ -1,0 +1,31 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def h2_tiny():
+    from workloads import make_config
+    return make_config("h2_tiny")
+
+
+@pytest.fixture(scope="session")
+def h6_small():
+    from workloads import make_config
+    return make_config("h6_small")
+
+
+@pytest.fixture(scope="session")
+def h4():
+    from workloads import make_config
+    return make_config("h4")
