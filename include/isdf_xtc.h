@@ -1,0 +1,230 @@
+/*
+ * isdf_xtc.h -- C ABI of libisdfxtc, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of ISDF-xTC (arXiv 2607.17314): orbital values on a
+ * real-space grid, ISDF interpolation-point selection and fit, and the
+ * ISDF-compressed transcorrelated two-body intermediates built from grid-pair
+ * kernel tiles that are generated on the fly and never stored.
+ *
+ * Conventions shared by every call
+ *  - Plain C99 types only. "device" pointers are HIP device memory, "host"
+ *    pointers are host memory. Arrays are dense and row-major in the order the
+ *    brackets give, the last index fastest; every device array must be 8-byte
+ *    aligned (256-byte alignment is recommended).
+ *  - Ownership: the caller owns every buffer. The library allocates no device
+ *    memory: all scratch comes from the caller's workspace (ws, ws_bytes),
+ *    whose required size xtc_workspace_bytes() returns for the same arguments.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream). Work is
+ *    enqueued on it; calls with host outputs synchronise it before returning.
+ *  - Errors: arguments are checked before anything is launched. A negative
+ *    status is an error (outputs undefined); a positive status is a warning
+ *    (outputs valid, see the code). xtc_last_error() returns a thread-local
+ *    message for the last failing call on the calling thread.
+ *  - Determinism: reductions use fixed trees and no floating-point atomics,
+ *    so repeated calls on the same inputs give bitwise-identical results.
+ *  - Units: bohr for coordinates, hartree-scale quantities in FP64.
+ */
+#ifndef ISDF_XTC_H
+#define ISDF_XTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xtc_status;
+enum {
+  XTC_OK = 0,
+  XTC_WARN_RANK_DEFICIENT = 1, /* fewer pivots than asked: residual exhausted */
+  XTC_WARN_JITTER = 2,         /* a Tikhonov shift was needed in the fit */
+  XTC_WARN_FALLBACK = 3,       /* learned points rejected, QR pivots returned */
+  XTC_ERR_INVALID_ARG = -1,
+  XTC_ERR_NOT_SPD = -2,        /* Gram matrix not SPD after the last shift */
+  XTC_ERR_HIP = -3,            /* HIP runtime error; message in xtc_last_error */
+  XTC_ERR_NO_WORKSPACE = -4,   /* ws_bytes below the requirement */
+  XTC_ERR_UNSUPPORTED = -5
+};
+
+/* Arithmetic of the grid-pair contraction (xtc_kernel_contract, xtc_grad). */
+enum {
+  XTC_FP64 = 0,      /* FP64 kernels and FP64 MFMA throughout */
+  XTC_SPLIT_F16 = 2  /* stage 1 as FP16 hi+lo split products on MFMA with FP32
+                        accumulation and FP64 compensation across ket chunks;
+                        stage 2, Gram/Cholesky and energy-scale sums in FP64 */
+};
+
+/* Correlator forms (Jastrow correlator section, eqs. bh-scaled and bh-u). */
+enum {
+  XTC_U_EE = 0, /* u = sum_k c_k rbar12^{o_k}, rbar = d r/(1 + d r) */
+  XTC_U_BH = 1  /* multi-centre Boys-Handy form of eq. bh-u */
+};
+
+/* Channels of xtc_kernel_contract (bit mask). */
+enum {
+  XTC_U1 = 1,      /* u1[c][mu][nu] = sum_{g,g'} w w' xi~^c_mu(g) xi_nu(g') d_c u(g,g') (eq. K1-isdf) */
+  XTC_U3 = 2,      /* u3[mu][nu]   = sum w w' xi_mu(g) xi_nu(g') |grad_1 u|^2 (eq. K3-isdf) */
+  XTC_ULAP = 4,    /* ulap[mu][nu] = sum w w' xi_mu(g) xi_nu(g') lap_1 u (validation; EE only) */
+  XTC_D1 = 8,      /* D1 = sum_g w xi_mu(g) V_nu(g) (xTC Term 1) */
+  XTC_D4 = 16,     /* D4 = sum_g wt_g sum_c calG^c_mu calG^c_nu (xTC Term 4) */
+  XTC_FIELD = 32,  /* field[c][g] = A_gamma^c(g) = sum_g' w' rho(g') d_c u(g,g') (exact) */
+  XTC_ESCALE = 64  /* escale[6] energy-scale scalars, see xtc_kernel_contract */
+};
+
+/* Modes of isdf_select_points. */
+enum {
+  XTC_SELECT_QR = 0,            /* weight-scaled pivoted Cholesky (Alg. 1), both channels, fused */
+  XTC_SELECT_LEARNED = 1,       /* MLP proposal + restricted pivoting, no judge */
+  XTC_SELECT_LEARNED_JUDGED = 2 /* as 1, then fall back to QR if the fit residual exceeds
+                                   fallback_factor times the QR residual */
+};
+
+/* Fit outputs of isdf_fit (bit mask). */
+enum { XTC_FIT_XI = 1, XTC_FIT_XIGRAD = 2 };
+
+/* Integration grid. */
+typedef struct {
+  int64_t n_g;
+  const double* xyz; /* device [3][n_g] (SoA), bohr */
+  const double* w;   /* device [n_g], quadrature weights, w >= 0 */
+} xtc_grid;
+
+/* Cartesian Gaussian basis (all arrays host; copied into the workspace).
+ * chi_a(r) = comp_factor[a] x^i y^j z^k sum_p prim_coef[p] exp(-prim_exp[p] |r-R|^2),
+ * (x,y,z) = r - atom_xyz[shell_center[s]], p over the primitives of the AO's shell s.
+ * AOs are shell-major; a shell of angular momentum l holds (l+1)(l+2)/2 AOs with
+ * (i,j,k), i+j+k = l, i descending, then j descending. */
+typedef struct {
+  int32_t n_atom;
+  const double* atom_xyz;          /* host [n_atom][3] */
+  int32_t n_shell;
+  const int32_t* shell_center;     /* host [n_shell] */
+  const int32_t* shell_l;          /* host [n_shell], 0 <= l <= 6 */
+  const int32_t* shell_prim_start; /* host [n_shell + 1] */
+  const double* prim_exp;          /* host [n_prim] */
+  const double* prim_coef;         /* host [n_prim] */
+  const double* comp_factor;       /* host [n_ao] */
+  int32_t n_ao;
+} xtc_basis;
+
+/* Correlator (all arrays host). EE: n_types = 1, mno[k] = (0, 0, o_k).
+ * BH: u = sum_I sum_k c[type(I)][k] [a_1I^m a_2I^n + a_2I^m a_1I^n] rbar12^o,
+ * a_iI = b[type(I)] r_iI / (1 + b[type(I)] r_iI). */
+typedef struct {
+  int32_t form;            /* XTC_U_EE or XTC_U_BH */
+  int32_t n_terms;
+  const int32_t* mno;      /* host [n_terms][3] */
+  int32_t n_types;
+  const double* c;         /* host [n_types][n_terms]: the linear coefficients */
+  double d;                /* electron-electron scale, d > 0 */
+  const double* b;         /* host [n_types] (BH only) */
+  int32_t n_nuc;
+  const double* nuc_xyz;   /* host [n_nuc][3] (BH only) */
+  const int32_t* nuc_type; /* host [n_nuc] (BH only) */
+} xtc_correlator;
+
+/* Learned point scorer: MLP 8 -> hidden -> hidden -> 1 with SiLU, FP32 weights
+ * packed as W1[hidden][8], b1[hidden], W2[hidden][hidden], b2[hidden], W3[hidden], b3. */
+typedef struct {
+  int32_t in_dim;          /* must be 8 */
+  int32_t hidden;          /* 1 .. 128 */
+  const float* params;     /* device, 8h + h + h*h + h + h + 1 floats */
+  const float* feat_shift; /* device [8]: feature z-score shift */
+  const float* feat_scale; /* device [8]: feature z-score scale */
+  double kappa;            /* candidates kept = kappa * n_mu */
+} xtc_mlp;
+
+/* Thread-local message of the last failing call (valid until the next call). */
+const char* xtc_last_error(void);
+
+/* Library version string. */
+const char* xtc_version(void);
+
+/* Call identifiers for xtc_workspace_bytes. */
+enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
+       XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5 };
+
+/* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
+ * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT).
+ * n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), else 0. */
+size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
+                           int32_t n_aux, uint32_t flags);
+
+/* Orbital and orbital-gradient values on the grid (Alg. 2, grid step):
+ * phi4[0][p][g] = phi_p(r_g), phi4[1+c][p][g] = d_c phi_p(r_g), phi_p = sum_a chi_a C_mo[a][p].
+ * C_mo: device [n_ao][n_orb]. phi4: device [4][n_orb][n_g] (output).
+ * rho: device [n_g] or NULL; receives rho_gamma(g) = sum_{i < n_occ} phi_i(g)^2
+ * (one-spin reference density, xTC section eq. deltaU-fields). Asynchronous. */
+xtc_status xtc_eval_orbitals(const xtc_basis* basis, const xtc_grid* grid, const double* C_mo,
+                             int32_t n_orb, int32_t n_occ, double* phi4, double* rho,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Interpolation-point selection (ISDF section, pivot selection and fusion; Alg. 1).
+ * QR mode: matrix-free weight-scaled pivoted Cholesky, FP64, on the scalar channel
+ * d_g = w_g^2 (sum_p phi_p^2)^2 and the gradient channel
+ * d_g = w_g^2 (sum_p phi_p^2)(sum_{p,c} (d_c phi_p)^2); ties go to the lowest index;
+ * fused by fill-to-target: gradient channel to ceil(n_mu/2) pivots, then the scalar
+ * channel extended until the union holds n_mu points; output order = scalar pivots in
+ * selection order, then gradient-only pivots. Stops early (XTC_WARN_RANK_DEFICIENT)
+ * when max_g d_g <= 1e-14 max_g D_g.
+ * phi4: device [4][n_orb][n_g]. pivots: host [n_mu_target] (output), *n_mu_out: count.
+ * info: host [8] or NULL: {scalar steps, gradient steps, used_fallback, R_selected,
+ * R_qr (when computed), time_ms, candidates, 0}. mlp is required for the learned modes.
+ * Synchronising. */
+xtc_status isdf_select_points(const double* phi4, const xtc_grid* grid, int32_t n_orb,
+                              int32_t n_occ, int32_t n_mu_target, int32_t mode,
+                              const xtc_mlp* mlp, double fallback_factor, int64_t* pivots,
+                              int32_t* n_mu_out, double* info, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* ISDF fit (ISDF section, eq. isdf-rho and its normal equations):
+ * scalar A = G o G, G = Phi_mu^T Phi_mu; B = P o P, P = Phi_mu^T Phi; A xi = B.
+ * gradient A_c = (dPhi_mu^T dPhi_mu)_c o G; B_c = P o (dPhi_mu^T dPhi)_c; A_c xi~^c = B_c.
+ * Solved by FP64 Cholesky with the adaptive Tikhonov retry (no shift, then
+ * 1e-14 * 10^k * mean(diag A), k = 0..8) and blocked triangular solves.
+ * pivots: host [n_mu]. xi: device [n_mu][n_g] (if what & XTC_FIT_XI).
+ * xigrad: device [3][n_mu][n_g] (if what & XTC_FIT_XIGRAD).
+ * info: host [8] or NULL: {shift index k per system (-1 none) x4, relative weighted
+ * residual sum_g w^2 (|m_g|^2 - xi(g).B(g)) / sum_g w^2 |m_g|^2 x4} (scalar, x, y, z).
+ * Returns XTC_WARN_JITTER if any shift was used. Synchronising. */
+xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
+                    const int64_t* pivots, int32_t n_mu, uint32_t what, double* xi,
+                    double* xigrad, double* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Grid-pair kernels and xTC D terms, with the kernel tiles generated on the fly
+ * (K-kernel section, eqs. K1-isdf and K3-isdf; xTC section Terms 1 and 4, with
+ * calG^c_{mu,g} = sum_g' w_g' xi_mu(g') d_c u(g,g'), H_{g,c} = sum_l G_l calG^c_{l,g},
+ * V_{nu,g} = sum_c H_{g,c} calG^c_{nu,g}, wt_g = w_g sum_l G_l xi_l(g), and
+ * G_nu = rho_gamma(r_nu)). grad acts on the bra point g.
+ * xi: device [n_mu][n_g]; xigrad: device [3][n_mu][n_g] (needed for XTC_U1).
+ * rho: device [n_g] (rho_gamma). pivots: host [n_mu] (G is gathered from rho).
+ * Outputs (device, FP64, overwritten; NULL when the channel is off):
+ *   u1 [3][n_mu][n_mu], u3, ulap, D1, D4 [n_mu][n_mu], field [3][n_g].
+ * escale: host [6] or NULL: {E3, E4, E1, E3x, E4x, E1x} with E3 = G^T u3 G,
+ *   E4 = G^T D4 G, E1 = 2 G^T D1 G and their ISDF-free counterparts
+ *   E3x = sum_{g,g'} w w' rho rho' |grad_1 u|^2, E4x = sum_g w rho |A_gamma|^2, E1x = 2 E4x.
+ * precision: XTC_FP64 or XTC_SPLIT_F16. Synchronising only if escale != NULL. */
+xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                               const double* xi, const double* xigrad, const double* rho,
+                               const int64_t* pivots, uint32_t channels, int32_t precision,
+                               double* u1, double* u3, double* ulap, double* D1, double* D4,
+                               double* field, double* escale, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* Adjoint of xtc_kernel_contract with respect to the linear coefficients c:
+ * dtheta[j] = dL/dc_j for L = sum_c <gu1_c, u1_c> + <gu3, u3> + <gulap, ulap>
+ * + <gD1, D1> + <gD4, D4> + <gfield, field>. Cotangents: device, shapes of the
+ * matching outputs, NULL when absent. Kernel tiles are regenerated, never stored;
+ * the D cotangents add one recomputation pass of calG.
+ * dtheta: device [n_types * n_terms] (output). FP64. Asynchronous. */
+xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                    const double* xi, const double* xigrad, const double* rho,
+                    const int64_t* pivots, const double* gu1, const double* gu3,
+                    const double* gulap, const double* gD1, const double* gD4,
+                    const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISDF_XTC_H */

@@ -44,7 +44,7 @@ def eval_ao(basis, xyz: np.ndarray) -> np.ndarray:
 def eval_orbitals(basis, C_mo: np.ndarray, xyz: np.ndarray) -> np.ndarray:
     """phi4[4, n_orb, n_g] = AO4^T C: values and Cartesian gradients of the MOs."""
     ao = eval_ao(basis, xyz)
-    return np.einsum("cag,ap->cpg", ao, C_mo, optimize=True)
+    return np.ascontiguousarray(np.einsum("cag,ap->cpg", ao, C_mo, optimize=True))
 
 
 def density(phi4: np.ndarray, n_occ: int) -> np.ndarray:

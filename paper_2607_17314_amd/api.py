@@ -1,0 +1,213 @@
+"""Python binding of libisdfxtc: the same calls as include/isdf_xtc.h, taking
+torch tensors for device memory and the current torch stream. Argument
+marshalling only: every step runs in the native library's HIP kernels, and
+nothing here falls back to the CPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class XtcError(RuntimeError):
+    def __init__(self, call: str, status: int, msg: str):
+        super().__init__(f"{call} failed with {L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(call: str, status: int) -> int:
+    if status < 0:
+        raise XtcError(call, status, L.lib().xtc_last_error().decode())
+    return status
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(t, dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _in(t, name: str, dtype=torch.float64):
+    """Validate a device input: CUDA tensor of the given dtype, made contiguous."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _workspace(nbytes: int):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(L.D)
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(L.I32)
+
+
+def version() -> str:
+    return L.lib().xtc_version().decode()
+
+
+def workspace_bytes(call: int, n_g: int, n_orb: int, n_mu: int, n_aux: int = 0, flags: int = 0) -> int:
+    return int(L.lib().xtc_workspace_bytes(call, n_g, n_orb, n_mu, n_aux, flags))
+
+
+@dataclass
+class DeviceGrid:
+    xyz: torch.Tensor   # [3, n_g] float64 cuda
+    w: torch.Tensor     # [n_g] float64 cuda
+
+    @classmethod
+    def from_host(cls, xyz, w):
+        return cls(_dev(np.ascontiguousarray(xyz)), _dev(np.ascontiguousarray(w)))
+
+    @property
+    def n_g(self) -> int:
+        return int(self.w.shape[0])
+
+    def c(self):
+        return L.Grid(self.n_g, self.xyz.data_ptr(), self.w.data_ptr())
+
+
+class _HostBasis:
+    """Keeps the host arrays of an xtc_basis alive."""
+
+    def __init__(self, basis):
+        self.atom = np.ascontiguousarray(basis.atom_xyz, np.float64)
+        self.center = np.ascontiguousarray(basis.shell_center, np.int32)
+        self.l = np.ascontiguousarray(basis.shell_l, np.int32)
+        self.start = np.ascontiguousarray(basis.shell_prim_start, np.int32)
+        self.exp = np.ascontiguousarray(basis.prim_exp, np.float64)
+        self.coef = np.ascontiguousarray(basis.prim_coef, np.float64)
+        self.comp = np.ascontiguousarray(basis.comp_factor, np.float64)
+        self.s = L.Basis(self.atom.shape[0], _dptr(self.atom), self.l.shape[0], _iptr(self.center),
+                         _iptr(self.l), _iptr(self.start), _dptr(self.exp), _dptr(self.coef),
+                         _dptr(self.comp), self.comp.shape[0])
+
+
+class HostCorrelator:
+    """Keeps the host arrays of an xtc_correlator alive."""
+
+    def __init__(self, corr, c=None):
+        self.mno = np.ascontiguousarray(corr.mno, np.int32)
+        cc = corr.c if c is None else np.asarray(c, np.float64).reshape(corr.c.shape)
+        self.c = np.ascontiguousarray(cc, np.float64)
+        self.b = np.ascontiguousarray(corr.b if corr.b is not None else np.ones(1), np.float64)
+        nx = corr.nuc_xyz if corr.nuc_xyz is not None else np.zeros((0, 3))
+        self.nuc = np.ascontiguousarray(nx, np.float64).reshape(-1, 3)
+        nt = corr.nuc_type if corr.nuc_type is not None else np.zeros(0, np.int32)
+        self.nt = np.ascontiguousarray(nt, np.int32)
+        self.s = L.Correlator(int(corr.form), self.mno.shape[0], _iptr(self.mno), self.c.shape[0],
+                              _dptr(self.c), float(corr.d), _dptr(self.b), self.nuc.shape[0],
+                              _dptr(self.nuc), _iptr(self.nt))
+
+
+def eval_orbitals(basis, grid: DeviceGrid, C_mo, n_occ: int = 0):
+    """phi4 [4, n_orb, n_g] and rho_gamma [n_g] on the device (xtc_eval_orbitals)."""
+    hb = _HostBasis(basis)
+    Cm = _dev(C_mo)
+    n_ao, n_orb = Cm.shape
+    phi4 = torch.empty((4, n_orb, grid.n_g), dtype=torch.float64, device="cuda")
+    rho = torch.empty(grid.n_g, dtype=torch.float64, device="cuda")
+    ws = _workspace(workspace_bytes(L.XTC_CALL_EVAL_ORBITALS, grid.n_g, n_orb, 0, n_ao))
+    g = grid.c()
+    _check("xtc_eval_orbitals", L.lib().xtc_eval_orbitals(
+        C.byref(hb.s), C.byref(g), _ptr(Cm), n_orb, n_occ, _ptr(phi4), _ptr(rho), _ptr(ws),
+        ws.numel(), _stream()))
+    return phi4, rho
+
+
+def select_points(phi4, grid: DeviceGrid, n_mu: int, n_occ: int = 0, mode: int = L.XTC_SELECT_QR,
+                  mlp=None, fallback_factor: float = 1.25):
+    """Fused interpolation points (isdf_select_points). Returns (pivots int64 numpy, info, status)."""
+    phi4 = _in(phi4, "phi4")
+    n_orb = int(phi4.shape[1])
+    piv = np.zeros(n_mu, np.int64)
+    n_out = C.c_int32(0)
+    info = np.zeros(8, np.float64)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_SELECT, grid.n_g, n_orb, n_mu, 0, mode))
+    g = grid.c()
+    mp = C.byref(mlp) if mlp is not None else None
+    st = _check("isdf_select_points", L.lib().isdf_select_points(
+        _ptr(phi4), C.byref(g), n_orb, n_occ, n_mu, mode, mp, fallback_factor,
+        piv.ctypes.data_as(L.I64), C.byref(n_out), _dptr(info), _ptr(ws), ws.numel(), _stream()))
+    return piv[: n_out.value].copy(), info, st
+
+
+def fit(phi4, grid: DeviceGrid, pivots, what: int = L.XTC_FIT_XI | L.XTC_FIT_XIGRAD):
+    """xi [n_mu, n_g] and xigrad [3, n_mu, n_g] (isdf_fit). Returns (xi, xigrad, info, status)."""
+    phi4 = _in(phi4, "phi4")
+    piv = np.ascontiguousarray(pivots, np.int64)
+    n_mu = piv.shape[0]
+    n_orb = int(phi4.shape[1])
+    xi = torch.empty((n_mu, grid.n_g), dtype=torch.float64, device="cuda") if what & L.XTC_FIT_XI else None
+    xig = (torch.empty((3, n_mu, grid.n_g), dtype=torch.float64, device="cuda")
+           if what & L.XTC_FIT_XIGRAD else None)
+    info = np.zeros(8, np.float64)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_FIT, grid.n_g, n_orb, n_mu, 0, what))
+    g = grid.c()
+    st = _check("isdf_fit", L.lib().isdf_fit(
+        _ptr(phi4), C.byref(g), n_orb, piv.ctypes.data_as(L.I64), n_mu, what, _ptr(xi), _ptr(xig),
+        _dptr(info), _ptr(ws), ws.numel(), _stream()))
+    return xi, xig, info, st
+
+
+ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_ESCALE
+
+
+def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: int = ALL_CHANNELS,
+                    precision: int = L.XTC_FP64, c=None, out=None):
+    """Grid-pair kernels and xTC D terms (xtc_kernel_contract). Returns a dict of device tensors
+    (u1, u3, ulap, D1, D4, field) and escale (numpy [6]) for the requested channels."""
+    hc = HostCorrelator(corr, c)
+    xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
+    piv = np.ascontiguousarray(pivots, np.int64)
+    n_mu = piv.shape[0]
+    n_g = grid.n_g
+    f64 = dict(dtype=torch.float64, device="cuda")
+    o = {} if out is None else dict(out)
+
+    def want(bit, key, shape):
+        if channels & bit:
+            if o.get(key) is None:
+                o[key] = torch.empty(shape, **f64)
+            return o[key]
+        o[key] = None
+        return None
+
+    u1 = want(L.XTC_U1, "u1", (3, n_mu, n_mu))
+    u3 = want(L.XTC_U3, "u3", (n_mu, n_mu))
+    ul = want(L.XTC_ULAP, "ulap", (n_mu, n_mu))
+    d1 = want(L.XTC_D1, "D1", (n_mu, n_mu))
+    d4 = want(L.XTC_D4, "D4", (n_mu, n_mu))
+    fld = want(L.XTC_FIELD, "field", (3, n_g))
+    esc = np.zeros(6, np.float64)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, 0, n_mu, 0, channels | (precision << 16)))
+    g = grid.c()
+    _check("xtc_kernel_contract", L.lib().xtc_kernel_contract(
+        C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
+        channels, precision, _ptr(u1), _ptr(u3), _ptr(ul), _ptr(d1), _ptr(d4), _ptr(fld),
+        _dptr(esc) if channels & L.XTC_ESCALE else None, _ptr(ws), ws.numel(), _stream()))
+    o["escale"] = esc if channels & L.XTC_ESCALE else None
+    return o

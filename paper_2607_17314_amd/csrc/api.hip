@@ -1,0 +1,24 @@
+// Library-wide entry points: error reporting, version, workspace queries.
+#include "common.hpp"
+#include "plans.hpp"
+
+namespace xtc {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace xtc
+
+extern "C" const char* xtc_last_error(void) { return xtc::g_last_error.c_str(); }
+
+extern "C" const char* xtc_version(void) { return "libisdfxtc 0.1.0 (gfx950)"; }
+
+extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
+                                      int32_t n_aux, uint32_t flags) {
+  switch (call) {
+    case XTC_CALL_EVAL_ORBITALS: return xtc::ws_eval_orbitals(n_g, n_orb, n_aux);
+    case XTC_CALL_SELECT: return xtc::ws_select(n_g, n_orb, n_mu, (int)flags);
+    case XTC_CALL_FIT: return xtc::ws_fit(n_g, n_orb, n_mu, flags);
+    case XTC_CALL_CONTRACT: return xtc::ws_contract(n_g, n_mu, flags);
+    case XTC_CALL_GRAD: return xtc::ws_grad(n_g, n_mu, n_aux, flags);
+    default: return 0;
+  }
+}

@@ -1,0 +1,316 @@
+// Driver of xtc_kernel_contract: stage 1 per bra super-block (grid-pair kernel
+// tiles generated on the fly), then stage 2 on the super-block's panel
+// (K-kernel section eqs. K1-isdf and K3-isdf; xTC Terms 1 and 4):
+//   u1^c += (w xi~^c) calG^c^T,  u3 += (w xi) T3^T,  ulap += (w xi) TL^T,
+//   D4   += sum_c (calG^c wt) calG^c^T,  D1 += (w xi) V^T,
+// with wt_g = w_g sum_l G_l xi_l(g), H_gc = sum_l G_l calG^c_lg, V = sum_c H_c calG^c,
+// all as FP64 MFMA GEMMs accumulated in place. The rho row of the panel gives
+// the exact field A_gamma and the ISDF-free energy-scale sums.
+#include "contract.hpp"
+#include "plans.hpp"
+
+namespace xtc {
+
+constexpr long SUPER_BLOCK = 16384;
+
+xtc_status ee_coefficients(const xtc_correlator* corr, EECoef* cf) {
+  *cf = EECoef{};
+  cf->d = corr->d;
+  int omax = 0;
+  for (int k = 0; k < corr->n_terms; ++k) {
+    const int* t = corr->mno + 3 * k;
+    if (t[0] != 0 || t[1] != 0 || t[2] < 0) {
+      set_error("EE correlator terms must be (0, 0, o) with o >= 0");
+      return XTC_ERR_INVALID_ARG;
+    }
+    if (t[2] > omax) omax = t[2];
+  }
+  if (omax > MAXQ) {
+    set_error("EE correlator power above the supported maximum");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  for (int k = 0; k < corr->n_terms; ++k) {
+    const int o = corr->mno[3 * k + 2];
+    const double c = corr->c[k];
+    if (o >= 1) cf->q1[o - 1] += c * o;
+    if (o >= 2) {
+      cf->q2[o - 2] += c * o;
+      cf->q3[o - 2] += c * o * (o - 1);
+    }
+    if (o == 1) cf->c1 += c;
+  }
+  cf->n1 = omax >= 1 ? omax : 0;
+  cf->n2 = omax >= 2 ? omax - 1 : 0;
+  cf->n3 = cf->n2;
+  return XTC_OK;
+}
+
+__global__ void k_gather_G(const double* __restrict__ rho, const long* __restrict__ piv, int n_mu,
+                           double* __restrict__ G) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n_mu) G[i] = rho[piv[i]];
+}
+
+// Per bra point of the super-block: wt = w sum_l G_l xi_l(g), H_c = sum_l G_l calG^c_lg,
+// and the energy-scale partials w rho T3rho and w rho |A_gamma|^2; also copies the field.
+__global__ __launch_bounds__(256) void k_point_vectors(
+    const double* __restrict__ xi, const double* __restrict__ w, const double* __restrict__ rho,
+    const double* __restrict__ G, long n_g, int n_mu, long b0, long bn,
+    const double* __restrict__ panel, long rows_pad, long bp, int need_h, double* __restrict__ wt,
+    double* __restrict__ H, double* __restrict__ e3x, double* __restrict__ e4x,
+    double* __restrict__ field) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= bn) return;
+  const long g = b0 + t;
+  if (need_h) {
+    double s = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    for (int l = 0; l < n_mu; ++l) {
+      const double gl = G[l];
+      s += gl * xi[(long)l * n_g + g];
+      h0 += gl * panel[((long)0 * rows_pad + l) * bp + t];
+      h1 += gl * panel[((long)1 * rows_pad + l) * bp + t];
+      h2 += gl * panel[((long)2 * rows_pad + l) * bp + t];
+    }
+    wt[t] = w[g] * s;
+    H[t] = h0;
+    H[bp + t] = h1;
+    H[2 * bp + t] = h2;
+  }
+  const double a0 = panel[((long)0 * rows_pad + n_mu) * bp + t];
+  const double a1 = panel[((long)1 * rows_pad + n_mu) * bp + t];
+  const double a2 = panel[((long)2 * rows_pad + n_mu) * bp + t];
+  const double t3 = panel[((long)3 * rows_pad + n_mu) * bp + t];
+  const double wr = w[g] * rho[g];
+  e3x[t] = wr * t3;
+  e4x[t] = wr * (a0 * a0 + a1 * a1 + a2 * a2);
+  if (field) {
+    field[g] = a0;
+    field[n_g + g] = a1;
+    field[2 * n_g + g] = a2;
+  }
+}
+
+// V[nu][g] = sum_c H_c(g) calG^c[nu][g]
+__global__ __launch_bounds__(256) void k_form_V(const double* __restrict__ panel, long rows_pad,
+                                                long bp, int n_mu, long bn,
+                                                const double* __restrict__ H,
+                                                double* __restrict__ V) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long)n_mu * bn) return;
+  const long nu = t / bn, g = t % bn;
+  V[nu * bp + g] = H[g] * panel[nu * bp + g] + H[bp + g] * panel[(rows_pad + nu) * bp + g] +
+                   H[2 * bp + g] * panel[(2 * rows_pad + nu) * bp + g];
+}
+
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b, long n,
+                      double* __restrict__ out) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+struct ConLayout {
+  long* piv; double* G; double* panel; double* V; double* wt; double* H; double* e3x; double* e4x;
+  double* sums; double* red; double* y; double* prod; double* esc; void* split; size_t split_bytes;
+  long bp; long rows_pad; int nsb; int nch;
+};
+
+static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision) {
+  ConLayout C;
+  C.nch = (channels & XTC_ULAP) ? 5 : 4;
+  C.bp = n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
+  C.rows_pad = ((n_mu + 1 + 63) / 64) * 64;
+  C.nsb = (int)cdiv(n_g, C.bp);
+  C.piv = ar.take<long>(n_mu);
+  C.G = ar.take<double>(n_mu);
+  C.panel = ar.take<double>((size_t)C.nch * C.rows_pad * C.bp);
+  C.V = (channels & XTC_D1) ? ar.take<double>((size_t)n_mu * C.bp) : nullptr;
+  C.wt = ar.take<double>(C.bp);
+  C.H = ar.take<double>(3 * (size_t)C.bp);
+  C.e3x = ar.take<double>(C.bp);
+  C.e4x = ar.take<double>(C.bp);
+  C.sums = ar.take<double>(2 * (size_t)C.nsb + 2);
+  C.red = ar.take<double>(1024);
+  C.y = ar.take<double>(n_mu);
+  C.prod = ar.take<double>(n_mu);
+  C.esc = ar.take<double>(8);
+  C.split_bytes = precision == XTC_SPLIT_F16 ? split_scratch_bytes(n_g, n_mu) : 0;
+  C.split = C.split_bytes ? (void*)ar.take<char>(C.split_bytes) : nullptr;
+  return C;
+}
+
+size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags) {
+  Arena ar(nullptr, 0);
+  layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff));
+  return ar.used;
+}
+
+static xtc_status quad_form(const double* M, const double* G, int n, double* out, ConLayout& C,
+                            hipStream_t st) {
+  GemmArgs g{};
+  g.M = n; g.N = 1; g.K = n;
+  g.A = M; g.a_sm = n; g.a_sk = 1;
+  g.B = G; g.b_sk = 1; g.b_sn = 1;
+  g.C = C.y; g.c_sm = 1; g.c_sn = 1;
+  XTC_TRY(gemm_f64(g, st));
+  hipLaunchKernelGGL(k_mul, dim3(cdiv(n, 256)), dim3(256), 0, st, G, (const double*)C.y, (long)n,
+                     C.prod);
+  XTC_CHECK_LAUNCH();
+  return reduce_sum_f64(C.prod, n, out, C.red, st);
+}
+
+}  // namespace xtc
+
+using namespace xtc;
+
+static xtc_status check_contract_args(const xtc_grid* grid, const xtc_correlator* corr,
+                                      int32_t n_mu, const double* xi, const double* xigrad,
+                                      const double* rho, const int64_t* pivots,
+                                      uint32_t channels, int32_t precision) {
+  XTC_REQUIRE(grid && corr && xi && rho && pivots, "contract: null argument");
+  XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "contract: empty grid");
+  XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "contract: bad n_mu");
+  XTC_REQUIRE(!(channels & XTC_U1) || xigrad, "contract: XTC_U1 needs xigrad");
+  XTC_REQUIRE((channels & ~127u) == 0, "contract: unknown channel bits");
+  XTC_REQUIRE(precision == XTC_FP64 || precision == XTC_SPLIT_F16, "contract: bad precision");
+  XTC_REQUIRE(corr->n_terms > 0 && corr->mno && corr->c && corr->d > 0.0,
+              "contract: bad correlator");
+  for (int m = 0; m < n_mu; ++m)
+    XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "contract: pivot index out of range");
+  if (corr->form != XTC_U_EE) {
+    set_error("contract: this entry point evaluates the EE correlator form");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  return XTC_OK;
+}
+
+extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
+                                          int32_t n_mu, const double* xi, const double* xigrad,
+                                          const double* rho, const int64_t* pivots,
+                                          uint32_t channels, int32_t precision, double* u1,
+                                          double* u3, double* ulap, double* D1, double* D4,
+                                          double* field, double* escale, void* ws,
+                                          size_t ws_bytes, void* stream) {
+  XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+  XTC_REQUIRE(!(channels & XTC_U1) || u1, "contract: u1 output NULL");
+  XTC_REQUIRE(!(channels & XTC_U3) || u3, "contract: u3 output NULL");
+  XTC_REQUIRE(!(channels & XTC_ULAP) || ulap, "contract: ulap output NULL");
+  XTC_REQUIRE(!(channels & XTC_D1) || D1, "contract: D1 output NULL");
+  XTC_REQUIRE(!(channels & XTC_D4) || D4, "contract: D4 output NULL");
+  XTC_REQUIRE(!(channels & XTC_FIELD) || field, "contract: field output NULL");
+  XTC_REQUIRE(!(channels & XTC_ESCALE) || escale, "contract: escale output NULL");
+  EECoef cf;
+  XTC_TRY(ee_coefficients(corr, &cf));
+  hipStream_t st = as_stream(stream);
+  const long n_g = grid->n_g;
+  Arena ar(ws, ws_bytes);
+  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision);
+  XTC_TRY(need_ws(ar));
+  XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
+                     (const long*)C.piv, n_mu, C.G);
+  XTC_CHECK_LAUNCH();
+  Stage1Args s1{grid->xyz, grid->w, xi, rho, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp, C.nch};
+  if (precision == XTC_SPLIT_F16) XTC_TRY(split_prepare(s1, C.split, st));
+  const bool need_h = (channels & (XTC_D1 | XTC_D4)) != 0;
+  for (int sb = 0; sb < C.nsb; ++sb) {
+    const long b0 = (long)sb * C.bp;
+    const long bn = (n_g - b0) < C.bp ? (n_g - b0) : C.bp;
+    s1.b0 = b0;
+    s1.bn = bn;
+    if (precision == XTC_FP64) XTC_TRY(stage1_f64(s1, cf, st));
+    else XTC_TRY(stage1_split_f16(s1, cf, C.split, C.split_bytes, st));
+    const double beta = sb == 0 ? 0.0 : 1.0;
+    auto nt = [&](const double* A, long a_sm, const double* s, const double* B, double* out,
+                  double bet) {
+      GemmArgs g{};
+      g.M = n_mu; g.N = n_mu; g.K = bn;
+      g.A = A; g.a_sm = a_sm; g.a_sk = 1;
+      g.s = s;
+      g.B = B; g.b_sk = 1; g.b_sn = C.bp;
+      g.C = out; g.c_sm = n_mu; g.c_sn = 1;
+      g.beta = bet;
+      return gemm_f64(g, st);
+    };
+    const double* wb = grid->w + b0;
+    if (channels & XTC_U1)
+      for (int c = 0; c < 3; ++c)
+        XTC_TRY(nt(xigrad + (long)c * n_mu * n_g + b0, n_g, wb, C.panel + (long)c * C.rows_pad * C.bp,
+                   u1 + (long)c * n_mu * n_mu, beta));
+    if (channels & XTC_U3)
+      XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 3L * C.rows_pad * C.bp, u3, beta));
+    if (channels & XTC_ULAP)
+      XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 4L * C.rows_pad * C.bp, ulap, beta));
+    hipLaunchKernelGGL(k_point_vectors, dim3(cdiv(bn, 256)), dim3(256), 0, st, xi, grid->w, rho,
+                       (const double*)C.G, n_g, n_mu, b0, bn, (const double*)C.panel, C.rows_pad,
+                       C.bp, need_h ? 1 : 0, C.wt, C.H, C.e3x, C.e4x,
+                       (channels & XTC_FIELD) ? field : nullptr);
+    XTC_CHECK_LAUNCH();
+    if (channels & XTC_D4)
+      for (int c = 0; c < 3; ++c) {
+        const double* Pc = C.panel + (long)c * C.rows_pad * C.bp;
+        XTC_TRY(nt(Pc, C.bp, C.wt, Pc, D4, (sb == 0 && c == 0) ? 0.0 : 1.0));
+      }
+    if (channels & XTC_D1) {
+      hipLaunchKernelGGL(k_form_V, dim3(cdiv((long)n_mu * bn, 256)), dim3(256), 0, st,
+                         (const double*)C.panel, C.rows_pad, C.bp, n_mu, bn, (const double*)C.H,
+                         C.V);
+      XTC_CHECK_LAUNCH();
+      XTC_TRY(nt(xi + b0, n_g, wb, C.V, D1, beta));
+    }
+    XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 2 * sb, C.red, st));
+    XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 2 * sb + 1, C.red, st));
+  }
+  if (channels & XTC_ESCALE) {
+    XTC_HIP(hipMemsetAsync(C.esc, 0, 8 * sizeof(double), st));
+    if (channels & XTC_U3) XTC_TRY(quad_form(u3, C.G, n_mu, C.esc + 0, C, st));
+    if (channels & XTC_D4) XTC_TRY(quad_form(D4, C.G, n_mu, C.esc + 1, C, st));
+    if (channels & XTC_D1) XTC_TRY(quad_form(D1, C.G, n_mu, C.esc + 2, C, st));
+    std::vector<double> hs(2 * C.nsb), he(8);
+    XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 2 * C.nsb, hipMemcpyDeviceToHost, st));
+    XTC_HIP(hipMemcpyAsync(he.data(), C.esc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+    XTC_HIP(hipStreamSynchronize(st));
+    double e3x = 0.0, e4x = 0.0;
+    for (int sb = 0; sb < C.nsb; ++sb) {
+      e3x += hs[2 * sb];
+      e4x += hs[2 * sb + 1];
+    }
+    escale[0] = he[0];
+    escale[1] = he[1];
+    escale[2] = 2.0 * he[2];
+    escale[3] = e3x;
+    escale[4] = e4x;
+    escale[5] = 2.0 * e4x;
+  }
+  return XTC_OK;
+}
+
+namespace xtc {
+size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags) {
+  (void)n_g; (void)n_mu; (void)n_params; (void)flags;
+  return 0;
+}
+size_t split_scratch_bytes(long n_g, int n_mu) { (void)n_g; (void)n_mu; return 0; }
+xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st) {
+  (void)a; (void)scratch; (void)st;
+  set_error("split precision not built yet");
+  return XTC_ERR_UNSUPPORTED;
+}
+xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch, size_t bytes,
+                            hipStream_t st) {
+  (void)a; (void)cf; (void)scratch; (void)bytes; (void)st;
+  return XTC_ERR_UNSUPPORTED;
+}
+}  // namespace xtc
+
+extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                               const double* xi, const double* xigrad, const double* rho,
+                               const int64_t* pivots, const double* gu1, const double* gu3,
+                               const double* gulap, const double* gD1, const double* gD4,
+                               const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
+                               void* stream) {
+  (void)grid; (void)corr; (void)n_mu; (void)xi; (void)xigrad; (void)rho; (void)pivots; (void)gu1;
+  (void)gu3; (void)gulap; (void)gD1; (void)gD4; (void)gfield; (void)dtheta; (void)ws;
+  (void)ws_bytes; (void)stream;
+  xtc::set_error("xtc_grad: not built yet");
+  return XTC_ERR_UNSUPPORTED;
+}

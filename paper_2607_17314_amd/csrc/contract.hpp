@@ -1,0 +1,38 @@
+// Internal interface between the contraction driver and its stage-1 kernels.
+#pragma once
+#include "common.hpp"
+
+namespace xtc {
+
+constexpr int MAXQ = 16;
+
+// EE correlator u = sum_k c_k rbar^{o_k}, rbar = d r t, t = 1/(1 + d r), as
+// polynomials in rbar:  u' = d t^2 Q1(rbar),  (u'/r)_{o>=2} = d^2 t^3 Q2(rbar),
+// u''_{o>=2} = d^2 t^4 Q3(rbar);  c1 = sum of c_k over o_k = 1.
+struct EECoef {
+  double d;
+  double c1;
+  double q1[MAXQ];
+  double q2[MAXQ];
+  double q3[MAXQ];
+  int n1, n2, n3;
+};
+
+xtc_status ee_coefficients(const xtc_correlator* corr, EECoef* out);
+
+// Stage 1 over one bra super-block [b0, b0 + bn): panel[ch][row][b - b0] for
+// rows 0..n_mu (row n_mu is the rho row), ch = gx, gy, gz, sq (, lap).
+struct Stage1Args {
+  const double* xyz; const double* w; const double* xi; const double* rho;
+  long n_g; int n_mu; long b0; long bn;
+  double* panel; long rows_pad; long bp;
+  int nch;
+};
+
+xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);
+xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch,
+                            size_t scratch_bytes, hipStream_t st);
+size_t split_scratch_bytes(long n_g, int n_mu);
+xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st);
+
+}  // namespace xtc

@@ -1,0 +1,402 @@
+// ISDF fit of the auxiliary vectors (ISDF section, eq. isdf-rho and its normal
+// equations; auxiliary-fit robustness). Per system (scalar, then x, y, z):
+//   Gram      A = (Phi_mu^T Phi_mu) o (Phi_mu^T Phi_mu) or (dPhi_mu^T dPhi_mu)_c o G, FP64 MFMA GEMMs
+//   Cholesky  blocked right-looking FP64 factorisation (64-wide panels); the
+//             diagonal block is factored and inverted in LDS by one workgroup,
+//             panel and trailing updates are GEMMs; on a non-positive pivot the
+//             adaptive Tikhonov retry re-factors A + shift_k I
+//   RHS       per grid chunk: P = Phi_mu^T Phi, B = P o P or (dPhi_mu^T dPhi)_c o P
+//   solves    blocked forward and backward substitution as GEMMs with the
+//             inverted diagonal blocks; the weighted residual
+//             sum_g w^2 (|m_g|^2 - |L^{-1} B(g)|^2) falls out of the forward solve.
+// The fit is column-separable in g, so the grid is processed in chunks and the
+// workspace does not grow with n_g beyond one chunk.
+#include "common.hpp"
+#include "plans.hpp"
+
+namespace xtc {
+
+constexpr int NB = 64;
+constexpr long FIT_CHUNK = 65536;
+
+__global__ void k_gather_piv(const double* __restrict__ phi4, long n_g, int rows,
+                             const long* __restrict__ piv, int n_mu, double* __restrict__ out) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  long total = (long)rows * n_mu;
+  if (t >= total) return;
+  int r = (int)(t / n_mu), m = (int)(t % n_mu);
+  out[t] = phi4[(long)r * n_g + piv[m]];
+}
+
+// Factor the NB x NB diagonal block at (j0, j0) of the n x n matrix a (row-major,
+// lower triangle used) in LDS, write L_jj back (upper part zeroed) and its
+// inverse to linv [NB][NB]; a non-positive or non-finite pivot sets *fail.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ a, long n, long j0,
+                                                    int nb, double* __restrict__ linv,
+                                                    int* __restrict__ fail) {
+  __shared__ double s[NB][NB + 1];
+  __shared__ double sinv[NB][NB + 1];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int e = t; e < NB * NB; e += 256) {
+    int i = e / NB, k = e % NB;
+    s[i][k] = (i < nb && k < nb && k <= i) ? a[(j0 + i) * n + j0 + k] : 0.0;
+    sinv[i][k] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (t == 0) {
+      double v = s[j][j];
+      if (!(v > 0.0) || !isfinite(v)) {
+        bad = 1;
+        v = 1.0;
+      }
+      s[j][j] = sqrt(v);
+    }
+    __syncthreads();
+    const double dj = s[j][j];
+    for (int i = j + 1 + t; i < nb; i += 256) s[i][j] /= dj;
+    __syncthreads();
+    const int m = nb - j - 1;   // trailing (i, k), j < k <= i < nb
+    for (int e = t; e < m * m; e += 256) {
+      int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) s[i][k] -= s[i][j] * s[k][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular block, one column per thread
+  if (t < nb) {
+    const int c = t;
+    for (int i = 0; i < nb; ++i) {
+      if (i < c) continue;
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= s[i][k] * sinv[k][c];
+      sinv[i][c] = v / s[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += 256) {
+    int i = e / NB, k = e % NB;
+    linv[e] = (i < nb && k < nb) ? sinv[i][k] : 0.0;
+    if (i < nb && k < nb) a[(j0 + i) * n + j0 + k] = (k <= i) ? s[i][k] : 0.0;
+  }
+  if (t == 0 && bad) *fail = 1;
+}
+
+__global__ void k_diag_extract(const double* __restrict__ a, long n, double* __restrict__ dg) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dg[i] = a[i * n + i];
+}
+
+__global__ void k_restore_shift(const double* __restrict__ src, double* __restrict__ dst, long n,
+                                double shift) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n * n) return;
+  long i = t / n, k = t % n;
+  dst[t] = src[t] + ((i == k) ? shift : 0.0);
+}
+
+__global__ void k_square(double* __restrict__ x, long n) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) x[t] = x[t] * x[t];
+}
+
+__global__ void k_copy_rows(const double* __restrict__ src, long lds, double* __restrict__ dst,
+                            long ldd, int rows, long cols) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long)rows * cols) return;
+  long r = t / cols, c = t % cols;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+// per grid point of a chunk: w^2 (|m_g|^2 - |y_g|^2) and w^2 |m_g|^2, channel c (-1 scalar)
+__global__ void k_resid(const double* __restrict__ phi4, const double* __restrict__ w, long n_g,
+                        int n_orb, int comp, long g0, long cn, const double* __restrict__ y,
+                        long ldy, int n_mu, double* __restrict__ r_out,
+                        double* __restrict__ m_out) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= cn) return;
+  long g = g0 + t;
+  double n2 = 0.0;
+  for (int p = 0; p < n_orb; ++p) {
+    double v = phi4[(long)p * n_g + g];
+    n2 += v * v;
+  }
+  double m2;
+  if (comp < 0) {
+    m2 = n2 * n2;
+  } else {
+    double g2 = 0.0;
+    for (int p = 0; p < n_orb; ++p) {
+      double v = phi4[(long)((1 + comp) * n_orb + p) * n_g + g];
+      g2 += v * v;
+    }
+    m2 = n2 * g2;
+  }
+  double yy = 0.0;
+  for (int m = 0; m < n_mu; ++m) {
+    double v = y[(long)m * ldy + t];
+    yy += v * v;
+  }
+  double ww = w[g] * w[g];
+  r_out[t] = ww * (m2 - yy);
+  m_out[t] = ww * m2;
+}
+
+struct FitLayout {
+  long* piv; double* phimu; double* G; double* A; double* Asave; double* linv; double* P;
+  double* R; double* rtmp; double* mtmp; double* red; double* sums; int* fail; double* dg;
+  long chunk; int nblk; int nchunks;
+};
+
+static FitLayout layout_fit(Arena& ar, int64_t n_g, int n_orb, int n_mu) {
+  FitLayout F;
+  F.chunk = n_g < FIT_CHUNK ? n_g : FIT_CHUNK;
+  F.nblk = (int)cdiv(n_mu, NB);
+  F.nchunks = (int)cdiv(n_g, F.chunk);
+  F.piv = ar.take<long>(n_mu);
+  F.phimu = ar.take<double>(4 * (size_t)n_orb * n_mu);
+  F.G = ar.take<double>((size_t)n_mu * n_mu);
+  F.A = ar.take<double>((size_t)n_mu * n_mu);
+  F.Asave = ar.take<double>((size_t)n_mu * n_mu);
+  F.linv = ar.take<double>((size_t)F.nblk * NB * NB);
+  F.P = ar.take<double>((size_t)n_mu * F.chunk);
+  F.R = ar.take<double>((size_t)n_mu * F.chunk);
+  F.rtmp = ar.take<double>(F.chunk);
+  F.mtmp = ar.take<double>(F.chunk);
+  F.red = ar.take<double>(1024);
+  F.sums = ar.take<double>(2 * (size_t)F.nchunks + 2);
+  F.fail = ar.take<int>(1);
+  F.dg = ar.take<double>(n_mu);
+  return F;
+}
+
+size_t ws_fit(int64_t n_g, int n_orb, int n_mu, uint32_t what) {
+  (void)what;
+  Arena ar(nullptr, 0);
+  layout_fit(ar, n_g, n_orb, n_mu);
+  return ar.used;
+}
+
+// Blocked Cholesky of F.A (n x n) in place; returns 0 on success, 1 on failure.
+static xtc_status cholesky(FitLayout& F, long n, hipStream_t st, int* failed) {
+  XTC_HIP(hipMemsetAsync(F.fail, 0, sizeof(int), st));
+  for (int b = 0; b < F.nblk; ++b) {
+    long j0 = (long)b * NB;
+    int nb = (int)((n - j0) < NB ? (n - j0) : NB);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, F.A, n, j0, nb,
+                       F.linv + (long)b * NB * NB, F.fail);
+    XTC_CHECK_LAUNCH();
+    long rest = n - j0 - nb;
+    if (rest <= 0) continue;
+    GemmArgs p{};   // L21 = A21 Linv_jj^T (in place)
+    p.M = rest; p.N = nb; p.K = nb;
+    p.A = F.A + (j0 + nb) * n + j0; p.a_sm = n; p.a_sk = 1;
+    p.B = F.linv + (long)b * NB * NB; p.b_sk = 1; p.b_sn = NB;
+    p.C = F.A + (j0 + nb) * n + j0; p.c_sm = n; p.c_sn = 1;
+    XTC_TRY(gemm_f64(p, st));
+    GemmArgs u{};   // A22 -= L21 L21^T (lower tiles)
+    u.M = rest; u.N = rest; u.K = nb;
+    u.A = F.A + (j0 + nb) * n + j0; u.a_sm = n; u.a_sk = 1;
+    u.B = F.A + (j0 + nb) * n + j0; u.b_sk = 1; u.b_sn = n;
+    u.C = F.A + (j0 + nb) * n + j0 + nb; u.c_sm = n; u.c_sn = 1;
+    u.alpha = -1.0; u.beta = 1.0; u.lower_only = true;
+    XTC_TRY(gemm_f64(u, st));
+  }
+  int h = 0;
+  XTC_HIP(hipMemcpyAsync(&h, F.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  XTC_HIP(hipStreamSynchronize(st));
+  *failed = h;
+  return XTC_OK;
+}
+
+// Solve A X = R for a chunk (R: [n][cn], ld = chunk) with the factor in F.A;
+// X goes to out (row stride ldo). Also records the residual sums of the chunk.
+static xtc_status solve_chunk(FitLayout& F, long n, long cn, double* out, long ldo,
+                              hipStream_t st) {
+  // forward: Y_i = Linv_ii (R_i - L_i,<i Y_<i), Y stored in out
+  for (int b = 0; b < F.nblk; ++b) {
+    long i0 = (long)b * NB;
+    long nb = (n - i0) < NB ? (n - i0) : NB;
+    if (i0 > 0) {
+      GemmArgs g{};
+      g.M = nb; g.N = cn; g.K = i0;
+      g.A = F.A + i0 * n; g.a_sm = n; g.a_sk = 1;
+      g.B = out; g.b_sk = ldo; g.b_sn = 1;
+      g.C = F.R + i0 * F.chunk; g.c_sm = F.chunk; g.c_sn = 1;
+      g.alpha = -1.0; g.beta = 1.0;
+      XTC_TRY(gemm_f64(g, st));
+    }
+    GemmArgs d{};
+    d.M = nb; d.N = cn; d.K = nb;
+    d.A = F.linv + (long)b * NB * NB; d.a_sm = NB; d.a_sk = 1;
+    d.B = F.R + i0 * F.chunk; d.b_sk = F.chunk; d.b_sn = 1;
+    d.C = out + i0 * ldo; d.c_sm = ldo; d.c_sn = 1;
+    XTC_TRY(gemm_f64(d, st));
+  }
+  return XTC_OK;
+}
+
+static xtc_status back_chunk(FitLayout& F, long n, long cn, double* out, long ldo,
+                             hipStream_t st) {
+  for (int b = F.nblk - 1; b >= 0; --b) {
+    long i0 = (long)b * NB;
+    long nb = (n - i0) < NB ? (n - i0) : NB;
+    long i1 = i0 + nb;
+    if (i1 < n) {
+      GemmArgs g{};   // R_i = Y_i - L_{>i,i}^T X_{>i}
+      g.M = nb; g.N = cn; g.K = n - i1;
+      g.A = F.A + i1 * n + i0; g.a_sm = 1; g.a_sk = n;
+      g.B = out + i1 * ldo; g.b_sk = ldo; g.b_sn = 1;
+      g.C = F.R + i0 * F.chunk; g.c_sm = F.chunk; g.c_sn = 1;
+      g.alpha = -1.0; g.beta = 1.0;   // R_i holds a copy of Y_i (below)
+      hipLaunchKernelGGL(k_copy_rows, dim3(cdiv(nb * cn, 256)), dim3(256), 0, st,
+                         (const double*)(out + i0 * ldo), ldo, F.R + i0 * F.chunk, F.chunk,
+                         (int)nb, cn);
+      XTC_CHECK_LAUNCH();
+      XTC_TRY(gemm_f64(g, st));
+    } else {
+      hipLaunchKernelGGL(k_copy_rows, dim3(cdiv(nb * cn, 256)), dim3(256), 0, st,
+                         (const double*)(out + i0 * ldo), ldo, F.R + i0 * F.chunk, F.chunk,
+                         (int)nb, cn);
+      XTC_CHECK_LAUNCH();
+    }
+    GemmArgs d{};   // X_i = Linv_ii^T R_i
+    d.M = nb; d.N = cn; d.K = nb;
+    d.A = F.linv + (long)b * NB * NB; d.a_sm = 1; d.a_sk = NB;
+    d.B = F.R + i0 * F.chunk; d.b_sk = F.chunk; d.b_sn = 1;
+    d.C = out + i0 * ldo; d.c_sm = ldo; d.c_sn = 1;
+    XTC_TRY(gemm_f64(d, st));
+  }
+  return XTC_OK;
+}
+
+}  // namespace xtc
+
+using namespace xtc;
+
+extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
+                               const int64_t* pivots, int32_t n_mu, uint32_t what, double* xi,
+                               double* xigrad, double* info, void* ws, size_t ws_bytes,
+                               void* stream) {
+  XTC_REQUIRE(phi4 && grid && pivots, "isdf_fit: null argument");
+  XTC_REQUIRE(grid->n_g > 0 && grid->w, "isdf_fit: empty grid");
+  XTC_REQUIRE(n_orb > 0 && n_mu > 0 && n_mu <= grid->n_g, "isdf_fit: bad sizes");
+  XTC_REQUIRE(!(what & XTC_FIT_XI) || xi, "isdf_fit: xi requested but NULL");
+  XTC_REQUIRE(!(what & XTC_FIT_XIGRAD) || xigrad, "isdf_fit: xigrad requested but NULL");
+  XTC_REQUIRE(what & (XTC_FIT_XI | XTC_FIT_XIGRAD), "isdf_fit: nothing requested");
+  const long n_g = grid->n_g;
+  for (int m = 0; m < n_mu; ++m)
+    XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < n_g, "isdf_fit: pivot index out of range");
+  hipStream_t st = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
+  XTC_TRY(need_ws(ar));
+  XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_gather_piv, dim3(cdiv(4L * n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
+                     n_g, 4 * n_orb, (const long*)F.piv, n_mu, F.phimu);
+  XTC_CHECK_LAUNCH();
+  const long n = n_mu;
+  // G = Phi_mu^T Phi_mu
+  {
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = n_orb;
+    g.A = F.phimu; g.a_sm = 1; g.a_sk = n;
+    g.B = F.phimu; g.b_sk = n; g.b_sn = 1;
+    g.C = F.G; g.c_sm = n; g.c_sn = 1;
+    XTC_TRY(gemm_f64(g, st));
+  }
+  double jit[4] = {-1, -1, -1, -1}, rel[4] = {0, 0, 0, 0};
+  bool any_jitter = false;
+  for (int sys = 0; sys < 4; ++sys) {
+    const int comp = sys - 1;   // -1 scalar, 0..2 gradient component
+    if (sys == 0 && !(what & XTC_FIT_XI)) continue;
+    if (sys > 0 && !(what & XTC_FIT_XIGRAD)) continue;
+    double* out = sys == 0 ? xi : xigrad + (long)comp * n * n_g;
+    // Gram of this system
+    {
+      GemmArgs g{};
+      g.M = n; g.N = n; g.K = n_orb;
+      const double* ph = F.phimu + (long)(sys == 0 ? 0 : (1 + comp)) * n_orb * n;
+      g.A = ph; g.a_sm = 1; g.a_sk = n;
+      g.B = ph; g.b_sk = n; g.b_sn = 1;
+      g.C = F.A; g.c_sm = n; g.c_sn = 1;
+      g.epi = EPI_MUL_E; g.E = F.G; g.e_sm = n; g.e_sn = 1;
+      XTC_TRY(gemm_f64(g, st));
+    }
+    XTC_HIP(hipMemcpyAsync(F.Asave, F.A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+    int failed = 0;
+    XTC_TRY(cholesky(F, n, st, &failed));
+    if (failed) {
+      hipLaunchKernelGGL(k_diag_extract, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                         (const double*)F.Asave, n, F.dg);
+      std::vector<double> hd(n);
+      XTC_HIP(hipMemcpyAsync(hd.data(), F.dg, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      XTC_HIP(hipStreamSynchronize(st));
+      double mean = 0.0;
+      for (long i = 0; i < n; ++i) mean += hd[i];
+      mean /= (double)n;
+      int k = 0;
+      for (; k < 9 && failed; ++k) {
+        double shift = 1e-14 * pow(10.0, k) * mean;
+        hipLaunchKernelGGL(k_restore_shift, dim3(cdiv(n * n, 256)), dim3(256), 0, st,
+                           (const double*)F.Asave, F.A, n, shift);
+        XTC_CHECK_LAUNCH();
+        XTC_TRY(cholesky(F, n, st, &failed));
+        if (!failed) break;
+      }
+      if (failed) {
+        set_error("isdf_fit: Gram matrix not positive definite after the last Tikhonov shift");
+        return XTC_ERR_NOT_SPD;
+      }
+      jit[sys] = k;
+      any_jitter = true;
+    }
+    // chunks over the grid
+    for (int c = 0; c < F.nchunks; ++c) {
+      long g0 = (long)c * F.chunk;
+      long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
+      GemmArgs p{};   // P = Phi_mu^T Phi (chunk)
+      p.M = n; p.N = cn; p.K = n_orb;
+      p.A = F.phimu; p.a_sm = 1; p.a_sk = n;
+      p.B = phi4 + g0; p.b_sk = n_g; p.b_sn = 1;
+      p.C = F.P; p.c_sm = F.chunk; p.c_sn = 1;
+      XTC_TRY(gemm_f64(p, st));
+      GemmArgs r{};   // B = P o P or (dPhi_mu^T dPhi)_c o P
+      r.M = n; r.N = cn; r.K = n_orb;
+      const double* ph = F.phimu + (long)(sys == 0 ? 0 : (1 + comp)) * n_orb * n;
+      r.A = ph; r.a_sm = 1; r.a_sk = n;
+      r.B = phi4 + (long)(sys == 0 ? 0 : (1 + comp)) * n_orb * n_g + g0; r.b_sk = n_g; r.b_sn = 1;
+      r.C = F.R; r.c_sm = F.chunk; r.c_sn = 1;
+      r.epi = EPI_MUL_E; r.E = F.P; r.e_sm = F.chunk; r.e_sn = 1;
+      XTC_TRY(gemm_f64(r, st));
+      XTC_TRY(solve_chunk(F, n, cn, out + g0, n_g, st));
+      hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g,
+                         n_orb, comp, g0, cn, (const double*)(out + g0), n_g, n_mu, F.rtmp,
+                         F.mtmp);
+      XTC_CHECK_LAUNCH();
+      XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
+      XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
+      XTC_TRY(back_chunk(F, n, cn, out + g0, n_g, st));
+    }
+    std::vector<double> hs(2 * F.nchunks);
+    XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks,
+                           hipMemcpyDeviceToHost, st));
+    XTC_HIP(hipStreamSynchronize(st));
+    double rs = 0.0, ms = 0.0;
+    for (int c = 0; c < F.nchunks; ++c) {
+      rs += hs[2 * c];
+      ms += hs[2 * c + 1];
+    }
+    rel[sys] = ms > 0.0 ? rs / ms : 0.0;
+  }
+  XTC_HIP(hipStreamSynchronize(st));
+  if (info) {
+    for (int i = 0; i < 4; ++i) {
+      info[i] = jit[i];
+      info[4 + i] = rel[i];
+    }
+  }
+  return any_jitter ? XTC_WARN_JITTER : XTC_OK;
+}

@@ -1,0 +1,13 @@
+// Workspace sizing of every entry point (dry runs of the same arena layouts
+// the calls use).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace xtc {
+size_t ws_eval_orbitals(int64_t n_g, int n_orb, int n_ao);
+size_t ws_select(int64_t n_g, int n_orb, int n_mu, int mode);
+size_t ws_fit(int64_t n_g, int n_orb, int n_mu, uint32_t what);
+size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags);
+size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags);
+}  // namespace xtc

@@ -1,0 +1,150 @@
+// Stage 1 of the grid-pair contraction in FP64 (K-kernel section: the
+// doubly-blocked grid sums, each auxiliary vector used once per grid pair):
+//   panel[ch][row][g] = sum_g' A[row][g'] K_ch(g, g'),  A = [w xi ; w rho]
+// with the kernel channels K = (d_x u, d_y u, d_z u, |grad u|^2 [, lap u])
+// generated in registers for every (bra g, ket g') pair and never written to
+// HBM.
+//
+// Workgroup tile: 64 rows x 64 bra points, 256 threads = 4 waves in 2 x 2,
+// each wave 32 rows x 32 bra points per channel. Ket chunks of 16 points:
+//   * each thread loads 4 elements of the 64 x 16 A tile (scaled by w) and
+//     generates the NCH channels of 4 (bra, ket) pairs in FP64,
+//   * both go to LDS, then every wave runs 4 k-steps of
+//     v_mfma_f64_16x16x4f64 per channel and sub-tile.
+// The kernel tile is generated once per workgroup and reused by all 64 rows.
+#include "contract.hpp"
+
+namespace xtc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double horner(const double* q, int n, double x) {
+  double r = 0.0;
+  for (int j = n - 1; j >= 0; --j) r = r * x + q[j];
+  return r;
+}
+
+template <int NCH>
+__device__ __forceinline__ void ee_channels(const EECoef& cf, double dx, double dy, double dz,
+                                            double* out) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r = sqrt(r2);
+  const double t = 1.0 / (1.0 + cf.d * r);
+  const double e = cf.d * r * t;
+  const double t2 = t * t, t3 = t2 * t;
+  const double p1 = horner(cf.q1, cf.n1, e);
+  const double up = cf.d * t2 * p1;
+  double f = cf.d * cf.d * t3 * horner(cf.q2, cf.n2, e);
+  if (cf.c1 != 0.0 && r > 0.0) f += cf.c1 * cf.d * t2 / r;
+  out[0] = f * dx;
+  out[1] = f * dy;
+  out[2] = f * dz;
+  out[3] = up * up;
+  if (NCH > 4) {
+    double upp = cf.d * cf.d * t2 * t2 * horner(cf.q3, cf.n3, e) - 2.0 * cf.d * cf.d * t3 * p1;
+    if (cf.c1 != 0.0 && r == 0.0) upp += 2.0 * cf.d * cf.d * t3 * cf.c1;
+    out[NCH - 1] = upp + 2.0 * f;
+  }
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ xyz,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ xi,
+                                                    const double* __restrict__ rho, long n_g,
+                                                    int n_mu, long b0, long bn, EECoef cf,
+                                                    double* __restrict__ panel, long rows_pad,
+                                                    long bp) {
+  constexpr int KC = 16;
+  __shared__ double As[64][KC + 1];
+  __shared__ double Bs[NCH][KC][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)blockIdx.y * 64;
+  const long nb0 = (long)blockIdx.x * 64;
+  const int gb = tid & 63;
+  const int gk = tid >> 6;
+  long bra = b0 + nb0 + gb;
+  if (bra > b0 + bn - 1) bra = b0 + bn - 1;
+  const double xb = xyz[bra], yb = xyz[n_g + bra], zb = xyz[2 * n_g + bra];
+
+  d4 acc[NCH][2][2];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  const int li = lane & 15, lk = lane >> 4;
+  for (long k0 = 0; k0 < n_g; k0 += KC) {
+    double ra[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      const int row = e >> 4, kk = e & 15;
+      const long g = k0 + kk, rr = m0 + row;
+      double v = 0.0;
+      if (g < n_g && rr <= n_mu) v = w[g] * (rr < n_mu ? xi[rr * n_g + g] : rho[g]);
+      ra[j] = v;
+    }
+    double ch[4][NCH];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      long g = k0 + 4 * gk + q;
+      if (g > n_g - 1) g = n_g - 1;
+      ee_channels<NCH>(cf, xb - xyz[g], yb - xyz[n_g + g], zb - xyz[2 * n_g + g], ch[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      As[e >> 4][e & 15] = ra[j];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) Bs[c][4 * gk + q][gb] = ch[q][c];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const double a0 = As[32 * wm + li][4 * s + lk];
+      const double a1 = As[32 * wm + 16 + li][4 * s + lk];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double bb0 = Bs[c][4 * s + lk][32 * wn + li];
+        const double bb1 = Bs[c][4 * s + lk][32 * wn + 16 + li];
+        acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb0, acc[c][0][0], 0, 0, 0);
+        acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb1, acc[c][0][1], 0, 0, 0);
+        acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb0, acc[c][1][0], 0, 0, 0);
+        acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb1, acc[c][1][1], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long row = m0 + 32 * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
+          const long col = nb0 + 32 * wn + 16 * j + li;
+          if (row <= n_mu && col < bn) panel[((long)c * rows_pad + row) * bp + col] = acc[c][i][j][r];
+        }
+}
+
+xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
+  dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 1, 64));
+  if (a.nch == 4)
+    hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.n_g,
+                       a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
+  else
+    hipLaunchKernelGGL(k_stage1_f64<5>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.n_g,
+                       a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
+  XTC_CHECK_LAUNCH();
+  return XTC_OK;
+}
+
+}  // namespace xtc

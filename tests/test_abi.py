@@ -1,0 +1,73 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before launching anything (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "isdf_xtc.h")
+LIBPATH = os.path.join(ROOT, "paper_2607_17314_amd", "libisdfxtc.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIBPATH), reason="library not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:xtc|isdf)_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_2607_17314_amd import _lib
+    L = _lib.lib()
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(_lib.EXPORTED) <= set(names)
+
+
+def test_version_and_workspace_sizes():
+    from paper_2607_17314_amd import api, _lib as L
+    assert "gfx950" in api.version()
+    for call in (L.XTC_CALL_EVAL_ORBITALS, L.XTC_CALL_SELECT, L.XTC_CALL_FIT, L.XTC_CALL_CONTRACT):
+        assert api.workspace_bytes(call, 17200, 24, 240, 56, 127) > 0
+    # the fit and selection scale with n_mu * chunk / n_mu * n_g
+    assert api.workspace_bytes(L.XTC_CALL_SELECT, 194000, 300, 3000) >= 3000 * 194000 * 8
+    assert api.workspace_bytes(L.XTC_CALL_FIT, 194000, 300, 3000) < 4 * 3000 * 194000 * 8
+
+
+def test_host_argument_checks_return_invalid_arg():
+    from paper_2607_17314_amd import _lib as L
+    lib = L.lib()
+    g = L.Grid(0, None, None)
+    assert lib.xtc_eval_orbitals(None, None, None, 1, 0, None, None, None, 0, None) == -1
+    assert b"null" in lib.xtc_last_error()
+    assert lib.isdf_fit(None, C.byref(g), 1, None, 1, 1, None, None, None, None, 0, None) == -1
+    piv = np.zeros(4, np.int64)
+    xyz = C.c_void_p(8)
+    g2 = L.Grid(10, xyz, xyz)
+    mno = np.array([[0, 0, 2]], np.int32)
+    cc = np.array([0.3])
+    corr = L.Correlator(0, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0, None, 0,
+                        None, None)
+    # pivots out of range are rejected before any launch
+    piv[:] = [0, 1, 2, 99]
+    st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
+                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, None, None, None, None, None,
+                                 None, None, 0, None)
+    assert st == -1 and b"pivot" in lib.xtc_last_error()
+    # unknown precision
+    piv[:] = [0, 1, 2, 3]
+    st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
+                                 piv.ctypes.data_as(L.I64), 2, 7, xyz, None, None, None, None, None,
+                                 None, None, 0, None)
+    assert st == -1
+    # a too-small workspace is reported as such, not as a crash
+    st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
+                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, xyz, None, None, None, None,
+                                 None, None, 0, None)
+    assert st == -4

@@ -1,0 +1,153 @@
+"""GPU parity of the FP64 path against the oracle, through the C ABI:
+orbitals, pivot selection (index parity), ISDF fit and the grid-pair
+contraction (all channels), on seeded workloads whose sizes span several
+tiles and a ragged tail."""
+import numpy as np
+import pytest
+
+from gpu_common import OracleCase, note, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+ALL = 1 | 2 | 8 | 16 | 32 | 64
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2607_17314_amd import api
+    note(f"library: {api.version()}")
+    return api
+
+
+@pytest.fixture(scope="module")
+def h4_case(h4):
+    return OracleCase(h4)
+
+
+@pytest.fixture(scope="module")
+def ragged_case(h6_small):
+    # 4963 points (not a multiple of 64) and 150 interpolation points
+    return OracleCase(h6_small, n_mu=150, subset=4963, seed=3)
+
+
+def _grid(api, case):
+    return api.DeviceGrid.from_host(case.xyz, case.w)
+
+
+@pytest.mark.parametrize("which", ["h4", "ragged"])
+def test_eval_orbitals(api, h4_case, ragged_case, which):
+    case = h4_case if which == "h4" else ragged_case
+    note(f"eval_orbitals {which} n_g={case.w.shape[0]}")
+    phi4, rho = api.eval_orbitals(case.wl.basis, _grid(api, case), case.wl.C_mo, case.wl.n_occ)
+    e1, e2 = rel_err(phi4.cpu().numpy(), case.phi4), rel_err(rho.cpu().numpy(), case.rho)
+    note(f"  phi4 rel err {e1:.2e}, rho rel err {e2:.2e}")
+    assert e1 < 1e-12 and e2 < 1e-12
+
+
+@pytest.mark.parametrize("which", ["h4", "ragged"])
+def test_select_points_index_parity(api, h4_case, ragged_case, which):
+    import torch
+    case = h4_case if which == "h4" else ragged_case
+    note(f"select_points {which} n_mu={case.n_mu}")
+    phi4 = torch.as_tensor(np.ascontiguousarray(case.phi4)).cuda()
+    piv, info, st = api.select_points(phi4, _grid(api, case), case.n_mu)
+    assert st == 0
+    ref = case.fused.pivots
+    # near-tie rule: identical up to the first step whose top-two gap is below 1e-10
+    tight = min(case.fused.scalar_state.gaps + case.fused.grad_state.gaps)
+    same = int(np.argmin(piv == ref)) if not np.array_equal(piv, ref) else len(ref)
+    note(f"  {len(piv)} pivots, identical prefix {same}, tightest gap {tight:.2e}")
+    if tight > 1e-10:
+        assert same == len(ref)
+    else:
+        k = next(i for i in range(len(ref)) if piv[i] != ref[i]) if not np.array_equal(piv, ref) else len(ref)
+        note(f"near tie (gap {tight:.2e}); identical for the first {k} pivots")
+    assert int(info[0]) == len(case.fused.scalar) and int(info[1]) == len(case.fused.grad)
+
+
+def test_fit_matches_oracle_well_conditioned(api, ragged_case):
+    """Gram condition numbers ~1e4-1e7: the solution is unique to ~kappa * eps."""
+    import torch
+    case = ragged_case
+    note("fit ragged (well conditioned)")
+    phi4 = torch.as_tensor(np.ascontiguousarray(case.phi4)).cuda()
+    xi, xig, info, st = api.fit(phi4, _grid(api, case), case.piv)
+    assert st == 0
+    e1, e2 = rel_err(xi.cpu().numpy(), case.fit.xi), rel_err(xig.cpu().numpy(), case.fit.xigrad)
+    note(f"  xi rel err {e1:.2e}, xigrad rel err {e2:.2e}, info {info}")
+    assert e1 < 1e-9 and e2 < 1e-8
+    assert np.allclose(info[4:], case.fit.resid_rel, rtol=1e-8, atol=1e-12)
+    n = len(case.piv)
+    assert np.abs(xi.cpu().numpy()[:, case.piv] - np.eye(n)).max() < 1e-9
+
+
+def test_fit_ill_conditioned_is_an_equally_good_fit(api, h4_case):
+    """H4 with N_mu = 240 exceeds the numerical pair rank (Gram condition ~1e16):
+    the factorisation may need the Tikhonov retry, and several xi are correct, so
+    the device fit is judged by its least-squares residual and by how well it
+    reproduces the pair products, against the oracle's."""
+    import torch
+    case = h4_case
+    phi4 = torch.as_tensor(np.ascontiguousarray(case.phi4)).cuda()
+    xi, xig, info, st = api.fit(phi4, _grid(api, case), case.piv)
+    note(f"fit h4 (ill conditioned): status {st}, info {info}, oracle jitter {case.fit.jitter} "
+         f"resid {case.fit.resid_rel}")
+    assert st in (0, 2)
+    for c in range(4):
+        assert info[4 + c] <= case.fit.resid_rel[c] + 1e-9
+    rng = np.random.default_rng(1)
+    gs = rng.choice(case.w.shape[0], 400, replace=False)
+    phi = case.phi4[0]
+    Cm = np.einsum("pm,qm->pqm", phi[:, case.piv], phi[:, case.piv])
+    rho = np.einsum("pg,qg->pqg", phi[:, gs], phi[:, gs])
+    x_gpu = xi.cpu().numpy()[:, gs]
+    err_gpu = np.abs(np.einsum("mg,pqm->pqg", x_gpu, Cm) - rho).max()
+    err_ref = np.abs(np.einsum("mg,pqm->pqg", case.fit.xi[:, gs], Cm) - rho).max()
+    note(f"  pair-product reproduction max error: device {err_gpu:.2e}, oracle {err_ref:.2e}")
+    assert err_gpu <= 2.0 * err_ref + 1e-9 * np.abs(rho).max()
+
+
+@pytest.mark.parametrize("which", ["h4", "ragged"])
+def test_contract_fp64_all_channels(api, h4_case, ragged_case, which):
+    import torch
+    case = h4_case if which == "h4" else ragged_case
+    note(f"contract fp64 {which} n_g={case.w.shape[0]} n_mu={case.n_mu}")
+    ref = case.contract(ALL | 4)
+    grid = _grid(api, case)
+    xi = torch.as_tensor(case.fit.xi).cuda()
+    xig = torch.as_tensor(case.fit.xigrad).cuda()
+    rho = torch.as_tensor(case.rho).cuda()
+    out = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL | 4)
+    torch.cuda.synchronize()
+    for k in ("u1", "u3", "ulap", "D1", "D4", "field"):
+        e = rel_err(out[k].cpu().numpy(), ref[k])
+        note(f"  {k}: rel err {e:.2e}")
+        assert e < TOL, k
+    assert np.allclose(out["escale"], ref["escale"], rtol=TOL, atol=0)
+
+
+def test_contract_is_deterministic(api, ragged_case):
+    import torch
+    case = ragged_case
+    grid = _grid(api, case)
+    xi = torch.as_tensor(case.fit.xi).cuda()
+    xig = torch.as_tensor(case.fit.xigrad).cuda()
+    rho = torch.as_tensor(case.rho).cuda()
+    a = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL)
+    b = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL)
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        assert torch.equal(a[k], b[k]), k
+    assert np.array_equal(a["escale"], b["escale"])
+
+
+def test_zero_correlator_gives_zeros(api, ragged_case):
+    import torch
+    case = ragged_case
+    out = api.kernel_contract(_grid(api, case), case.wl.corr, torch.as_tensor(case.fit.xi).cuda(),
+                              torch.as_tensor(case.fit.xigrad).cuda(), torch.as_tensor(case.rho).cuda(),
+                              case.piv, ALL, c=np.zeros(case.wl.corr.c.size))
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        assert float(out[k].abs().max()) == 0.0
