@@ -1,0 +1,154 @@
+"""Benchmark of the ISDF-xTC hot path on one MI355X.
+
+One step = the whole path over the H20 workload (194,000 grid points, 300
+orbitals, N_mu = 3000): orbital values and gradients on the grid, fused
+interpolation-point selection, ISDF fit of xi and xi~, and the grid-pair
+contraction with every channel (u1, u3, D1, D4, field, energy-scale sums),
+with inputs resident in HBM. Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--precision split|fp64] [--compare-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {"fp64": 78.6, "f16": 2500.0}   # TFLOP/s, dense MFMA (MI355X datasheet)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--config", default="h20")
+    p.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    p.add_argument("--compare-fp64", action="store_true",
+                   help="also time the plain FP64 form and report its time-to-V and the error")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-bra", type=int, default=1024, help="bra points in the CPU-oracle sample")
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path is single-GPU in this build); got --gpus {a.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    from workloads import make_config
+
+    wl = make_config(a.config)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+    C_mo = torch.as_tensor(wl.C_mo, device=dev)
+    prec = L.XTC_SPLIT_F16 if a.precision == "split" else L.XTC_FP64
+    chans = api.ALL_CHANNELS
+    torch.cuda.synchronize()
+
+    def step(precision):
+        phi4, rho = api.eval_orbitals(wl.basis, grid, C_mo, wl.n_occ)
+        piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
+        xi, xig, _, _ = api.fit(phi4, grid, piv)
+        out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, precision)
+        return out, piv
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    for i in range(a.warmup):
+        step(prec)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{a.warmup} done")
+    with api.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            out, piv = step(prec)
+            log(f"timed step {i + 1}/{a.steps} enqueued")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+    tm = kt.result
+    n_g, n_mu = wl.n_g, len(piv)
+    pairs = float(n_g) * n_g
+    alg_stage1 = 8.0 * (n_mu + 1) * pairs          # 4 channels x 2 flops x (N_mu + rho row) per pair
+    value = alg_stage1 / dt / 1e12
+
+    s1 = tm["stage1"]
+    launch_ms = s1["ms"] / max(1, s1["launches"])
+    per_launch_flops = alg_stage1 / max(1, s1["launches"] / a.steps)
+    achieved = per_launch_flops / (launch_ms * 1e-3) / 1e12
+    peak = PEAKS["f16"] if prec == L.XTC_SPLIT_F16 else PEAKS["fp64"]
+
+    res = {
+        "metric": "ISDF-xTC build time & grid-pair TFLOP/s vs FP64 GPU form at 1e-6 rel err, 1 GPU",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(dt * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16x2-split/f32acc/f64" if prec == L.XTC_SPLIT_F16 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config}: linear H20 chain, {n_g} grid points, {wl.n_orb} orbitals, "
+                               f"N_mu={n_mu}, 4-term e-e correlator; time-to-V = orbitals + pivots + fit + "
+                               f"contraction (u1,u3,D1,D4,field,escale)",
+                   "n_g": n_g, "n_orb": wl.n_orb, "n_mu": n_mu, "precision": a.precision},
+        "time_to_V_s": round(dt, 4),
+        "stage_ms": {k: round(v["ms"] / a.steps, 2) for k, v in tm.items() if v["launches"]},
+        "roofline": {"bound": "mfma", "kernel": "stage-1 fused pair kernel",
+                     "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "launch_ms": round(launch_ms, 3), "launches_per_step": s1["launches"] // a.steps},
+    }
+    if a.compare_fp64 and prec != L.XTC_FP64:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref, _ = step(L.XTC_FP64)
+        torch.cuda.synchronize()
+        res["fp64_time_to_V_s"] = round(time.perf_counter() - t0, 4)
+        errs = {}
+        for k in ("u1", "u3", "D1", "D4", "field"):
+            r = ref[k]
+            errs[k] = float((out[k] - r).abs().max() / r.abs().max())
+        errs["escale"] = float(np.max(np.abs(out["escale"] - ref["escale"]) / np.abs(ref["escale"])))
+        res["max_rel_err_vs_fp64"] = errs
+        res["speedup_vs_fp64_form"] = round(res["fp64_time_to_V_s"] / dt, 3)
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        res["cpu_baseline"] = cpu_baseline(wl, n_mu, a.cpu_bra)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(wl, n_mu, n_bra):
+    """The FP64 CPU oracle's contraction on a bounded sample: n_bra bra points
+    against every ket point, N_mu interpolation vectors of the workload's shape."""
+    import numpy as np
+
+    from oracle import contract as oc
+    rng = np.random.default_rng(0)
+    xi = rng.standard_normal((n_mu, wl.n_g))
+    xig = rng.standard_normal((3, n_mu, wl.n_g))
+    rho = rng.random(wl.n_g)
+    G = rho[:n_mu]
+    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oc.contract(wl.grid_xyz, wl.grid_w, wl.corr, xi, xig, G, rho, 1 | 2 | 8 | 16 | 32,
+                bra_range=(0, n_bra))
+    dt = time.perf_counter() - t0
+    flops = 8.0 * (n_mu + 1) * n_bra * wl.n_g
+    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"stage 1 + stage 2 of {n_bra} bra points x {wl.n_g} ket points, N_mu={n_mu}, "
+                      f"all channels; {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

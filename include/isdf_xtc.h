@@ -224,6 +224,16 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
                     const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
                     void* stream);
 
+/* Kernel timing for measurement: HIP events recorded on the call's stream around
+ * each launch of the timed stages. mode 1: reset and start collecting; 0: stop and
+ * reset; 2: synchronise the recorded events and write, per category c,
+ * out[2c] = summed milliseconds and out[2c+1] = number of launches.
+ * Categories: 0 stage-1 pair kernel, 1 stage-2 GEMMs, 2 pivot selection,
+ * 3 fit, 4 orbitals, 5 adjoint pair kernel, 6 MLP, 7 split-operand preparation.
+ * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
+#define XTC_TIMING_CATEGORIES 8
+xtc_status xtc_timing(int32_t mode, double* out);
+
 #ifdef __cplusplus
 }
 #endif

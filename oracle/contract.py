@@ -37,7 +37,9 @@ U1, U3, ULAP, D1, D4, FIELD, ESCALE = 1, 2, 4, 8, 16, 32, 64
 
 
 def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
-             bra_block: int = 128, ket_block: int = 2048):
+             bra_block: int = 128, ket_block: int = 2048, bra_range=None):
+    """All outputs of the docstring above. bra_range = (start, stop) restricts the
+    sum over bra points g to that range (used to time a sample of the work)."""
     n_mu, n_g = xi.shape
     lap = bool(channels & ULAP)
     need_g = bool(channels & (U1 | D1 | D4))
@@ -53,7 +55,7 @@ def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
     t3rho = np.zeros(n_g)
     def stage1(b0):
         """Stage 1 for one bra block: sums over every ket point."""
-        b1 = min(n_g, b0 + bra_block)
+        b1 = min(hi, b0 + bra_block)
         nb = b1 - b0
         calG = np.zeros((3, n_mu, nb))
         T3 = np.zeros((n_mu, nb))
@@ -72,13 +74,14 @@ def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
                 TL += wxi[:, k0:k1] @ K["lap"].T
         return calG, T3, TL, fld, t3r
 
-    starts = list(range(0, n_g, bra_block))
+    lo, hi = (0, n_g) if bra_range is None else bra_range
+    starts = list(range(lo, hi, bra_block))
     workers = max(1, min(len(starts), int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))))
     # one BLAS thread per worker: the workers already use every core
     with threadpool_limits(1 if workers > 1 else None), ThreadPoolExecutor(workers) as ex:
         # blocks are consumed in bra order, so every sum below has a fixed order
         for b0, (calG, T3, TL, fld, t3r) in zip(starts, ex.map(stage1, starts)):
-            b1 = min(n_g, b0 + bra_block)
+            b1 = min(hi, b0 + bra_block)
             field[:, b0:b1] = fld
             t3rho[b0:b1] = t3r
             wb = w[b0:b1]

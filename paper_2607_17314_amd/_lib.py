@@ -82,9 +82,12 @@ def lib() -> C.CDLL:
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, P, P, P, P,
                            P, P, P, P, C.c_size_t, P]
+    L.xtc_timing.restype = st
+    L.xtc_timing.argtypes = [C.c_int32, D]
     _lib = L
     return L
 
 
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
-            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad"]
+            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing"]
+TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep"]

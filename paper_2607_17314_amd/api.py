@@ -211,3 +211,22 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
         _dptr(esc) if channels & L.XTC_ESCALE else None, _ptr(ws), ws.numel(), _stream()))
     o["escale"] = esc if channels & L.XTC_ESCALE else None
     return o
+
+
+class KernelTimer:
+    """Collects the library's per-stage kernel timings (xtc_timing) over a region."""
+
+    def __enter__(self):
+        _check("xtc_timing", L.lib().xtc_timing(1, None))
+        return self
+
+    def read(self) -> dict:
+        out = np.zeros(2 * len(L.TIMING_CATEGORIES), np.float64)
+        _check("xtc_timing", L.lib().xtc_timing(2, _dptr(out)))
+        return {k: {"ms": float(out[2 * i]), "launches": int(out[2 * i + 1])}
+                for i, k in enumerate(L.TIMING_CATEGORIES)}
+
+    def __exit__(self, *exc):
+        self.result = self.read()
+        L.lib().xtc_timing(0, None)
+        return False

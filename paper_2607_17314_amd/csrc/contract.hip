@@ -8,6 +8,7 @@
 // the exact field A_gamma and the ISDF-free energy-scale sums.
 #include "contract.hpp"
 #include "plans.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -210,15 +211,22 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
                      (const long*)C.piv, n_mu, C.G);
   XTC_CHECK_LAUNCH();
   Stage1Args s1{grid->xyz, grid->w, xi, rho, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp, C.nch};
-  if (precision == XTC_SPLIT_F16) XTC_TRY(split_prepare(s1, C.split, st));
+  if (precision == XTC_SPLIT_F16) {
+    size_t tk = timing_begin(TM_SPLIT_PREP, st);
+    XTC_TRY(split_prepare(s1, C.split, st));
+    timing_end(tk, st);
+  }
   const bool need_h = (channels & (XTC_D1 | XTC_D4)) != 0;
   for (int sb = 0; sb < C.nsb; ++sb) {
     const long b0 = (long)sb * C.bp;
     const long bn = (n_g - b0) < C.bp ? (n_g - b0) : C.bp;
     s1.b0 = b0;
     s1.bn = bn;
+    size_t tk = timing_begin(TM_STAGE1, st);
     if (precision == XTC_FP64) XTC_TRY(stage1_f64(s1, cf, st));
     else XTC_TRY(stage1_split_f16(s1, cf, C.split, C.split_bytes, st));
+    timing_end(tk, st);
+    size_t tk2 = timing_begin(TM_STAGE2, st);
     const double beta = sb == 0 ? 0.0 : 1.0;
     auto nt = [&](const double* A, long a_sm, const double* s, const double* B, double* out,
                   double bet) {
@@ -259,6 +267,7 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
     }
     XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 2 * sb, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 2 * sb + 1, C.red, st));
+    timing_end(tk2, st);
   }
   if (channels & XTC_ESCALE) {
     XTC_HIP(hipMemsetAsync(C.esc, 0, 8 * sizeof(double), st));

@@ -13,6 +13,7 @@
 // workspace does not grow with n_g beyond one chunk.
 #include "common.hpp"
 #include "plans.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -293,6 +294,7 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
   Arena ar(ws, ws_bytes);
   FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
   XTC_TRY(need_ws(ar));
+  size_t tk = timing_begin(TM_FIT, st);
   XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_gather_piv, dim3(cdiv(4L * n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
                      n_g, 4 * n_orb, (const long*)F.piv, n_mu, F.phimu);
@@ -391,6 +393,7 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
     }
     rel[sys] = ms > 0.0 ? rs / ms : 0.0;
   }
+  timing_end(tk, st);
   XTC_HIP(hipStreamSynchronize(st));
   if (info) {
     for (int i = 0; i < 4; ++i) {

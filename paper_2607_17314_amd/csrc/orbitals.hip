@@ -5,6 +5,7 @@
 // over the occupied orbitals.
 #include "common.hpp"
 #include "plans.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -158,9 +159,11 @@ extern "C" xtc_status xtc_eval_orbitals(const xtc_basis* basis, const xtc_grid* 
   XTC_HIP(hipMemcpyAsync(L.ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.prim, prim.data(), sizeof(double) * prim.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.comp, basis->comp_factor, sizeof(double) * n_ao, hipMemcpyHostToDevice, st));
+  XTC_HIP(hipStreamSynchronize(st));   // host staging vectors end with this call
   BasisDev b{L.atom_xyz, L.ints, L.ints + basis->n_shell, L.ints + 2 * basis->n_shell,
              L.prim, L.prim + n_prim, L.comp, basis->n_shell, n_ao};
   const long n_g = grid->n_g;
+  size_t tk = timing_begin(TM_ORBITALS, st);
   for (long g0 = 0; g0 < n_g; g0 += L.chunk) {
     long cn = (n_g - g0) < L.chunk ? (n_g - g0) : L.chunk;
     hipLaunchKernelGGL(k_eval_ao, dim3(cdiv(cn, 256)), dim3(256), 0, st, b, grid->xyz, n_g, g0,
@@ -180,5 +183,6 @@ extern "C" xtc_status xtc_eval_orbitals(const xtc_basis* basis, const xtc_grid* 
     hipLaunchKernelGGL(k_density, dim3(cdiv(n_g, 256)), dim3(256), 0, st, phi4, n_g, n_occ, rho);
     XTC_CHECK_LAUNCH();
   }
+  timing_end(tk, st);
   return XTC_OK;
 }

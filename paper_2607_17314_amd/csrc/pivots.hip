@@ -15,6 +15,7 @@
 // order is fixed, so repeated runs select identical pivots.
 #include "common.hpp"
 #include "plans.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -325,6 +326,9 @@ extern "C" xtc_status isdf_select_points(const double* phi4, const xtc_grid* gri
   if (info)
     for (int i = 0; i < 8; ++i) info[i] = 0.0;
   Arena ar(ws, ws_bytes);
-  return xtc_select_qr(phi4, grid, n_orb, n_mu_target, pivots, n_mu_out, info, ar,
-                       as_stream(stream));
+  size_t tk = timing_begin(TM_SELECT, as_stream(stream));
+  xtc_status s = xtc_select_qr(phi4, grid, n_orb, n_mu_target, pivots, n_mu_out, info, ar,
+                               as_stream(stream));
+  timing_end(tk, as_stream(stream));
+  return s;
 }
