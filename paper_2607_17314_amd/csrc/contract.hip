@@ -52,30 +52,22 @@ __global__ void k_gather_G(const double* __restrict__ rho, const long* __restric
   if (i < n_mu) G[i] = rho[piv[i]];
 }
 
-// Per bra point of the super-block: wt = w sum_l G_l xi_l(g), H_c = sum_l G_l calG^c_lg,
+// Per bra point of the super-block: wt = w rhot, H_c from the panel's rhot row,
 // and the energy-scale partials w rho T3rho and w rho |A_gamma|^2; also copies the field.
 __global__ __launch_bounds__(256) void k_point_vectors(
-    const double* __restrict__ xi, const double* __restrict__ w, const double* __restrict__ rho,
-    const double* __restrict__ G, long n_g, int n_mu, long b0, long bn,
-    const double* __restrict__ panel, long rows_pad, long bp, int need_h, double* __restrict__ wt,
-    double* __restrict__ H, double* __restrict__ e3x, double* __restrict__ e4x,
+    const double* __restrict__ rhot, const double* __restrict__ w, const double* __restrict__ rho,
+    long n_g, int n_mu, long b0, long bn, const double* __restrict__ panel, long rows_pad, long bp,
+    int need_h, double* __restrict__ wt, double* __restrict__ H, double* __restrict__ e3x,
+    double* __restrict__ e4x, double* __restrict__ e3, double* __restrict__ e4,
     double* __restrict__ field) {
   long t = (long)blockIdx.x * 256 + threadIdx.x;
   if (t >= bn) return;
   const long g = b0 + t;
   if (need_h) {
-    double s = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
-    for (int l = 0; l < n_mu; ++l) {
-      const double gl = G[l];
-      s += gl * xi[(long)l * n_g + g];
-      h0 += gl * panel[((long)0 * rows_pad + l) * bp + t];
-      h1 += gl * panel[((long)1 * rows_pad + l) * bp + t];
-      h2 += gl * panel[((long)2 * rows_pad + l) * bp + t];
-    }
-    wt[t] = w[g] * s;
-    H[t] = h0;
-    H[bp + t] = h1;
-    H[2 * bp + t] = h2;
+    wt[t] = w[g] * rhot[g];
+    H[t] = panel[((long)0 * rows_pad + n_mu + 1) * bp + t];
+    H[bp + t] = panel[((long)1 * rows_pad + n_mu + 1) * bp + t];
+    H[2 * bp + t] = panel[((long)2 * rows_pad + n_mu + 1) * bp + t];
   }
   const double a0 = panel[((long)0 * rows_pad + n_mu) * bp + t];
   const double a1 = panel[((long)1 * rows_pad + n_mu) * bp + t];
@@ -84,6 +76,15 @@ __global__ __launch_bounds__(256) void k_point_vectors(
   const double wr = w[g] * rho[g];
   e3x[t] = wr * t3;
   e4x[t] = wr * (a0 * a0 + a1 * a1 + a2 * a2);
+  // ISDF energy-scale terms on the rhot row: G^T u3 G = sum_g w rhot T3rhot,
+  // G^T D4 G = sum_g w rhot |H|^2 = (1/2) 2 G^T D1 G
+  const double h0 = panel[((long)0 * rows_pad + n_mu + 1) * bp + t];
+  const double h1 = panel[((long)1 * rows_pad + n_mu + 1) * bp + t];
+  const double h2 = panel[((long)2 * rows_pad + n_mu + 1) * bp + t];
+  const double t3t = panel[((long)3 * rows_pad + n_mu + 1) * bp + t];
+  const double wrt = w[g] * rhot[g];
+  e3[t] = wrt * t3t;
+  e4[t] = wrt * (h0 * h0 + h1 * h1 + h2 * h2);
   if (field) {
     field[g] = a0;
     field[n_g + g] = a1;
@@ -110,8 +111,8 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b
 }
 
 struct ConLayout {
-  long* piv; double* G; double* panel; double* V; double* wt; double* H; double* e3x; double* e4x;
-  double* sums; double* red; double* y; double* prod; double* esc; void* split; size_t split_bytes;
+  long* piv; double* G; double* rhot; double* panel; double* V; double* wt; double* H; double* e3x;
+  double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
   long bp; long rows_pad; int nsb; int nch;
 };
 
@@ -119,22 +120,23 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
-  C.rows_pad = ((n_mu + 1 + 63) / 64) * 64;
+  C.rows_pad = ((n_mu + 2 + 63) / 64) * 64;
   C.nsb = (int)cdiv(n_g, C.bp);
   C.piv = ar.take<long>(n_mu);
   C.G = ar.take<double>(n_mu);
+  C.rhot = ar.take<double>(n_g);
   C.panel = ar.take<double>((size_t)C.nch * C.rows_pad * C.bp);
   C.V = (channels & XTC_D1) ? ar.take<double>((size_t)n_mu * C.bp) : nullptr;
   C.wt = ar.take<double>(C.bp);
   C.H = ar.take<double>(3 * (size_t)C.bp);
   C.e3x = ar.take<double>(C.bp);
   C.e4x = ar.take<double>(C.bp);
-  C.sums = ar.take<double>(2 * (size_t)C.nsb + 2);
+  C.e3 = ar.take<double>(C.bp);
+  C.e4 = ar.take<double>(C.bp);
+  C.sums = ar.take<double>(4 * (size_t)C.nsb + 4);
   C.red = ar.take<double>(1024);
-  C.y = ar.take<double>(n_mu);
-  C.prod = ar.take<double>(n_mu);
-  C.esc = ar.take<double>(8);
-  C.split_bytes = precision == XTC_SPLIT_F16 ? split_scratch_bytes(n_g, n_mu) : 0;
+  C.split_bytes = precision == XTC_SPLIT_F16
+                      ? split_scratch_bytes(n_g, n_mu) + rho_row_scratch_bytes(C.bp) : 0;
   C.split = C.split_bytes ? (void*)ar.take<char>(C.split_bytes) : nullptr;
   return C;
 }
@@ -143,20 +145,6 @@ size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags) {
   Arena ar(nullptr, 0);
   layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff));
   return ar.used;
-}
-
-static xtc_status quad_form(const double* M, const double* G, int n, double* out, ConLayout& C,
-                            hipStream_t st) {
-  GemmArgs g{};
-  g.M = n; g.N = 1; g.K = n;
-  g.A = M; g.a_sm = n; g.a_sk = 1;
-  g.B = G; g.b_sk = 1; g.b_sn = 1;
-  g.C = C.y; g.c_sm = 1; g.c_sn = 1;
-  XTC_TRY(gemm_f64(g, st));
-  hipLaunchKernelGGL(k_mul, dim3(cdiv(n, 256)), dim3(256), 0, st, G, (const double*)C.y, (long)n,
-                     C.prod);
-  XTC_CHECK_LAUNCH();
-  return reduce_sum_f64(C.prod, n, out, C.red, st);
 }
 
 }  // namespace xtc
@@ -210,7 +198,16 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
                      (const long*)C.piv, n_mu, C.G);
   XTC_CHECK_LAUNCH();
-  Stage1Args s1{grid->xyz, grid->w, xi, rho, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp, C.nch};
+  {
+    GemmArgs g{};   // ISDF density rhot = G^T xi
+    g.M = 1; g.N = n_g; g.K = n_mu;
+    g.A = C.G; g.a_sm = 1; g.a_sk = 1;
+    g.B = xi; g.b_sk = n_g; g.b_sn = 1;
+    g.C = C.rhot; g.c_sm = n_g; g.c_sn = 1;
+    XTC_TRY(gemm_f64(g, st));
+  }
+  Stage1Args s1{grid->xyz, grid->w, xi, rho, C.rhot, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp,
+                C.nch};
   if (precision == XTC_SPLIT_F16) {
     size_t tk = timing_begin(TM_SPLIT_PREP, st);
     XTC_TRY(split_prepare(s1, C.split, st));
@@ -248,10 +245,10 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
       XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 3L * C.rows_pad * C.bp, u3, beta));
     if (channels & XTC_ULAP)
       XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 4L * C.rows_pad * C.bp, ulap, beta));
-    hipLaunchKernelGGL(k_point_vectors, dim3(cdiv(bn, 256)), dim3(256), 0, st, xi, grid->w, rho,
-                       (const double*)C.G, n_g, n_mu, b0, bn, (const double*)C.panel, C.rows_pad,
-                       C.bp, need_h ? 1 : 0, C.wt, C.H, C.e3x, C.e4x,
-                       (channels & XTC_FIELD) ? field : nullptr);
+    hipLaunchKernelGGL(k_point_vectors, dim3(cdiv(bn, 256)), dim3(256), 0, st,
+                       (const double*)C.rhot, grid->w, rho, n_g, n_mu, b0, bn,
+                       (const double*)C.panel, C.rows_pad, C.bp, need_h ? 1 : 0, C.wt, C.H, C.e3x,
+                       C.e4x, C.e3, C.e4, (channels & XTC_FIELD) ? field : nullptr);
     XTC_CHECK_LAUNCH();
     if (channels & XTC_D4)
       for (int c = 0; c < 3; ++c) {
@@ -265,27 +262,26 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
       XTC_CHECK_LAUNCH();
       XTC_TRY(nt(xi + b0, n_g, wb, C.V, D1, beta));
     }
-    XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 2 * sb, C.red, st));
-    XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 2 * sb + 1, C.red, st));
+    XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 4 * sb, C.red, st));
+    XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 4 * sb + 1, C.red, st));
+    XTC_TRY(reduce_sum_f64(C.e3, bn, C.sums + 4 * sb + 2, C.red, st));
+    XTC_TRY(reduce_sum_f64(C.e4, bn, C.sums + 4 * sb + 3, C.red, st));
     timing_end(tk2, st);
   }
   if (channels & XTC_ESCALE) {
-    XTC_HIP(hipMemsetAsync(C.esc, 0, 8 * sizeof(double), st));
-    if (channels & XTC_U3) XTC_TRY(quad_form(u3, C.G, n_mu, C.esc + 0, C, st));
-    if (channels & XTC_D4) XTC_TRY(quad_form(D4, C.G, n_mu, C.esc + 1, C, st));
-    if (channels & XTC_D1) XTC_TRY(quad_form(D1, C.G, n_mu, C.esc + 2, C, st));
-    std::vector<double> hs(2 * C.nsb), he(8);
-    XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 2 * C.nsb, hipMemcpyDeviceToHost, st));
-    XTC_HIP(hipMemcpyAsync(he.data(), C.esc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+    std::vector<double> hs(4 * C.nsb);
+    XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 4 * C.nsb, hipMemcpyDeviceToHost, st));
     XTC_HIP(hipStreamSynchronize(st));
-    double e3x = 0.0, e4x = 0.0;
+    double e3x = 0.0, e4x = 0.0, e3 = 0.0, e4 = 0.0;
     for (int sb = 0; sb < C.nsb; ++sb) {
-      e3x += hs[2 * sb];
-      e4x += hs[2 * sb + 1];
+      e3x += hs[4 * sb];
+      e4x += hs[4 * sb + 1];
+      e3 += hs[4 * sb + 2];
+      e4 += hs[4 * sb + 3];
     }
-    escale[0] = he[0];
-    escale[1] = he[1];
-    escale[2] = 2.0 * he[2];
+    escale[0] = e3;
+    escale[1] = e4;
+    escale[2] = 2.0 * e4;
     escale[3] = e3x;
     escale[4] = e4x;
     escale[5] = 2.0 * e4x;
@@ -297,17 +293,6 @@ namespace xtc {
 size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags) {
   (void)n_g; (void)n_mu; (void)n_params; (void)flags;
   return 0;
-}
-size_t split_scratch_bytes(long n_g, int n_mu) { (void)n_g; (void)n_mu; return 0; }
-xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st) {
-  (void)a; (void)scratch; (void)st;
-  set_error("split precision not built yet");
-  return XTC_ERR_UNSUPPORTED;
-}
-xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch, size_t bytes,
-                            hipStream_t st) {
-  (void)a; (void)cf; (void)scratch; (void)bytes; (void)st;
-  return XTC_ERR_UNSUPPORTED;
 }
 }  // namespace xtc
 

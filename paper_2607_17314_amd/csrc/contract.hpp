@@ -21,9 +21,11 @@ struct EECoef {
 xtc_status ee_coefficients(const xtc_correlator* corr, EECoef* out);
 
 // Stage 1 over one bra super-block [b0, b0 + bn): panel[ch][row][b - b0] for
-// rows 0..n_mu (row n_mu is the rho row), ch = gx, gy, gz, sq (, lap).
+// rows 0..n_mu + 1, ch = gx, gy, gz, sq (, lap). Row n_mu uses the reference
+// density rho_gamma (exact field), row n_mu + 1 the ISDF density
+// rhot = sum_l G_l xi_l, so that its gradient channels are H_{g,c} = sum_l G_l calG^c_{l,g}.
 struct Stage1Args {
-  const double* xyz; const double* w; const double* xi; const double* rho;
+  const double* xyz; const double* w; const double* xi; const double* rho; const double* rhot;
   long n_g; int n_mu; long b0; long bn;
   double* panel; long rows_pad; long bp;
   int nch;
@@ -33,6 +35,7 @@ xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);
 xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch,
                             size_t scratch_bytes, hipStream_t st);
 size_t split_scratch_bytes(long n_g, int n_mu);
+size_t rho_row_scratch_bytes(long bp);
 xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st);
 
 }  // namespace xtc

@@ -1,6 +1,6 @@
 // Stage 1 of the grid-pair contraction in FP64 (K-kernel section: the
 // doubly-blocked grid sums, each auxiliary vector used once per grid pair):
-//   panel[ch][row][g] = sum_g' A[row][g'] K_ch(g, g'),  A = [w xi ; w rho]
+//   panel[ch][row][g] = sum_g' A[row][g'] K_ch(g, g'),  A = [w xi ; w rho ; w rhot]
 // with the kernel channels K = (d_x u, d_y u, d_z u, |grad u|^2 [, lap u])
 // generated in registers for every (bra g, ket g') pair and never written to
 // HBM.
@@ -51,7 +51,8 @@ template <int NCH>
 __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ xyz,
                                                     const double* __restrict__ w,
                                                     const double* __restrict__ xi,
-                                                    const double* __restrict__ rho, long n_g,
+                                                    const double* __restrict__ rho,
+                                                    const double* __restrict__ rhot, long n_g,
                                                     int n_mu, long b0, long bn, EECoef cf,
                                                     double* __restrict__ panel, long rows_pad,
                                                     long bp) {
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ x
       const int row = e >> 4, kk = e & 15;
       const long g = k0 + kk, rr = m0 + row;
       double v = 0.0;
-      if (g < n_g && rr <= n_mu) v = w[g] * (rr < n_mu ? xi[rr * n_g + g] : rho[g]);
+      if (g < n_g && rr <= n_mu + 1)
+        v = w[g] * (rr < n_mu ? xi[rr * n_g + g] : (rr == n_mu ? rho[g] : rhot[g]));
       ra[j] = v;
     }
     double ch[4][NCH];
@@ -131,17 +133,17 @@ __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ x
         for (int r = 0; r < 4; ++r) {
           const long row = m0 + 32 * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
           const long col = nb0 + 32 * wn + 16 * j + li;
-          if (row <= n_mu && col < bn) panel[((long)c * rows_pad + row) * bp + col] = acc[c][i][j][r];
+          if (row <= n_mu + 1 && col < bn) panel[((long)c * rows_pad + row) * bp + col] = acc[c][i][j][r];
         }
 }
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
-  dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 1, 64));
+  dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 2, 64));
   if (a.nch == 4)
-    hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.n_g,
+    hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
   else
-    hipLaunchKernelGGL(k_stage1_f64<5>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.n_g,
+    hipLaunchKernelGGL(k_stage1_f64<5>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
   XTC_CHECK_LAUNCH();
   return XTC_OK;
