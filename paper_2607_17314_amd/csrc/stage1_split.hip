@@ -28,7 +28,7 @@ typedef float f16x __attribute__((ext_vector_type(16)));
 constexpr int SR = 256;        // rows per workgroup
 constexpr int SB = 32;         // bra points per workgroup
 constexpr int SKC = 128;       // ket points per chunk (8 k-steps of 16)
-constexpr int SMED = 64;       // chunks per FP32 medium sum
+constexpr int SMED = 64;       // chunks per FP32 medium sum (then FP64)
 
 struct SplitCoef {
   float d;
@@ -182,11 +182,11 @@ __device__ __forceinline__ float hornerf(const float* q, float x) {
 // Four scaled channels of one pair: (d_x u, d_y u, d_z u) 2^eg and |grad u|^2 2^es.
 // EVEN: every power o_k is even (no o = 1 term), so Q1(e) = e P1(e^2), Q2(e) = P2(e^2)
 // with the coefficients of q1, q2 stored compacted (q1[i] = coef of e^(2i+1), q2[i] of e^(2i)).
-template <bool EVEN>
+template <bool EVEN, int NQ>
 __device__ __forceinline__ void split_channels(const SplitCoef& k, float dx, float dy, float dz,
                                                float* o) {
   const float r2 = dx * dx + dy * dy + dz * dz;
-  const float r = __builtin_sqrtf(r2);
+  const float r = __builtin_amdgcn_sqrtf(r2);   // v_sqrt_f32, 1 ulp
   const float dr = k.d * r;
   const float t = __builtin_amdgcn_rcpf(1.0f + dr);
   const float e = dr * t;
@@ -194,8 +194,8 @@ __device__ __forceinline__ void split_channels(const SplitCoef& k, float dx, flo
   float up, f;
   if (EVEN) {
     const float e2 = e * e;
-    up = k.d * t2 * e * hornerf<MAXQ / 2>(k.q1, e2);
-    f = k.d * k.d * t2 * t * hornerf<MAXQ / 2>(k.q2, e2);
+    up = k.d * t2 * e * hornerf<NQ>(k.q1, e2);
+    f = k.d * k.d * t2 * t * hornerf<NQ>(k.q2, e2);
   } else {
     up = k.d * t2 * hornerf<MAXQ>(k.q1, e);
     f = k.d * k.d * t2 * t * hornerf<MAXQ>(k.q2, e);
@@ -208,7 +208,7 @@ __device__ __forceinline__ void split_channels(const SplitCoef& k, float dx, flo
   o[3] = up * up * k.ss;
 }
 
-template <bool EVEN>
+template <bool EVEN, int NQ>
 __global__ __launch_bounds__(512) void k_stage1_split(const h8* __restrict__ At,
                                                       const int* __restrict__ sA,
                                                       const float* __restrict__ kc, long n_g_pad,
@@ -216,7 +216,9 @@ __global__ __launch_bounds__(512) void k_stage1_split(const h8* __restrict__ At,
                                                       long n_g, int n_mu, long b0, long bn,
                                                       SplitCoef k, double* __restrict__ panel,
                                                       long rows_pad_panel, long bp) {
-  extern __shared__ h8 Bs[];   // [2][8 ksteps][4 ch][2 hl][64 lanes]
+  extern __shared__ h8 Bs[];   // [2][8 ksteps][4 ch][2 hl][64 lanes], then coordinates
+  // ket coordinates of a chunk, double-buffered: [2][6][SKC] floats after the fragments
+  float* Kc = (float*)(Bs + 2 * 8 * 8 * 64);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long row0 = (long)blockIdx.y * SR;
   const long nb0 = (long)blockIdx.x * SB;
@@ -232,38 +234,51 @@ __global__ __launch_bounds__(512) void k_stage1_split(const h8* __restrict__ At,
   const h8* Aw = At + rb * nks * 2 * 64 + lane;
   const long nchunks = n_g_pad / SKC;
 
-  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-  auto generate = [&](long c, int buf) {
-    const long kbase = c * SKC + 16 * gj + 8 * (ld >> 5);
-    h4* dst = (h4*)(Bs + ((long)(buf * 8 + gj) * 8) * 64 + ld);
+  // One pair of the next chunk is generated per k-step of the current chunk, so the
+  // vector units work in the shadow of the matrix-core instructions; the fragments
+  // are written to the other LDS buffer after the chunk's last k-step. Ket
+  // coordinates come from LDS, loaded from HBM one chunk earlier still.
+  const int kofs = 16 * gj + 8 * (ld >> 5);
+  auto gen_pair = [&](const float* kcb, int e, h8 (&fr)[4][2]) {
+    const int g = kofs + e;
+    const float dx = (bxh - kcb[g]) + (bxl - kcb[3 * SKC + g]);
+    const float dy = (byh - kcb[SKC + g]) + (byl - kcb[4 * SKC + g]);
+    const float dz = (bzh - kcb[2 * SKC + g]) + (bzl - kcb[5 * SKC + g]);
+    float o[4];
+    split_channels<EVEN, NQ>(k, dx, dy, dz, o);
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      h4 fr[4][2];
+    for (int ch = 0; ch < 4; ++ch) {
+      const _Float16 h = (_Float16)o[ch];
+      fr[ch][0][e] = h;
+      fr[ch][1][e] = (_Float16)(o[ch] - (float)h);
+    }
+  };
+  auto store_frags = [&](int buf, h8 (&fr)[4][2]) {
+    h8* dst = Bs + ((long)(buf * 8 + gj) * 8) * 64 + ld;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const long g = kbase + 4 * half + e;
-        const float dx = (bxh - kc[g]) + (bxl - kc[3 * n_g_pad + g]);
-        const float dy = (byh - kc[n_g_pad + g]) + (byl - kc[4 * n_g_pad + g]);
-        const float dz = (bzh - kc[2 * n_g_pad + g]) + (bzl - kc[5 * n_g_pad + g]);
-        float o[4];
-        split_channels<EVEN>(k, dx, dy, dz, o);
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-          const _Float16 h = (_Float16)o[ch];
-          fr[ch][0][e] = h;
-          fr[ch][1][e] = (_Float16)(o[ch] - (float)h);
-        }
-      }
-      // an h8 slot is two h4 halves: elements 4*half .. 4*half + 3
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        dst[((ch * 2 + 0) * 64) * 2 + half] = fr[ch][0];
-        dst[((ch * 2 + 1) * 64) * 2 + half] = fr[ch][1];
-      }
+    for (int ch = 0; ch < 4; ++ch) {
+      dst[(ch * 2 + 0) * 64] = fr[ch][0];
+      dst[(ch * 2 + 1) * 64] = fr[ch][1];
+    }
+  };
+  // coordinates of chunk c: 6 x SKC floats = 768, two per thread (threads 0..383)
+  auto load_coords = [&](long c, float& v0, float& v1) {
+    v0 = v1 = 0.0f;
+    if (tid < 384 && c < nchunks) {
+      const int q = tid * 2, comp = q / SKC, off = q % SKC;
+      const float* src = kc + (long)comp * n_g_pad + c * SKC + off;
+      v0 = src[0];
+      v1 = src[1];
+    }
+  };
+  auto store_coords = [&](int cb, float v0, float v1) {
+    if (tid < 384) {
+      Kc[cb * 6 * SKC + tid * 2] = v0;
+      Kc[cb * 6 * SKC + tid * 2 + 1] = v1;
     }
   };
 
-  f16x med[4];
+  f16x med[4], acc[4];
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
@@ -288,41 +303,57 @@ __global__ __launch_bounds__(512) void k_stage1_split(const h8* __restrict__ At,
     }
   };
 
-  generate(0, 0);
+  {
+    float v0, v1;
+    load_coords(0, v0, v1);
+    store_coords(0, v0, v1);
+    load_coords(1, v0, v1);
+    store_coords(1, v0, v1);
+    __syncthreads();
+    h8 fr[4][2];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) gen_pair(Kc, e, fr);
+    store_frags(0, fr);
+  }
   __syncthreads();
   bool first_flush = true;
+  const long last_ks = nks - 1;
+  h8 a0h = Aw[0], a0l = Aw[64];
   for (long c = 0; c < nchunks; ++c) {
     const int buf = (int)(c & 1);
-    if (c + 1 < nchunks) generate(c + 1, buf ^ 1);
-    f16x acc[4];
+    const bool more = c + 1 < nchunks;
+    const h8* Bb = Bs + (long)buf * 8 * 8 * 64 + lane;
+    const float* kcb = Kc + ((c + 1) & 1) * 6 * SKC;   // coordinates of chunk c + 1
+    float cv0, cv1;
+    load_coords(c + 2, cv0, cv1);                      // for the generation during chunk c + 1
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ch][r] = 0.0f;
-    const h8* Bb = Bs + (long)buf * 8 * 8 * 64 + lane;
-    h8 ah = Aw[(c * 8 * 2 + 0) * 64];
-    h8 al = Aw[(c * 8 * 2 + 1) * 64];
-#pragma unroll 1
+    h8 fr[4][2];
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
-      // prefetch the next k-step's A fragments (the chunk's last step reads ahead into the
-      // next chunk, which exists or is the zero padding of the tiled copy)
-      const long ksn = c * 8 + j + 1 < nks ? c * 8 + j + 1 : c * 8 + j;
-      const h8 ahn = Aw[(ksn * 2 + 0) * 64];
-      const h8 aln = Aw[(ksn * 2 + 1) * 64];
+      long ks1 = c * 8 + j + 1;                        // A one k-step ahead
+      if (ks1 > last_ks) ks1 = last_ks;
+      const h8 a1h = Aw[ks1 * 128];
+      const h8 a1l = Aw[ks1 * 128 + 64];
       h8 b[4];
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch) b[ch] = Bb[((j * 4 + ch) * 2 + 0) * 64];
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, b[ch], acc[ch], 0, 0, 0);
+      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0l, b[ch], acc[ch], 0, 0, 0);
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, b[ch], acc[ch], 0, 0, 0);
+      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0h, b[ch], acc[ch], 0, 0, 0);
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch) b[ch] = Bb[((j * 4 + ch) * 2 + 1) * 64];
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, b[ch], acc[ch], 0, 0, 0);
-      ah = ahn;
-      al = aln;
+      for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0h, b[ch], acc[ch], 0, 0, 0);
+      if (more) gen_pair(kcb, j, fr);
+      a0h = a1h;
+      a0l = a1l;
     }
+    if (more) store_frags(buf ^ 1, fr);
+    store_coords(c & 1, cv0, cv1);                     // chunk c + 2 into the freed buffer
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) med[ch] += acc[ch];
     if ((c + 1) % SMED == 0 || c + 1 == nchunks) {
@@ -466,15 +497,19 @@ xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch
   const bool even = even_powers(cf);
   split_coef(cf, &k, even);
   dim3 grid(cdiv(a.bn, SB), (unsigned)(S.rows_pad / SR));
-  const size_t smem = sizeof(h8) * 2 * 8 * 8 * 64;
-  if (even)
-    hipLaunchKernelGGL(k_stage1_split<true>, grid, dim3(512), smem, st, (const h8*)S.A,
-                       (const int*)S.sA, (const float*)S.kc, S.n_g_pad, S.nks, a.xyz, a.n_g,
-                       a.n_mu, a.b0, a.bn, k, a.panel, a.rows_pad, a.bp);
-  else
-    hipLaunchKernelGGL(k_stage1_split<false>, grid, dim3(512), smem, st, (const h8*)S.A,
-                       (const int*)S.sA, (const float*)S.kc, S.n_g_pad, S.nks, a.xyz, a.n_g,
-                       a.n_mu, a.b0, a.bn, k, a.panel, a.rows_pad, a.bp);
+  const size_t smem = sizeof(h8) * 2 * 8 * 8 * 64 + sizeof(float) * 2 * 6 * SKC;
+  // compacted even-power polynomials of degree < 4 (powers up to 8) use the short form
+  bool short_even = even;
+  for (int j = 4; j < MAXQ / 2; ++j)
+    if (k.q1[j] != 0.0f || k.q2[j] != 0.0f) short_even = false;
+#define XTC_LAUNCH_SPLIT(EV, NQV)                                                              \
+  hipLaunchKernelGGL((k_stage1_split<EV, NQV>), grid, dim3(512), smem, st, (const h8*)S.A,     \
+                     (const int*)S.sA, (const float*)S.kc, S.n_g_pad, S.nks, a.xyz, a.n_g,    \
+                     a.n_mu, a.b0, a.bn, k, a.panel, a.rows_pad, a.bp)
+  if (short_even) XTC_LAUNCH_SPLIT(true, 4);
+  else if (even) XTC_LAUNCH_SPLIT(true, MAXQ / 2);
+  else XTC_LAUNCH_SPLIT(false, MAXQ);
+#undef XTC_LAUNCH_SPLIT
   XTC_CHECK_LAUNCH();
   // the rho row (exact field and the ISDF-free energy-scale sums) in FP64
   double* part = (double*)((char*)scratch + split_scratch_bytes(a.n_g, a.n_mu));
