@@ -230,3 +230,60 @@ class KernelTimer:
         self.result = self.read()
         L.lib().xtc_timing(0, None)
         return False
+
+
+def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None):
+    """dL/dc for L = sum over the given cotangents <cot[k], output k> (xtc_grad).
+    cot keys: u1, u3, ulap, D1, D4, field (device tensors of the outputs' shapes).
+    Returns a float64 device tensor [n_types * n_terms]."""
+    hc = HostCorrelator(corr, c)
+    xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
+    piv = np.ascontiguousarray(pivots, np.int64)
+    n_mu = piv.shape[0]
+    cv = {k: _in(cot.get(k), k) for k in ("u1", "u3", "ulap", "D1", "D4", "field")}
+    out = torch.empty(hc.c.size, dtype=torch.float64, device="cuda")
+    flags = 1 if cv["ulap"] is not None else 0
+    ws = _workspace(workspace_bytes(L.XTC_CALL_GRAD, grid.n_g, 0, n_mu, hc.c.size, flags))
+    g = grid.c()
+    _check("xtc_grad", L.lib().xtc_grad(
+        C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
+        _ptr(cv["u1"]), _ptr(cv["u3"]), _ptr(cv["ulap"]), _ptr(cv["D1"]), _ptr(cv["D4"]),
+        _ptr(cv["field"]), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+_OUT_KEYS = ("u1", "u3", "ulap", "D1", "D4", "field")
+_OUT_BITS = {"u1": L.XTC_U1, "u3": L.XTC_U3, "ulap": L.XTC_ULAP, "D1": L.XTC_D1, "D4": L.XTC_D4,
+             "field": L.XTC_FIELD}
+
+
+class XtcContract(torch.autograd.Function):
+    """Differentiable contraction: outputs (u1, u3, ulap, D1, D4, field) as functions of the
+    linear correlator coefficients theta. The backward pass calls xtc_grad, which regenerates
+    the kernel tiles instead of storing them; only the inputs are saved."""
+
+    @staticmethod
+    def forward(ctx, theta, grid, corr, xi, xigrad, rho, pivots, channels):
+        c = theta.detach().to("cpu", torch.float64).numpy()
+        out = kernel_contract(grid, corr, xi, xigrad, rho, pivots, channels & ~L.XTC_ESCALE,
+                              L.XTC_FP64, c=c)
+        ctx.save_for_backward(theta)
+        ctx.args = (grid, corr, xi, xigrad, rho, pivots)
+        ctx.present = [k for k in _OUT_KEYS if channels & _OUT_BITS[k]]
+        return tuple(out[k] for k in ctx.present)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        (theta,) = ctx.saved_tensors
+        grid, corr, xi, xigrad, rho, pivots = ctx.args
+        cot = {k: (gr.contiguous() if gr is not None else None) for k, gr in zip(ctx.present, grads)}
+        c = theta.detach().to("cpu", torch.float64).numpy()
+        d = grad(grid, corr, xi, xigrad, rho, pivots, cot, c=c)
+        return d.to(theta.device, theta.dtype).reshape(theta.shape), None, None, None, None, None, None, None
+
+
+def contract_autograd(theta, grid, corr, xi, xigrad, rho, pivots, channels):
+    """Functional form of XtcContract; returns a dict of the requested outputs."""
+    keys = [k for k in _OUT_KEYS if channels & _OUT_BITS[k]]
+    outs = XtcContract.apply(theta, grid, corr, xi, xigrad, rho, pivots, channels)
+    return dict(zip(keys, outs))

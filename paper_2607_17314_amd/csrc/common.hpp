@@ -71,7 +71,7 @@ inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 // ---------------------------------------------------------------------------
 // Generic FP64 GEMM (MFMA 16x16x4, tile 64x64x16):
-//   C[m, n] = alpha * sum_k A[m, k] s[k] B[k, n]   (+ beta * D[m, n])
+//   C[m, n] = alpha * sn[n] * sum_k A[m, k] s[k] B[k, n]   (+ beta * D[m, n])
 // then an optional epilogue: C <- C * E[m, n] (Hadamard) or C <- C * C.
 // Strides are in elements; A/B may be k- or m/n-contiguous.
 enum Epilogue { EPI_NONE = 0, EPI_MUL_E = 1, EPI_SQUARE = 2 };
@@ -88,6 +88,7 @@ struct GemmArgs {
   int epi = EPI_NONE;
   const double* E = nullptr; long e_sm = 0, e_sn = 0;
   bool lower_only = false;    // skip tiles strictly above the diagonal (m < n)
+  const double* sn = nullptr; // per-column scale of the product: alpha * sn[n] * (A B)[m, n]
 };
 
 xtc_status gemm_f64(const GemmArgs& g, hipStream_t st);

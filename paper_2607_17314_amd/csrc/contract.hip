@@ -289,22 +289,5 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   return XTC_OK;
 }
 
-namespace xtc {
-size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags) {
-  (void)n_g; (void)n_mu; (void)n_params; (void)flags;
-  return 0;
-}
-}  // namespace xtc
 
-extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
-                               const double* xi, const double* xigrad, const double* rho,
-                               const int64_t* pivots, const double* gu1, const double* gu3,
-                               const double* gulap, const double* gD1, const double* gD4,
-                               const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
-                               void* stream) {
-  (void)grid; (void)corr; (void)n_mu; (void)xi; (void)xigrad; (void)rho; (void)pivots; (void)gu1;
-  (void)gu3; (void)gulap; (void)gD1; (void)gD4; (void)gfield; (void)dtheta; (void)ws;
-  (void)ws_bytes; (void)stream;
-  xtc::set_error("xtc_grad: not built yet");
-  return XTC_ERR_UNSUPPORTED;
-}
+

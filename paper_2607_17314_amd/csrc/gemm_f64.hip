@@ -102,6 +102,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
         long n = n0 + 32 * wn + 16 * bj + li;
         if (m >= g.M || n >= g.N) continue;
         double v = g.alpha * acc[bi][bj][r];
+        if (g.sn) v *= g.sn[n];
         if (g.beta != 0.0) {
           const double* D = g.D ? g.D : g.C;
           v += g.beta * D[m * g.c_sm + n * g.c_sn];

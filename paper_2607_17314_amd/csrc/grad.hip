@@ -1,0 +1,403 @@
+// Adjoint of xtc_kernel_contract with respect to the linear correlator
+// coefficients c_k (EE form u = sum_k c_k rbar^{o_k}), in FP64.
+//
+// All outputs are built from the stage-1 panel P[ch][row][g] = sum_g' A[row][g'] K_ch(g, g')
+// (rows: w xi_mu, w rho_gamma, w rhot). Reverse mode in two parts:
+//  1. stage-2 adjoints give the panel cotangent Pbar[ch][row][g] (GEMMs with the output
+//     cotangents, plus the D1 term through H, whose cotangent lands on the rhot row);
+//  2. dL/dc_k = sum_{g,g'} sum_ch M_ch(g,g') dK_ch(g,g')/dc_k with
+//     M_ch(g,g') = sum_row Pbar[ch][row][g] A[row][g'],
+//     formed tile by tile on the matrix cores (v_mfma_f64_16x16x4f64) and contracted at
+//     once with the per-pair derivative basis; M is never stored.
+// For the channels: dK_c/dc_k = f_k Delta_c (c = x, y, z), d|grad u|^2/dc_k = 2 u' u'_k,
+// d lap u/dc_k = lap_k, with f_k, u'_k, lap_k the kernels of the unit coefficient e_k.
+// The kernel tiles are regenerated from coordinates; the D cotangents add one
+// recomputation of the forward panel per bra super-block.
+#include "contract.hpp"
+#include "plans.hpp"
+#include "timing.hpp"
+
+namespace xtc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr long GSUPER = 16384;
+constexpr int GT = 64;        // bra x ket tile
+constexpr int GK = 16;        // rows per LDS stage
+constexpr int KSEG = 8;       // ket segments (grid y)
+
+struct GradBasis {
+  double d;
+  int n;               // parameters
+  int o[MAXQ];         // powers
+  int omax;
+};
+
+// Per-pair contribution to dL/dc_k for every k, given M for the NCH channels.
+template <int NCH>
+__device__ __forceinline__ void pair_grad(const EECoef& cf, const GradBasis& gb, double dx,
+                                          double dy, double dz, const double* m, double* dth) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double d = gb.d;
+  const double t = 1.0 / (1.0 + d * r);
+  const double e = d * r * t;
+  const double t2 = t * t, t3 = t2 * t, t4 = t2 * t2;
+  double p1 = 0.0;
+  for (int j = cf.n1 - 1; j >= 0; --j) p1 = p1 * e + cf.q1[j];
+  const double up = d * t2 * p1;                      // u' at the current coefficients
+  const double sf = m[0] * dx + m[1] * dy + m[2] * dz;
+  const double s3 = 2.0 * up * m[3];
+  const double s4 = NCH > 4 ? m[4] : 0.0;
+  double ep[MAXQ + 1];
+  ep[0] = 1.0;
+  for (int j = 1; j <= gb.omax; ++j) ep[j] = ep[j - 1] * e;
+  for (int k = 0; k < gb.n; ++k) {
+    const int o = gb.o[k];
+    double fk = 0.0, upk = 0.0, lapk = 0.0;
+    if (o >= 2) {
+      fk = d * d * t3 * o * ep[o - 2];
+      upk = d * t2 * o * ep[o - 1];
+      lapk = d * d * t4 * o * (o - 1) * ep[o - 2] - 2.0 * d * d * t3 * o * ep[o - 1] + 2.0 * fk;
+    } else if (o == 1) {
+      upk = d * t2;
+      if (r > 0.0) {
+        fk = d * t2 / r;
+        lapk = -2.0 * d * d * t3 + 2.0 * fk;
+      }
+    }
+    dth[k] += sf * fk + s3 * upk + s4 * lapk;
+  }
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) void k_grad_pairs(
+    const double* __restrict__ Pb, long rows_pad, long bp, int n_rows,
+    const double* __restrict__ xi, const double* __restrict__ rho, const double* __restrict__ rhot,
+    const double* __restrict__ w, const double* __restrict__ xyz, long n_g, int n_mu, long b0,
+    long bn, EECoef cf, GradBasis gb, double* __restrict__ partials) {
+  __shared__ double Gs[NCH][GK][GT + 1];   // Pbar rows x bra
+  __shared__ double As[GK][GT + 1];        // A rows x ket
+  __shared__ double bxyz[3][GT];
+  __shared__ double kxyz[3][GT];
+  __shared__ double red[4][MAXQ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const long bt0 = (long)blockIdx.x * GT;               // bra tile origin within the block
+  const long per = ((n_g + KSEG - 1) / KSEG + GT - 1) / GT * GT;
+  const long k_lo = (long)blockIdx.y * per;
+  const long k_hi = k_lo + per < n_g ? k_lo + per : n_g;
+  if (tid < GT) {
+    long b = b0 + bt0 + tid;
+    if (b > b0 + bn - 1) b = b0 + bn - 1;
+    bxyz[0][tid] = xyz[b];
+    bxyz[1][tid] = xyz[n_g + b];
+    bxyz[2][tid] = xyz[2 * n_g + b];
+  }
+  double dth[MAXQ];
+  for (int k = 0; k < MAXQ; ++k) dth[k] = 0.0;
+
+  for (long kc = k_lo; kc < k_hi; kc += GT) {
+    __syncthreads();
+    if (tid < GT) {
+      long g = kc + tid;
+      if (g > n_g - 1) g = n_g - 1;
+      kxyz[0][tid] = xyz[g];
+      kxyz[1][tid] = xyz[n_g + g];
+      kxyz[2][tid] = xyz[2 * n_g + g];
+    }
+    d4 acc[NCH][2][2];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < n_rows; r0 += GK) {
+      __syncthreads();
+      // Pbar tile: NCH x 16 rows x 64 bra (bra contiguous in memory)
+      for (int e = tid; e < NCH * GK * GT; e += 256) {
+        const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
+        const long row = r0 + rr, b = bt0 + bb;
+        Gs[c][rr][bb] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
+      }
+      // A tile: 16 rows x 64 ket
+      for (int e = tid; e < GK * GT; e += 256) {
+        const int rr = e / GT, kk = e % GT;
+        const long row = r0 + rr, g = kc + kk;
+        double v = 0.0;
+        if (row < n_rows && g < k_hi)
+          v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
+        As[rr][kk] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < GK / 4; ++s) {
+        const double b0v = As[4 * s + lk][32 * wn + li];
+        const double b1v = As[4 * s + lk][32 * wn + 16 + li];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const double a0 = Gs[c][4 * s + lk][32 * wm + li];
+          const double a1 = Gs[c][4 * s + lk][32 * wm + 16 + li];
+          acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[c][0][0], 0, 0, 0);
+          acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[c][0][1], 0, 0, 0);
+          acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[c][1][0], 0, 0, 0);
+          acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[c][1][1], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: the 16 pairs this lane holds, D[(l/16) + 4r][l%16] = M[bra][ket]
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int bi = 32 * wm + 16 * i + lk + 4 * r;
+          const int kj = 32 * wn + 16 * j + li;
+          if (bt0 + bi >= bn || kc + kj >= k_hi) continue;
+          double m[NCH];
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) m[c] = acc[c][i][j][r];
+          pair_grad<NCH>(cf, gb, bxyz[0][bi] - kxyz[0][kj], bxyz[1][bi] - kxyz[1][kj],
+                         bxyz[2][bi] - kxyz[2][kj], m, dth);
+        }
+  }
+  // deterministic block reduction of the parameter partials
+  for (int k = 0; k < gb.n; ++k) {
+    double v = dth[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (tid < gb.n) {
+    const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[blk * MAXQ + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  }
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partials, long nblk, int n,
+                               double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (long b = 0; b < nblk; ++b) s += partials[b * MAXQ + k];
+  out[k] = s;
+}
+
+__global__ void k_sym(const double* __restrict__ a, long n, double* __restrict__ s) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n * n) return;
+  long i = t / n, j = t % n;
+  s[t] = a[t] + a[j * n + i];
+}
+
+__global__ void k_gather_G2(const double* __restrict__ rho, const long* __restrict__ piv, int n_mu,
+                            double* __restrict__ G) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n_mu) G[i] = rho[piv[i]];
+}
+
+__global__ void k_fill_rows(double* __restrict__ Pb, long rows_pad, long bp, int nch, int n_mu,
+                            long b0, long bn, const double* __restrict__ gfield, long n_g) {
+  // rho row: field cotangent (channels x, y, z), 0 for the other channels; rhot row: 0
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= bn) return;
+  for (int c = 0; c < nch; ++c) {
+    Pb[((long)c * rows_pad + n_mu) * bp + t] = (c < 3 && gfield) ? gfield[c * n_g + b0 + t] : 0.0;
+    Pb[((long)c * rows_pad + n_mu + 1) * bp + t] = 0.0;
+  }
+}
+
+// D1 term: Pbar^c[nu][g] += Pd[nu][g] H_c(g); Pbar^c[rhot row][g] = sum_nu Pd[nu][g] F^c[nu][g]
+__global__ void k_d1_terms(double* __restrict__ Pb, const double* __restrict__ F,
+                           const double* __restrict__ Pd, long rows_pad, long bp, int n_mu,
+                           long bn) {
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= bn) return;
+  for (int c = 0; c < 3; ++c) {
+    const double H = F[((long)c * rows_pad + n_mu + 1) * bp + t];
+    double hb = 0.0;
+    for (int nu = 0; nu < n_mu; ++nu) {
+      const double p = Pd[(long)nu * bp + t];
+      Pb[((long)c * rows_pad + nu) * bp + t] += p * H;
+      hb += p * F[((long)c * rows_pad + nu) * bp + t];
+    }
+    Pb[((long)c * rows_pad + n_mu + 1) * bp + t] = hb;
+  }
+}
+
+__global__ void k_mul_vec(const double* __restrict__ a, const double* __restrict__ b, long n,
+                          double* __restrict__ out) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+struct GradLayout {
+  long* piv; double* G; double* rhot; double* wt; double* F; double* Pb; double* Pd; double* S4;
+  double* partials; long bp; long rows_pad; int nsb; int nch; long nblk;
+};
+
+static GradLayout layout_grad(Arena& ar, int64_t n_g, int n_mu, uint32_t flags) {
+  GradLayout L;
+  L.nch = (flags & 1) ? 5 : 4;               // bit 0: Laplacian cotangent present
+  L.bp = n_g < GSUPER ? ((n_g + 63) / 64) * 64 : GSUPER;
+  L.rows_pad = ((n_mu + 2 + 63) / 64) * 64;
+  L.nsb = (int)cdiv(n_g, L.bp);
+  L.nblk = (long)cdiv(L.bp, GT) * KSEG;
+  L.piv = ar.take<long>(n_mu);
+  L.G = ar.take<double>(n_mu);
+  L.rhot = ar.take<double>(n_g);
+  L.wt = ar.take<double>(n_g);
+  L.F = ar.take<double>(4 * (size_t)L.rows_pad * L.bp);
+  L.Pb = ar.take<double>((size_t)L.nch * L.rows_pad * L.bp);
+  L.Pd = ar.take<double>((size_t)n_mu * L.bp);
+  L.S4 = ar.take<double>((size_t)n_mu * n_mu);
+  L.partials = ar.take<double>((size_t)L.nsb * L.nblk * MAXQ);
+  return L;
+}
+
+size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags) {
+  (void)n_params;
+  Arena ar(nullptr, 0);
+  layout_grad(ar, n_g, n_mu, flags);
+  return ar.used;
+}
+
+}  // namespace xtc
+
+using namespace xtc;
+
+extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                               const double* xi, const double* xigrad, const double* rho,
+                               const int64_t* pivots, const double* gu1, const double* gu3,
+                               const double* gulap, const double* gD1, const double* gD4,
+                               const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
+                               void* stream) {
+  XTC_REQUIRE(grid && corr && xi && rho && pivots && dtheta, "xtc_grad: null argument");
+  XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "xtc_grad: empty grid");
+  XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "xtc_grad: bad n_mu");
+  XTC_REQUIRE(!gu1 || xigrad, "xtc_grad: the u1 cotangent needs xigrad");
+  XTC_REQUIRE(corr->n_terms > 0 && corr->n_terms <= MAXQ && corr->mno && corr->c && corr->d > 0.0,
+              "xtc_grad: bad correlator");
+  for (int m = 0; m < n_mu; ++m)
+    XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "xtc_grad: pivot index out of range");
+  if (corr->form != XTC_U_EE) {
+    set_error("xtc_grad: this entry point differentiates the EE correlator form");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  EECoef cf;
+  XTC_TRY(ee_coefficients(corr, &cf));
+  GradBasis gb{};
+  gb.d = corr->d;
+  gb.n = corr->n_terms;
+  gb.omax = 0;
+  for (int k = 0; k < gb.n; ++k) {
+    gb.o[k] = corr->mno[3 * k + 2];
+    if (gb.o[k] > gb.omax) gb.omax = gb.o[k];
+  }
+  hipStream_t st = as_stream(stream);
+  const long n_g = grid->n_g;
+  Arena ar(ws, ws_bytes);
+  GradLayout L = layout_grad(ar, n_g, n_mu, gulap ? 1u : 0u);
+  XTC_TRY(need_ws(ar));
+  size_t tk = timing_begin(TM_GRAD, st);
+  XTC_HIP(hipMemcpyAsync(L.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_gather_G2, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho, (const long*)L.piv,
+                     n_mu, L.G);
+  {
+    GemmArgs g{};   // rhot = G^T xi
+    g.M = 1; g.N = n_g; g.K = n_mu;
+    g.A = L.G; g.a_sm = 1; g.a_sk = 1;
+    g.B = xi; g.b_sk = n_g; g.b_sn = 1;
+    g.C = L.rhot; g.c_sm = n_g; g.c_sn = 1;
+    XTC_TRY(gemm_f64(g, st));
+  }
+  hipLaunchKernelGGL(k_mul_vec, dim3(cdiv(n_g, 256)), dim3(256), 0, st, grid->w,
+                     (const double*)L.rhot, n_g, L.wt);
+  XTC_CHECK_LAUNCH();
+  if (gD4) {
+    hipLaunchKernelGGL(k_sym, dim3(cdiv((long)n_mu * n_mu, 256)), dim3(256), 0, st, gD4, (long)n_mu,
+                       L.S4);
+    XTC_CHECK_LAUNCH();
+  }
+  const bool need_fwd = gD1 || gD4;
+  Stage1Args s1{grid->xyz, grid->w, xi, rho, L.rhot, n_g, n_mu, 0, 0, L.F, L.rows_pad, L.bp, 4};
+  for (int sb = 0; sb < L.nsb; ++sb) {
+    const long b0 = (long)sb * L.bp;
+    const long bn = (n_g - b0) < L.bp ? (n_g - b0) : L.bp;
+    if (need_fwd) {
+      s1.b0 = b0;
+      s1.bn = bn;
+      XTC_TRY(stage1_f64(s1, cf, st));
+    }
+    // Pbar for rows 0..n_mu-1 of every channel
+    auto tn = [&](const double* cot, const double* B, long b_sk, const double* sn, double* C,
+                  double beta) {
+      GemmArgs g{};   // C[nu][g] = sn[g] sum_mu cot[mu][nu] B[mu][g] + beta C
+      g.M = n_mu; g.N = bn; g.K = n_mu;
+      g.A = cot; g.a_sm = 1; g.a_sk = n_mu;
+      g.B = B; g.b_sk = b_sk; g.b_sn = 1;
+      g.sn = sn;
+      g.C = C; g.c_sm = L.bp; g.c_sn = 1;
+      g.beta = beta;
+      return gemm_f64(g, st);
+    };
+    const double* wb = grid->w + b0;
+    for (int c = 0; c < L.nch; ++c) {
+      double* Pc = L.Pb + (long)c * L.rows_pad * L.bp;
+      bool have = false;
+      const double* cot = nullptr;
+      const double* B = nullptr;
+      if (c < 3 && gu1) { cot = gu1 + (long)c * n_mu * n_mu; B = xigrad + (long)c * n_mu * n_g + b0; }
+      if (c == 3 && gu3) { cot = gu3; B = xi + b0; }
+      if (c == 4 && gulap) { cot = gulap; B = xi + b0; }
+      if (cot) {
+        XTC_TRY(tn(cot, B, n_g, wb, Pc, 0.0));
+        have = true;
+      }
+      if (c < 3 && gD4) {
+        GemmArgs g{};   // += wt (S4 F^c)
+        g.M = n_mu; g.N = bn; g.K = n_mu;
+        g.A = L.S4; g.a_sm = n_mu; g.a_sk = 1;
+        g.B = L.F + (long)c * L.rows_pad * L.bp; g.b_sk = L.bp; g.b_sn = 1;
+        g.sn = L.wt + b0;
+        g.C = Pc; g.c_sm = L.bp; g.c_sn = 1;
+        g.beta = have ? 1.0 : 0.0;
+        XTC_TRY(gemm_f64(g, st));
+        have = true;
+      }
+      if (!have) XTC_HIP(hipMemsetAsync(Pc, 0, sizeof(double) * L.rows_pad * L.bp, st));
+    }
+    hipLaunchKernelGGL(k_fill_rows, dim3(cdiv(bn, 256)), dim3(256), 0, st, L.Pb, L.rows_pad, L.bp,
+                       L.nch, n_mu, b0, bn, gfield, n_g);
+    XTC_CHECK_LAUNCH();
+    if (gD1) {
+      XTC_TRY(tn(gD1, xi + b0, n_g, wb, L.Pd, 0.0));   // Pd = w (gD1^T xi)
+      hipLaunchKernelGGL(k_d1_terms, dim3(cdiv(bn, 256)), dim3(256), 0, st, L.Pb,
+                         (const double*)L.F, (const double*)L.Pd, L.rows_pad, L.bp, n_mu, bn);
+      XTC_CHECK_LAUNCH();
+    }
+    dim3 gridp(cdiv(bn, GT), KSEG);
+    double* part = L.partials + (long)sb * L.nblk * MAXQ;
+    if (L.nch == 4)
+      hipLaunchKernelGGL(k_grad_pairs<4>, gridp, dim3(256), 0, st, (const double*)L.Pb, L.rows_pad,
+                         L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w, grid->xyz, n_g,
+                         n_mu, b0, bn, cf, gb, part);
+    else
+      hipLaunchKernelGGL(k_grad_pairs<5>, gridp, dim3(256), 0, st, (const double*)L.Pb, L.rows_pad,
+                         L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w, grid->xyz, n_g,
+                         n_mu, b0, bn, cf, gb, part);
+    XTC_CHECK_LAUNCH();
+    // unused block slots of a short last super-block stay zero
+    if ((long)gridp.x * KSEG < L.nblk)
+      XTC_HIP(hipMemsetAsync(part + (long)gridp.x * KSEG * MAXQ, 0,
+                             sizeof(double) * (L.nblk - (long)gridp.x * KSEG) * MAXQ, st));
+  }
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
+                     (long)L.nsb * L.nblk, gb.n, dtheta);
+  XTC_CHECK_LAUNCH();
+  timing_end(tk, st);
+  return XTC_OK;
+}

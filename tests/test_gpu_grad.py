@@ -1,0 +1,79 @@
+"""GPU adjoint (xtc_grad) against the oracle's forward-mode derivatives and
+against central finite differences of the device forward pass, through the
+C ABI and through the torch.autograd.Function."""
+import numpy as np
+import pytest
+
+from gpu_common import note
+
+pytestmark = pytest.mark.gpu
+
+ALL = 1 | 2 | 4 | 8 | 16 | 32
+
+
+@pytest.fixture(scope="module")
+def problem(h6_small):
+    from oracle import fit, orbitals, pivots
+    wl = h6_small
+    phi4 = orbitals.eval_orbitals(wl.basis, wl.C_mo, wl.grid_xyz)
+    idx = np.sort(np.random.default_rng(5).choice(wl.n_g, 1300, replace=False))   # ragged size
+    xyz, w, phi4 = np.ascontiguousarray(wl.grid_xyz[:, idx]), wl.grid_w[idx].copy(), phi4[:, :, idx]
+    fp = pivots.select_fused(phi4, w, 70)
+    fr = fit.fit(phi4, w, fp.pivots)
+    rho = orbitals.density(phi4, wl.n_occ)
+    rng = np.random.default_rng(33)
+    n = len(fp.pivots)
+    cot = {"u1": rng.normal(size=(3, n, n)) / n, "u3": rng.normal(size=(n, n)) / n,
+           "ulap": rng.normal(size=(n, n)) / n, "D1": rng.normal(size=(n, n)) / n,
+           "D4": rng.normal(size=(n, n)) / n, "field": rng.normal(size=(3, len(w))) / np.sqrt(len(w))}
+    return wl, xyz, w, fp.pivots, fr, rho, cot
+
+
+def _device(api, problem):
+    import torch
+    wl, xyz, w, piv, fr, rho, cot = problem
+    grid = api.DeviceGrid.from_host(xyz, w)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    return grid, t(fr.xi), t(fr.xigrad), t(rho), {k: t(v) for k, v in cot.items()}
+
+
+@pytest.mark.parametrize("subset", ["all", "u1u3", "D-only"])
+def test_adjoint_matches_oracle(problem, subset):
+    import torch
+    from oracle import adjoint
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, cot = problem
+    keys = {"all": list(cot), "u1u3": ["u1", "u3", "field"], "D-only": ["D1", "D4"]}[subset]
+    c_sub = {k: cot[k] for k in keys}
+    ref = adjoint.dL_dc(xyz, w, wl.corr, fr.xi, fr.xigrad, rho[piv], rho, c_sub)
+    grid, xi, xig, rh, dcot = _device(api, problem)
+    got = api.grad(grid, wl.corr, xi, xig, rh, piv, {k: dcot[k] for k in keys}).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    note(f"adjoint {subset}: device {got}, oracle {ref}, rel err {err:.2e}")
+    assert err < 1e-10
+
+
+def test_adjoint_matches_central_differences_and_autograd(problem):
+    import torch
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, cot = problem
+    grid, xi, xig, rh, dcot = _device(api, problem)
+    theta = torch.tensor(wl.corr.c.ravel(), dtype=torch.float64, requires_grad=True)
+    outs = api.contract_autograd(theta, grid, wl.corr, xi, xig, rh, piv, ALL)
+    loss = sum((outs[k] * dcot[k]).sum() for k in outs)
+    loss.backward()
+    g_auto = theta.grad.numpy().copy()
+    h = 1e-4
+    fd = np.zeros_like(g_auto)
+    for j in range(theta.numel()):
+        vals = []
+        for s in (+1, -1):
+            c = wl.corr.c.ravel().copy()
+            c[j] += s * h
+            o = api.kernel_contract(grid, wl.corr, xi, xig, rh, piv, ALL, c=c)
+            vals.append(sum(float((o[k] * dcot[k]).sum()) for k in ("u1", "u3", "ulap", "D1", "D4", "field")))
+        fd[j] = (vals[0] - vals[1]) / (2 * h)
+    err = np.abs(g_auto - fd).max() / np.abs(fd).max()
+    note(f"autograd {g_auto} vs central FD {fd}: rel err {err:.2e}")
+    # every output is a polynomial of degree <= 2 in c: central differences are exact up to rounding
+    assert err < 1e-7
