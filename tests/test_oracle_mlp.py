@@ -1,0 +1,56 @@
+"""Pins of the learned-point oracle: finite-difference gradients, the Adam
+closed form on a quadratic, feature definitions and top-k selection."""
+import numpy as np
+
+from oracle import mlp, orbitals
+
+
+def test_loss_gradient_matches_central_differences():
+    h = 6
+    rng = np.random.default_rng(0)
+    p = mlp.init_params(h, 1) + 0.1 * rng.normal(size=mlp.n_params(h))
+    x = rng.normal(size=(8, 40))
+    y = (rng.random(40) < 0.3).astype(float)
+    loss, g = mlp.loss_grad(p, h, x, y, 2.5)
+    fd = np.zeros_like(p)
+    eps = 1e-6
+    for j in range(p.size):
+        e = np.zeros_like(p)
+        e[j] = eps
+        fd[j] = (mlp.loss_grad(p + e, h, x, y, 2.5)[0] - mlp.loss_grad(p - e, h, x, y, 2.5)[0]) / (2 * eps)
+    assert np.abs(fd - g).max() < 1e-7 * max(1.0, np.abs(g).max())
+    assert mlp.n_params(64) == 4801
+
+
+def test_adam_on_a_quadratic():
+    # for f = 0.5 |p|^2 the first Adam step moves every coordinate by lr (bias-corrected)
+    p = np.array([1.0, -2.0, 3.0])
+    p1, m, v = mlp.adam(p, p.copy(), np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(p1, p - 0.01 * np.sign(p), rtol=1e-6)
+
+
+def test_features_definitions(h2_tiny):
+    phi4 = orbitals.eval_orbitals(h2_tiny.basis, h2_tiny.C_mo, h2_tiny.grid_xyz)
+    f = mlp.features(phi4, h2_tiny.grid_w, 1, h2_tiny.grid_xyz, h2_tiny.atom_xyz)
+    assert f.shape == (8, h2_tiny.n_g)
+    assert np.allclose(np.exp(f[3]), phi4[0, 0] ** 2 + 1e-30)
+    # grad rho by central differences at a few points
+    idx = [3, 77, 300]
+    hh = 1e-5
+    for g in idx:
+        gr = []
+        for c in range(3):
+            e = np.zeros((3, 1))
+            e[c] = hh
+            xp = orbitals.eval_orbitals(h2_tiny.basis, h2_tiny.C_mo, h2_tiny.grid_xyz[:, [g]] + e)[0, 0, 0] ** 2
+            xm = orbitals.eval_orbitals(h2_tiny.basis, h2_tiny.C_mo, h2_tiny.grid_xyz[:, [g]] - e)[0, 0, 0] ** 2
+            gr.append((xp - xm) / (2 * hh))
+        assert np.isclose(np.exp(f[4, g]), np.linalg.norm(gr), rtol=1e-6)
+    # the two-nuclei case repeats the farther distance for the third slot
+    assert np.allclose(f[6], f[7])
+
+
+def test_top_candidates_ties_and_order():
+    s = np.array([0.5, 2.0, 2.0, -1.0, 2.0, 0.7])
+    assert mlp.top_candidates(s, 2).tolist() == [1, 2]
+    assert mlp.top_candidates(s, 4).tolist() == [1, 2, 4, 5]
