@@ -123,7 +123,8 @@ typedef struct {
   const int32_t* nuc_type; /* host [n_nuc] (BH only) */
 } xtc_correlator;
 
-/* Learned point scorer: MLP 8 -> hidden -> hidden -> 1 with SiLU, FP32 weights
+/* Learned point scorer (not part of the paper; see isdf_select_points):
+ * MLP 8 -> hidden -> hidden -> 1 with SiLU on z-scored log features, FP32 weights
  * packed as W1[hidden][8], b1[hidden], W2[hidden][hidden], b2[hidden], W3[hidden], b3. */
 typedef struct {
   int32_t in_dim;          /* must be 8 */
@@ -131,7 +132,12 @@ typedef struct {
   const float* params;     /* device, 8h + h + h*h + h + h + 1 floats */
   const float* feat_shift; /* device [8]: feature z-score shift */
   const float* feat_scale; /* device [8]: feature z-score scale */
-  double kappa;            /* candidates kept = kappa * n_mu */
+  double kappa;            /* candidates kept = ceil(kappa * n_mu), clamped to n_g */
+  int32_t n_nuc;           /* nuclei for the distance features */
+  const double* nuc_xyz;   /* host [n_nuc][3] */
+  int32_t judge;           /* 0: reference residual from the fit below; 1: run the QR
+                              selection and use its residual (validation) */
+  double ref_a, ref_b;     /* judge 0: log R_ref = ref_a + ref_b log(n_mu / n_orb) */
 } xtc_mlp;
 
 /* Thread-local message of the last failing call (valid until the next call). */
@@ -142,7 +148,7 @@ const char* xtc_version(void);
 
 /* Call identifiers for xtc_workspace_bytes. */
 enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
-       XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5 };
+       XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7 };
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
  * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT).
@@ -160,6 +166,11 @@ xtc_status xtc_eval_orbitals(const xtc_basis* basis, const xtc_grid* grid, const
                              void* ws, size_t ws_bytes, void* stream);
 
 /* Interpolation-point selection (ISDF section, pivot selection and fusion; Alg. 1).
+ * Learned modes (not in the paper): score every point with the MLP, keep the
+ * ceil(kappa n_mu) best (ties to the lowest index), run the same fused pivoting
+ * restricted to those candidates; XTC_SELECT_LEARNED_JUDGED then computes the
+ * weighted scalar-channel fit residual R of the proposal over the whole grid and
+ * falls back to the QR selection (XTC_WARN_FALLBACK) when R > fallback_factor R_ref.
  * QR mode: matrix-free weight-scaled pivoted Cholesky, FP64, on the scalar channel
  * d_g = w_g^2 (sum_p phi_p^2)^2 and the gradient channel
  * d_g = w_g^2 (sum_p phi_p^2)(sum_{p,c} (d_c phi_p)^2); ties go to the lowest index;
@@ -233,6 +244,29 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
 #define XTC_TIMING_CATEGORIES 8
 xtc_status xtc_timing(int32_t mode, double* out);
+
+/* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,
+ * sum (grad phi)^2, rho_gamma, |grad rho_gamma|, and the three smallest nuclear
+ * distances (the last repeated if n_nuc < 3); log(x + 1e-30), computed in FP64.
+ * phi4: device [4][n_orb][n_g]. nuc_xyz: host [n_nuc][3]. feats: device float [8][n_g]. */
+xtc_status xtc_mlp_features(const double* phi4, const xtc_grid* grid, int32_t n_orb, int32_t n_occ,
+                            int32_t n_nuc, const double* nuc_xyz, float* feats, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* MLP logits of n points: logits[i] = s(feats[:, i]) with the z-scoring of mlp. FP32. */
+xtc_status xtc_mlp_forward(const xtc_mlp* mlp, const float* feats, int64_t ld, int64_t n,
+                           float* logits, void* stream);
+
+/* Weighted binary cross-entropy of n points (labels 0/1, float) and its gradient
+ * w.r.t. the packed parameters: L = mean [pw y softplus(-s) + (1 - y) softplus(s)].
+ * loss: device float [1]; grad: device float [n_params]. Deterministic. */
+xtc_status xtc_mlp_loss_grad(const xtc_mlp* mlp, const float* feats, int64_t ld, int64_t n,
+                             const float* labels, float pos_weight, float* loss, float* grad,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step on device arrays (t = step number, from 1). */
+xtc_status xtc_adam_step(float* params, const float* grad, float* m, float* v, int32_t n,
+                         float lr, float beta1, float beta2, float eps, int32_t t, void* stream);
 
 #ifdef __cplusplus
 }

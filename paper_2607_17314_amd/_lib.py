@@ -14,6 +14,7 @@ XTC_U1, XTC_U3, XTC_ULAP, XTC_D1, XTC_D4, XTC_FIELD, XTC_ESCALE = 1, 2, 4, 8, 16
 XTC_SELECT_QR, XTC_SELECT_LEARNED, XTC_SELECT_LEARNED_JUDGED = 0, 1, 2
 XTC_FIT_XI, XTC_FIT_XIGRAD = 1, 2
 XTC_CALL_EVAL_ORBITALS, XTC_CALL_SELECT, XTC_CALL_FIT, XTC_CALL_CONTRACT, XTC_CALL_GRAD = 1, 2, 3, 4, 5
+XTC_CALL_FEATURES, XTC_CALL_MLP_GRAD = 6, 7
 
 STATUS_NAMES = {0: "XTC_OK", 1: "XTC_WARN_RANK_DEFICIENT", 2: "XTC_WARN_JITTER",
                 3: "XTC_WARN_FALLBACK", -1: "XTC_ERR_INVALID_ARG", -2: "XTC_ERR_NOT_SPD",
@@ -43,7 +44,8 @@ class Correlator(C.Structure):
 
 class Mlp(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("params", P), ("feat_shift", P),
-                ("feat_scale", P), ("kappa", C.c_double)]
+                ("feat_scale", P), ("kappa", C.c_double), ("n_nuc", C.c_int32), ("nuc_xyz", D),
+                ("judge", C.c_int32), ("ref_a", C.c_double), ("ref_b", C.c_double)]
 
 
 _lib = None
@@ -84,10 +86,22 @@ def lib() -> C.CDLL:
                            P, P, P, P, C.c_size_t, P]
     L.xtc_timing.restype = st
     L.xtc_timing.argtypes = [C.c_int32, D]
+    L.xtc_mlp_features.restype = st
+    L.xtc_mlp_features.argtypes = [P, C.POINTER(Grid), C.c_int32, C.c_int32, C.c_int32, D, P, P,
+                                   C.c_size_t, P]
+    L.xtc_mlp_forward.restype = st
+    L.xtc_mlp_forward.argtypes = [C.POINTER(Mlp), P, C.c_int64, C.c_int64, P, P]
+    L.xtc_mlp_loss_grad.restype = st
+    L.xtc_mlp_loss_grad.argtypes = [C.POINTER(Mlp), P, C.c_int64, C.c_int64, P, C.c_float, P, P, P,
+                                    C.c_size_t, P]
+    L.xtc_adam_step.restype = st
+    L.xtc_adam_step.argtypes = [P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                C.c_int32, P]
     _lib = L
     return L
 
 
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
-            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing"]
+            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing",
+            "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep"]

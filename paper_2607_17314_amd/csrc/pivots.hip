@@ -259,11 +259,16 @@ using namespace xtc;
 xtc_status xtc_select_qr(const double* phi4, const xtc_grid* grid, int n_orb, int n_mu,
                          int64_t* pivots, int32_t* n_mu_out, double* info, Arena& ar,
                          hipStream_t st);
+xtc_status xtc_select_learned(const double* phi4, const xtc_grid* grid, int n_orb, int n_occ,
+                              int n_mu, int mode, const xtc_mlp* mlp, double fallback_factor,
+                              int64_t* pivots, int32_t* n_mu_out, double* info, Arena& ar,
+                              hipStream_t st);
 
 xtc_status xtc_select_qr(const double* phi4, const xtc_grid* grid, int n_orb, int n_mu,
                          int64_t* pivots, int32_t* n_mu_out, double* info, Arena& ar,
                          hipStream_t st) {
   const long n_g = grid->n_g;
+  const size_t mark = ar.used;
   SelLayout S = layout_sel(ar, n_g, n_mu);
   XTC_TRY(need_ws(ar));
   XTC_HIP(hipMemsetAsync(S.mark, 0, n_g, st));
@@ -300,6 +305,7 @@ xtc_status xtc_select_qr(const double* phi4, const xtc_grid* grid, int n_orb, in
     info[0] = ns;
     info[1] = ng;
   }
+  ar.used = mark;
   return n < n_mu ? XTC_WARN_RANK_DEFICIENT : XTC_OK;
 }
 
@@ -314,21 +320,24 @@ extern "C" xtc_status isdf_select_points(const double* phi4, const xtc_grid* gri
                                          const xtc_mlp* mlp, double fallback_factor,
                                          int64_t* pivots, int32_t* n_mu_out, double* info,
                                          void* ws, size_t ws_bytes, void* stream) {
-  (void)n_occ; (void)mlp; (void)fallback_factor;
   XTC_REQUIRE(phi4 && grid && pivots && n_mu_out, "isdf_select_points: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->w, "isdf_select_points: empty grid");
   XTC_REQUIRE(n_orb > 0 && n_mu_target > 0 && n_mu_target <= grid->n_g,
               "isdf_select_points: bad sizes");
-  if (mode != XTC_SELECT_QR) {
-    set_error("isdf_select_points: learned modes not built yet");
-    return XTC_ERR_UNSUPPORTED;
-  }
+  XTC_REQUIRE(mode == XTC_SELECT_QR || mode == XTC_SELECT_LEARNED ||
+                  mode == XTC_SELECT_LEARNED_JUDGED,
+              "isdf_select_points: unknown mode");
+  XTC_REQUIRE(mode == XTC_SELECT_QR || mlp, "isdf_select_points: learned modes need an mlp");
   if (info)
     for (int i = 0; i < 8; ++i) info[i] = 0.0;
   Arena ar(ws, ws_bytes);
   size_t tk = timing_begin(TM_SELECT, as_stream(stream));
-  xtc_status s = xtc_select_qr(phi4, grid, n_orb, n_mu_target, pivots, n_mu_out, info, ar,
-                               as_stream(stream));
+  xtc_status s = mode == XTC_SELECT_QR
+                     ? xtc_select_qr(phi4, grid, n_orb, n_mu_target, pivots, n_mu_out, info, ar,
+                                     as_stream(stream))
+                     : xtc_select_learned(phi4, grid, n_orb, n_occ, n_mu_target, mode, mlp,
+                                          fallback_factor, pivots, n_mu_out, info, ar,
+                                          as_stream(stream));
   timing_end(tk, as_stream(stream));
   return s;
 }
