@@ -120,7 +120,7 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
-  C.rows_pad = ((n_mu + 2 + 63) / 64) * 64;
+  C.rows_pad = ((n_mu + 2 + 255) / 256) * 256;   // whole row tiles of the split kernel
   C.nsb = (int)cdiv(n_g, C.bp);
   C.piv = ar.take<long>(n_mu);
   C.G = ar.take<double>(n_mu);
