@@ -239,10 +239,12 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * each launch of the timed stages. mode 1: reset and start collecting; 0: stop and
  * reset; 2: synchronise the recorded events and write, per category c,
  * out[2c] = summed milliseconds and out[2c+1] = number of launches.
- * Categories: 0 stage-1 pair kernel, 1 stage-2 GEMMs, 2 pivot selection,
- * 3 fit, 4 orbitals, 5 adjoint pair kernel, 6 MLP, 7 split-operand preparation.
+ * Categories: 0 stage 1 (pair kernel and density rows, per bra super-block),
+ * 1 stage-2 GEMMs, 2 pivot selection, 3 fit, 4 orbitals, 5 adjoint pair kernel,
+ * 6 MLP, 7 split-operand preparation, 8 the stage-1 pair kernel alone (one entry
+ * per kernel launch).
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 8
+#define XTC_TIMING_CATEGORIES 9
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

@@ -104,4 +104,5 @@ def lib() -> C.CDLL:
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
             "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing",
             "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
-TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep"]
+TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
+                     "stage1_kernel"]

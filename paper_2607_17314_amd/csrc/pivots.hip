@@ -145,36 +145,55 @@ __global__ __launch_bounds__(PIV_BLOCK) void k_pick(const double* __restrict__ p
   for (int l = threadIdx.x; l < s_step; l += PIV_BLOCK) lstar[l] = L[(long)l * n_g + gs];
 }
 
+// dot(x[i * stride], y[i]) over i < n with sixteen loads in flight and four
+// accumulators combined in a fixed order (the column is memory-bound; a single
+// dependent chain would leave one load outstanding per wave)
+__device__ __forceinline__ double strided_dot(const double* __restrict__ x, long stride,
+                                              const double* __restrict__ y, int n) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = 0;
+  for (; i + 16 <= n; i += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = x[(long)(i + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u & 3] += v[u] * y[i + u];
+  }
+  for (; i < n; ++i) a[0] += x[(long)i * stride] * y[i];
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 __global__ __launch_bounds__(PIV_BLOCK) void k_column(const double* __restrict__ phi4,
                                                       const double* __restrict__ w, long n_g,
                                                       int n_orb, int channel, double* __restrict__ L,
                                                       const double* __restrict__ lstar,
                                                       PivCtl* ctl, double* __restrict__ d,
                                                       double* __restrict__ pd,
-                                                      long* __restrict__ pg) {
-  extern __shared__ double sphi[];   // [4][n_orb] orbitals at the pivot (channel 1), [n_orb] else
+                                                      long* __restrict__ pg, int lrow_in_lds) {
+  // orbitals at the pivot ([4][n_orb] for channel 1, [n_orb] else), then L[.][g*]
+  extern __shared__ double sphi[];
   if (ctl->stop) return;
   const int mu = ctl->step - 1;
   const long gs = ctl->gstar;
   const double inv = 1.0 / sqrt(ctl->dstar);
   const int nrows = channel == 0 ? n_orb : 4 * n_orb;
+  double* sl = sphi + nrows;
   for (int i = threadIdx.x; i < nrows; i += PIV_BLOCK) sphi[i] = phi4[(long)i * n_g + gs];
+  if (lrow_in_lds)
+    for (int i = threadIdx.x; i < mu; i += PIV_BLOCK) sl[i] = lstar[i];
   __syncthreads();
   long g = (long)blockIdx.x * PIV_BLOCK + threadIdx.x;
   Cand c{-1.0, 0x7fffffffffffffffL};
   if (g < n_g) {
-    double a = 0.0;
-    for (int p = 0; p < n_orb; ++p) a += phi4[(long)p * n_g + g] * sphi[p];
+    const double a = strided_dot(phi4 + g, n_g, sphi, n_orb);
     double s;
     if (channel == 0) {
       s = w[g] * w[gs] * a * a;
     } else {
-      double bb = 0.0;
-      for (int q = n_orb; q < 4 * n_orb; ++q) bb += phi4[(long)q * n_g + g] * sphi[q];
+      const double bb = strided_dot(phi4 + (long)n_orb * n_g + g, n_g, sphi + n_orb, 3 * n_orb);
       s = w[g] * w[gs] * a * bb;
     }
-    double acc = 0.0;
-    for (int l = 0; l < mu; ++l) acc += L[(long)l * n_g + g] * lstar[l];
+    const double acc = lrow_in_lds ? strided_dot(L + g, n_g, sl, mu) : strided_dot(L + g, n_g, lstar, mu);
     double col = (s - acc) * inv;
     L[(long)mu * n_g + g] = col;
     double dn = d[g] - col * col;
@@ -229,7 +248,10 @@ static xtc_status run_channel(const double* phi4, const double* w, long n_g, int
   XTC_CHECK_LAUNCH();
   (void)fill_target;
   PivCtl h{};
-  const size_t smem = sizeof(double) * (channel == 0 ? n_orb : 4 * n_orb);
+  // pivot orbitals and, up to 8192 steps, the pivot's Cholesky row in LDS
+  const int lrow_in_lds = max_steps <= 8192;
+  const size_t smem =
+      sizeof(double) * ((channel == 0 ? n_orb : 4 * n_orb) + (lrow_in_lds ? max_steps : 0));
   const int mode = channel == 0 ? 1 : 0;
   const int batch = 64;
   int done_steps = 0;
@@ -239,7 +261,7 @@ static xtc_status run_channel(const double* phi4, const double* w, long n_g, int
       hipLaunchKernelGGL(k_pick, dim3(1), dim3(PIV_BLOCK), 0, st, S.pd, S.pg, S.nparts, S.ctl,
                          piv_out, S.L, n_g, S.lstar, S.mark, mode, s == 0 ? 1 : 0);
       hipLaunchKernelGGL(k_column, dim3(nb), dim3(PIV_BLOCK), smem, st, phi4, w, n_g, n_orb,
-                         channel, S.L, S.lstar, S.ctl, S.d, S.pd, S.pg);
+                         channel, S.L, S.lstar, S.ctl, S.d, S.pd, S.pg, lrow_in_lds);
     }
     XTC_CHECK_LAUNCH();
     XTC_HIP(hipMemcpyAsync(&h, S.ctl, sizeof(PivCtl), hipMemcpyDeviceToHost, st));

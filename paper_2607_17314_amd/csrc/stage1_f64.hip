@@ -13,6 +13,7 @@
 //     v_mfma_f64_16x16x4f64 per channel and sub-tile.
 // The kernel tile is generated once per workgroup and reused by all 64 rows.
 #include "contract.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -139,12 +140,14 @@ __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ x
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
   dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 2, 64));
+  const size_t tk = timing_begin(TM_S1_KERNEL, st);
   if (a.nch == 4)
     hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
   else
     hipLaunchKernelGGL(k_stage1_f64<5>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
+  timing_end(tk, st);
   XTC_CHECK_LAUNCH();
   return XTC_OK;
 }

@@ -25,6 +25,7 @@
 //   D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
 #include <type_traits>
 #include "contract.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -664,9 +665,11 @@ xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch
   hipLaunchKernelGGL((k_stage1_split<EV, NQV, SPLIT_WAVES>), grid, dim3(64 * SPLIT_WAVES), smem, st, (const h8*)S.A, \
                      (const int*)S.sA, (const float*)S.kc, S.n_g_pad, S.nks, a.xyz, a.n_g,    \
                      a.n_mu, a.b0, a.bn, k, a.panel, a.rows_pad, a.bp, c0, c1, first)
+    const size_t tk = timing_begin(TM_S1_KERNEL, st);
     if (short_even) XTC_LAUNCH_SPLIT(true, 4);
     else if (even) XTC_LAUNCH_SPLIT(true, MAXQ / 2);
     else XTC_LAUNCH_SPLIT(false, MAXQ);
+    timing_end(tk, st);
     XTC_CHECK_LAUNCH();
   }
 #undef XTC_LAUNCH_SPLIT
