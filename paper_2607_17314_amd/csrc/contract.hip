@@ -9,6 +9,7 @@
 #include "contract.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
+#include "gemm_split.hpp"
 
 namespace xtc {
 
@@ -113,6 +114,7 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b
 struct ConLayout {
   long* piv; double* G; double* rhot; double* panel; double* V; double* wt; double* H; double* e3x;
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
+  void* gsplit; size_t gsplit_bytes;
   long bp; long rows_pad; int nsb; int nch;
 };
 
@@ -138,6 +140,9 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   C.split_bytes = precision == XTC_SPLIT_F16
                       ? split_scratch_bytes(n_g, n_mu) + rho_row_scratch_bytes(C.bp) : 0;
   C.split = C.split_bytes ? (void*)ar.take<char>(C.split_bytes) : nullptr;
+  // stage-2 GEMMs in split precision: the split operand tiles of one product
+  C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
+  C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   return C;
 }
 
@@ -234,7 +239,8 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
       g.B = B; g.b_sk = 1; g.b_sn = C.bp;
       g.C = out; g.c_sm = n_mu; g.c_sn = 1;
       g.beta = bet;
-      return gemm_f64(g, st);
+      return precision == XTC_SPLIT_F16 ? gemm_split_nt(g, C.gsplit, C.gsplit_bytes, st)
+                                        : gemm_f64(g, st);
     };
     const double* wb = grid->w + b0;
     if (channels & XTC_U1)
