@@ -8,6 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libisdfxtc.so")
 
 XTC_OK, XTC_WARN_RANK_DEFICIENT, XTC_WARN_JITTER, XTC_WARN_FALLBACK = 0, 1, 2, 3
+XTC_ERR_INVALID_ARG, XTC_ERR_NOT_SPD, XTC_ERR_HIP, XTC_ERR_NO_WORKSPACE, XTC_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 XTC_FP64, XTC_SPLIT_F16 = 0, 2
 XTC_U_EE, XTC_U_BH = 0, 1
 XTC_U1, XTC_U3, XTC_ULAP, XTC_D1, XTC_D4, XTC_FIELD, XTC_ESCALE = 1, 2, 4, 8, 16, 32, 64

@@ -10,6 +10,7 @@
 #include "plans.hpp"
 #include "timing.hpp"
 #include "gemm_split.hpp"
+#include "bh.hpp"
 
 namespace xtc {
 
@@ -114,7 +115,7 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b
 struct ConLayout {
   long* piv; double* G; double* rhot; double* panel; double* V; double* wt; double* H; double* e3x;
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
-  void* gsplit; size_t gsplit_bytes;
+  void* gsplit; size_t gsplit_bytes; BHTable* bh;
   long bp; long rows_pad; int nsb; int nch;
 };
 
@@ -143,6 +144,7 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   // stage-2 GEMMs in split precision: the split operand tiles of one product
   C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
   C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
+  C.bh = ar.take<BHTable>(1);
   return C;
 }
 
@@ -170,8 +172,13 @@ static xtc_status check_contract_args(const xtc_grid* grid, const xtc_correlator
               "contract: bad correlator");
   for (int m = 0; m < n_mu; ++m)
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "contract: pivot index out of range");
-  if (corr->form != XTC_U_EE) {
-    set_error("contract: this entry point evaluates the EE correlator form");
+  XTC_REQUIRE(corr->form == XTC_U_EE || corr->form == XTC_U_BH, "contract: unknown correlator form");
+  if (corr->form == XTC_U_BH && precision != XTC_FP64) {
+    set_error("contract: the BH correlator is evaluated on the FP64 path only");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  if (corr->form == XTC_U_BH && (channels & XTC_ULAP)) {
+    set_error("contract: the Laplacian channel is defined for the EE form only");
     return XTC_ERR_UNSUPPORTED;
   }
   return XTC_OK;
@@ -193,12 +200,16 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   XTC_REQUIRE(!(channels & XTC_FIELD) || field, "contract: field output NULL");
   XTC_REQUIRE(!(channels & XTC_ESCALE) || escale, "contract: escale output NULL");
   EECoef cf;
-  XTC_TRY(ee_coefficients(corr, &cf));
+  BHTable bt;
+  const bool bh = corr->form == XTC_U_BH;
+  if (bh) XTC_TRY(bh_build(corr, &bt, &cf));
+  else XTC_TRY(ee_coefficients(corr, &cf));
   hipStream_t st = as_stream(stream);
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
   ConLayout C = layout_con(ar, n_g, n_mu, channels, precision);
   XTC_TRY(need_ws(ar));
+  if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
                      (const long*)C.piv, n_mu, C.G);
@@ -213,6 +224,7 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   }
   Stage1Args s1{grid->xyz, grid->w, xi, rho, C.rhot, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp,
                 C.nch};
+  if (bh) s1.bh = C.bh;
   if (precision == XTC_SPLIT_F16) {
     size_t tk = timing_begin(TM_SPLIT_PREP, st);
     XTC_TRY(split_prepare(s1, C.split, st));

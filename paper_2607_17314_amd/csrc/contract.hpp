@@ -24,11 +24,14 @@ xtc_status ee_coefficients(const xtc_correlator* corr, EECoef* out);
 // rows 0..n_mu + 1, ch = gx, gy, gz, sq (, lap). Row n_mu uses the reference
 // density rho_gamma (exact field), row n_mu + 1 the ISDF density
 // rhot = sum_l G_l xi_l, so that its gradient channels are H_{g,c} = sum_l G_l calG^c_{l,g}.
+struct BHTable;
+
 struct Stage1Args {
   const double* xyz; const double* w; const double* xi; const double* rho; const double* rhot;
   long n_g; int n_mu; long b0; long bn;
   double* panel; long rows_pad; long bp;
   int nch;
+  const BHTable* bh = nullptr;   // device table of a BH correlator (FP64 path), or nullptr for EE
 };
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);

@@ -12,6 +12,7 @@
 //   * both go to LDS, then every wave runs 4 k-steps of
 //     v_mfma_f64_16x16x4f64 per channel and sub-tile.
 // The kernel tile is generated once per workgroup and reused by all 64 rows.
+#include "bh.hpp"
 #include "contract.hpp"
 #include "timing.hpp"
 
@@ -138,10 +139,181 @@ __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ x
         }
 }
 
+// BH form (four channels): per pair, from the workgroup's LDS tables of
+//   TB[I][a, grad a][bra]  (the 64 bra points, filled once) and
+//   TK[ket][I][o][m] = gamma_{I,o,m}(ket) = sum_n csym[m][n][o] a_I(ket)^n  (per ket chunk),
+// the nuclear sums F_o and grad F_o, then N, S and the channels (see bh.hpp).
+__device__ __forceinline__ void bh_channels(const EECoef& cf, const BHTable* __restrict__ T,
+                                            int nn, const double (*TB)[4][64], int gb,
+                                            const double (*TK)[BH_NO][BH_NP], double dx,
+                                            double dy, double dz, double* out) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double t = 1.0 / (1.0 + cf.d * r);
+  const double e = cf.d * r * t;
+  const double t2 = t * t;
+  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
+  double GF[BH_NO][3] = {};
+  for (int I = 0; I < nn; ++I) {
+    const double a1 = TB[I][0][gb], ax = TB[I][1][gb], ay = TB[I][2][gb], az = TB[I][3][gb];
+    const double a2 = a1 * a1, a3 = a2 * a1;
+#pragma unroll
+    for (int o = 0; o < BH_NO; ++o) {
+      const double* g = TK[I][o];
+      F[o] += g[0] + a1 * g[1] + a2 * g[2] + a3 * g[3];
+      const double Dv = g[1] + 2.0 * a1 * g[2] + 3.0 * a2 * g[3];
+      GF[o][0] += Dv * ax;
+      GF[o][1] += Dv * ay;
+      GF[o][2] += Dv * az;
+    }
+  }
+  const double E[BH_NO] = {1.0, e, e * e, e * e * e};
+  double N[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) N[c] = GF[0][c] + E[1] * GF[1][c] + E[2] * GF[2][c] + E[3] * GF[3][c];
+  double S = cf.d * t2 * (F[1] + 2.0 * E[1] * F[2] + 3.0 * E[2] * F[3] + horner(cf.q1, cf.n1, e));
+  if (r > 0.0) {
+    const double sr = S / r;
+    out[0] = N[0] + sr * dx;
+    out[1] = N[1] + sr * dy;
+    out[2] = N[2] + sr * dz;
+    out[3] = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
+  } else {
+    out[0] = N[0];
+    out[1] = N[1];
+    out[2] = N[2];
+    out[3] = N[0] * N[0] + N[1] * N[1] + N[2] * N[2] + S * S;
+  }
+}
+
+// Same tile and MFMA structure as k_stage1_f64 (four channels), with the BH tables in LDS.
+__global__ __launch_bounds__(256) void k_stage1_f64_bh(
+    const double* __restrict__ xyz, const double* __restrict__ w, const double* __restrict__ xi,
+    const double* __restrict__ rho, const double* __restrict__ rhot, long n_g, int n_mu, long b0,
+    long bn, EECoef cf, const BHTable* __restrict__ T, double* __restrict__ panel, long rows_pad,
+    long bp) {
+  constexpr int KC = 16, NCH = 4;
+  __shared__ double As[64][KC + 1];
+  __shared__ double Bs[NCH][KC][65];
+  __shared__ double TB[BH_MAXNUC][4][64];
+  __shared__ double TK[KC][BH_MAXNUC][BH_NO][BH_NP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)blockIdx.y * 64;
+  const long nb0 = (long)blockIdx.x * 64;
+  const int gb = tid & 63;
+  const int gk = tid >> 6;
+  const int nn = T->n_nuc;
+  long bra = b0 + nb0 + gb;
+  if (bra > b0 + bn - 1) bra = b0 + bn - 1;
+  const double xb = xyz[bra], yb = xyz[n_g + bra], zb = xyz[2 * n_g + bra];
+  for (int e = tid; e < nn * 64; e += 256) {
+    const int I = e / 64, bb = e % 64;
+    long b = b0 + nb0 + bb;
+    if (b > b0 + bn - 1) b = b0 + bn - 1;
+    double v[4];
+    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
+  }
+
+  d4 acc[NCH][2][2];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  const int li = lane & 15, lk = lane >> 4;
+  for (long k0 = 0; k0 < n_g; k0 += KC) {
+    double ra[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      const int row = e >> 4, kk = e & 15;
+      const long g = k0 + kk, rr = m0 + row;
+      double v = 0.0;
+      if (g < n_g && rr <= n_mu + 1)
+        v = w[g] * (rr < n_mu ? xi[rr * n_g + g] : (rr == n_mu ? rho[g] : rhot[g]));
+      ra[j] = v;
+    }
+    // ket tables of this chunk (the previous chunk's generation has passed the
+    // barrier before its MFMA phase, so TK is free)
+    for (int e = tid; e < KC * nn; e += 256) {
+      const int kk = e / nn, I = e % nn;
+      long g = k0 + kk;
+      if (g > n_g - 1) g = n_g - 1;
+      const double a = bh_a(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g]);
+      const double A2[BH_NP] = {1.0, a, a * a, a * a * a};
+      const int ty = T->type[I];
+#pragma unroll
+      for (int o = 0; o < BH_NO; ++o)
+#pragma unroll
+        for (int m = 0; m < BH_NP; ++m) {
+          double s = 0.0;
+#pragma unroll
+          for (int n = 0; n < BH_NP; ++n) s += T->csym[ty][m][n][o] * A2[n];
+          TK[kk][I][o][m] = s;
+        }
+    }
+    __syncthreads();
+    double ch[4][NCH];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * gk + q;
+      long g = k0 + kk;
+      if (g > n_g - 1) g = n_g - 1;
+      bh_channels(cf, T, nn, TB, gb, TK[kk], xb - xyz[g], yb - xyz[n_g + g], zb - xyz[2 * n_g + g],
+                  ch[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      As[e >> 4][e & 15] = ra[j];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) Bs[c][4 * gk + q][gb] = ch[q][c];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const double a0 = As[32 * wm + li][4 * s + lk];
+      const double a1 = As[32 * wm + 16 + li][4 * s + lk];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double bb0 = Bs[c][4 * s + lk][32 * wn + li];
+        const double bb1 = Bs[c][4 * s + lk][32 * wn + 16 + li];
+        acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb0, acc[c][0][0], 0, 0, 0);
+        acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb1, acc[c][0][1], 0, 0, 0);
+        acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb0, acc[c][1][0], 0, 0, 0);
+        acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb1, acc[c][1][1], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long row = m0 + 32 * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
+          const long col = nb0 + 32 * wn + 16 * j + li;
+          if (row <= n_mu + 1 && col < bn) panel[((long)c * rows_pad + row) * bp + col] = acc[c][i][j][r];
+        }
+}
+
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
   dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 2, 64));
   const size_t tk = timing_begin(TM_S1_KERNEL, st);
-  if (a.nch == 4)
+  if (a.bh) {
+    XTC_REQUIRE(a.nch == 4, "BH correlator: the Laplacian channel is defined for the EE form only");
+    hipLaunchKernelGGL(k_stage1_f64_bh, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot,
+                       a.n_g, a.n_mu, a.b0, a.bn, cf, a.bh, a.panel, a.rows_pad, a.bp);
+  } else if (a.nch == 4)
     hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
   else
