@@ -13,6 +13,7 @@
 // d lap u/dc_k = lap_k, with f_k, u'_k, lap_k the kernels of the unit coefficient e_k.
 // The kernel tiles are regenerated from coordinates; the D cotangents add one
 // recomputation of the forward panel per bra super-block.
+#include "bh.hpp"
 #include "contract.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
@@ -177,12 +178,270 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
   }
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partials, long nblk, int n,
+// --- multi-centre Boys-Handy form ---------------------------------------------------
+// Per-pair adjoint for the BH correlator (see bh.hpp for N, S and csym). With the
+// cotangent projections
+//   r12 > 0:  V = M_vec + 2 M_sq grad u,  W = V . rhat12;
+//   r12 = 0:  V = M_vec + 2 M_sq N,       W = 2 M_sq S,
+// the derivative of the pair's contribution with respect to the coefficient of the
+// term (m, n, o) of type t is
+//   sum_{I of type t} [ (V . grad a_1I) rbar^o dP_mn + W o rbar^{o-1} d t^2 P_mn ],
+//   P_mn = a_1^m a_2^n + a_1^n a_2^m,  dP_mn = m a_1^{m-1} a_2^n + n a_1^{n-1} a_2^m.
+// Z[t][m][n][o] accumulates the (m, n) half of both sums; the parameter is
+// Z[t][m][n][o] + Z[t][n][m][o]. The (0, 0, o) terms need only the nucleus-free sum
+// Zee[o] = sum W o rbar^{o-1} d t^2 (times 2 per nucleus of the type).
+constexpr int ZS = BH_MAXTYPE * 64 + MAXQ + 1;   // BH partial stride
+
+template <int NT>
+__device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __restrict__ T,
+                                             const double (*Cs)[BH_NP][BH_NP][BH_NO],
+                                             int nn, const double (*TB)[4][GT], int bi,
+                                             const double (*TA)[GT], int kj, double dx, double dy,
+                                             double dz, const double* m, double* z, double* zee,
+                                             int omax_ee) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double t = 1.0 / (1.0 + cf.d * r);
+  const double e = cf.d * r * t;
+  const double dedr = cf.d * t * t;
+  // forward: F_o and grad F_o at this pair
+  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
+  double GF[BH_NO][3] = {};
+  for (int I = 0; I < nn; ++I) {
+    const int ty = T->type[I];
+    const double a1 = TB[I][0][bi], a2 = TA[I][kj];
+    const double A1[BH_NP] = {1.0, a1, a1 * a1, a1 * a1 * a1};
+    const double dA1[BH_NP] = {0.0, 1.0, 2.0 * a1, 3.0 * a1 * a1};
+    const double A2[BH_NP] = {1.0, a2, a2 * a2, a2 * a2 * a2};
+#pragma unroll
+    for (int o = 0; o < BH_NO; ++o) {
+      double f = 0.0, dv = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < BH_NP; ++mm) {
+        double g = 0.0;
+#pragma unroll
+        for (int n = 0; n < BH_NP; ++n) g += Cs[ty][mm][n][o] * A2[n];
+        f += A1[mm] * g;
+        dv += dA1[mm] * g;
+      }
+      F[o] += f;
+      GF[o][0] += dv * TB[I][1][bi];
+      GF[o][1] += dv * TB[I][2][bi];
+      GF[o][2] += dv * TB[I][3][bi];
+    }
+  }
+  const double E[BH_NO] = {1.0, e, e * e, e * e * e};
+  double N[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) N[c] = GF[0][c] + E[1] * GF[1][c] + E[2] * GF[2][c] + E[3] * GF[3][c];
+  double p1 = 0.0;
+  for (int j = cf.n1 - 1; j >= 0; --j) p1 = p1 * e + cf.q1[j];
+  const double S = dedr * (F[1] + 2.0 * E[1] * F[2] + 3.0 * E[2] * F[3] + p1);
+  double V[3], W;
+  if (r > 0.0) {
+    const double sr = S / r;
+    const double G0 = N[0] + sr * dx, G1 = N[1] + sr * dy, G2 = N[2] + sr * dz;
+    V[0] = m[0] + 2.0 * m[3] * G0;
+    V[1] = m[1] + 2.0 * m[3] * G1;
+    V[2] = m[2] + 2.0 * m[3] * G2;
+    W = (V[0] * dx + V[1] * dy + V[2] * dz) / r;
+  } else {
+    V[0] = m[0] + 2.0 * m[3] * N[0];
+    V[1] = m[1] + 2.0 * m[3] * N[1];
+    V[2] = m[2] + 2.0 * m[3] * N[2];
+    W = 2.0 * m[3] * S;
+  }
+  const double wd = W * dedr;
+  const double ES[BH_NO] = {0.0, wd, 2.0 * e * wd, 3.0 * e * e * wd};
+  // electron-electron (0, 0, o) terms: W o e^{o-1} d t^2
+  {
+    double ep = 1.0;   // e^{o-1}
+    for (int o = 1; o <= omax_ee; ++o) {
+      zee[o] += o * ep * wd;
+      ep *= e;
+    }
+  }
+  for (int I = 0; I < nn; ++I) {
+    const int ty = T->type[I];
+    const double a1 = TB[I][0][bi], a2 = TA[I][kj];
+    const double q = V[0] * TB[I][1][bi] + V[1] * TB[I][2][bi] + V[2] * TB[I][3][bi];
+    const double A1[BH_NP] = {1.0, a1, a1 * a1, a1 * a1 * a1};
+    const double dA1[BH_NP] = {0.0, 1.0, 2.0 * a1, 3.0 * a1 * a1};
+    const double A2[BH_NP] = {1.0, a2, a2 * a2, a2 * a2 * a2};
+    // Z[ty][mm][n][o] += (q dA1[mm] E[o] + A1[mm] ES[o]) A2[n]; ty is uniform across the wave
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      if (tt != ty) continue;
+#pragma unroll
+      for (int mm = 0; mm < BH_NP; ++mm)
+#pragma unroll
+        for (int o = 0; o < BH_NO; ++o) {
+          const double u = q * dA1[mm] * E[o] + A1[mm] * ES[o];
+#pragma unroll
+          for (int n = 0; n < BH_NP; ++n) z[tt * 64 + mm * 16 + n * 4 + o] += u * A2[n];
+        }
+    }
+  }
+}
+
+// M tiles exactly as k_grad_pairs (four channels), then the BH per-pair adjoint.
+template <int NT>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int n_rows,
+                     const double* __restrict__ xi, const double* __restrict__ rho,
+                     const double* __restrict__ rhot, const double* __restrict__ w,
+                     const double* __restrict__ xyz, long n_g, int n_mu, long b0, long bn,
+                     EECoef cf, const BHTable* __restrict__ T, int omax_ee,
+                     double* __restrict__ partials) {
+  constexpr int NCH = 4;
+  __shared__ double Gs[NCH][GK][GT + 1];
+  __shared__ double As[GK][GT + 1];
+  __shared__ double bxyz[3][GT];
+  __shared__ double kxyz[3][GT];
+  __shared__ double TB[BH_MAXNUC][4][GT];
+  __shared__ double TA[BH_MAXNUC][GT];
+  __shared__ double Cs[BH_MAXTYPE][BH_NP][BH_NP][BH_NO];
+  __shared__ double red[4][ZS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nn = T->n_nuc;
+  const long bt0 = (long)blockIdx.x * GT;
+  const long per = ((n_g + KSEG - 1) / KSEG + GT - 1) / GT * GT;
+  const long k_lo = (long)blockIdx.y * per;
+  const long k_hi = k_lo + per < n_g ? k_lo + per : n_g;
+  if (tid < GT) {
+    long b = b0 + bt0 + tid;
+    if (b > b0 + bn - 1) b = b0 + bn - 1;
+    bxyz[0][tid] = xyz[b];
+    bxyz[1][tid] = xyz[n_g + b];
+    bxyz[2][tid] = xyz[2 * n_g + b];
+  }
+  for (int e = tid; e < nn * GT; e += 256) {
+    const int I = e / GT, bb = e % GT;
+    long b = b0 + bt0 + bb;
+    if (b > b0 + bn - 1) b = b0 + bn - 1;
+    double v[4];
+    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
+  }
+  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
+    (&Cs[0][0][0][0])[e] = (&T->csym[0][0][0][0])[e];
+  double z[NT * 64];
+#pragma unroll
+  for (int k = 0; k < NT * 64; ++k) z[k] = 0.0;
+  double zee[MAXQ + 1];
+#pragma unroll
+  for (int k = 0; k <= MAXQ; ++k) zee[k] = 0.0;
+
+  for (long kc = k_lo; kc < k_hi; kc += GT) {
+    __syncthreads();
+    if (tid < GT) {
+      long g = kc + tid;
+      if (g > n_g - 1) g = n_g - 1;
+      kxyz[0][tid] = xyz[g];
+      kxyz[1][tid] = xyz[n_g + g];
+      kxyz[2][tid] = xyz[2 * n_g + g];
+    }
+    for (int e = tid; e < nn * GT; e += 256) {
+      const int I = e / GT, kk = e % GT;
+      long g = kc + kk;
+      if (g > n_g - 1) g = n_g - 1;
+      TA[I][kk] = bh_a(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g]);
+    }
+    d4 acc[NCH][2][2];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < n_rows; r0 += GK) {
+      __syncthreads();
+      for (int e = tid; e < NCH * GK * GT; e += 256) {
+        const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
+        const long row = r0 + rr, b = bt0 + bb;
+        Gs[c][rr][bb] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
+      }
+      for (int e = tid; e < GK * GT; e += 256) {
+        const int rr = e / GT, kk = e % GT;
+        const long row = r0 + rr, g = kc + kk;
+        double v = 0.0;
+        if (row < n_rows && g < k_hi)
+          v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
+        As[rr][kk] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < GK / 4; ++s) {
+        const double b0v = As[4 * s + lk][32 * wn + li];
+        const double b1v = As[4 * s + lk][32 * wn + 16 + li];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const double a0 = Gs[c][4 * s + lk][32 * wm + li];
+          const double a1 = Gs[c][4 * s + lk][32 * wm + 16 + li];
+          acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[c][0][0], 0, 0, 0);
+          acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[c][0][1], 0, 0, 0);
+          acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[c][1][0], 0, 0, 0);
+          acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[c][1][1], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int bi = 32 * wm + 16 * i + lk + 4 * r;
+          const int kj = 32 * wn + 16 * j + li;
+          if (bt0 + bi >= bn || kc + kj >= k_hi) continue;
+          double mv[NCH];
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) mv[c] = acc[c][i][j][r];
+          pair_grad_bh<NT>(cf, T, Cs, nn, TB, bi, TA, kj, bxyz[0][bi] - kxyz[0][kj],
+                           bxyz[1][bi] - kxyz[1][kj], bxyz[2][bi] - kxyz[2][kj], mv, z, zee,
+                           omax_ee);
+        }
+  }
+  // deterministic block reduction: [NT * 64 Z entries][MAXQ + 1 Zee entries]
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NT * 64 + MAXQ + 1; ++k) {
+    double v = k < NT * 64 ? z[k] : zee[k - NT * 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+  for (int k = tid; k < ZS; k += 256) {
+    const double v = k < NT * 64 + MAXQ + 1
+                         ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
+    partials[blk * ZS + k] = v;
+  }
+}
+
+// dtheta[p] = scale_p (Zsum[i1_p] + Zsum[i2_p]) (i2 < 0: one term)
+struct BHParamMap {
+  int i1, i2;
+  double scale;
+};
+
+__global__ void k_bh_params(const double* __restrict__ zsum, const BHParamMap* __restrict__ map,
+                            int n, double* __restrict__ out) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  const BHParamMap q = map[p];
+  out[p] = q.scale * (zsum[q.i1] + (q.i2 >= 0 ? zsum[q.i2] : 0.0));
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partials, long nblk, int n, int stride,
                                double* __restrict__ out) {
-  const int k = threadIdx.x;
+  const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
   double s = 0.0;
-  for (long b = 0; b < nblk; ++b) s += partials[b * MAXQ + k];
+  for (long b = 0; b < nblk; ++b) s += partials[b * stride + k];
   out[k] = s;
 }
 
@@ -236,10 +495,11 @@ __global__ void k_mul_vec(const double* __restrict__ a, const double* __restrict
 
 struct GradLayout {
   long* piv; double* G; double* rhot; double* wt; double* F; double* Pb; double* Pd; double* S4;
-  double* partials; long bp; long rows_pad; int nsb; int nch; long nblk;
+  double* partials; BHTable* bh; double* zsum; BHParamMap* pmap;
+  long bp; long rows_pad; int nsb; int nch; long nblk;
 };
 
-static GradLayout layout_grad(Arena& ar, int64_t n_g, int n_mu, uint32_t flags) {
+static GradLayout layout_grad(Arena& ar, int64_t n_g, int n_mu, int n_params, uint32_t flags) {
   GradLayout L;
   L.nch = (flags & 1) ? 5 : 4;               // bit 0: Laplacian cotangent present
   L.bp = n_g < GSUPER ? ((n_g + 63) / 64) * 64 : GSUPER;
@@ -254,14 +514,17 @@ static GradLayout layout_grad(Arena& ar, int64_t n_g, int n_mu, uint32_t flags) 
   L.Pb = ar.take<double>((size_t)L.nch * L.rows_pad * L.bp);
   L.Pd = ar.take<double>((size_t)n_mu * L.bp);
   L.S4 = ar.take<double>((size_t)n_mu * n_mu);
-  L.partials = ar.take<double>((size_t)L.nsb * L.nblk * MAXQ);
+  // per-block partial sums; the stride fits the BH parameter table (the EE form uses MAXQ)
+  L.partials = ar.take<double>((size_t)L.nsb * L.nblk * ZS);
+  L.bh = ar.take<BHTable>(1);
+  L.zsum = ar.take<double>(ZS);
+  L.pmap = ar.take<BHParamMap>(n_params > 0 ? n_params : 1);
   return L;
 }
 
 size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags) {
-  (void)n_params;
   Arena ar(nullptr, 0);
-  layout_grad(ar, n_g, n_mu, flags);
+  layout_grad(ar, n_g, n_mu, n_params, flags);
   return ar.used;
 }
 
@@ -279,29 +542,64 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "xtc_grad: empty grid");
   XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "xtc_grad: bad n_mu");
   XTC_REQUIRE(!gu1 || xigrad, "xtc_grad: the u1 cotangent needs xigrad");
-  XTC_REQUIRE(corr->n_terms > 0 && corr->n_terms <= MAXQ && corr->mno && corr->c && corr->d > 0.0,
+  XTC_REQUIRE(corr->n_terms > 0 && corr->mno && corr->c && corr->d > 0.0,
               "xtc_grad: bad correlator");
+  XTC_REQUIRE(corr->form == XTC_U_EE || corr->form == XTC_U_BH, "xtc_grad: unknown correlator form");
+  const bool bh = corr->form == XTC_U_BH;
+  XTC_REQUIRE(bh || corr->n_terms <= MAXQ, "xtc_grad: too many EE terms");
   for (int m = 0; m < n_mu; ++m)
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "xtc_grad: pivot index out of range");
-  if (corr->form != XTC_U_EE) {
-    set_error("xtc_grad: this entry point differentiates the EE correlator form");
+  if (bh && gulap) {
+    set_error("xtc_grad: the Laplacian channel is defined for the EE form only");
     return XTC_ERR_UNSUPPORTED;
   }
   EECoef cf;
-  XTC_TRY(ee_coefficients(corr, &cf));
-  GradBasis gb{};
+  BHTable bt;
+  int omax_ee = 0;
+  const int n_params = bh ? corr->n_types * corr->n_terms : corr->n_terms;
+  std::vector<BHParamMap> pmap;
+  if (bh) {
+    XTC_TRY(bh_build(corr, &bt, &cf));
+    omax_ee = cf.n1;
+    // parameter p = type * n_terms + k -> entries of the summed [types x 64 Z][Zee] table
+    const int nz = bt.n_types * 64;
+    for (int t = 0; t < corr->n_types; ++t)
+      for (int k = 0; k < corr->n_terms; ++k) {
+        const int m = corr->mno[3 * k], n = corr->mno[3 * k + 1], o = corr->mno[3 * k + 2];
+        BHParamMap q;
+        if (m == 0 && n == 0) {
+          q.i1 = nz + o;
+          q.i2 = -1;
+          q.scale = 2.0 * bt.n_of_type[t];
+        } else {
+          q.i1 = t * 64 + m * 16 + n * 4 + o;
+          q.i2 = t * 64 + n * 16 + m * 4 + o;
+          q.scale = 1.0;
+        }
+        pmap.push_back(q);
+      }
+  } else {
+    XTC_TRY(ee_coefficients(corr, &cf));
+  }
+  GradBasis gb{};   // EE form only (at most MAXQ terms)
   gb.d = corr->d;
-  gb.n = corr->n_terms;
-  gb.omax = 0;
-  for (int k = 0; k < gb.n; ++k) {
-    gb.o[k] = corr->mno[3 * k + 2];
-    if (gb.o[k] > gb.omax) gb.omax = gb.o[k];
+  if (!bh) {
+    gb.n = corr->n_terms;
+    for (int k = 0; k < gb.n; ++k) {
+      gb.o[k] = corr->mno[3 * k + 2];
+      if (gb.o[k] > gb.omax) gb.omax = gb.o[k];
+    }
   }
   hipStream_t st = as_stream(stream);
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
-  GradLayout L = layout_grad(ar, n_g, n_mu, gulap ? 1u : 0u);
+  GradLayout L = layout_grad(ar, n_g, n_mu, n_params, gulap ? 1u : 0u);
   XTC_TRY(need_ws(ar));
+  if (bh) {
+    XTC_HIP(hipMemcpyAsync(L.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
+    XTC_HIP(hipMemcpyAsync(L.pmap, pmap.data(), sizeof(BHParamMap) * pmap.size(),
+                           hipMemcpyHostToDevice, st));
+  }
   size_t tk = timing_begin(TM_GRAD, st);
   XTC_HIP(hipMemcpyAsync(L.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_gather_G2, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho, (const long*)L.piv,
@@ -324,6 +622,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   }
   const bool need_fwd = gD1 || gD4;
   Stage1Args s1{grid->xyz, grid->w, xi, rho, L.rhot, n_g, n_mu, 0, 0, L.F, L.rows_pad, L.bp, 4};
+  if (bh) s1.bh = L.bh;
   for (int sb = 0; sb < L.nsb; ++sb) {
     const long b0 = (long)sb * L.bp;
     const long bn = (n_g - b0) < L.bp ? (n_g - b0) : L.bp;
@@ -380,8 +679,17 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
       XTC_CHECK_LAUNCH();
     }
     dim3 gridp(cdiv(bn, GT), KSEG);
-    double* part = L.partials + (long)sb * L.nblk * MAXQ;
-    if (L.nch == 4)
+    const int stride = bh ? ZS : MAXQ;
+    double* part = L.partials + (long)sb * L.nblk * stride;
+    if (bh && bt.n_types == 1)
+      hipLaunchKernelGGL(k_grad_pairs_bh<1>, gridp, dim3(256), 0, st, (const double*)L.Pb,
+                         L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,
+                         grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part);
+    else if (bh)
+      hipLaunchKernelGGL(k_grad_pairs_bh<2>, gridp, dim3(256), 0, st, (const double*)L.Pb,
+                         L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,
+                         grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part);
+    else if (L.nch == 4)
       hipLaunchKernelGGL(k_grad_pairs<4>, gridp, dim3(256), 0, st, (const double*)L.Pb, L.rows_pad,
                          L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w, grid->xyz, n_g,
                          n_mu, b0, bn, cf, gb, part);
@@ -392,11 +700,19 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     XTC_CHECK_LAUNCH();
     // unused block slots of a short last super-block stay zero
     if ((long)gridp.x * KSEG < L.nblk)
-      XTC_HIP(hipMemsetAsync(part + (long)gridp.x * KSEG * MAXQ, 0,
-                             sizeof(double) * (L.nblk - (long)gridp.x * KSEG) * MAXQ, st));
+      XTC_HIP(hipMemsetAsync(part + (long)gridp.x * KSEG * stride, 0,
+                             sizeof(double) * (L.nblk - (long)gridp.x * KSEG) * stride, st));
   }
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
-                     (long)L.nsb * L.nblk, gb.n, dtheta);
+  if (bh) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(cdiv(ZS, 256)), dim3(256), 0, st,
+                       (const double*)L.partials, (long)L.nsb * L.nblk, ZS, ZS, L.zsum);
+    XTC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_bh_params, dim3(cdiv(n_params, 256)), dim3(256), 0, st,
+                       (const double*)L.zsum, (const BHParamMap*)L.pmap, n_params, dtheta);
+  } else {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
+                       (long)L.nsb * L.nblk, gb.n, MAXQ, dtheta);
+  }
   XTC_CHECK_LAUNCH();
   timing_end(tk, st);
   return XTC_OK;

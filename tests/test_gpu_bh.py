@@ -61,3 +61,77 @@ def test_bh_split_path_is_refused(bh_problem):
     with pytest.raises(api.XtcError) as ei:
         api.kernel_contract(grid, corr, xi, xig, rh, piv, CH, precision=L.XTC_SPLIT_F16)
     assert ei.value.status == L.XTC_ERR_UNSUPPORTED
+
+
+def _two_type(corr):
+    """The same 48 terms on alternating nucleus types with distinct b and c."""
+    from workloads import Correlator
+    n = corr.nuc_xyz.shape[0]
+    rng = np.random.default_rng(11)
+    c = rng.uniform(-0.5, 0.5, size=(2, corr.n_terms)) / n
+    return Correlator(corr.form, corr.mno, c, corr.d, np.array([1.0, 1.3]), corr.nuc_xyz,
+                      (np.arange(n) % 2).astype(np.int32))
+
+
+@pytest.fixture(scope="module")
+def bh_small(h6_small):
+    """A smaller ragged subset for the adjoint (the oracle differentiates 48-96 units)."""
+    from oracle import fit, orbitals, pivots
+    from workloads import bh_correlator
+    wl = h6_small
+    phi4 = orbitals.eval_orbitals(wl.basis, wl.C_mo, wl.grid_xyz)
+    idx = np.sort(np.random.default_rng(8).choice(wl.n_g, 700, replace=False))
+    xyz, w, phi4 = np.ascontiguousarray(wl.grid_xyz[:, idx]), wl.grid_w[idx].copy(), phi4[:, :, idx]
+    fp = pivots.select_fused(phi4, w, 40)
+    fr = fit.fit(phi4, w, fp.pivots)
+    rho = orbitals.density(phi4, wl.n_occ)
+    n = len(fp.pivots)
+    rng = np.random.default_rng(34)
+    cot = {"u1": rng.normal(size=(3, n, n)) / n, "u3": rng.normal(size=(n, n)) / n,
+           "D1": rng.normal(size=(n, n)) / n, "D4": rng.normal(size=(n, n)) / n,
+           "field": rng.normal(size=(3, len(w))) / np.sqrt(len(w))}
+    return wl, xyz, w, fp.pivots, fr, rho, bh_correlator(wl.atom_xyz), cot
+
+
+@pytest.mark.parametrize("types", [1, 2])
+def test_bh_adjoint_matches_oracle(bh_small, types):
+    import torch
+    from oracle import adjoint
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, corr, cot = bh_small
+    if types == 2:
+        corr = _two_type(corr)
+    ref = adjoint.dL_dc(xyz, w, corr, fr.xi, fr.xigrad, rho[piv], rho, cot)
+    grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    got = api.grad(grid, corr, xi, xig, rh, piv, {k: t(v) for k, v in cot.items()}).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    note(f"BH adjoint, {types} type(s), {got.size} parameters: rel err {err:.2e}")
+    assert got.shape == ref.shape
+    assert err < 1e-10
+
+
+def test_bh_adjoint_matches_central_differences(bh_small):
+    """Every output is a polynomial of degree <= 2 in c, so central differences are
+    exact up to rounding."""
+    import torch
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, corr, cot = bh_small
+    grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    dc = {k: t(v) for k, v in cot.items()}
+    g = api.grad(grid, corr, xi, xig, rh, piv, dc).cpu().numpy()
+
+    def L(c):
+        out = api.kernel_contract(grid, corr, xi, xig, rh, piv, CH & ~64, c=c)
+        return sum(float(torch.sum(dc[k] * out[k])) for k in ("u1", "u3", "D1", "D4", "field"))
+
+    c0 = corr.c.ravel().copy()
+    h = 1e-4
+    for j in (0, 17, 40):
+        cp, cm = c0.copy(), c0.copy()
+        cp[j] += h
+        cm[j] -= h
+        fd = (L(cp) - L(cm)) / (2 * h)
+        note(f"  dL/dc[{j}]: adjoint {g[j]:.12e}, central difference {fd:.12e}")
+        assert abs(g[j] - fd) <= 1e-7 * max(1.0, np.abs(g).max())
