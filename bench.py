@@ -38,6 +38,9 @@ def parse():
                    help="also time the plain FP64 form and report its time-to-V and the error")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bra", type=int, default=1024, help="bra points in the CPU-oracle sample")
+    p.add_argument("--grad", action="store_true",
+                   help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
+                        "and the field (D1/D4 cotangents add one recomputation of stage 1)")
     return p.parse_args()
 
 
@@ -63,11 +66,14 @@ def main():
     chans = api.ALL_CHANNELS
     torch.cuda.synchronize()
 
+    last = {}
+
     def step(precision):
         phi4, rho = api.eval_orbitals(wl.basis, grid, C_mo, wl.n_occ)
         piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
         xi, xig, _, _ = api.fit(phi4, grid, piv)
         out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, precision)
+        last.update(xi=xi, xig=xig, rho=rho)
         return out, piv
 
     def log(msg):
@@ -99,6 +105,8 @@ def main():
     achieved = per_launch_flops / (launch_ms * 1e-3) / 1e12
     peak = PEAKS["f16"] if prec == L.XTC_SPLIT_F16 else PEAKS["fp64"]
 
+    corr_desc = ("4-term e-e correlator" if wl.corr.form == 0 else
+                 f"{wl.corr.n_terms}-term multi-centre Boys-Handy correlator ({wl.corr.nuc_xyz.shape[0]} nuclei)")
     res = {
         "metric": "ISDF-xTC build time & grid-pair TFLOP/s vs FP64 GPU form at 1e-6 rel err, 1 GPU",
         "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps,
@@ -107,7 +115,7 @@ def main():
         "dtype": "f16x2-split/f32acc/f64" if prec == L.XTC_SPLIT_F16 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{a.config}: linear H20 chain, {n_g} grid points, {wl.n_orb} orbitals, "
-                               f"N_mu={n_mu}, 4-term e-e correlator; time-to-V = orbitals + pivots + fit + "
+                               f"N_mu={n_mu}, {corr_desc}; time-to-V = orbitals + pivots + fit + "
                                f"contraction (u1,u3,D1,D4,field,escale)",
                    "n_g": n_g, "n_orb": wl.n_orb, "n_mu": n_mu, "precision": a.precision},
         "time_to_V_s": round(dt, 4),
@@ -121,6 +129,21 @@ def main():
     if prec == L.XTC_SPLIT_F16:
         # three FP16 products per algorithmic product (hi.hi, hi.lo, lo.hi)
         res["roofline"]["executed_mfma_frac"] = round(3.0 * achieved / peak, 4)
+    if a.grad:
+        n = n_mu
+        rng = np.random.default_rng(33)
+        cot = {k: torch.as_tensor(v, device=dev) for k, v in (
+            ("u1", rng.normal(size=(3, n, n)) / n), ("u3", rng.normal(size=(n, n)) / n),
+            ("field", rng.normal(size=(3, n_g)) / np.sqrt(n_g)))}
+        log("timing the adjoint")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = api.grad(grid, wl.corr, last["xi"], last["xig"], last["rho"], piv, cot)
+        torch.cuda.synchronize()
+        res["adjoint_s"] = round(time.perf_counter() - t0, 4)
+        res["adjoint_n_params"] = int(g.numel())
+        res["adjoint_cotangents"] = "u1, u3, field"
+        log(f"adjoint done in {res['adjoint_s']} s")
     if a.compare_fp64 and prec != L.XTC_FP64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
