@@ -148,11 +148,13 @@ const char* xtc_version(void);
 
 /* Call identifiers for xtc_workspace_bytes. */
 enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
-       XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7 };
+       XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7,
+       XTC_CALL_EXCHANGE = 8 };
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
- * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT).
- * n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), else 0. */
+ * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT) or
+ * the precision (EXCHANGE). n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), the
+ * projector rank n_q (EXCHANGE), else 0. */
 size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
                            int32_t n_aux, uint32_t flags);
 
@@ -222,6 +224,33 @@ xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
                                double* field, double* escale, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* Exchange intermediates of xTC Terms 2 and 3 through the low-rank projector
+ * (xTC section, "Terms 2 and 3 (non-factorizable)", "Low-rank projector for Terms
+ * 2 and 3"; pipeline section, symmetry paragraph). With gamma = LQ LQ^T,
+ *   P[s a][nu]   = phi_s(r_nu) sum_t phi_t(r_nu) LQ[t][a],
+ *   R^c[s a](g)  = sum_nu P[s a][nu] calG^c_{nu,g},   Q[s a](g) = sum_nu P[s a][nu] xi_nu(g),
+ *   X2[q][s][mu] = sum_g w_g xi_mu(g) sum_{a,c} R^c[s a](g) R^c[q a](g),
+ *   X3[q][s][mu] = sum_{g,c} w_g calG^c_{mu,g} sum_a (Q[s a] R^c[q a] + R^c[s a] Q[q a])(g),
+ * so that Term2 = -sum_mu C^p_r(mu) X2[q][s][mu] and Term3 likewise with X3.
+ * calG is regenerated per bra super-block from the grid-pair kernel tiles (as in
+ * xtc_kernel_contract); only the q <= s half is computed and mirrored.
+ * xi: device [n_mu][n_g]. phi_piv: device [n_orb][n_mu], phi_p at the pivots.
+ * lq: device [n_orb][n_q], n_q = 1..32 (the projector; for a closed-shell
+ * reference the occupied columns of the identity). X2, X3: device
+ * [n_orb][n_orb][n_mu] (outputs, FP64, overwritten; either may be NULL).
+ * precision: XTC_FP64, or XTC_SPLIT_F16 (stage 1 and the X products as split
+ * FP16 MFMA products with FP64 accumulation across chunks; EE correlator only).
+ * [bra_begin, bra_end): the bra points g summed over (0 <= begin <= end <= n_g; the
+ * ket sum inside calG always covers the whole grid). (0, n_g) gives X; disjoint
+ * ranges give partial sums that add up to X (the bra sharding across devices).
+ * Workspace: xtc_workspace_bytes(XTC_CALL_EXCHANGE, n_g, n_orb, n_mu, n_q,
+ * precision). Synchronising. */
+xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                              const double* xi, int32_t n_orb, const double* phi_piv,
+                              int32_t n_q, const double* lq, int32_t precision,
+                              int64_t bra_begin, int64_t bra_end, double* X2, double* X3,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of xtc_kernel_contract with respect to the linear coefficients c:
  * dtheta[j] = dL/dc_j for L = sum_c <gu1_c, u1_c> + <gu3, u3> + <gulap, ulap>
  * + <gD1, D1> + <gD4, D4> + <gfield, field>. Cotangents: device, shapes of the
@@ -242,9 +271,10 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * Categories: 0 stage 1 (pair kernel and density rows, per bra super-block),
  * 1 stage-2 GEMMs, 2 pivot selection, 3 fit, 4 orbitals, 5 adjoint pair kernel,
  * 6 MLP, 7 split-operand preparation, 8 the stage-1 pair kernel alone (one entry
- * per kernel launch).
+ * per kernel launch), 9 exchange projections and pair products, 10 exchange X
+ * products (operand splitting included).
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 9
+#define XTC_TIMING_CATEGORIES 11
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

@@ -15,7 +15,7 @@ XTC_U1, XTC_U3, XTC_ULAP, XTC_D1, XTC_D4, XTC_FIELD, XTC_ESCALE = 1, 2, 4, 8, 16
 XTC_SELECT_QR, XTC_SELECT_LEARNED, XTC_SELECT_LEARNED_JUDGED = 0, 1, 2
 XTC_FIT_XI, XTC_FIT_XIGRAD = 1, 2
 XTC_CALL_EVAL_ORBITALS, XTC_CALL_SELECT, XTC_CALL_FIT, XTC_CALL_CONTRACT, XTC_CALL_GRAD = 1, 2, 3, 4, 5
-XTC_CALL_FEATURES, XTC_CALL_MLP_GRAD = 6, 7
+XTC_CALL_FEATURES, XTC_CALL_MLP_GRAD, XTC_CALL_EXCHANGE = 6, 7, 8
 
 STATUS_NAMES = {0: "XTC_OK", 1: "XTC_WARN_RANK_DEFICIENT", 2: "XTC_WARN_JITTER",
                 3: "XTC_WARN_FALLBACK", -1: "XTC_ERR_INVALID_ARG", -2: "XTC_ERR_NOT_SPD",
@@ -85,6 +85,10 @@ def lib() -> C.CDLL:
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, P, P, P, P,
                            P, P, P, P, C.c_size_t, P]
+    L.xtc_exchange_terms.restype = st
+    L.xtc_exchange_terms.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P,
+                                     C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int64, C.c_int64,
+                                     P, P, P, C.c_size_t, P]
     L.xtc_timing.restype = st
     L.xtc_timing.argtypes = [C.c_int32, D]
     L.xtc_mlp_features.restype = st
@@ -104,6 +108,7 @@ def lib() -> C.CDLL:
 
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
             "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing",
+            "xtc_exchange_terms",
             "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
-                     "stage1_kernel"]
+                     "stage1_kernel", "x_pairs", "x_gemm"]

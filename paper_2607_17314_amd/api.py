@@ -216,6 +216,30 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
     return o
 
 
+def exchange_terms(grid: DeviceGrid, corr, xi, phi_piv, lq, precision: int = L.XTC_FP64,
+                   want=("X2", "X3"), c=None, bra=None):
+    """Exchange intermediates of xTC Terms 2 and 3 (xtc_exchange_terms).
+    xi [n_mu][n_g], phi_piv [n_orb][n_mu] (orbitals at the pivots), lq [n_orb][n_q] with
+    gamma = lq lq^T; bra = (begin, end) restricts the bra sum (default: the whole grid).
+    Returns {"X2", "X3"}: device float64 [n_orb][n_orb][n_mu] (None if not requested)."""
+    hc = HostCorrelator(corr, c)
+    xi, phi_piv, lq = _in(xi, "xi"), _in(phi_piv, "phi_piv"), _in(lq, "lq")
+    n_mu = xi.shape[0]
+    n_orb, n_q = lq.shape
+    if phi_piv.shape != (n_orb, n_mu):
+        raise ValueError(f"phi_piv must be [n_orb={n_orb}][n_mu={n_mu}], got {tuple(phi_piv.shape)}")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    X2 = torch.empty((n_orb, n_orb, n_mu), **f64) if "X2" in want else None
+    X3 = torch.empty((n_orb, n_orb, n_mu), **f64) if "X3" in want else None
+    b0, b1 = (0, grid.n_g) if bra is None else bra
+    ws = _workspace(workspace_bytes(L.XTC_CALL_EXCHANGE, grid.n_g, n_orb, n_mu, n_q, precision))
+    g = grid.c()
+    _check("xtc_exchange_terms", L.lib().xtc_exchange_terms(
+        C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), n_orb, _ptr(phi_piv), n_q, _ptr(lq), precision,
+        b0, b1, _ptr(X2), _ptr(X3), _ptr(ws), ws.numel(), _stream()))
+    return {"X2": X2, "X3": X3}
+
+
 class KernelTimer:
     """Collects the library's per-stage kernel timings (xtc_timing) over a region."""
 

@@ -1,7 +1,8 @@
 // Split-precision NT GEMM on the CDNA4 matrix cores, for stage 2 of the
-// contraction (the dense Xi / K-panel products):
-//   C[m][n] (+)= sum_k A[m][k] s[k] B[n][k],
-// A and B FP64 with k contiguous, C FP64 row-major.
+// contraction (the dense Xi / K-panel products) and the exchange intermediates:
+//   C[m][n] (+)= sum_seg sum_k A_seg[m][k] s_seg[k] B_seg[n][k],
+// A FP64 with k or m contiguous, B FP64 with k contiguous, C FP64 row-major. The
+// segments (up to four products summed) are concatenated along k.
 //
 // Each operand is first cut into FP16 pairs, x 2^e ~= x_hi + x_lo, with one
 // power-of-two exponent e per row (row max scaled into [2^14, 2^15)), and stored
@@ -27,75 +28,100 @@ typedef float g16 __attribute__((ext_vector_type(16)));
 constexpr int ST = 128;     // C tile (M and N)
 constexpr int SK2 = 256;    // k padding: a pair of 128-point chunks
 
-struct SplitTiles {
-  g8* t;
-  int* e;
-};
-
 static long round_up(long x, long m) { return ((x + m - 1) / m) * m; }
 
-size_t gemm_split_scratch_bytes(long M, long N, long K) {
-  const long Mp = round_up(M, ST), Np = round_up(N, ST), Kp = round_up(K, SK2);
+// k-steps of one segment and of the concatenation (a whole number of chunk pairs)
+static long seg_steps(long K) { return round_up(K, 16) / 16; }
+static long total_steps(long K, int nseg) { return round_up(seg_steps(K) * nseg, SK2 / 16); }
+
+size_t gemm_split_seg_scratch_bytes(long M, long N, long K, int nseg) {
+  const long Mp = round_up(M, ST), Np = round_up(N, ST), nks = total_steps(K, nseg);
   Arena ar(nullptr, 0);
-  ar.take<g8>((size_t)(Mp / 32) * (Kp / 16) * 128);
+  ar.take<g8>((size_t)(Mp / 32) * nks * 128);
   ar.take<int>(Mp);
-  ar.take<g8>((size_t)(Np / 32) * (Kp / 16) * 128);
+  ar.take<g8>((size_t)(Np / 32) * nks * 128);
   ar.take<int>(Np);
   return ar.used + 256;
 }
 
-// one block per padded row: e with max_k |x[r][k] s[k]| 2^e in [2^14, 2^15); 0 for
-// rows past `rows` and for all-zero rows
-__global__ __launch_bounds__(256) void k_row_exp(const double* __restrict__ X, long ld, long rows,
-                                                 long K, const double* __restrict__ s,
-                                                 int* __restrict__ e) {
+size_t gemm_split_scratch_bytes(long M, long N, long K) {
+  return gemm_split_seg_scratch_bytes(M, N, K, 1);
+}
+
+// One operand over its segments: value(r, k) = X[seg][r sm + k sk] s[seg][k].
+struct SegOperand {
+  const double* X[SPLIT_MAXSEG];
+  const double* s[SPLIT_MAXSEG];
+  long sm, sk;
+  long K;
+  int nseg;
+};
+
+__device__ inline double seg_value(const SegOperand& o, int seg, long r, long k) {
+  double v = o.X[seg][r * o.sm + k * o.sk];
+  if (o.s[seg]) v *= o.s[seg][k];
+  return v;
+}
+
+__device__ inline int exp_of_max(double m) {
+  int ex = 0;
+  if (m > 0.0) {
+    frexp(m, &ex);   // m = f 2^ex, f in [0.5, 1)
+    return 15 - ex;
+  }
+  return 0;
+}
+
+// k contiguous (sk 1): one block per padded row; e with max |value| 2^e in [2^14, 2^15),
+// 0 for rows past `rows` and for all-zero rows
+__global__ __launch_bounds__(256) void k_row_exp(SegOperand o, long rows, int* __restrict__ e) {
   __shared__ double red[256];
   const long r = blockIdx.x;
   double m = 0.0;
   if (r < rows)
-    for (long k = threadIdx.x; k < K; k += 256) {
-      double v = X[r * ld + k];
-      if (s) v *= s[k];
-      m = fmax(m, fabs(v));
-    }
+    for (int sg = 0; sg < o.nseg; ++sg)
+      for (long k = threadIdx.x; k < o.K; k += 256) m = fmax(m, fabs(seg_value(o, sg, r, k)));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    int ex = 0, out = 0;
-    if (red[0] > 0.0) {
-      frexp(red[0], &ex);   // red = f 2^ex, f in [0.5, 1)
-      out = 15 - ex;
-    }
-    e[r] = out;
-  }
+  if (threadIdx.x == 0) e[r] = exp_of_max(red[0]);
 }
 
-// one thread per (row block, k-step, lane): 8 consecutive k of one row, split
-__global__ __launch_bounds__(256) void k_split_tiles(const double* __restrict__ X, long ld,
-                                                     long rows, long K, const double* __restrict__ s,
+// rows contiguous (sm 1): one thread per padded row, the k loop reads whole lines
+__global__ __launch_bounds__(256) void k_col_exp(SegOperand o, long rows, long rows_pad,
+                                                 int* __restrict__ e) {
+  const long r = (long)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows_pad) return;
+  double m = 0.0;
+  if (r < rows)
+    for (int sg = 0; sg < o.nseg; ++sg)
+      for (long k = 0; k < o.K; ++k) m = fmax(m, fabs(seg_value(o, sg, r, k)));
+  e[r] = exp_of_max(m);
+}
+
+// one thread per (row block, k-step, lane): 8 consecutive k of one row, split;
+// k-step ks covers segment ks / nks_seg; steps past the last segment are zero
+__global__ __launch_bounds__(256) void k_split_tiles(SegOperand o, long rows,
                                                      const int* __restrict__ e, long nrb, long nks,
-                                                     g8* __restrict__ T) {
+                                                     long nks_seg, g8* __restrict__ T) {
   const long t = (long)blockIdx.x * 256 + threadIdx.x;
   if (t >= nrb * nks * 64) return;
   const int lane = (int)(t % 64);
   const long ks = (t / 64) % nks;
   const long rb = t / (64 * nks);
   const long r = rb * 32 + (lane % 32);
-  const long k0 = ks * 16 + 8 * (lane / 32);
+  const int sg = (int)(ks / nks_seg);
+  const long k0 = (ks % nks_seg) * 16 + 8 * (lane / 32);
   const double sc = ldexp(1.0, e[r]);
   g8 hi, lo;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const long k = k0 + q;
     double v = 0.0;
-    if (r < rows && k < K) {
-      v = X[r * ld + k];
-      if (s) v *= s[k];
-    }
+    if (r < rows && sg < o.nseg && k < o.K) v = seg_value(o, sg, r, k);
     v *= sc;
     const _Float16 h = (_Float16)(float)v;
     hi[q] = h;
@@ -207,37 +233,62 @@ void k_gemm_split_nt(const g8* __restrict__ At, const int* __restrict__ eA,
   }
 }
 
-xtc_status gemm_split_nt(const GemmArgs& g, void* scratch, size_t bytes, hipStream_t st) {
-  XTC_REQUIRE(g.a_sk == 1 && g.b_sk == 1 && g.c_sn == 1,
-              "split GEMM: operands need k contiguous and C row-major");
-  XTC_REQUIRE(g.alpha == 1.0 && (g.beta == 0.0 || g.beta == 1.0) && g.D == nullptr &&
-                  g.epi == EPI_NONE && g.sn == nullptr && !g.lower_only,
-              "split GEMM: only C = A s B^T or C += A s B^T");
-  XTC_REQUIRE(bytes >= gemm_split_scratch_bytes(g.M, g.N, g.K), "split GEMM: scratch too small");
-  if (g.M <= 0 || g.N <= 0) return XTC_OK;
-  const long Mp = round_up(g.M, ST), Np = round_up(g.N, ST), Kp = round_up(g.K, SK2);
-  const long nks = Kp / 16;
+// split both operands of C (+)= sum_seg A_seg diag(s_seg) B_seg^T and run the MFMA kernel
+static xtc_status split_operand(const SegOperand& o, long rows, long rows_pad, long nks,
+                                long nks_seg, int* e, g8* T, hipStream_t st) {
+  if (o.sk == 1)
+    hipLaunchKernelGGL(k_row_exp, dim3(rows_pad), dim3(256), 0, st, o, rows, e);
+  else
+    hipLaunchKernelGGL(k_col_exp, dim3(cdiv(rows_pad, 256)), dim3(256), 0, st, o, rows, rows_pad,
+                       e);
+  XTC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_split_tiles, dim3(cdiv((rows_pad / 32) * nks * 64, 256)), dim3(256), 0, st,
+                     o, rows, (const int*)e, rows_pad / 32, nks, nks_seg, T);
+  XTC_CHECK_LAUNCH();
+  return XTC_OK;
+}
+
+xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg, double* C,
+                          long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st) {
+  XTC_REQUIRE(nseg >= 1 && nseg <= SPLIT_MAXSEG, "split GEMM: 1 to 4 segments");
+  XTC_REQUIRE(bytes >= gemm_split_seg_scratch_bytes(M, N, K, nseg), "split GEMM: scratch too small");
+  SegOperand a{}, b{};
+  a.sm = seg[0].a_sm; a.sk = seg[0].a_sk; a.K = K; a.nseg = nseg;
+  b.sm = seg[0].b_sn; b.sk = seg[0].b_sk; b.K = K; b.nseg = nseg;
+  XTC_REQUIRE(a.sk == 1 || a.sm == 1, "split GEMM: A needs k or m contiguous");
+  XTC_REQUIRE(b.sk == 1, "split GEMM: B needs k contiguous");
+  for (int i = 0; i < nseg; ++i) {
+    XTC_REQUIRE(seg[i].A && seg[i].B, "split GEMM: null segment operand");
+    XTC_REQUIRE(seg[i].a_sm == a.sm && seg[i].a_sk == a.sk && seg[i].b_sn == b.sm &&
+                    seg[i].b_sk == b.sk,
+                "split GEMM: segments need one layout");
+    a.X[i] = seg[i].A; a.s[i] = seg[i].s;
+    b.X[i] = seg[i].B; b.s[i] = nullptr;
+  }
+  if (M <= 0 || N <= 0) return XTC_OK;
+  const long Mp = round_up(M, ST), Np = round_up(N, ST);
+  const long nks_seg = seg_steps(K), nks = total_steps(K, nseg);
   Arena ar(scratch, bytes);
   g8* At = ar.take<g8>((size_t)(Mp / 32) * nks * 128);
   int* eA = ar.take<int>(Mp);
   g8* Bt = ar.take<g8>((size_t)(Np / 32) * nks * 128);
   int* eB = ar.take<int>(Np);
-  hipLaunchKernelGGL(k_row_exp, dim3(Mp), dim3(256), 0, st, g.A, g.a_sm, g.M, g.K, g.s, eA);
-  XTC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_split_tiles, dim3(cdiv((Mp / 32) * nks * 64, 256)), dim3(256), 0, st, g.A,
-                     g.a_sm, g.M, g.K, g.s, (const int*)eA, Mp / 32, nks, At);
-  XTC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_row_exp, dim3(Np), dim3(256), 0, st, g.B, g.b_sn, g.N, g.K,
-                     (const double*)nullptr, eB);
-  XTC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_split_tiles, dim3(cdiv((Np / 32) * nks * 64, 256)), dim3(256), 0, st, g.B,
-                     g.b_sn, g.N, g.K, (const double*)nullptr, (const int*)eB, Np / 32, nks, Bt);
-  XTC_CHECK_LAUNCH();
+  XTC_TRY(split_operand(a, M, Mp, nks, nks_seg, eA, At, st));
+  XTC_TRY(split_operand(b, N, Np, nks, nks_seg, eB, Bt, st));
   hipLaunchKernelGGL(k_gemm_split_nt, dim3(Np / ST, Mp / ST), dim3(256), 0, st, (const g8*)At,
-                     (const int*)eA, (const g8*)Bt, (const int*)eB, g.M, g.N, nks, g.C, g.c_sm,
-                     g.beta == 1.0 ? 1 : 0);
+                     (const int*)eA, (const g8*)Bt, (const int*)eB, M, N, nks, C, ldc,
+                     accumulate ? 1 : 0);
   XTC_CHECK_LAUNCH();
   return XTC_OK;
+}
+
+xtc_status gemm_split_nt(const GemmArgs& g, void* scratch, size_t bytes, hipStream_t st) {
+  XTC_REQUIRE(g.b_sk == 1 && g.c_sn == 1, "split GEMM: B needs k contiguous and C row-major");
+  XTC_REQUIRE(g.alpha == 1.0 && (g.beta == 0.0 || g.beta == 1.0) && g.D == nullptr &&
+                  g.epi == EPI_NONE && g.sn == nullptr && !g.lower_only,
+              "split GEMM: only C = A s B^T or C += A s B^T");
+  SplitSeg sg{g.A, g.a_sm, g.a_sk, g.s, g.B, g.b_sn, g.b_sk};
+  return gemm_split_seg(g.M, g.N, g.K, &sg, 1, g.C, g.c_sm, g.beta == 1.0, scratch, bytes, st);
 }
 
 }  // namespace xtc

@@ -14,4 +14,5 @@ size_t ws_features(int64_t n_g);
 size_t ws_mlp_grad(int64_t n, int hidden);
 size_t ws_learned(int64_t n_g, int n_orb, int n_mu, double kappa);
 size_t ws_fit_residual(int64_t n_g, int n_orb, int n_mu);
+size_t ws_exchange(int64_t n_g, int n_orb, int n_mu, int n_q, int precision);
 }  // namespace xtc

@@ -674,6 +674,7 @@ xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch
   }
 #undef XTC_LAUNCH_SPLIT
   // the rho row (exact field and the ISDF-free energy-scale sums) in FP64
+  if (!a.rho_rows) return XTC_OK;
   double* part = (double*)((char*)scratch + split_scratch_bytes(a.n_g, a.n_mu));
   return rho_row_f64(a, cf, part, st);
 }
