@@ -38,9 +38,9 @@ def parse():
                    help="also time the plain FP64 form and report its time-to-V and the error")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bra", type=int, default=1024, help="bra points in the CPU-oracle sample")
-    p.add_argument("--exchange", type=int, default=0, metavar="NBRA",
-                   help="also time the xTC Terms 2-3 exchange intermediates X2, X3 (split precision, "
-                        "low-rank projector of the occupied orbitals) over the first NBRA bra points")
+    p.add_argument("--exchange", action="store_true",
+                   help="also time one step with the xTC Terms 2-3 intermediates X2, X3 formed in the "
+                        "same contraction pass (low-rank projector of the occupied orbitals)")
     p.add_argument("--grad", action="store_true",
                    help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
                         "and the field (D1/D4 cotangents add one recomputation of stage 1)")
@@ -148,7 +148,7 @@ def main():
         res["adjoint_cotangents"] = "u1, u3, field"
         log(f"adjoint done in {res['adjoint_s']} s")
     if a.exchange:
-        res["exchange"] = exchange_bench(a, wl, grid, last, piv, prec, log)
+        res["exchange"] = exchange_bench(wl, grid, C_mo, chans, prec, log)
     if a.compare_fp64 and prec != L.XTC_FP64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -168,41 +168,43 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def exchange_bench(a, wl, grid, last, piv, prec, log):
-    """X2 and X3 over the first a.exchange bra points (each bra point's X contribution
-    needs its calG column over the whole ket grid). Algorithmic flops: the X products,
-    2 N_pair N_mu per bra point and product (one for X2, three for X3, N_pair = the
-    q <= s orbital pairs), plus the calG stage 1 (8 N_mu per grid pair) and the
-    projections R, Q (8 N_orb N_occ N_mu per bra point)."""
+def exchange_bench(wl, grid, C_mo, chans, prec, log):
+    """One whole step with X2 and X3 formed in the contraction pass from the same calG
+    panels. Algorithmic flops of the X part: the X products, 2 N_pair N_mu per grid
+    point and product (one for X2, three for X3; N_pair = the q <= s orbital pairs),
+    plus the projections R, Q (8 N_orb N_occ N_mu per grid point)."""
     import torch
 
     from paper_2607_17314_amd import api
-    n_orb, n_mu, n_q = wl.n_orb, len(piv), wl.n_occ
-    nb = min(a.exchange, wl.n_g)
-    phi_piv = last["phi4"][0][:, torch.as_tensor(piv, device="cuda")].contiguous()
+    n_orb, n_q = wl.n_orb, wl.n_occ
     lq = torch.zeros((n_orb, n_q), dtype=torch.float64, device="cuda")
     lq[torch.arange(n_q), torch.arange(n_q)] = 1.0     # closed-shell projector: occupied columns
-    log(f"timing the exchange intermediates over {nb} bra points")
+    log("timing one step with the exchange intermediates")
     torch.cuda.synchronize()
     with api.KernelTimer() as kt:
         t0 = time.perf_counter()
-        x = api.exchange_terms(grid, wl.corr, last["xi"], phi_piv, lq, prec, bra=(0, nb))
+        phi4, rho = api.eval_orbitals(wl.basis, grid, C_mo, wl.n_occ)
+        piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
+        xi, xig, _, _ = api.fit(phi4, grid, piv)
+        phi_piv = phi4[0][:, torch.as_tensor(piv, device="cuda")].contiguous()
+        out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, prec,
+                                  exchange={"phi_piv": phi_piv, "lq": lq})
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     tm = kt.result
+    n_mu = len(piv)
     npair = n_orb * (n_orb + 1) // 2
-    fx = 2.0 * npair * n_mu * nb * 4
-    fs1 = 8.0 * n_mu * nb * wl.n_g
-    frq = 8.0 * n_orb * n_q * n_mu * nb
-    gemm_ms = tm["x_gemm"]["ms"]
-    out = {"bra_points": nb, "n_q": n_q, "n_pair": npair, "time_s": round(dt, 4),
-           "tflops_total": round((fx + fs1 + frq) / dt / 1e12, 2),
-           "x_products_tflops": round(fx / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms else None,
+    fx = 2.0 * npair * n_mu * wl.n_g * 4
+    frq = 8.0 * n_orb * n_q * n_mu * wl.n_g
+    x_ms = tm["x_pairs"]["ms"] + tm["x_gemm"]["ms"]
+    res = {"time_to_V_with_X_s": round(dt, 4), "n_q": n_q, "n_pair": npair,
+           "x_part_s": round(x_ms * 1e-3, 4),
+           "x_products_tflops": round(fx / (tm["x_gemm"]["ms"] * 1e-3) / 1e12, 2),
+           "x_part_tflops": round((fx + frq) / (x_ms * 1e-3) / 1e12, 2),
            "stage_ms": {k: round(v["ms"], 2) for k, v in tm.items() if v["launches"]},
-           "full_grid_estimate_s": round(dt * wl.n_g / nb, 1),
-           "x_abs_max": [float(x["X2"].abs().max()), float(x["X3"].abs().max())]}
-    log(f"exchange done in {dt:.3f} s")
-    return out
+           "x_abs_max": [float(out["X2"].abs().max()), float(out["X3"].abs().max())]}
+    log(f"step with exchange done in {dt:.3f} s")
+    return res
 
 
 def cpu_baseline(wl, n_mu, n_bra):

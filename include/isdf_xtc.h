@@ -140,6 +140,18 @@ typedef struct {
   double ref_a, ref_b;     /* judge 0: log R_ref = ref_a + ref_b log(n_mu / n_orb) */
 } xtc_mlp;
 
+/* Exchange intermediates requested from xtc_kernel_contract (xTC Terms 2 and 3,
+ * see xtc_exchange_terms for the definitions): the orbitals at the pivots, the
+ * projector gamma = lq lq^T and the outputs. All pointers are device memory. */
+typedef struct {
+  int32_t n_orb;
+  const double* phi_piv; /* [n_orb][n_mu] */
+  int32_t n_q;           /* projector rank, 1..32 */
+  const double* lq;      /* [n_orb][n_q] */
+  double* X2;            /* [n_orb][n_orb][n_mu] or NULL */
+  double* X3;            /* [n_orb][n_orb][n_mu] or NULL */
+} xtc_exchange;
+
 /* Thread-local message of the last failing call (valid until the next call). */
 const char* xtc_last_error(void);
 
@@ -154,7 +166,8 @@ enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
  * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT) or
  * the precision (EXCHANGE). n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), the
- * projector rank n_q (EXCHANGE), else 0. */
+ * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_orb > 0
+ * asks for them), else 0. */
 size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
                            int32_t n_aux, uint32_t flags);
 
@@ -216,13 +229,18 @@ xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
  * escale: host [6] or NULL: {E3, E4, E1, E3x, E4x, E1x} with E3 = G^T u3 G,
  *   E4 = G^T D4 G, E1 = 2 G^T D1 G and their ISDF-free counterparts
  *   E3x = sum_{g,g'} w w' rho rho' |grad_1 u|^2, E4x = sum_g w rho |A_gamma|^2, E1x = 2 E4x.
- * precision: XTC_FP64 or XTC_SPLIT_F16. Synchronising only if escale != NULL. */
+ * precision: XTC_FP64 or XTC_SPLIT_F16.
+ * ex: NULL, or the exchange intermediates X2, X3 of xTC Terms 2 and 3 to form in the
+ *   same pass from the same calG panels (Alg. 2, xTC-correction step; definitions at
+ *   xtc_exchange_terms); with ex the workspace query takes n_orb = ex->n_orb and
+ *   n_aux = ex->n_q.
+ * Synchronising only if escale != NULL. */
 xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                                const double* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, uint32_t channels, int32_t precision,
                                double* u1, double* u3, double* ulap, double* D1, double* D4,
-                               double* field, double* escale, void* ws, size_t ws_bytes,
-                               void* stream);
+                               double* field, double* escale, const xtc_exchange* ex, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* Exchange intermediates of xTC Terms 2 and 3 through the low-rank projector
  * (xTC section, "Terms 2 and 3 (non-factorizable)", "Low-rank projector for Terms
@@ -272,9 +290,10 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * 1 stage-2 GEMMs, 2 pivot selection, 3 fit, 4 orbitals, 5 adjoint pair kernel,
  * 6 MLP, 7 split-operand preparation, 8 the stage-1 pair kernel alone (one entry
  * per kernel launch), 9 exchange projections and pair products, 10 exchange X
- * products (operand splitting included).
+ * products (operand splitting included), 11 the exchange's stage 1 on the projected
+ * rows (split path).
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 11
+#define XTC_TIMING_CATEGORIES 12
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

@@ -48,16 +48,18 @@ def density_projector(gamma: np.ndarray, tol: float = 1e-12) -> np.ndarray:
     return V[:, keep] * np.sqrt(lam[keep])[None, :]
 
 
-def calG(xyz, w, corr, xi, bra_block: int = 256):
-    """calG[c, mu, g] = sum_g' w_g' xi_mu(g') d_c u(g, g') (bra-blocked)."""
+def calG(xyz, w, corr, xi, bra_block: int = 256, bra=None):
+    """calG[c, mu, g] = sum_g' w_g' xi_mu(g') d_c u(g, g') (bra-blocked); with bra = (b, e)
+    only the bra points b <= g < e (columns g - b), the ket sum still over the whole grid."""
     n_mu, n_g = xi.shape
+    lo, hi = (0, n_g) if bra is None else bra
     wxi = xi * w[None, :]
-    out = np.zeros((3, n_mu, n_g))
-    for b0 in range(0, n_g, bra_block):
-        b1 = min(n_g, b0 + bra_block)
+    out = np.zeros((3, n_mu, hi - lo))
+    for b0 in range(lo, hi, bra_block):
+        b1 = min(hi, b0 + bra_block)
         K = pair_kernels(corr, xyz[:, b0:b1], xyz)
         for c, key in enumerate(("gx", "gy", "gz")):
-            out[c, :, b0:b1] = wxi @ K[key].T
+            out[c, :, b0 - lo:b1 - lo] = wxi @ K[key].T
     return out
 
 

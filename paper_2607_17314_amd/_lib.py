@@ -43,6 +43,11 @@ class Correlator(C.Structure):
                 ("nuc_type", I32)]
 
 
+class Exchange(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("phi_piv", P), ("n_q", C.c_int32), ("lq", P), ("X2", P),
+                ("X3", P)]
+
+
 class Mlp(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("params", P), ("feat_shift", P),
                 ("feat_scale", P), ("kappa", C.c_double), ("n_nuc", C.c_int32), ("nuc_xyz", D),
@@ -81,7 +86,8 @@ def lib() -> C.CDLL:
                            C.c_size_t, P]
     L.xtc_kernel_contract.restype = st
     L.xtc_kernel_contract.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64,
-                                      C.c_uint32, C.c_int32, P, P, P, P, P, P, D, P, C.c_size_t, P]
+                                      C.c_uint32, C.c_int32, P, P, P, P, P, P, D,
+                                      C.POINTER(Exchange), P, C.c_size_t, P]
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, P, P, P, P,
                            P, P, P, P, C.c_size_t, P]
@@ -111,4 +117,4 @@ EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_or
             "xtc_exchange_terms",
             "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
-                     "stage1_kernel", "x_pairs", "x_gemm"]
+                     "stage1_kernel", "x_pairs", "x_gemm", "x_stage1"]

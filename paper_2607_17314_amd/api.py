@@ -180,9 +180,11 @@ ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_E
 
 
 def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: int = ALL_CHANNELS,
-                    precision: int = L.XTC_FP64, c=None, out=None):
+                    precision: int = L.XTC_FP64, c=None, out=None, exchange=None):
     """Grid-pair kernels and xTC D terms (xtc_kernel_contract). Returns a dict of device tensors
-    (u1, u3, ulap, D1, D4, field) and escale (numpy [6]) for the requested channels."""
+    (u1, u3, ulap, D1, D4, field) and escale (numpy [6]) for the requested channels.
+    exchange: None, or {"phi_piv": [n_orb][n_mu], "lq": [n_orb][n_q], "want": ("X2", "X3")}
+    to form the xTC Terms 2-3 intermediates in the same pass (keys X2, X3 of the result)."""
     hc = HostCorrelator(corr, c)
     xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
     piv = np.ascontiguousarray(pivots, np.int64)
@@ -206,12 +208,24 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
     d4 = want(L.XTC_D4, "D4", (n_mu, n_mu))
     fld = want(L.XTC_FIELD, "field", (3, n_g))
     esc = np.zeros(6, np.float64)
-    ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, 0, n_mu, 0, channels | (precision << 16)))
+    exs, n_orb, n_q = None, 0, 0
+    if exchange is not None:
+        phi_piv, lq = _in(exchange["phi_piv"], "phi_piv"), _in(exchange["lq"], "lq")
+        n_orb, n_q = lq.shape
+        if phi_piv.shape != (n_orb, n_mu):
+            raise ValueError(f"phi_piv must be [n_orb={n_orb}][n_mu={n_mu}], got {tuple(phi_piv.shape)}")
+        want_x = exchange.get("want", ("X2", "X3"))
+        for k in ("X2", "X3"):
+            o[k] = torch.empty((n_orb, n_orb, n_mu), **f64) if k in want_x else None
+        exs = L.Exchange(n_orb, _ptr(phi_piv), n_q, _ptr(lq), _ptr(o["X2"]), _ptr(o["X3"]))
+    ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, n_orb, n_mu, n_q,
+                                    channels | (precision << 16)))
     g = grid.c()
     _check("xtc_kernel_contract", L.lib().xtc_kernel_contract(
         C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
         channels, precision, _ptr(u1), _ptr(u3), _ptr(ul), _ptr(d1), _ptr(d4), _ptr(fld),
-        _dptr(esc) if channels & L.XTC_ESCALE else None, _ptr(ws), ws.numel(), _stream()))
+        _dptr(esc) if channels & L.XTC_ESCALE else None, C.byref(exs) if exs is not None else None,
+        _ptr(ws), ws.numel(), _stream()))
     o["escale"] = esc if channels & L.XTC_ESCALE else None
     return o
 

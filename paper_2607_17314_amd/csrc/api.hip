@@ -29,7 +29,7 @@ extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, 
     case XTC_CALL_FEATURES: return xtc::ws_features(n_g);
     case XTC_CALL_MLP_GRAD: return xtc::ws_mlp_grad(n_g, n_aux);
     case XTC_CALL_FIT: return xtc::ws_fit(n_g, n_orb, n_mu, flags);
-    case XTC_CALL_CONTRACT: return xtc::ws_contract(n_g, n_mu, flags);
+    case XTC_CALL_CONTRACT: return xtc::ws_contract(n_g, n_mu, flags, n_orb, n_aux);
     case XTC_CALL_GRAD: return xtc::ws_grad(n_g, n_mu, n_aux, flags);
     case XTC_CALL_EXCHANGE: return xtc::ws_exchange(n_g, n_orb, n_mu, n_aux, (int)flags);
     default: return 0;

@@ -11,6 +11,7 @@
 #include "timing.hpp"
 #include "gemm_split.hpp"
 #include "bh.hpp"
+#include "exchange.hpp"
 
 namespace xtc {
 
@@ -117,9 +118,11 @@ struct ConLayout {
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
   void* gsplit; size_t gsplit_bytes; BHTable* bh;
   long bp; long rows_pad; int nsb; int nch;
+  ExWork ex;   // exchange intermediates (when requested)
 };
 
-static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision) {
+static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision,
+                            int n_orb, int n_q) {
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
@@ -145,12 +148,14 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
   C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   C.bh = ar.take<BHTable>(1);
+  C.ex = ExWork{};
+  if (n_orb > 0) ex_layout(ar, n_g, C.bp, n_mu, n_orb, n_q, precision, &C.ex);
   return C;
 }
 
-size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags) {
+size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q) {
   Arena ar(nullptr, 0);
-  layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff));
+  layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q);
   return ar.used;
 }
 
@@ -189,9 +194,10 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
                                           const double* rho, const int64_t* pivots,
                                           uint32_t channels, int32_t precision, double* u1,
                                           double* u3, double* ulap, double* D1, double* D4,
-                                          double* field, double* escale, void* ws,
-                                          size_t ws_bytes, void* stream) {
+                                          double* field, double* escale, const xtc_exchange* ex,
+                                          void* ws, size_t ws_bytes, void* stream) {
   XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+  if (ex) XTC_TRY(check_exchange_args(ex, n_mu));
   XTC_REQUIRE(!(channels & XTC_U1) || u1, "contract: u1 output NULL");
   XTC_REQUIRE(!(channels & XTC_U3) || u3, "contract: u3 output NULL");
   XTC_REQUIRE(!(channels & XTC_ULAP) || ulap, "contract: ulap output NULL");
@@ -207,10 +213,12 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   hipStream_t st = as_stream(stream);
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
-  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision);
+  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, ex ? ex->n_orb : 0,
+                           ex ? ex->n_q : 0);
   XTC_TRY(need_ws(ar));
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  if (ex) XTC_TRY(ex_prepare(C.ex, ex->phi_piv, ex->lq, grid->xyz, grid->w, xi, n_g, st));
   hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
                      (const long*)C.piv, n_mu, C.G);
   XTC_CHECK_LAUNCH();
@@ -285,7 +293,12 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
     XTC_TRY(reduce_sum_f64(C.e3, bn, C.sums + 4 * sb + 2, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e4, bn, C.sums + 4 * sb + 3, C.red, st));
     timing_end(tk2, st);
+    // xTC Terms 2 and 3 from the same calG panel
+    if (ex)
+      XTC_TRY(ex_block(C.ex, cf, C.panel, C.rows_pad, grid->xyz, xi, n_g, grid->w, b0, bn,
+                       sb == 0, ex->X2 != nullptr, ex->X3 != nullptr, st));
   }
+  if (ex) XTC_TRY(ex_finish(C.ex, ex->X2, ex->X3, false, st));
   if (channels & XTC_ESCALE) {
     std::vector<double> hs(4 * C.nsb);
     XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 4 * C.nsb, hipMemcpyDeviceToHost, st));

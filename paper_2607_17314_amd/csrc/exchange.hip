@@ -19,49 +19,65 @@
 // the quadrature weight as the per-k scale and FP64 accumulation across chunks.
 #include "bh.hpp"
 #include "contract.hpp"
+#include "exchange.hpp"
 #include "gemm_split.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
 
 namespace xtc {
 
-constexpr long XSUPER = 16384;   // bra super-block
+constexpr long XSUPER = 16384;   // bra super-block of the standalone call
 constexpr long XCH = 2048;       // bra chunk of the pair products and X GEMMs
 constexpr int XOB = 64;          // orbital block of the pair kernel
 
-struct ExLayout {
-  double* phia; double* P; double* panel; void* split; size_t split_bytes;
-  double* RQ; double* T; double* Xp; int2* tiles; void* gsplit; size_t gsplit_bytes;
-  BHTable* bh; long bp; long rows_pad; long npair; long npl; long tpart; int ntile;
-};
-
 static inline long round_to(long x, long m) { return ((x + m - 1) / m) * m; }
+
+void ex_layout(Arena& ar, long n_g, long bp, int n_mu, int n_orb, int n_q, int precision,
+               ExWork* W) {
+  W->n_orb = n_orb;
+  W->n_q = n_q;
+  W->n_mu = n_mu;
+  W->bp = bp;
+  W->precision = precision;
+  W->npair = (long)n_orb * (n_orb + 1) / 2;
+  W->npl = round_to(W->npair, 32);
+  const int nb = (int)cdiv(n_orb, XOB);
+  W->ntile = nb * (nb + 1) / 2;
+  const long nr = (long)n_orb * n_q;
+  W->nr = nr;
+  const long xch = bp < XCH ? bp : XCH;
+  W->tpart = xch * W->npl;
+  W->phia = ar.take<double>((size_t)n_q * n_mu);
+  W->P = ar.take<double>((size_t)nr * n_mu);
+  W->RQ = ar.take<double>((size_t)4 * nr * bp);
+  W->T = ar.take<double>((size_t)4 * W->tpart);
+  W->Xp = ar.take<double>((size_t)2 * W->npair * n_mu);
+  W->tiles = ar.take<int2>(W->ntile);
+  const bool split = precision == XTC_SPLIT_F16;
+  W->gsplit_bytes = split ? gemm_split_seg_scratch_bytes(W->npair, n_mu, xch, 3) : 0;
+  W->gsplit = W->gsplit_bytes ? (void*)ar.take<char>(W->gsplit_bytes) : nullptr;
+  W->rows_padR = round_to(nr + 2, 256);
+  W->Qf = split ? ar.take<double>((size_t)nr * n_g) : nullptr;
+  W->splitQ_bytes = split ? split_scratch_bytes(n_g, (int)nr) + rho_row_scratch_bytes(bp) : 0;
+  W->splitQ = W->splitQ_bytes ? (void*)ar.take<char>(W->splitQ_bytes) : nullptr;
+  W->panelR = split ? ar.take<double>((size_t)4 * W->rows_padR * bp) : nullptr;
+}
+
+struct ExLayout {
+  double* panel; void* split; size_t split_bytes; BHTable* bh; long bp; long rows_pad;
+  ExWork W;
+};
 
 static ExLayout layout_ex(Arena& ar, int64_t n_g, int n_mu, int n_orb, int n_q, int precision) {
   ExLayout L;
   L.bp = n_g < XSUPER ? round_to(n_g, 64) : XSUPER;
   L.rows_pad = round_to(n_mu + 2, 256);
-  L.npair = (long)n_orb * (n_orb + 1) / 2;
-  L.npl = round_to(L.npair, 32);
-  const int nb = (int)cdiv(n_orb, XOB);
-  L.ntile = nb * (nb + 1) / 2;
-  const long nr = (long)n_orb * n_q;
-  const long xch = L.bp < XCH ? L.bp : XCH;
-  L.tpart = xch * L.npl;
-  L.phia = ar.take<double>((size_t)n_q * n_mu);
-  L.P = ar.take<double>((size_t)nr * n_mu);
   L.panel = ar.take<double>((size_t)4 * L.rows_pad * L.bp);
   L.split_bytes = precision == XTC_SPLIT_F16
                       ? split_scratch_bytes(n_g, n_mu) + rho_row_scratch_bytes(L.bp) : 0;
   L.split = L.split_bytes ? (void*)ar.take<char>(L.split_bytes) : nullptr;
-  L.RQ = ar.take<double>((size_t)4 * nr * L.bp);
-  L.T = ar.take<double>((size_t)4 * L.tpart);
-  L.Xp = ar.take<double>((size_t)2 * L.npair * n_mu);
-  L.tiles = ar.take<int2>(L.ntile);
-  L.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_seg_scratch_bytes(L.npair, n_mu, xch, 3)
-                                              : 0;
-  L.gsplit = L.gsplit_bytes ? (void*)ar.take<char>(L.gsplit_bytes) : nullptr;
   L.bh = ar.take<BHTable>(1);
+  ex_layout(ar, n_g, L.bp, n_mu, n_orb, n_q, precision, &L.W);
   return L;
 }
 
@@ -69,6 +85,18 @@ size_t ws_exchange(int64_t n_g, int n_orb, int n_mu, int n_q, int precision) {
   Arena ar(nullptr, 0);
   layout_ex(ar, n_g, n_mu, n_orb, n_q, precision);
   return ar.used;
+}
+
+// upper-triangular tile table of the 64-orbital blocks: tile t -> (q block, s block)
+__global__ void k_fill_tiles(int nb, int ntile, int2* __restrict__ tiles) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntile) return;
+  int r = t, qb = 0;
+  while (r >= nb - qb) {
+    r -= nb - qb;
+    ++qb;
+  }
+  tiles[t] = make_int2(qb, qb + r);
 }
 
 // P[(s, a)][nu] = phi_s(nu) phia[a][nu]
@@ -176,6 +204,184 @@ __global__ void k_unpack_sym(const double* __restrict__ Xp, int n_orb, int n_mu,
   X[t] = Xp[pair_index(q, s, n_orb) * n_mu + mu];
 }
 
+xtc_status ex_prepare(ExWork& W, const double* phi_piv, const double* lq, const double* xyz,
+                      const double* w, const double* xi, long n_g, hipStream_t st) {
+  const int nb = (int)cdiv(W.n_orb, XOB);
+  hipLaunchKernelGGL(k_fill_tiles, dim3(cdiv(W.ntile, 256)), dim3(256), 0, st, nb, W.ntile,
+                     W.tiles);
+  XTC_CHECK_LAUNCH();
+  const long nr = W.nr;
+  GemmArgs g{};   // phia[a][nu] = sum_t LQ[t][a] phi_t(nu)
+  g.M = W.n_q; g.N = W.n_mu; g.K = W.n_orb;
+  g.A = lq; g.a_sm = 1; g.a_sk = W.n_q;
+  g.B = phi_piv; g.b_sk = W.n_mu; g.b_sn = 1;
+  g.C = W.phia; g.c_sm = W.n_mu; g.c_sn = 1;
+  XTC_TRY(gemm_f64(g, st));
+  hipLaunchKernelGGL(k_proj_rows, dim3(cdiv(nr * W.n_mu, 256)), dim3(256), 0, st, phi_piv,
+                     (const double*)W.phia, W.n_orb, W.n_q, W.n_mu, W.P);
+  XTC_CHECK_LAUNCH();
+  if (W.precision == XTC_SPLIT_F16) {
+    // Q[s a][g] = sum_nu P[s a][nu] xi_nu(g) over the whole grid, in FP64: the sum over
+    // the pivots cancels strongly, so it is done before the split contraction
+    for (long g0 = 0; g0 < n_g; g0 += 1L << 20) {
+      GemmArgs q{};
+      q.M = nr; q.N = (n_g - g0) < (1L << 20) ? (n_g - g0) : (1L << 20); q.K = W.n_mu;
+      q.A = W.P; q.a_sm = W.n_mu; q.a_sk = 1;
+      q.B = xi + g0; q.b_sk = n_g; q.b_sn = 1;
+      q.C = W.Qf + g0; q.c_sm = n_g; q.c_sn = 1;
+      XTC_TRY(gemm_f64(q, st));
+    }
+    Stage1Args sq{xyz, w, W.Qf, w, w, n_g, (int)nr, 0, 0, W.panelR, W.rows_padR, W.bp, 4};
+    sq.rho_rows = false;
+    XTC_TRY(split_prepare(sq, W.splitQ, st));
+  }
+  return XTC_OK;
+}
+
+// RQ[g][ch][sa] = panelR[ch][sa][g] (ch < 3) or Qf[sa][b0 + g] (ch 3): 64 x 64 tiles
+// through LDS so that both the reads (g fastest) and the writes (sa fastest) are whole lines
+__global__ __launch_bounds__(256) void k_gather_rq(const double* __restrict__ panelR,
+                                                   long rows_padR, long bp,
+                                                   const double* __restrict__ Qf, long n_g,
+                                                   long b0, long bn, long nr,
+                                                   double* __restrict__ RQ) {
+  __shared__ double tile[64][65];
+  const int ch = blockIdx.z;
+  const long sa0 = (long)blockIdx.y * 64, g0 = (long)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const long sa = sa0 + r, g = g0 + tx;
+    double v = 0.0;
+    if (sa < nr && g < bn)
+      v = ch < 3 ? panelR[((long)ch * rows_padR + sa) * bp + g] : Qf[sa * n_g + b0 + g];
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const long g = g0 + r, sa = sa0 + tx;
+    if (g < bn && sa < nr) RQ[(g * 4 + ch) * nr + sa] = tile[tx][r];
+  }
+}
+
+xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_pad,
+                    const double* xyz, const double* xi, long n_g, const double* w, long b0,
+                    long bn, bool first, bool want2, bool want3, hipStream_t st) {
+  const long nr = W.nr;
+  const long bp = W.bp;
+  const int n_mu = W.n_mu;
+  if (W.precision == XTC_SPLIT_F16) {
+    // R^c_{sa}(g) = sum_g' w Q_{sa}(g') d_c u(g, g'): the split stage 1 on the projected
+    // rows, so that each R row is split relative to its own scale
+    Stage1Args sq{xyz, w, W.Qf, w, w, n_g, (int)nr, b0, bn, W.panelR, W.rows_padR, bp, 4};
+    sq.rho_rows = false;
+    size_t tk0 = timing_begin(TM_X_STAGE1, st);
+    XTC_TRY(stage1_split_f16(sq, cf, W.splitQ, W.splitQ_bytes, st));
+    timing_end(tk0, st);
+    size_t tk1 = timing_begin(TM_X_PAIRS, st);
+    hipLaunchKernelGGL(k_gather_rq, dim3(cdiv(bn, 64), cdiv(nr, 64), 4), dim3(256), 0, st,
+                       (const double*)W.panelR, W.rows_padR, bp, (const double*)W.Qf, n_g, b0,
+                       bn, nr, W.RQ);
+    XTC_CHECK_LAUNCH();
+    timing_end(tk1, st);
+  }
+  // FP64 path: RQ[g][ch][s a] with R^c = P calG^c (ch 0..2) and Q = P xi (ch 3)
+  size_t tk1 = timing_begin(TM_X_PAIRS, st);
+  for (int ch = 0; ch < 4 && W.precision == XTC_FP64; ++ch) {
+    GemmArgs g{};
+    g.M = nr; g.N = bn; g.K = n_mu;
+    g.A = W.P; g.a_sm = n_mu; g.a_sk = 1;
+    if (ch < 3) {
+      g.B = panel + (long)ch * rows_pad * bp; g.b_sk = bp; g.b_sn = 1;
+    } else {
+      g.B = xi + b0; g.b_sk = n_g; g.b_sn = 1;
+    }
+    g.C = W.RQ + (long)ch * nr; g.c_sm = 1; g.c_sn = 4 * nr;
+    XTC_TRY(gemm_f64(g, st));
+  }
+  timing_end(tk1, st);
+  for (long g0 = 0; g0 < bn; g0 += XCH) {
+    const long cn = (bn - g0) < XCH ? (bn - g0) : XCH;
+    size_t tk2 = timing_begin(TM_X_PAIRS, st);
+    dim3 gp((unsigned)W.ntile, (unsigned)cn);
+    if (W.n_q <= 16)
+      hipLaunchKernelGGL(k_x_pairs<16>, gp, dim3(256), 0, st, (const double*)W.RQ,
+                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, W.npl, W.tpart, W.T);
+    else
+      hipLaunchKernelGGL(k_x_pairs<32>, gp, dim3(256), 0, st, (const double*)W.RQ,
+                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, W.npl, W.tpart, W.T);
+    XTC_CHECK_LAUNCH();
+    timing_end(tk2, st);
+    // Xp2 (+)= T2 diag(w) xi^T ;  Xp3 (+)= sum_c T3^c diag(w) calG^c^T
+    const bool init = first && g0 == 0;
+    const double* wc = w + b0 + g0;
+    size_t tk3 = timing_begin(TM_X_GEMM, st);
+    if (want2) {
+      if (W.precision == XTC_SPLIT_F16) {
+        SplitSeg sg{W.T, 1, W.npl, wc, xi + b0 + g0, n_g, 1};
+        XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, &sg, 1, W.Xp, n_mu, !init, W.gsplit,
+                               W.gsplit_bytes, st));
+      } else {
+        GemmArgs g{};
+        g.M = W.npair; g.N = n_mu; g.K = cn;
+        g.A = W.T; g.a_sm = 1; g.a_sk = W.npl;
+        g.s = wc;
+        g.B = xi + b0 + g0; g.b_sk = 1; g.b_sn = n_g;
+        g.C = W.Xp; g.c_sm = n_mu; g.c_sn = 1;
+        g.beta = init ? 0.0 : 1.0;
+        XTC_TRY(gemm_f64(g, st));
+      }
+    }
+    if (want3) {
+      double* X3p = W.Xp + W.npair * n_mu;
+      SplitSeg sg[3];
+      for (int c = 0; c < 3; ++c)
+        sg[c] = SplitSeg{W.T + (1 + c) * W.tpart, 1, W.npl, wc,
+                         panel + (long)c * rows_pad * bp + g0, bp, 1};
+      if (W.precision == XTC_SPLIT_F16) {
+        XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, sg, 3, X3p, n_mu, !init, W.gsplit,
+                               W.gsplit_bytes, st));
+      } else {
+        for (int c = 0; c < 3; ++c) {
+          GemmArgs g{};
+          g.M = W.npair; g.N = n_mu; g.K = cn;
+          g.A = sg[c].A; g.a_sm = 1; g.a_sk = W.npl;
+          g.s = wc;
+          g.B = sg[c].B; g.b_sk = 1; g.b_sn = bp;
+          g.C = X3p; g.c_sm = n_mu; g.c_sn = 1;
+          g.beta = (init && c == 0) ? 0.0 : 1.0;
+          XTC_TRY(gemm_f64(g, st));
+        }
+      }
+    }
+    timing_end(tk3, st);
+  }
+  return XTC_OK;
+}
+
+xtc_status ex_finish(ExWork& W, double* X2, double* X3, bool empty, hipStream_t st) {
+  const long ntot = (long)W.n_orb * W.n_orb * W.n_mu;
+  for (int i = 0; i < 2; ++i) {
+    double* X = i == 0 ? X2 : X3;
+    if (!X) continue;
+    if (empty)
+      hipLaunchKernelGGL(k_zero, dim3(cdiv(ntot, 256)), dim3(256), 0, st, X, ntot);
+    else
+      hipLaunchKernelGGL(k_unpack_sym, dim3(cdiv(ntot, 256)), dim3(256), 0, st,
+                         (const double*)(W.Xp + (long)i * W.npair * W.n_mu), W.n_orb, W.n_mu, X);
+    XTC_CHECK_LAUNCH();
+  }
+  return XTC_OK;
+}
+
+xtc_status check_exchange_args(const xtc_exchange* ex, int32_t n_mu) {
+  XTC_REQUIRE(ex->phi_piv && ex->lq, "exchange: null phi_piv or lq");
+  XTC_REQUIRE(ex->X2 || ex->X3, "exchange: no output requested");
+  XTC_REQUIRE(ex->n_orb > 0, "exchange: n_orb must be positive");
+  XTC_REQUIRE(ex->n_q > 0 && ex->n_q <= 32, "exchange: projector rank must be 1..32");
+  (void)n_mu;
+  return XTC_OK;
+}
+
 }  // namespace xtc
 
 using namespace xtc;
@@ -186,11 +392,11 @@ extern "C" xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correla
                                          int32_t precision, int64_t bra_begin, int64_t bra_end,
                                          double* X2, double* X3, void* ws, size_t ws_bytes,
                                          void* stream) {
-  XTC_REQUIRE(grid && corr && xi && phi_piv && lq, "exchange: null argument");
-  XTC_REQUIRE(X2 || X3, "exchange: no output requested");
+  XTC_REQUIRE(grid && corr && xi, "exchange: null argument");
+  const xtc_exchange ex{n_orb, phi_piv, n_q, lq, X2, X3};
+  XTC_TRY(check_exchange_args(&ex, n_mu));
   XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "exchange: empty grid");
-  XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g && n_orb > 0, "exchange: bad sizes");
-  XTC_REQUIRE(n_q > 0 && n_q <= 32, "exchange: projector rank must be 1..32");
+  XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "exchange: bad n_mu");
   XTC_REQUIRE(bra_begin >= 0 && bra_begin <= bra_end && bra_end <= grid->n_g,
               "exchange: bra range outside the grid");
   XTC_REQUIRE(precision == XTC_FP64 || precision == XTC_SPLIT_F16, "exchange: bad precision");
@@ -212,28 +418,13 @@ extern "C" xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correla
   Arena ar(ws, ws_bytes);
   ExLayout L = layout_ex(ar, n_g, n_mu, n_orb, n_q, precision);
   XTC_TRY(need_ws(ar));
+  if (bra_end == bra_begin) {
+    XTC_TRY(ex_finish(L.W, X2, X3, true, st));
+    XTC_HIP(hipStreamSynchronize(st));
+    return XTC_OK;
+  }
   if (bh) XTC_HIP(hipMemcpyAsync(L.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
-  std::vector<int2> tl;
-  {
-    const int nb = (int)cdiv(n_orb, XOB);
-    for (int qb = 0; qb < nb; ++qb)
-      for (int sb = qb; sb < nb; ++sb) tl.push_back(make_int2(qb, sb));
-    XTC_HIP(hipMemcpyAsync(L.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice,
-                           st));
-  }
-  const long nr = (long)n_orb * n_q;
-  {
-    // phia[a][nu] = sum_t LQ[t][a] phi_t(nu)
-    GemmArgs g{};
-    g.M = n_q; g.N = n_mu; g.K = n_orb;
-    g.A = lq; g.a_sm = 1; g.a_sk = n_q;
-    g.B = phi_piv; g.b_sk = n_mu; g.b_sn = 1;
-    g.C = L.phia; g.c_sm = n_mu; g.c_sn = 1;
-    XTC_TRY(gemm_f64(g, st));
-  }
-  hipLaunchKernelGGL(k_proj_rows, dim3(cdiv(nr * n_mu, 256)), dim3(256), 0, st, phi_piv,
-                     (const double*)L.phia, n_orb, n_q, n_mu, L.P);
-  XTC_CHECK_LAUNCH();
+  XTC_TRY(ex_prepare(L.W, phi_piv, lq, grid->xyz, grid->w, xi, n_g, st));
   // the panel's density rows are not used here: w stands in for rho and rhot
   Stage1Args s1{grid->xyz, grid->w, xi, grid->w, grid->w, n_g, n_mu, 0, 0, L.panel,
                 L.rows_pad, L.bp, 4};
@@ -243,16 +434,6 @@ extern "C" xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correla
     size_t tk = timing_begin(TM_SPLIT_PREP, st);
     XTC_TRY(split_prepare(s1, L.split, st));
     timing_end(tk, st);
-  }
-  const long ntot = (long)n_orb * n_orb * n_mu;
-  if (bra_end == bra_begin) {
-    for (double* X : {X2, X3})
-      if (X) {
-        hipLaunchKernelGGL(k_zero, dim3(cdiv(ntot, 256)), dim3(256), 0, st, X, ntot);
-        XTC_CHECK_LAUNCH();
-      }
-    XTC_HIP(hipStreamSynchronize(st));
-    return XTC_OK;
   }
   const int nsb = (int)cdiv(bra_end - bra_begin, L.bp);
   for (int sb = 0; sb < nsb; ++sb) {
@@ -264,89 +445,10 @@ extern "C" xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correla
     if (precision == XTC_FP64) XTC_TRY(stage1_f64(s1, cf, st));
     else XTC_TRY(stage1_split_f16(s1, cf, L.split, L.split_bytes, st));
     timing_end(tk, st);
-    // RQ[g][ch][s a]: R^c = P calG^c (ch 0..2) and Q = P xi (ch 3) over the block
-    size_t tk1 = timing_begin(TM_X_PAIRS, st);
-    for (int ch = 0; ch < 4; ++ch) {
-      GemmArgs g{};
-      g.M = nr; g.N = bn; g.K = n_mu;
-      g.A = L.P; g.a_sm = n_mu; g.a_sk = 1;
-      if (ch < 3) {
-        g.B = L.panel + (long)ch * L.rows_pad * L.bp; g.b_sk = L.bp; g.b_sn = 1;
-      } else {
-        g.B = xi + b0; g.b_sk = n_g; g.b_sn = 1;
-      }
-      g.C = L.RQ + (long)ch * nr; g.c_sm = 1; g.c_sn = 4 * nr;
-      XTC_TRY(gemm_f64(g, st));
-    }
-    timing_end(tk1, st);
-    for (long g0 = 0; g0 < bn; g0 += XCH) {
-      const long cn = (bn - g0) < XCH ? (bn - g0) : XCH;
-      size_t tk2 = timing_begin(TM_X_PAIRS, st);
-      dim3 gp((unsigned)L.ntile, (unsigned)cn);
-      if (n_q <= 16)
-        hipLaunchKernelGGL(k_x_pairs<16>, gp, dim3(256), 0, st, (const double*)L.RQ,
-                           (const int2*)L.tiles, n_orb, n_q, g0, L.npl, L.tpart, L.T);
-      else
-        hipLaunchKernelGGL(k_x_pairs<32>, gp, dim3(256), 0, st, (const double*)L.RQ,
-                           (const int2*)L.tiles, n_orb, n_q, g0, L.npl, L.tpart, L.T);
-      XTC_CHECK_LAUNCH();
-      timing_end(tk2, st);
-      // Xp2 (+)= T2 diag(w) xi^T ;  Xp3 (+)= sum_c T3^c diag(w) calG^c^T
-      const bool first = sb == 0 && g0 == 0;
-      const double* wc = grid->w + b0 + g0;
-      size_t tk3 = timing_begin(TM_X_GEMM, st);
-      if (X2) {
-        if (precision == XTC_SPLIT_F16) {
-          SplitSeg sg{L.T, 1, L.npl, wc, xi + b0 + g0, n_g, 1};
-          XTC_TRY(gemm_split_seg(L.npair, n_mu, cn, &sg, 1, L.Xp, n_mu, !first, L.gsplit,
-                                 L.gsplit_bytes, st));
-        } else {
-          GemmArgs g{};
-          g.M = L.npair; g.N = n_mu; g.K = cn;
-          g.A = L.T; g.a_sm = 1; g.a_sk = L.npl;
-          g.s = wc;
-          g.B = xi + b0 + g0; g.b_sk = 1; g.b_sn = n_g;
-          g.C = L.Xp; g.c_sm = n_mu; g.c_sn = 1;
-          g.beta = first ? 0.0 : 1.0;
-          XTC_TRY(gemm_f64(g, st));
-        }
-      }
-      if (X3) {
-        double* X3p = L.Xp + L.npair * n_mu;
-        SplitSeg sg[3];
-        for (int c = 0; c < 3; ++c)
-          sg[c] = SplitSeg{L.T + (1 + c) * L.tpart, 1, L.npl, wc,
-                           L.panel + (long)c * L.rows_pad * L.bp + g0, L.bp, 1};
-        if (precision == XTC_SPLIT_F16) {
-          XTC_TRY(gemm_split_seg(L.npair, n_mu, cn, sg, 3, X3p, n_mu, !first, L.gsplit,
-                                 L.gsplit_bytes, st));
-        } else {
-          for (int c = 0; c < 3; ++c) {
-            GemmArgs g{};
-            g.M = L.npair; g.N = n_mu; g.K = cn;
-            g.A = sg[c].A; g.a_sm = 1; g.a_sk = L.npl;
-            g.s = wc;
-            g.B = sg[c].B; g.b_sk = 1; g.b_sn = L.bp;
-            g.C = X3p; g.c_sm = n_mu; g.c_sn = 1;
-            g.beta = (first && c == 0) ? 0.0 : 1.0;
-            XTC_TRY(gemm_f64(g, st));
-          }
-        }
-      }
-      timing_end(tk3, st);
-    }
+    XTC_TRY(ex_block(L.W, cf, L.panel, L.rows_pad, grid->xyz, xi, n_g, grid->w, b0, bn, sb == 0,
+                     X2 != nullptr, X3 != nullptr, st));
   }
-  if (X2) {
-    hipLaunchKernelGGL(k_unpack_sym, dim3(cdiv(ntot, 256)), dim3(256), 0, st,
-                       (const double*)L.Xp, n_orb, n_mu, X2);
-    XTC_CHECK_LAUNCH();
-  }
-  if (X3) {
-    hipLaunchKernelGGL(k_unpack_sym, dim3(cdiv(ntot, 256)), dim3(256), 0, st,
-                       (const double*)(L.Xp + L.npair * n_mu), n_orb, n_mu, X3);
-    XTC_CHECK_LAUNCH();
-  }
-  // the tile table is host memory read by the copy above
+  XTC_TRY(ex_finish(L.W, X2, X3, false, st));
   XTC_HIP(hipStreamSynchronize(st));
   return XTC_OK;
 }

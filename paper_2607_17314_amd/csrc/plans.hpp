@@ -8,7 +8,7 @@ namespace xtc {
 size_t ws_eval_orbitals(int64_t n_g, int n_orb, int n_ao);
 size_t ws_select(int64_t n_g, int n_orb, int n_mu, int mode);
 size_t ws_fit(int64_t n_g, int n_orb, int n_mu, uint32_t what);
-size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags);
+size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q);
 size_t ws_grad(int64_t n_g, int n_mu, int n_params, uint32_t flags);
 size_t ws_features(int64_t n_g);
 size_t ws_mlp_grad(int64_t n, int hidden);

@@ -58,16 +58,53 @@ def test_host_argument_checks_return_invalid_arg():
     piv[:] = [0, 1, 2, 99]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 0, xyz, None, None, None, None, None,
-                                 None, None, 0, None)
+                                 None, None, None, 0, None)
     assert st == -1 and b"pivot" in lib.xtc_last_error()
     # unknown precision
     piv[:] = [0, 1, 2, 3]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 7, xyz, None, None, None, None, None,
-                                 None, None, 0, None)
+                                 None, None, None, 0, None)
     assert st == -1
     # a too-small workspace is reported as such, not as a crash
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 0, xyz, xyz, None, None, None, None,
-                                 None, None, 0, None)
+                                 None, None, None, 0, None)
     assert st == -4
+
+
+def test_exchange_argument_checks_return_invalid_arg():
+    """xtc_exchange_terms and the exchange block of xtc_kernel_contract reject bad
+    sizes, ranges and missing outputs before anything is launched."""
+    from paper_2607_17314_amd import _lib as L
+    lib = L.lib()
+    xyz = C.c_void_p(8)
+    g = L.Grid(10, xyz, xyz)
+    mno = np.array([[0, 0, 2]], np.int32)
+    cc = np.array([0.3])
+    corr = L.Correlator(0, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0, None, 0,
+                        None, None)
+    ex = lib.xtc_exchange_terms
+    # projector rank 0 and 33
+    for nq in (0, 33):
+        assert ex(C.byref(g), C.byref(corr), 4, xyz, 6, xyz, nq, xyz, 0, 0, 10, xyz, xyz, None, 0,
+                  None) == -1
+        assert b"rank" in lib.xtc_last_error()
+    # bra range outside the grid, reversed range
+    assert ex(C.byref(g), C.byref(corr), 4, xyz, 6, xyz, 2, xyz, 0, 0, 11, xyz, xyz, None, 0, None) == -1
+    assert ex(C.byref(g), C.byref(corr), 4, xyz, 6, xyz, 2, xyz, 0, 5, 4, xyz, xyz, None, 0, None) == -1
+    assert b"bra range" in lib.xtc_last_error()
+    # no output
+    assert ex(C.byref(g), C.byref(corr), 4, xyz, 6, xyz, 2, xyz, 0, 0, 10, None, None, None, 0,
+              None) == -1
+    # the workspace query grows with the exchange block of the contraction
+    base = lib.xtc_workspace_bytes(L.XTC_CALL_CONTRACT, 20000, 0, 200, 0, 2)
+    with_x = lib.xtc_workspace_bytes(L.XTC_CALL_CONTRACT, 20000, 60, 200, 3, 2)
+    assert with_x > base + 2 * (60 * 61 // 2) * 200 * 8
+    # the contraction's exchange block is checked too
+    piv = np.arange(4, dtype=np.int64)
+    exs = L.Exchange(6, xyz, 40, xyz, xyz, None)
+    st = lib.xtc_kernel_contract(C.byref(g), C.byref(corr), 4, xyz, xyz, xyz,
+                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, None, None, None, None, None,
+                                 None, C.byref(exs), None, 0, None)
+    assert st == -1 and b"rank" in lib.xtc_last_error()

@@ -27,7 +27,7 @@ def ex_problem(h6_small):
     mix = np.random.default_rng(22).normal(size=(N_FUN, phi4.shape[1])) / np.sqrt(phi4.shape[1])
     phi = mix @ phi4[0]
     cG = exchange.calG(xyz, w, wl.corr, fr.xi)
-    return wl, xyz, w, fp.pivots, fr, phi, cG
+    return wl, xyz, w, fp.pivots, fr, phi, cG, orbitals.density(phi4, wl.n_occ)
 
 
 def _projector(n_q, seed):
@@ -53,7 +53,7 @@ def _run(api, wl, xyz, w, xi, phi_piv, LQ, precision, corr=None):
 def test_exchange_matches_oracle(ex_problem, n_q, precision, tol):
     from oracle import exchange
     from paper_2607_17314_amd import api
-    wl, xyz, w, piv, fr, phi, cG = ex_problem
+    wl, xyz, w, piv, fr, phi, cG, rho = ex_problem
     LQ = _projector(n_q, 30 + n_q)
     note(f"exchange: n_g={len(w)} n_mu={len(piv)} n_orb={N_FUN} n_q={LQ.shape[1]} "
          f"precision={precision}")
@@ -72,7 +72,7 @@ def test_exchange_single_output(ex_problem):
     import torch
     from paper_2607_17314_amd import _lib as L
     from paper_2607_17314_amd import api
-    wl, xyz, w, piv, fr, phi, cG = ex_problem
+    wl, xyz, w, piv, fr, phi, cG, rho = ex_problem
     LQ = _projector(4, 41)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
     grid = api.DeviceGrid.from_host(xyz, w)
@@ -121,7 +121,7 @@ def test_exchange_bra_ranges_add_up(ex_problem):
     import torch
     from paper_2607_17314_amd import _lib as L
     from paper_2607_17314_amd import api
-    wl, xyz, w, piv, fr, phi, cG = ex_problem
+    wl, xyz, w, piv, fr, phi, cG, rho = ex_problem
     LQ = _projector(3, 43)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
     grid = api.DeviceGrid.from_host(xyz, w)
@@ -137,3 +137,128 @@ def test_exchange_bra_ranges_add_up(ex_problem):
         note(f"  {k}: split-range sum vs whole grid {e:.2e}")
         assert e < 1e-12, k
         assert float(none[k].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+def test_fused_contraction_pass_gives_the_same_x(ex_problem, precision):
+    """X2, X3 formed inside xtc_kernel_contract from its own calG panels equal the
+    standalone call's, bit for bit, and the contraction outputs are unchanged."""
+    import torch
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, phi, cG, rho = ex_problem
+    LQ = _projector(6, 44)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    grid = api.DeviceGrid.from_host(xyz, w)
+    ch = 1 | 2 | 8 | 16 | 32 | 64
+    xi, xig, rh = t(fr.xi), t(fr.xigrad), t(rho)
+    alone = api.exchange_terms(grid, wl.corr, xi, t(phi[:, piv]), t(LQ), precision)
+    plain = api.kernel_contract(grid, wl.corr, xi, xig, rh, piv, ch, precision)
+    fused = api.kernel_contract(grid, wl.corr, xi, xig, rh, piv, ch, precision,
+                                exchange={"phi_piv": t(phi[:, piv]), "lq": t(LQ)})
+    torch.cuda.synchronize()
+    for k in ("X2", "X3"):
+        assert torch.equal(fused[k], alone[k]), k
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        assert torch.equal(fused[k], plain[k]), k
+    assert np.array_equal(fused["escale"], plain["escale"])
+
+
+@pytest.fixture(scope="module")
+def h20_exchange():
+    """The H20 grid (194,000 points) with N_mu = 3000 seeded interpolation vectors,
+    300 orbital functions at the pivots and the closed-shell projector of 10
+    occupied orbitals: the shapes the benchmark runs."""
+    from workloads import make_config
+    wl = make_config("h20")
+    rng = np.random.default_rng(52)
+    xi = rng.standard_normal((wl.n_mu, wl.n_g))
+    phi_piv = rng.standard_normal((wl.n_orb, wl.n_mu)) / np.sqrt(wl.n_orb)
+    LQ = np.zeros((wl.n_orb, wl.n_occ))
+    LQ[np.arange(wl.n_occ), np.arange(wl.n_occ)] = 1.0
+    return wl, xi, phi_piv, LQ
+
+
+H20_BRA = (70001, 72101)    # a 2048-point chunk and a 52-point tail
+
+
+def test_full_size_fp64_exchange_on_a_bra_range_matches_oracle(h20_exchange):
+    """FP64 X2, X3 at the full H20 shape over a ragged bra range against the oracle's
+    restricted sums (calG of those bra points over all 194,000 ket points)."""
+    import torch
+    from oracle import exchange
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    wl, xi, phi_piv, LQ = h20_exchange
+    b0, b1 = H20_BRA
+    note(f"h20 exchange: bra range [{b0}, {b1}), n_mu={wl.n_mu}, n_orb={wl.n_orb}, n_q={LQ.shape[1]}")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+    got = api.exchange_terms(grid, wl.corr, t(xi), t(phi_piv), t(LQ), L.XTC_FP64, bra=(b0, b1))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    note("  oracle calG over the bra range")
+    cG = exchange.calG(wl.grid_xyz, wl.grid_w, wl.corr, xi, bra=(b0, b1))
+    # the oracle's x_terms reads phi only at the pivots: pass phi_piv as the "grid" values
+    note("  oracle X over the bra range")
+    ref = exchange.x_terms(phi_piv, np.arange(wl.n_mu), xi[:, b0:b1], cG, wl.grid_w[b0:b1], LQ)
+    for k in ("X2", "X3"):
+        e = rel_err(got[k], ref[k])
+        fro = np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k])
+        note(f"  {k}: rel max err {e:.2e}, rel Frobenius {fro:.2e}")
+        assert e < 1e-10 and fro < 1e-10, k
+
+
+@pytest.fixture(scope="module")
+def h20_fitted():
+    """The H20 workload's own interpolation vectors (orbitals, fused pivots and fit on
+    the device): the value structure the split bound is stated for."""
+    import torch
+    from paper_2607_17314_amd import api
+    from workloads import make_config
+    wl = make_config("h20")
+    grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+    phi4, rho = api.eval_orbitals(wl.basis, grid, torch.as_tensor(wl.C_mo).cuda(), wl.n_occ)
+    piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
+    xi, xig, _, _ = api.fit(phi4, grid, piv)
+    phi_piv = phi4[0][:, torch.as_tensor(piv, device="cuda")].contiguous()
+    lq = torch.zeros((wl.n_orb, wl.n_occ), dtype=torch.float64, device="cuda")
+    lq[torch.arange(wl.n_occ), torch.arange(wl.n_occ)] = 1.0
+    del phi4
+    return wl, grid, xi, xig, rho, piv, phi_piv, lq
+
+
+def test_full_size_split_exchange_vs_fp64(h20_fitted):
+    """Split vs FP64 X2, X3 at the full H20 size on the workload's fitted interpolation
+    vectors, over a ragged bra range."""
+    import torch
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    wl, grid, xi, xig, rho, piv, phi_piv, lq = h20_fitted
+    note(f"h20 fitted: split vs fp64 exchange over {H20_BRA}")
+    f = api.exchange_terms(grid, wl.corr, xi, phi_piv, lq, L.XTC_FP64, bra=H20_BRA)
+    s = api.exchange_terms(grid, wl.corr, xi, phi_piv, lq, L.XTC_SPLIT_F16, bra=H20_BRA)
+    torch.cuda.synchronize()
+    for k in ("X2", "X3"):
+        e = float((s[k] - f[k]).abs().max() / f[k].abs().max())
+        fro = float(torch.linalg.norm(s[k] - f[k]) / torch.linalg.norm(f[k]))
+        note(f"  {k}: split vs fp64 rel max err {e:.2e}, rel Frobenius {fro:.2e}")
+        assert e < 1e-6 and fro < 1e-6, k
+
+
+def test_full_size_fused_pass_equals_standalone(h20_fitted):
+    """At the full H20 size, X from the fused contraction pass equals the standalone
+    call over the whole grid bit for bit, and X is symmetric in its orbital pair."""
+    import torch
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    wl, grid, xi, xig, rho, piv, phi_piv, lq = h20_fitted
+    note("h20: fused contraction + exchange")
+    fused = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, 1 | 2 | 8 | 16, L.XTC_SPLIT_F16,
+                                exchange={"phi_piv": phi_piv, "lq": lq})
+    note("h20: standalone exchange")
+    alone = api.exchange_terms(grid, wl.corr, xi, phi_piv, lq, L.XTC_SPLIT_F16)
+    torch.cuda.synchronize()
+    for k in ("X2", "X3"):
+        assert torch.equal(fused[k], alone[k]), k
+        assert torch.equal(fused[k], fused[k].transpose(0, 1)), k
+        assert bool(torch.isfinite(fused[k]).all()), k

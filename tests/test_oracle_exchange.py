@@ -72,3 +72,19 @@ def test_x_is_quadratic_in_the_correlator(fullrank):
     z = exchange.calG(wl.grid_xyz, wl.grid_w, wl.corr.with_c(0.0 * wl.corr.c), fr.xi)
     x0 = exchange.x_terms(phi4[0], fp.pivots, fr.xi, z, wl.grid_w, LQ)
     assert not np.any(x0["X2"]) and not np.any(x0["X3"])
+
+
+def test_bra_range_of_calG_and_x_is_the_restricted_sum(fullrank):
+    """calG over a bra range equals those columns of the whole-grid calG, and X over
+    two complementary bra ranges adds up to the whole-grid X."""
+    wl, phi4, fp, fr, cG = fullrank
+    w, n = wl.grid_w, wl.grid_w.shape[0]
+    cut = n // 3
+    part = exchange.calG(wl.grid_xyz, w, wl.corr, fr.xi, bra=(cut, n))
+    assert np.abs(part - cG[:, :, cut:]).max() <= 1e-14 * np.abs(cG).max()
+    LQ = exchange.density_projector(exchange.occupied_gamma(phi4.shape[1], wl.n_occ))
+    whole = exchange.x_terms(phi4[0], fp.pivots, fr.xi, cG, w, LQ)
+    a = exchange.x_terms(phi4[0], fp.pivots, fr.xi[:, :cut], cG[:, :, :cut], w[:cut], LQ)
+    b = exchange.x_terms(phi4[0], fp.pivots, fr.xi[:, cut:], part, w[cut:], LQ)
+    for k in ("X2", "X3"):
+        assert np.abs(a[k] + b[k] - whole[k]).max() <= 1e-12 * np.abs(whole[k]).max(), k
