@@ -17,6 +17,7 @@
 // and one three-segment GEMM for X3 (the three gradient channels concatenated
 // along k), in split FP16 on MFMA on the mixed path or FP64 MFMA otherwise, with
 // the quadrature weight as the per-k scale and FP64 accumulation across chunks.
+#include <climits>
 #include "bh.hpp"
 #include "contract.hpp"
 #include "exchange.hpp"
@@ -29,6 +30,7 @@ namespace xtc {
 constexpr long XSUPER = 16384;   // bra super-block of the standalone call
 constexpr long XCH = 2048;       // bra chunk of the pair products and X GEMMs
 constexpr int XOB = 64;          // orbital block of the pair kernel
+constexpr int XGB = 16;          // bra points per workgroup of the pair kernel
 
 static inline long round_to(long x, long m) { return ((x + m - 1) / m) * m; }
 
@@ -61,6 +63,12 @@ void ex_layout(Arena& ar, long n_g, long bp, int n_mu, int n_orb, int n_q, int p
   W->splitQ_bytes = split ? split_scratch_bytes(n_g, (int)nr) + rho_row_scratch_bytes(bp) : 0;
   W->splitQ = W->splitQ_bytes ? (void*)ar.take<char>(W->splitQ_bytes) : nullptr;
   W->panelR = split ? ar.take<double>((size_t)4 * W->rows_padR * bp) : nullptr;
+  // per-run exponent maxima of the pair products and the X products' A row scales
+  const long nrun = cdiv(xch, XGB);
+  W->pex_stride = nrun * W->npl;
+  W->pex = split ? ar.take<int>((size_t)2 * W->pex_stride) : nullptr;
+  W->ex2 = split ? ar.take<int>(round_to(W->npair, 128)) : nullptr;
+  W->ex3 = split ? ar.take<int>(round_to(W->npair, 128)) : nullptr;
 }
 
 struct ExLayout {
@@ -114,59 +122,106 @@ __host__ __device__ inline long pair_index(int q, int s, int n_orb) {
   return (long)q * n_orb - (long)q * (q - 1) / 2 + (s - q);
 }
 
-// Pair products of one bra point for one (q block, s block) tile of 64 x 64
-// orbitals (q block <= s block). LDS holds both blocks' rows [ch][a][orbital]
-// (ch = R^x, R^y, R^z, Q); thread (tq, ts) owns q = q0 + 4 tq + i and
-// s = s0 + ts + 16 j (i, j < 4), so a row of 16 threads stores 16 consecutive pairs.
+// Pair products for a run of XGB bra points and one (q block, s block) tile of 64 x 64
+// orbitals (q block <= s block). Per point, LDS holds both blocks' rows [ch][a][orbital]
+// (ch = R^x, R^y, R^z, Q); thread (tq, ts) owns q = q0 + 4 tq + i and s = s0 + ts + 16 j
+// (i, j < 4), so a row of 16 threads stores 16 consecutive pairs.
 // RQ: [bp][4][n_orb n_q] (point-major); T: [4][xch][npl], part stride tpart.
+// With pex != nullptr the kernel also records, per pair and per run of points, the
+// largest binary exponent of |T2 w| (pex[0]) and of |T3^c w| over c (pex[1]); zeros
+// count as INT_MIN. The split GEMM's row scales are then the maxima over the runs.
+
 template <int NQ>
 __global__ __launch_bounds__(256) void k_x_pairs(const double* __restrict__ RQ,
                                                  const int2* __restrict__ tiles, int n_orb,
-                                                 int n_q, long g0, long npl, long tpart,
-                                                 double* __restrict__ T) {
+                                                 int n_q, long g0, long cn, long npl, long tpart,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ T, int* __restrict__ pex,
+                                                 long pex_stride) {
   __shared__ double Lq[4][NQ][XOB];
   __shared__ double Ls[4][NQ][XOB];
   const int2 tl = tiles[blockIdx.x];
   const int q0 = tl.x * XOB, s0 = tl.y * XOB;
-  const long gl = blockIdx.y;              // point within the chunk
   const long nr = (long)n_orb * n_q;
-  const double* src = RQ + (g0 + gl) * 4 * nr;
-  for (int e = threadIdx.x; e < 4 * XOB * n_q; e += 256) {
-    const int ch = e / (XOB * n_q), r = e % (XOB * n_q);
-    const int o = r / n_q, a = r % n_q;
-    Lq[ch][a][o] = q0 + o < n_orb ? src[ch * nr + (long)(q0 + o) * n_q + a] : 0.0;
-    Ls[ch][a][o] = s0 + o < n_orb ? src[ch * nr + (long)(s0 + o) * n_q + a] : 0.0;
-  }
-  __syncthreads();
   const int tq = threadIdx.x >> 4, ts = threadIdx.x & 15;
-  double t2[4][4], t3[3][4][4];
+  int ex2[4][4], ex3[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      t2[i][j] = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) t3[c][i][j] = 0.0;
+    for (int j = 0; j < 4; ++j) ex2[i][j] = ex3[i][j] = INT_MIN;
+  const long gb = (long)blockIdx.y * XGB;
+  const long ge = gb + XGB < cn ? gb + XGB : cn;
+  for (long gl = gb; gl < ge; ++gl) {
+    const double* src = RQ + (g0 + gl) * 4 * nr;
+    __syncthreads();   // the previous point's rows are no longer read
+    for (int e = threadIdx.x; e < 4 * XOB * n_q; e += 256) {
+      const int ch = e / (XOB * n_q), r = e % (XOB * n_q);
+      const int o = r / n_q, a = r % n_q;
+      Lq[ch][a][o] = q0 + o < n_orb ? src[ch * nr + (long)(q0 + o) * n_q + a] : 0.0;
+      Ls[ch][a][o] = s0 + o < n_orb ? src[ch * nr + (long)(s0 + o) * n_q + a] : 0.0;
     }
-  for (int a = 0; a < n_q; ++a) {
-    double rq[4][4], rs[4][4];   // [ch][i], [ch][j]
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        rq[ch][i] = Lq[ch][a][4 * tq + i];
-        rs[ch][i] = Ls[ch][a][ts + 16 * i];
-      }
+    __syncthreads();
+    double t2[4][4], t3[3][4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
+        t2[i][j] = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          t2[i][j] = fma(rq[c][i], rs[c][j], t2[i][j]);
-          t3[c][i][j] = fma(rs[3][j], rq[c][i], fma(rs[c][j], rq[3][i], t3[c][i][j]));
+        for (int c = 0; c < 3; ++c) t3[c][i][j] = 0.0;
+      }
+    for (int a = 0; a < n_q; ++a) {
+      double rq[4][4], rs[4][4];   // [ch][i], [ch][j]
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rq[ch][i] = Lq[ch][a][4 * tq + i];
+          rs[ch][i] = Ls[ch][a][ts + 16 * i];
         }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            t2[i][j] = fma(rq[c][i], rs[c][j], t2[i][j]);
+            t3[c][i][j] = fma(rs[3][j], rq[c][i], fma(rs[c][j], rq[3][i], t3[c][i][j]));
+          }
+    }
+    const double wg = pex ? w[g0 + gl] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = q0 + 4 * tq + i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int s = s0 + ts + 16 * j;
+        if (q <= s && s < n_orb) {
+          double* out = T + gl * npl + pair_index(q, s, n_orb);
+          out[0] = t2[i][j];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[(1 + c) * tpart] = t3[c][i][j];
+          if (pex) {
+            int e;
+            double v = fabs(t2[i][j] * wg);
+            if (v > 0.0) {
+              frexp(v, &e);
+              ex2[i][j] = max(ex2[i][j], e);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              v = fabs(t3[c][i][j] * wg);
+              if (v > 0.0) {
+                frexp(v, &e);
+                ex3[i][j] = max(ex3[i][j], e);
+              }
+            }
+          }
+        }
+      }
+    }
   }
+  if (!pex) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int q = q0 + 4 * tq + i;
@@ -174,13 +229,30 @@ __global__ __launch_bounds__(256) void k_x_pairs(const double* __restrict__ RQ,
     for (int j = 0; j < 4; ++j) {
       const int s = s0 + ts + 16 * j;
       if (q <= s && s < n_orb) {
-        double* out = T + gl * npl + pair_index(q, s, n_orb);
-        out[0] = t2[i][j];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[(1 + c) * tpart] = t3[c][i][j];
+        const long k = pair_index(q, s, n_orb);
+        pex[(long)blockIdx.y * npl + k] = ex2[i][j];
+        pex[pex_stride + (long)blockIdx.y * npl + k] = ex3[i][j];
       }
     }
   }
+}
+
+// Row scales of the split X products from the per-run exponent maxima:
+// e = 15 - max_run ex (the row max times 2^e lies in [2^14, 2^15)), 0 for all-zero rows
+// and for the padding rows up to rows_pad.
+__global__ void k_pair_scales(const int* __restrict__ pex, long pex_stride, int nrun, long npair,
+                              long npl, long rows_pad, int* __restrict__ e2,
+                              int* __restrict__ e3) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= rows_pad) return;
+  int m2 = INT_MIN, m3 = INT_MIN;
+  if (k < npair)
+    for (int r = 0; r < nrun; ++r) {
+      m2 = max(m2, pex[(long)r * npl + k]);
+      m3 = max(m3, pex[pex_stride + (long)r * npl + k]);
+    }
+  e2[k] = m2 == INT_MIN ? 0 : 15 - m2;
+  e3[k] = m3 == INT_MIN ? 0 : 15 - m3;
 }
 
 __global__ void k_zero(double* __restrict__ x, long n) {
@@ -302,14 +374,23 @@ xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_
   for (long g0 = 0; g0 < bn; g0 += XCH) {
     const long cn = (bn - g0) < XCH ? (bn - g0) : XCH;
     size_t tk2 = timing_begin(TM_X_PAIRS, st);
-    dim3 gp((unsigned)W.ntile, (unsigned)cn);
+    dim3 gp((unsigned)W.ntile, cdiv(cn, XGB));
+    const bool split = W.precision == XTC_SPLIT_F16;
     if (W.n_q <= 16)
       hipLaunchKernelGGL(k_x_pairs<16>, gp, dim3(256), 0, st, (const double*)W.RQ,
-                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, W.npl, W.tpart, W.T);
+                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, cn, W.npl, W.tpart, w + b0,
+                         W.T, split ? W.pex : nullptr, W.pex_stride);
     else
       hipLaunchKernelGGL(k_x_pairs<32>, gp, dim3(256), 0, st, (const double*)W.RQ,
-                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, W.npl, W.tpart, W.T);
+                         (const int2*)W.tiles, W.n_orb, W.n_q, g0, cn, W.npl, W.tpart, w + b0,
+                         W.T, split ? W.pex : nullptr, W.pex_stride);
     XTC_CHECK_LAUNCH();
+    if (split) {
+      const long rp = round_to(W.npair, 128);
+      hipLaunchKernelGGL(k_pair_scales, dim3(cdiv(rp, 256)), dim3(256), 0, st, (const int*)W.pex,
+                         W.pex_stride, (int)cdiv(cn, XGB), W.npair, W.npl, rp, W.ex2, W.ex3);
+      XTC_CHECK_LAUNCH();
+    }
     timing_end(tk2, st);
     // Xp2 (+)= T2 diag(w) xi^T ;  Xp3 (+)= sum_c T3^c diag(w) calG^c^T
     const bool init = first && g0 == 0;
@@ -319,7 +400,7 @@ xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_
       if (W.precision == XTC_SPLIT_F16) {
         SplitSeg sg{W.T, 1, W.npl, wc, xi + b0 + g0, n_g, 1};
         XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, &sg, 1, W.Xp, n_mu, !init, W.gsplit,
-                               W.gsplit_bytes, st));
+                               W.gsplit_bytes, st, W.ex2));
       } else {
         GemmArgs g{};
         g.M = W.npair; g.N = n_mu; g.K = cn;
@@ -339,7 +420,7 @@ xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_
                          panel + (long)c * rows_pad * bp + g0, bp, 1};
       if (W.precision == XTC_SPLIT_F16) {
         XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, sg, 3, X3p, n_mu, !init, W.gsplit,
-                               W.gsplit_bytes, st));
+                               W.gsplit_bytes, st, W.ex3));
       } else {
         for (int c = 0; c < 3; ++c) {
           GemmArgs g{};

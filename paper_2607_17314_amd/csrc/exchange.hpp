@@ -14,6 +14,7 @@ struct ExWork {
   double* phia; double* P; double* RQ; double* T; double* Xp; int2* tiles;
   void* gsplit; size_t gsplit_bytes;
   double* Qf; void* splitQ; size_t splitQ_bytes; double* panelR; long rows_padR;
+  int* pex; int* ex2; int* ex3; long pex_stride;
   long npair, npl, tpart, bp, nr;
   int ntile, n_orb, n_q, n_mu, precision;
 };

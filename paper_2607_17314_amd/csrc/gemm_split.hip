@@ -235,12 +235,14 @@ void k_gemm_split_nt(const g8* __restrict__ At, const int* __restrict__ eA,
 
 // split both operands of C (+)= sum_seg A_seg diag(s_seg) B_seg^T and run the MFMA kernel
 static xtc_status split_operand(const SegOperand& o, long rows, long rows_pad, long nks,
-                                long nks_seg, int* e, g8* T, hipStream_t st) {
-  if (o.sk == 1)
+                                long nks_seg, int* e, g8* T, hipStream_t st, bool have_e) {
+  if (have_e) {
+  } else if (o.sk == 1) {
     hipLaunchKernelGGL(k_row_exp, dim3(rows_pad), dim3(256), 0, st, o, rows, e);
-  else
+  } else {
     hipLaunchKernelGGL(k_col_exp, dim3(cdiv(rows_pad, 256)), dim3(256), 0, st, o, rows, rows_pad,
                        e);
+  }
   XTC_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_split_tiles, dim3(cdiv((rows_pad / 32) * nks * 64, 256)), dim3(256), 0, st,
                      o, rows, (const int*)e, rows_pad / 32, nks, nks_seg, T);
@@ -249,7 +251,8 @@ static xtc_status split_operand(const SegOperand& o, long rows, long rows_pad, l
 }
 
 xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg, double* C,
-                          long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st) {
+                          long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st,
+                          const int* eA_given) {
   XTC_REQUIRE(nseg >= 1 && nseg <= SPLIT_MAXSEG, "split GEMM: 1 to 4 segments");
   XTC_REQUIRE(bytes >= gemm_split_seg_scratch_bytes(M, N, K, nseg), "split GEMM: scratch too small");
   SegOperand a{}, b{};
@@ -273,8 +276,9 @@ xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg,
   int* eA = ar.take<int>(Mp);
   g8* Bt = ar.take<g8>((size_t)(Np / 32) * nks * 128);
   int* eB = ar.take<int>(Np);
-  XTC_TRY(split_operand(a, M, Mp, nks, nks_seg, eA, At, st));
-  XTC_TRY(split_operand(b, N, Np, nks, nks_seg, eB, Bt, st));
+  if (eA_given) eA = const_cast<int*>(eA_given);
+  XTC_TRY(split_operand(a, M, Mp, nks, nks_seg, eA, At, st, eA_given != nullptr));
+  XTC_TRY(split_operand(b, N, Np, nks, nks_seg, eB, Bt, st, false));
   hipLaunchKernelGGL(k_gemm_split_nt, dim3(Np / ST, Mp / ST), dim3(256), 0, st, (const g8*)At,
                      (const int*)eA, (const g8*)Bt, (const int*)eB, M, N, nks, C, ldc,
                      accumulate ? 1 : 0);

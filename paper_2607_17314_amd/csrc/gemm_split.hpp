@@ -19,8 +19,11 @@ struct SplitSeg {
 // C (+)= sum_seg A_seg diag(s_seg) B_seg^T over nseg (1..4) segments of K each, one
 // MFMA launch with one FP32 medium sum over the concatenated k range; C row-major
 // with row stride ldc. scratch: gemm_split_seg_scratch_bytes(M, N, K, nseg) bytes.
+// eA: nullptr, or the A row scales already known (device, M rounded up to 128 entries:
+// max_k |A(m, k) s(k)| 2^eA[m] in [2^14, 2^15), 0 for zero and padding rows).
 xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg, double* C,
-                          long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st);
+                          long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st,
+                          const int* eA = nullptr);
 size_t gemm_split_seg_scratch_bytes(long M, long N, long K, int nseg);
 
 // C = A diag(s) B^T (beta 0) or C += A diag(s) B^T (beta 1); A [M][K] with k or m
