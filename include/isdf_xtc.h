@@ -152,6 +152,23 @@ typedef struct {
   double* X3;            /* [n_orb][n_orb][n_mu] or NULL */
 } xtc_exchange;
 
+/* Inputs of the four-index assembly (xtc_assembly_prepare, xtc_assembly_panel,
+ * xtc_one_body): the orbitals at the pivots and the ISDF intermediates of
+ * xtc_kernel_contract and xtc_exchange_terms. All pointers are device memory. */
+typedef struct {
+  int32_t n_orb, n_mu;
+  const double* phi4_piv; /* [4][n_orb][n_mu]: phi_p and d_c phi_p at the pivots */
+  const double* u1;       /* [3][n_mu][n_mu] */
+  const double* u3;       /* [n_mu][n_mu] */
+  const double* D1;       /* [n_mu][n_mu] */
+  const double* D4;       /* [n_mu][n_mu] */
+  const double* X2;       /* [n_orb][n_orb][n_mu] or NULL (taken as zero) */
+  const double* X3;       /* [n_orb][n_orb][n_mu] or NULL (taken as zero) */
+} xtc_assembly;
+
+/* Outputs of the four-index assembly (bit mask). */
+enum { XTC_ASM_K = 1, XTC_ASM_DU = 2, XTC_ASM_W = 4 };
+
 /* Thread-local message of the last failing call (valid until the next call). */
 const char* xtc_last_error(void);
 
@@ -161,11 +178,12 @@ const char* xtc_version(void);
 /* Call identifiers for xtc_workspace_bytes. */
 enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
        XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7,
-       XTC_CALL_EXCHANGE = 8 };
+       XTC_CALL_EXCHANGE = 8, XTC_CALL_ASSEMBLY = 9, XTC_CALL_ONE_BODY = 10 };
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
  * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT) or
- * the precision (EXCHANGE). n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), the
+ * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none).
+ * n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), the
  * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_orb > 0
  * asks for them), else 0. */
 size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
@@ -268,6 +286,37 @@ xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correlator* corr, 
                               int32_t n_q, const double* lq, int32_t precision,
                               int64_t bra_begin, int64_t bra_end, double* X2, double* X3,
                               void* ws, size_t ws_bytes, void* stream);
+
+/* Four-index assembly of the two-body corrections (K-kernel section, eq.
+ * K-recombine-final with eqs. K1-isdf and K3-isdf; xTC section, eq.
+ * delta-u-dx-kernels and the final assembly; Hamiltonian assembly section):
+ *   K  = 1/2 P12 [K1 - K1swap + K3],  K1swap^{pq}_{rs} = K1^{rs}_{pq},
+ *   dU = -P12 [C (D4 + 2 D1) C - C (X2 + X3)],   W = -K + dU,
+ * P12 T^{pq}_{rs} = T^{pq}_{rs} + T^{qp}_{sr}, C^p_r(mu) = phi_p phi_r (r_mu).
+ * xtc_assembly_prepare forms the pair factors and their projections once into the
+ * workspace (size: xtc_workspace_bytes(XTC_CALL_ASSEMBLY, 0, n_orb, n_mu, 0, outputs));
+ * xtc_assembly_panel then writes, for p0 <= p < p1, the panels
+ *   K, dU, W: device [p1 - p0][n_orb][n_orb][n_orb], element [p - p0][r][q][s] = T^{pq}_{rs}
+ * (electron 1's pair (p, r) first, then electron 2's (q, s)); NULL where the output is
+ * not in `outputs`. The panel call reads the prepared workspace: pass the same ws, the
+ * same inputs and the same outputs mask, unchanged since the prepare call. Panels may
+ * be computed in any order and repeated. FP64 MFMA throughout. Asynchronous. */
+xtc_status xtc_assembly_prepare(const xtc_assembly* a, uint32_t outputs, void* ws,
+                                size_t ws_bytes, void* stream);
+xtc_status xtc_assembly_panel(const xtc_assembly* a, uint32_t outputs, int32_t p0, int32_t p1,
+                              double* K, double* dU, double* W, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* xTC one-body pieces (Hamiltonian assembly section, eqs. xtc-deltah, xtc-fock,
+ * xtc-const) from partial traces over the first n_occ (occupied) orbitals, without the
+ * four-index tensors:
+ *   dh_{pq} = -1/2 sum_o (2 dU^{po}_{qo} - dU^{po}_{oq}),
+ *   f_{pq}  = dh_{pq} + sum_i (2 W^{pi}_{qi} - W^{pi}_{iq}),
+ *   e0      = -2/3 sum_i dh_{ii} + e_nuc.
+ * dh, f: device [n_orb][n_orb] or NULL; e0: host [1] or NULL (synchronising when set).
+ * Workspace: xtc_workspace_bytes(XTC_CALL_ONE_BODY, 0, n_orb, n_mu, 0, 0). FP64. */
+xtc_status xtc_one_body(const xtc_assembly* a, int32_t n_occ, double e_nuc, double* dh,
+                        double* f, double* e0, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of xtc_kernel_contract with respect to the linear coefficients c:
  * dtheta[j] = dL/dc_j for L = sum_c <gu1_c, u1_c> + <gu3, u3> + <gulap, ulap>

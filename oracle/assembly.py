@@ -77,3 +77,37 @@ def fock_xtc(dh, W, n_occ):
 
 def e0_xtc(dh, n_occ, e_nuc):
     return -2.0 / 3.0 * float(np.trace(dh[:n_occ, :n_occ])) + e_nuc
+
+
+def _k1_entry(Pm, u1, p, q, r, s):
+    """K1^{pq}_{rs} = sum_{c mu nu} u1^c_{mu nu} phi_p d_c phi_r (mu) phi_q phi_s (nu)."""
+    a = Pm[0, p] * Pm[1:4, r]                 # [c, mu]
+    b = Pm[0, q] * Pm[0, s]                   # [nu]
+    return float(np.einsum("cm,cmn,n->", a, u1, b))
+
+
+def _pair_entry(Pm, M, p, r, q, s):
+    """sum_{mu nu} C^p_r(mu) M_{mu nu} C^q_s(nu)."""
+    return float((Pm[0, p] * Pm[0, r]) @ M @ (Pm[0, q] * Pm[0, s]))
+
+
+def w_entry(phi4_piv, u1, u3, D1, D4, X, p, q, r, s):
+    """One element W^{pq}_{rs} = -K^{pq}_{rs} + dU^{pq}_{rs} from the definitions (for
+    sampled checks at sizes where the tensors are not formed). phi4_piv [4][n_orb][n_mu],
+    X [n_orb][n_orb][n_mu] or None."""
+    Pm = phi4_piv
+    D = D4 + 2.0 * D1
+
+    def s_part(p, q, r, s):      # K1 - K1swap + K3 at (p, q, r, s)
+        return (_k1_entry(Pm, u1, p, q, r, s) - _k1_entry(Pm, u1, r, s, p, q)
+                + _pair_entry(Pm, u3, p, r, q, s))
+
+    def t_part(p, q, r, s):      # C D C - C X at (p, q, r, s)
+        v = _pair_entry(Pm, D, p, r, q, s)
+        if X is not None:
+            v -= float((Pm[0, p] * Pm[0, r]) @ X[q, s])
+        return v
+
+    K = 0.5 * (s_part(p, q, r, s) + s_part(q, p, s, r))
+    dU = -(t_part(p, q, r, s) + t_part(q, p, s, r))
+    return -K + dU

@@ -254,6 +254,53 @@ def exchange_terms(grid: DeviceGrid, corr, xi, phi_piv, lq, precision: int = L.X
     return {"X2": X2, "X3": X3}
 
 
+class Assembly:
+    """Four-index assembly of K, dU and W (xtc_assembly_prepare / xtc_assembly_panel).
+    phi4_piv [4][n_orb][n_mu]; u1 [3][n_mu][n_mu]; u3, D1, D4 [n_mu][n_mu]; X2, X3
+    [n_orb][n_orb][n_mu] or None. The prepared factors live in this object's workspace."""
+
+    def __init__(self, phi4_piv, u1, u3, D1, D4, X2=None, X3=None, outputs=L.XTC_ASM_W):
+        self.t = [_in(x, n) for x, n in ((phi4_piv, "phi4_piv"), (u1, "u1"), (u3, "u3"),
+                                          (D1, "D1"), (D4, "D4"), (X2, "X2"), (X3, "X3"))]
+        phi = self.t[0]
+        self.n_orb, self.n_mu = int(phi.shape[1]), int(phi.shape[2])
+        self.outputs = outputs
+        self.s = L.Assembly(self.n_orb, self.n_mu, *[_ptr(x) for x in self.t])
+        self.ws = _workspace(workspace_bytes(L.XTC_CALL_ASSEMBLY, 0, self.n_orb, self.n_mu, 0, outputs))
+        _check("xtc_assembly_prepare", L.lib().xtc_assembly_prepare(
+            C.byref(self.s), outputs, _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def panel(self, p0: int, p1: int, out=None):
+        """{"K", "dU", "W"}: device [p1 - p0][n_orb][n_orb][n_orb], element [p - p0][r][q][s]."""
+        n = self.n_orb
+        o = {} if out is None else dict(out)
+        for k, bit in (("K", L.XTC_ASM_K), ("dU", L.XTC_ASM_DU), ("W", L.XTC_ASM_W)):
+            if self.outputs & bit:
+                if o.get(k) is None or o[k].shape[0] != p1 - p0:
+                    o[k] = torch.empty((p1 - p0, n, n, n), dtype=torch.float64, device="cuda")
+            else:
+                o[k] = None
+        _check("xtc_assembly_panel", L.lib().xtc_assembly_panel(
+            C.byref(self.s), self.outputs, p0, p1, _ptr(o["K"]), _ptr(o["dU"]), _ptr(o["W"]),
+            _ptr(self.ws), self.ws.numel(), _stream()))
+        return o
+
+
+def one_body(phi4_piv, u1, u3, D1, D4, X2, X3, n_occ: int, e_nuc: float = 0.0):
+    """xTC one-body pieces (xtc_one_body): dh, f (device [n_orb][n_orb]) and e0 (float)."""
+    t = [_in(x, n) for x, n in ((phi4_piv, "phi4_piv"), (u1, "u1"), (u3, "u3"), (D1, "D1"),
+                                (D4, "D4"), (X2, "X2"), (X3, "X3"))]
+    n_orb, n_mu = int(t[0].shape[1]), int(t[0].shape[2])
+    s = L.Assembly(n_orb, n_mu, *[_ptr(x) for x in t])
+    dh = torch.empty((n_orb, n_orb), dtype=torch.float64, device="cuda")
+    f = torch.empty_like(dh)
+    e0 = np.zeros(1, np.float64)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_ONE_BODY, 0, n_orb, n_mu, 0, 0))
+    _check("xtc_one_body", L.lib().xtc_one_body(C.byref(s), n_occ, e_nuc, _ptr(dh), _ptr(f),
+                                                _dptr(e0), _ptr(ws), ws.numel(), _stream()))
+    return dh, f, float(e0[0])
+
+
 class KernelTimer:
     """Collects the library's per-stage kernel timings (xtc_timing) over a region."""
 

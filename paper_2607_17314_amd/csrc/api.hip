@@ -32,6 +32,8 @@ extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, 
     case XTC_CALL_CONTRACT: return xtc::ws_contract(n_g, n_mu, flags, n_orb, n_aux);
     case XTC_CALL_GRAD: return xtc::ws_grad(n_g, n_mu, n_aux, flags);
     case XTC_CALL_EXCHANGE: return xtc::ws_exchange(n_g, n_orb, n_mu, n_aux, (int)flags);
+    case XTC_CALL_ASSEMBLY: return xtc::ws_assembly(n_orb, n_mu, flags);
+    case XTC_CALL_ONE_BODY: return xtc::ws_one_body(n_orb, n_mu);
     default: return 0;
   }
 }

@@ -74,3 +74,20 @@ def test_one_body_pieces_of_an_outer_product_tensor():
     assert np.allclose(f, dh + 2.0 * c * np.trace(d[:n_occ, :n_occ]) - c[:, :n_occ] @ d[:n_occ, :],
                        rtol=1e-13, atol=1e-13)
     assert assembly.e0_xtc(np.eye(n), n_occ, 1.25) == pytest.approx(-2.0 / 3.0 * n_occ + 1.25)
+
+
+def test_single_element_form_equals_the_tensors(fullrank):
+    """assembly.w_entry (used for sampled checks at large sizes) reproduces the tensor
+    assembly element by element."""
+    wl, phi4, fp, fr, out, x, ref = fullrank
+    K = assembly.k_tensor(phi4, fp.pivots, out["u1"], out["u3"])
+    dU = assembly.du_tensor(phi4, fp.pivots, out["D1"], out["D4"], x["X2"], x["X3"])
+    W = assembly.w_tensor(K, dU)
+    X = x["X2"] + x["X3"]
+    Pm = np.ascontiguousarray(phi4[:, :, fp.pivots])
+    n = phi4.shape[1]
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        p, q, r, s = (int(v) for v in rng.integers(n, size=4))
+        got = assembly.w_entry(Pm, out["u1"], out["u3"], out["D1"], out["D4"], X, p, q, r, s)
+        assert got == pytest.approx(W[p, q, r, s], rel=1e-12, abs=1e-14 * np.abs(W).max())
