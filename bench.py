@@ -41,6 +41,10 @@ def parse():
     p.add_argument("--exchange", action="store_true",
                    help="also time one step with the xTC Terms 2-3 intermediates X2, X3 formed in the "
                         "same contraction pass (low-rank projector of the occupied orbitals)")
+    p.add_argument("--assembly", action="store_true",
+                   help="also time the four-index assembly of W = -K + dU in orbital panels and the "
+                        "xTC one-body pieces (implies --exchange)")
+    p.add_argument("--panel", type=int, default=20, help="orbital panel width of the assembly")
     p.add_argument("--grad", action="store_true",
                    help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
                         "and the field (D1/D4 cotangents add one recomputation of stage 1)")
@@ -147,8 +151,11 @@ def main():
         res["adjoint_n_params"] = int(g.numel())
         res["adjoint_cotangents"] = "u1, u3, field"
         log(f"adjoint done in {res['adjoint_s']} s")
-    if a.exchange:
-        res["exchange"] = exchange_bench(wl, grid, C_mo, chans, prec, log)
+    if a.exchange or a.assembly:
+        res["exchange"], inter = exchange_bench(wl, grid, C_mo, chans, prec, log)
+        if a.assembly:
+            res["assembly"] = assembly_bench(wl, inter, a.panel, log)
+        del inter
     if a.compare_fp64 and prec != L.XTC_FP64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -204,6 +211,49 @@ def exchange_bench(wl, grid, C_mo, chans, prec, log):
            "stage_ms": {k: round(v["ms"], 2) for k, v in tm.items() if v["launches"]},
            "x_abs_max": [float(out["X2"].abs().max()), float(out["X3"].abs().max())]}
     log(f"step with exchange done in {dt:.3f} s")
+    inter = {"phi4_piv": phi4[:, :, torch.as_tensor(piv, device="cuda")].contiguous(),
+             "u1": out["u1"], "u3": out["u3"], "D1": out["D1"], "D4": out["D4"],
+             "X2": out["X2"], "X3": out["X3"]}
+    return res, inter
+
+
+def assembly_bench(wl, inter, width, log):
+    """W = -K + dU for every p in panels of `width` orbitals into one reused panel buffer
+    (FP64), after one prepare; then dh, f and E0. Per panel the product has
+    2 (width N_orb) N_orb^2 (4 N_mu) flops and writes width N_orb^3 FP64 elements."""
+    import torch
+
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    n, n_mu = wl.n_orb, inter["u3"].shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    asm = api.Assembly(inter["phi4_piv"], inter["u1"], inter["u3"], inter["D1"], inter["D4"],
+                       inter["X2"], inter["X3"], outputs=L.XTC_ASM_W)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    buf = None
+    t0 = time.perf_counter()
+    for p0 in range(0, n, width):
+        buf = asm.panel(p0, min(n, p0 + width), out=buf if buf is not None and min(n, p0 + width) - p0 == width else None)
+    torch.cuda.synchronize()
+    t_pan = time.perf_counter() - t0
+    wmax = float(buf["W"].abs().max())
+    del asm, buf
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dh, f, e0 = api.one_body(inter["phi4_piv"], inter["u1"], inter["u3"], inter["D1"], inter["D4"],
+                             inter["X2"], inter["X3"], wl.n_occ, 0.0)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    flops = 2.0 * n * n * n * n * 4 * n_mu
+    res = {"panel_width": width, "prepare_s": round(t_prep, 4), "panels_s": round(t_pan, 4),
+           "one_body_s": round(t_one, 4), "w_elements": n ** 4,
+           "panel_tflops": round(flops / t_pan / 1e12, 2),
+           "panel_write_gbs": round(8.0 * n ** 4 / t_pan / 1e9, 1),
+           "e0_minus_enuc": e0, "w_abs_max_last_panel": wmax,
+           "f_abs_max": float(f.abs().max())}
+    log(f"assembly: prepare {t_prep:.3f} s, panels {t_pan:.3f} s, one-body {t_one:.3f} s")
     return res
 
 
