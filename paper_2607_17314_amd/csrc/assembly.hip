@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_x_transpose(const double* __restrict__ 
 // every operand k-major ([k][ld], the m or n index contiguous), K = kseg per segment.
 // 128 x 128 tile of out per workgroup, 4 waves of 64 x 64 (4 x 4 blocks of
 // v_mfma_f64_16x16x4f64), k-tiles of 16 through LDS with the next tile prefetched in
-// registers. A k-tile may straddle two segments: each element finds its own segment.
+// registers. The k loop runs over (segment, k-tile) pairs, so the segment, its
+// pointers and coefficient are uniform per tile; a segment's last tile is zero-padded.
 struct AsmSegs {
   const double* R[4];
   const double* S[4];
@@ -143,39 +144,41 @@ struct AsmSegs {
 
 constexpr int AT = 128, AK = 16, ALD = AT + 2;
 
-__global__ __launch_bounds__(256) void k_asm_panel(AsmSegs sg, long M, long N,
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_asm_panel(AsmSegs sg, long M, long N,
                                                    double* __restrict__ out, long ldc) {
   __shared__ double As[AK][ALD];
   __shared__ double Bs[AK][ALD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const long m0 = (long)blockIdx.y * AT, n0 = (long)blockIdx.x * AT;
-  const long Kt = sg.kseg * sg.nseg;
+  const int tps = (int)((sg.kseg + AK - 1) / AK);   // k-tiles per segment
+  const int ntiles = tps * sg.nseg;
+  const int ld = (int)sg.ld;                          // n_orb^2 < 2^31
+  const int mlim = (int)(M - m0 < AT ? M - m0 : AT), nlim = (int)(N - n0 < AT ? N - n0 : AT);
   double ra[8], rb[8];
-  auto load = [&](long k0) {
+  auto load = [&](int t) {
+    const int s = t / tps;
+    const int k0 = (t - s * tps) * AK;
+    const int kl = (int)sg.kseg - k0;                 // rows left in this segment
+    const double* Rt = sg.R[s] + (long)k0 * sg.ld + sg.m_off + m0;
+    const double* St = sg.S[s] + (long)k0 * sg.ld + n0;
+    const double c = sg.coef[s];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int e = tid + 256 * j;
-      const int mm = e % AT, kk = e / AT;
-      const long k = k0 + kk;
-      double va = 0.0, vb = 0.0;
-      if (k < Kt) {
-        const int s = (int)(k / sg.kseg);
-        const long kl = k - (long)s * sg.kseg;
-        const long m = m0 + mm, n = n0 + mm;
-        if (m < M) va = sg.coef[s] * sg.R[s][kl * sg.ld + sg.m_off + m];
-        if (n < N) vb = sg.S[s][kl * sg.ld + n];
-      }
-      ra[j] = va;
-      rb[j] = vb;
+      const int mm = e & (AT - 1), kk = e >> 7;
+      const bool kin = kk < kl;
+      ra[j] = (kin && mm < mlim) ? c * Rt[kk * ld + mm] : 0.0;
+      rb[j] = (kin && mm < nlim) ? St[kk * ld + mm] : 0.0;
     }
   };
   auto stash = [&]() {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int e = tid + 256 * j;
-      As[e / AT][e % AT] = ra[j];
-      Bs[e / AT][e % AT] = rb[j];
+      As[e >> 7][e & (AT - 1)] = ra[j];
+      Bs[e >> 7][e & (AT - 1)] = rb[j];
     }
   };
   d4v acc[4][4];
@@ -185,11 +188,11 @@ __global__ __launch_bounds__(256) void k_asm_panel(AsmSegs sg, long M, long N,
     for (int j = 0; j < 4; ++j) acc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
   const int li = lane & 15, lk = lane >> 4;
   load(0);
-  for (long k0 = 0; k0 < Kt; k0 += AK) {
+  for (int t = 0; t < ntiles; ++t) {
     __syncthreads();
     stash();
     __syncthreads();
-    if (k0 + AK < Kt) load(k0 + AK);
+    if (t + 1 < ntiles) load(t + 1);
 #pragma unroll
     for (int s = 0; s < AK / 4; ++s) {
       double a[4], b[4];
