@@ -156,6 +156,12 @@ def main():
         if a.assembly:
             res["assembly"] = assembly_bench(wl, inter, a.panel, log)
         del inter
+        if not a.no_cpu_baseline:
+            log("timing the CPU oracle sample of the exchange intermediates")
+            res["exchange"]["cpu_baseline"] = exchange_cpu_baseline(wl, 128)
+            if a.assembly:
+                log("timing the CPU oracle sample of the assembly")
+                res["assembly"]["cpu_baseline"] = assembly_cpu_baseline(wl, 1)
     if a.compare_fp64 and prec != L.XTC_FP64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -210,6 +216,15 @@ def exchange_bench(wl, grid, C_mo, chans, prec, log):
            "x_part_tflops": round((fx + frq) / (x_ms * 1e-3) / 1e12, 2),
            "stage_ms": {k: round(v["ms"], 2) for k, v in tm.items() if v["launches"]},
            "x_abs_max": [float(out["X2"].abs().max()), float(out["X3"].abs().max())]}
+    xm = tm["x_mfma"]
+    if xm["launches"]:
+        ach = fx / (xm["ms"] * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "split X-product kernel (k_gemm_split_nt)",
+                           "achieved": round(ach, 2), "peak": PEAKS["f16"], "unit": "TFLOP/s",
+                           "frac": round(ach / PEAKS["f16"], 4),
+                           "executed_mfma_frac": round(3.0 * ach / PEAKS["f16"], 4), "traffic": None,
+                           "launch_ms": round(xm["ms"] / xm["launches"], 3),
+                           "launches": xm["launches"]}
     log(f"step with exchange done in {dt:.3f} s")
     inter = {"phi4_piv": phi4[:, :, torch.as_tensor(piv, device="cuda")].contiguous(),
              "u1": out["u1"], "u3": out["u3"], "D1": out["D1"], "D4": out["D4"],
@@ -233,11 +248,13 @@ def assembly_bench(wl, inter, width, log):
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t0
     buf = None
-    t0 = time.perf_counter()
-    for p0 in range(0, n, width):
-        buf = asm.panel(p0, min(n, p0 + width), out=buf if buf is not None and min(n, p0 + width) - p0 == width else None)
-    torch.cuda.synchronize()
-    t_pan = time.perf_counter() - t0
+    with api.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        for p0 in range(0, n, width):
+            p1 = min(n, p0 + width)
+            buf = asm.panel(p0, p1, out=buf if buf is not None and p1 - p0 == width else None)
+        torch.cuda.synchronize()
+        t_pan = time.perf_counter() - t0
     wmax = float(buf["W"].abs().max())
     del asm, buf
     torch.cuda.synchronize()
@@ -253,8 +270,64 @@ def assembly_bench(wl, inter, width, log):
            "panel_write_gbs": round(8.0 * n ** 4 / t_pan / 1e9, 1),
            "e0_minus_enuc": e0, "w_abs_max_last_panel": wmax,
            "f_abs_max": float(f.abs().max())}
+    ap = kt.result["asm_panel"]
+    if ap["launches"]:
+        ach = flops / (ap["ms"] * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "assembly panel kernel (k_asm_panel)",
+                           "achieved": round(ach, 2), "peak": PEAKS["fp64"], "unit": "TFLOP/s",
+                           "frac": round(ach / PEAKS["fp64"], 4), "traffic": None,
+                           "launch_ms": round(ap["ms"] / ap["launches"], 3),
+                           "launches": ap["launches"]}
     log(f"assembly: prepare {t_prep:.3f} s, panels {t_pan:.3f} s, one-body {t_one:.3f} s")
     return res
+
+
+def exchange_cpu_baseline(wl, n_bra):
+    """The oracle's exchange intermediates on a bounded sample: calG of n_bra bra points
+    over every ket point and X2, X3 over those bra points, on seeded inputs of the
+    workload's shapes. Work counted as on the GPU: the X products (8 N_pair N_mu per bra
+    point) and calG (6 N_mu per grid pair)."""
+    import numpy as np
+
+    from oracle import exchange as oex
+    n_mu, n, nq = wl.n_mu, wl.n_orb, wl.n_occ
+    rng = np.random.default_rng(0)
+    xi = rng.standard_normal((n_mu, wl.n_g))
+    phi = rng.standard_normal((n, n_mu)) / np.sqrt(n)
+    LQ = np.zeros((n, nq))
+    LQ[np.arange(nq), np.arange(nq)] = 1.0
+    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    cG = oex.calG(wl.grid_xyz, wl.grid_w, wl.corr, xi, bra=(0, n_bra))
+    oex.x_terms(phi, np.arange(n_mu), xi[:, :n_bra], cG, wl.grid_w[:n_bra], LQ)
+    dt = time.perf_counter() - t0
+    npair = n * (n + 1) // 2
+    flops = (8.0 * npair * n_mu + 6.0 * n_mu * wl.n_g) * n_bra
+    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"calG and X2, X3 over {n_bra} bra points x {wl.n_g} ket points, N_mu={n_mu}, "
+                      f"{n} orbitals, n_q={nq}; {dt:.1f} s"}
+
+
+def assembly_cpu_baseline(wl, n_p=1):
+    """The oracle's W panel for n_p orbitals (assembly.w_panel, from the definitions) on
+    seeded inputs of the workload's shapes; work counted as on the GPU,
+    2 n_p N_orb^3 4 N_mu flops."""
+    import numpy as np
+
+    from oracle import assembly as oasm
+    n_mu, n = wl.n_mu, wl.n_orb
+    rng = np.random.default_rng(1)
+    phi = rng.standard_normal((4, n, n_mu)) / np.sqrt(n)
+    u1 = rng.standard_normal((3, n_mu, n_mu)) / n_mu
+    u3, D1, D4 = (rng.standard_normal((n_mu, n_mu)) / n_mu for _ in range(3))
+    X = rng.standard_normal((n, n, n_mu)) / n_mu
+    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oasm.w_panel(phi, u1, u3, D1, D4, X, 0, n_p)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * n_p * n ** 3 * 4 * n_mu
+    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"W panel of {n_p} of {n} orbitals, N_mu={n_mu}; {dt:.1f} s"}
 
 
 def cpu_baseline(wl, n_mu, n_bra):

@@ -340,9 +340,10 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * 6 MLP, 7 split-operand preparation, 8 the stage-1 pair kernel alone (one entry
  * per kernel launch), 9 exchange projections and pair products, 10 exchange X
  * products (operand splitting included), 11 the exchange's stage 1 on the projected
- * rows (split path).
+ * rows (split path), 12 the exchange's split X-product kernel alone (one entry per
+ * launch), 13 the assembly panel kernel (one entry per launch).
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 12
+#define XTC_TIMING_CATEGORIES 14
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

@@ -111,3 +111,27 @@ def w_entry(phi4_piv, u1, u3, D1, D4, X, p, q, r, s):
     K = 0.5 * (s_part(p, q, r, s) + s_part(q, p, s, r))
     dU = -(t_part(p, q, r, s) + t_part(q, p, s, r))
     return -K + dU
+
+
+def w_panel(phi4_piv, u1, u3, D1, D4, X, p0, p1):
+    """W^{pq}_{rs} for p0 <= p < p1 from the definitions (array [p - p0, q, r, s]), at sizes
+    where the full tensors are not formed. phi4_piv [4][n_orb][n_mu], X [n_orb][n_orb][n_mu]
+    or None."""
+    C = np.einsum("pm,rm->prm", phi4_piv[0], phi4_piv[0])
+    Ct = np.einsum("pm,crm->cprm", phi4_piv[0], phi4_piv[1:4])
+    Cp, Ctp = C[p0:p1], Ct[:, p0:p1]                       # p restricted
+    D = D4 + 2.0 * D1
+    # S^{pq}_{rs} = K1^{pq}_{rs} - K1^{rs}_{pq} + K3^{pq}_{rs}
+    S = (np.einsum("cmn,cprm,qsn->pqrs", u1, Ctp, C, optimize=True)
+         - np.einsum("cmn,crpm,sqn->pqrs", u1, Ct[:, :, p0:p1], C, optimize=True)
+         + np.einsum("mn,prm,qsn->pqrs", u3, Cp, C, optimize=True))
+    # S^{qp}_{sr} = K1^{qp}_{sr} - K1^{sr}_{qp} + K3^{qp}_{sr}
+    Sx = (np.einsum("cmn,cqsm,prn->pqrs", u1, Ct, Cp, optimize=True)
+          - np.einsum("cmn,csqm,rpn->pqrs", u1, Ct, C[:, p0:p1], optimize=True)
+          + np.einsum("mn,qsm,prn->pqrs", u3, C, Cp, optimize=True))
+    T = np.einsum("mn,prm,qsn->pqrs", D, Cp, C, optimize=True)
+    Tx = np.einsum("mn,qsm,prn->pqrs", D, C, Cp, optimize=True)
+    if X is not None:
+        T = T - np.einsum("prm,qsm->pqrs", Cp, X, optimize=True)
+        Tx = Tx - np.einsum("qsm,prm->pqrs", C, X[p0:p1], optimize=True)
+    return -0.5 * (S + Sx) - (T + Tx)

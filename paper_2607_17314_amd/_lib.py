@@ -131,4 +131,4 @@ EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_or
             "xtc_exchange_terms", "xtc_assembly_prepare", "xtc_assembly_panel", "xtc_one_body",
             "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
-                     "stage1_kernel", "x_pairs", "x_gemm", "x_stage1"]
+                     "stage1_kernel", "x_pairs", "x_gemm", "x_stage1", "x_mfma", "asm_panel"]

@@ -16,6 +16,7 @@
 // occupied orbitals, formed from the same factors without the four-index tensors.
 #include "common.hpp"
 #include "plans.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -409,7 +410,9 @@ extern "C" xtc_status xtc_assembly_panel(const xtc_assembly* a, uint32_t outputs
     if (!(outputs & o.bit)) continue;
     AsmSegs s = segs_for(L, o.P, o.a, o.b, o.x, a->n_mu);
     s.m_off = (long)p0 * n;
+    const size_t tk = timing_begin(TM_ASM_PANEL, st);
     hipLaunchKernelGGL(k_asm_panel, grid, dim3(256), 0, st, s, M, N, o.dst, N);
+    timing_end(tk, st);
     XTC_CHECK_LAUNCH();
   }
   return XTC_OK;

@@ -400,7 +400,7 @@ xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_
       if (W.precision == XTC_SPLIT_F16) {
         SplitSeg sg{W.T, 1, W.npl, wc, xi + b0 + g0, n_g, 1};
         XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, &sg, 1, W.Xp, n_mu, !init, W.gsplit,
-                               W.gsplit_bytes, st, W.ex2));
+                               W.gsplit_bytes, st, W.ex2, TM_X_MFMA));
       } else {
         GemmArgs g{};
         g.M = W.npair; g.N = n_mu; g.K = cn;
@@ -420,7 +420,7 @@ xtc_status ex_block(ExWork& W, const EECoef& cf, const double* panel, long rows_
                          panel + (long)c * rows_pad * bp + g0, bp, 1};
       if (W.precision == XTC_SPLIT_F16) {
         XTC_TRY(gemm_split_seg(W.npair, n_mu, cn, sg, 3, X3p, n_mu, !init, W.gsplit,
-                               W.gsplit_bytes, st, W.ex3));
+                               W.gsplit_bytes, st, W.ex3, TM_X_MFMA));
       } else {
         for (int c = 0; c < 3; ++c) {
           GemmArgs g{};

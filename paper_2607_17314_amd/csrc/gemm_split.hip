@@ -19,6 +19,7 @@
 // current one is multiplied; scheduling fences keep those loads in place.
 #include "common.hpp"
 #include "gemm_split.hpp"
+#include "timing.hpp"
 
 namespace xtc {
 
@@ -252,7 +253,7 @@ static xtc_status split_operand(const SegOperand& o, long rows, long rows_pad, l
 
 xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg, double* C,
                           long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st,
-                          const int* eA_given) {
+                          const int* eA_given, int timing_category) {
   XTC_REQUIRE(nseg >= 1 && nseg <= SPLIT_MAXSEG, "split GEMM: 1 to 4 segments");
   XTC_REQUIRE(bytes >= gemm_split_seg_scratch_bytes(M, N, K, nseg), "split GEMM: scratch too small");
   SegOperand a{}, b{};
@@ -279,9 +280,11 @@ xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg,
   if (eA_given) eA = const_cast<int*>(eA_given);
   XTC_TRY(split_operand(a, M, Mp, nks, nks_seg, eA, At, st, eA_given != nullptr));
   XTC_TRY(split_operand(b, N, Np, nks, nks_seg, eB, Bt, st, false));
+  const size_t tk = timing_category >= 0 ? timing_begin(timing_category, st) : (size_t)-1;
   hipLaunchKernelGGL(k_gemm_split_nt, dim3(Np / ST, Mp / ST), dim3(256), 0, st, (const g8*)At,
                      (const int*)eA, (const g8*)Bt, (const int*)eB, M, N, nks, C, ldc,
                      accumulate ? 1 : 0);
+  timing_end(tk, st);
   XTC_CHECK_LAUNCH();
   return XTC_OK;
 }

@@ -23,7 +23,7 @@ struct SplitSeg {
 // max_k |A(m, k) s(k)| 2^eA[m] in [2^14, 2^15), 0 for zero and padding rows).
 xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg, double* C,
                           long ldc, bool accumulate, void* scratch, size_t bytes, hipStream_t st,
-                          const int* eA = nullptr);
+                          const int* eA = nullptr, int timing_category = -1);
 size_t gemm_split_seg_scratch_bytes(long M, long N, long K, int nseg);
 
 // C = A diag(s) B^T (beta 0) or C += A diag(s) B^T (beta 1); A [M][K] with k or m

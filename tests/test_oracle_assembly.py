@@ -91,3 +91,14 @@ def test_single_element_form_equals_the_tensors(fullrank):
         p, q, r, s = (int(v) for v in rng.integers(n, size=4))
         got = assembly.w_entry(Pm, out["u1"], out["u3"], out["D1"], out["D4"], X, p, q, r, s)
         assert got == pytest.approx(W[p, q, r, s], rel=1e-12, abs=1e-14 * np.abs(W).max())
+
+
+def test_panel_form_equals_the_tensors(fullrank):
+    """assembly.w_panel (the bounded-sample form) reproduces the tensor assembly."""
+    wl, phi4, fp, fr, out, x, ref = fullrank
+    K = assembly.k_tensor(phi4, fp.pivots, out["u1"], out["u3"])
+    dU = assembly.du_tensor(phi4, fp.pivots, out["D1"], out["D4"], x["X2"], x["X3"])
+    W = assembly.w_tensor(K, dU)
+    Pm = np.ascontiguousarray(phi4[:, :, fp.pivots])
+    got = assembly.w_panel(Pm, out["u1"], out["u3"], out["D1"], out["D4"], x["X2"] + x["X3"], 1, 3)
+    assert np.abs(got - W[1:3]).max() <= 1e-12 * np.abs(W).max()
