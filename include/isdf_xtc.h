@@ -323,12 +323,14 @@ xtc_status xtc_one_body(const xtc_assembly* a, int32_t n_occ, double e_nuc, doub
  * + <gD1, D1> + <gD4, D4> + <gfield, field>. Cotangents: device, shapes of the
  * matching outputs, NULL when absent. Kernel tiles are regenerated, never stored;
  * the D cotangents add one recomputation pass of calG.
- * dtheta: device [n_types * n_terms] (output). FP64. Asynchronous. */
+ * dtheta: device [n_types * n_terms] (output). dd: device [1] or NULL; with the EE
+ * form it receives dL/dd for the scale d of rbar = d r / (1 + d r), a nonlinear
+ * parameter (XTC_ERR_UNSUPPORTED for the BH form). FP64. Asynchronous. */
 xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                     const double* xi, const double* xigrad, const double* rho,
                     const int64_t* pivots, const double* gu1, const double* gu3,
                     const double* gulap, const double* gD1, const double* gD4,
-                    const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
+                    const double* gfield, double* dtheta, double* dd, void* ws, size_t ws_bytes,
                     void* stream);
 
 /* Kernel timing for measurement: HIP events recorded on the call's stream around

@@ -97,3 +97,24 @@ def dL_dc(xyz, w, corr, xi, xigrad, G, rho, cot: dict, bra_block: int = 128, ket
                     s += np.sum(cot["field"][:, b0:b1] * dfld[j])
                 grad[j] += s
     return grad
+
+
+def loss(out: dict, cot: dict) -> complex:
+    """L = sum over the cotangent keys of <cot[k], out[k]>."""
+    return sum(np.sum(cot[k] * out[k]) for k in ("u1", "u3", "ulap", "D1", "D4", "field")
+               if cot.get(k) is not None)
+
+
+def dL_dd(xyz, w, corr, xi, xigrad, G, rho, cot: dict, h: float = 1e-30):
+    """dL/dd for the EE correlator scale d (rbar = d r / (1 + d r)) by the complex step:
+    L(d + i h) = L(d) + i h L'(d) - h^2 L''(d)/2 + ..., so L'(d) = Im L(d + i h) / h with
+    no subtractive cancellation. The contraction is carried with a complex d."""
+    from dataclasses import replace
+
+    from .contract import contract
+    ch = 0
+    for k, bit in (("u1", 1), ("u3", 2), ("ulap", 4), ("D1", 8), ("D4", 16), ("field", 32)):
+        if cot.get(k) is not None:
+            ch |= bit
+    out = contract(xyz, w, replace(corr, d=corr.d + 1j * h), xi, xigrad, G, rho, ch)
+    return float(np.imag(loss(out, cot)) / h)

@@ -41,27 +41,30 @@ def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
     """All outputs of the docstring above. bra_range = (start, stop) restricts the
     sum over bra points g to that range (used to time a sample of the work)."""
     n_mu, n_g = xi.shape
+    # accumulators take the type of the correlator's d: a complex d carries a complex
+    # step through every sum (the derivative in d, see adjoint.dL_dd)
+    dt = np.result_type(float, corr.d)
     lap = bool(channels & ULAP)
     need_g = bool(channels & (U1 | D1 | D4))
     wxi = xi * w[None, :]
     wrho = w * rho
     out = {}
-    u1 = np.zeros((3, n_mu, n_mu)) if channels & U1 else None
-    u3 = np.zeros((n_mu, n_mu)) if channels & U3 else None
-    ul = np.zeros((n_mu, n_mu)) if lap else None
-    d1 = np.zeros((n_mu, n_mu)) if channels & D1 else None
-    d4 = np.zeros((n_mu, n_mu)) if channels & D4 else None
-    field = np.zeros((3, n_g))
-    t3rho = np.zeros(n_g)
+    u1 = np.zeros((3, n_mu, n_mu), dt) if channels & U1 else None
+    u3 = np.zeros((n_mu, n_mu), dt) if channels & U3 else None
+    ul = np.zeros((n_mu, n_mu), dt) if lap else None
+    d1 = np.zeros((n_mu, n_mu), dt) if channels & D1 else None
+    d4 = np.zeros((n_mu, n_mu), dt) if channels & D4 else None
+    field = np.zeros((3, n_g), dt)
+    t3rho = np.zeros(n_g, dt)
     def stage1(b0):
         """Stage 1 for one bra block: sums over every ket point."""
         b1 = min(hi, b0 + bra_block)
         nb = b1 - b0
-        calG = np.zeros((3, n_mu, nb))
-        T3 = np.zeros((n_mu, nb))
-        TL = np.zeros((n_mu, nb)) if lap else None
-        fld = np.zeros((3, nb))
-        t3r = np.zeros(nb)
+        calG = np.zeros((3, n_mu, nb), dt)
+        T3 = np.zeros((n_mu, nb), dt)
+        TL = np.zeros((n_mu, nb), dt) if lap else None
+        fld = np.zeros((3, nb), dt)
+        t3r = np.zeros(nb, dt)
         for k0 in range(0, n_g, ket_block):
             k1 = min(n_g, k0 + ket_block)
             K = pair_kernels(corr, xyz[:, b0:b1], xyz[:, k0:k1], want_lap=lap)
@@ -105,15 +108,15 @@ def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
     if channels & FIELD:
         out["field"] = field
     if channels & ESCALE:
-        e = np.zeros(6)
+        e = np.zeros(6, dt)
         if u3 is not None:
             e[0] = G @ u3 @ G
         if d4 is not None:
             e[1] = G @ d4 @ G
         if d1 is not None:
             e[2] = 2.0 * (G @ d1 @ G)
-        e[3] = float(np.dot(wrho, t3rho))
-        e[4] = float(np.dot(wrho, np.einsum("cg,cg->g", field, field)))
+        e[3] = np.dot(wrho, t3rho)
+        e[4] = np.dot(wrho, np.einsum("cg,cg->g", field, field))
         e[5] = 2.0 * e[4]
         out["escale"] = e
     return out

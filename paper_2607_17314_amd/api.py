@@ -320,24 +320,26 @@ class KernelTimer:
         return False
 
 
-def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None):
+def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None, want_d=False):
     """dL/dc for L = sum over the given cotangents <cot[k], output k> (xtc_grad).
     cot keys: u1, u3, ulap, D1, D4, field (device tensors of the outputs' shapes).
-    Returns a float64 device tensor [n_types * n_terms]."""
+    Returns a float64 device tensor [n_types * n_terms]; with want_d (EE form) also
+    dL/dd as a float64 device tensor [1]: (dtheta, dd)."""
     hc = HostCorrelator(corr, c)
     xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]
     cv = {k: _in(cot.get(k), k) for k in ("u1", "u3", "ulap", "D1", "D4", "field")}
     out = torch.empty(hc.c.size, dtype=torch.float64, device="cuda")
+    dd = torch.empty(1, dtype=torch.float64, device="cuda") if want_d else None
     flags = 1 if cv["ulap"] is not None else 0
     ws = _workspace(workspace_bytes(L.XTC_CALL_GRAD, grid.n_g, 0, n_mu, hc.c.size, flags))
     g = grid.c()
     _check("xtc_grad", L.lib().xtc_grad(
         C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
         _ptr(cv["u1"]), _ptr(cv["u3"]), _ptr(cv["ulap"]), _ptr(cv["D1"]), _ptr(cv["D4"]),
-        _ptr(cv["field"]), _ptr(out), _ptr(ws), ws.numel(), _stream()))
-    return out
+        _ptr(cv["field"]), _ptr(out), _ptr(dd), _ptr(ws), ws.numel(), _stream()))
+    return (out, dd) if want_d else out
 
 
 _OUT_KEYS = ("u1", "u3", "ulap", "D1", "D4", "field")

@@ -32,6 +32,8 @@ struct GradBasis {
   int n;               // parameters
   int o[MAXQ];         // powers
   int omax;
+  int want_d;          // also dL/dd (slot n)
+  double c[MAXQ];      // the coefficients (for dL/dd)
 };
 
 // Per-pair contribution to dL/dc_k for every k, given M for the NCH channels.
@@ -52,22 +54,37 @@ __device__ __forceinline__ void pair_grad(const EECoef& cf, const GradBasis& gb,
   double ep[MAXQ + 1];
   ep[0] = 1.0;
   for (int j = 1; j <= gb.omax; ++j) ep[j] = ep[j - 1] * e;
+  double dd = 0.0;
   for (int k = 0; k < gb.n; ++k) {
     const int o = gb.o[k];
     double fk = 0.0, upk = 0.0, lapk = 0.0;
+    double fd = 0.0, upd = 0.0, lapd = 0.0;   // d/dd of the unit-coefficient kernels
     if (o >= 2) {
       fk = d * d * t3 * o * ep[o - 2];
       upk = d * t2 * o * ep[o - 1];
       lapk = d * d * t4 * o * (o - 1) * ep[o - 2] - 2.0 * d * d * t3 * o * ep[o - 1] + 2.0 * fk;
+      if (gb.want_d) {
+        // d/dd [d^2 t^3 e^m] = d t^3 e^m (2 - 3e + m t), d/dd [d t^2 e^m] = t^2 e^m (1 - 2e + m t),
+        // d/dd [d^2 t^4 e^m] = d t^4 e^m (2 - 4e + m t)   (t' = -r t^2, e' = r t^2)
+        fd = o * d * t3 * ep[o - 2] * (2.0 - 3.0 * e + (o - 2) * t);
+        upd = o * t2 * ep[o - 1] * (1.0 - 2.0 * e + (o - 1) * t);
+        lapd = o * (o - 1) * d * t4 * ep[o - 2] * (2.0 - 4.0 * e + (o - 2) * t) -
+               2.0 * o * d * t3 * ep[o - 1] * (2.0 - 3.0 * e + (o - 1) * t) + 2.0 * fd;
+      }
     } else if (o == 1) {
       upk = d * t2;
+      upd = t2 * (1.0 - 2.0 * e);
       if (r > 0.0) {
         fk = d * t2 / r;
         lapk = -2.0 * d * d * t3 + 2.0 * fk;
+        fd = t2 * (1.0 / r - 2.0 * d * t);
+        lapd = -2.0 * d * t3 * (2.0 - 3.0 * e) + 2.0 * fd;
       }
     }
     dth[k] += sf * fk + s3 * upk + s4 * lapk;
+    dd += gb.c[k] * (sf * fd + s3 * upd + s4 * lapd);
   }
+  if (gb.want_d) dth[gb.n] += dd;
 }
 
 template <int NCH>
@@ -80,7 +97,7 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
   __shared__ double As[GK][GT + 1];        // A rows x ket
   __shared__ double bxyz[3][GT];
   __shared__ double kxyz[3][GT];
-  __shared__ double red[4][MAXQ];
+  __shared__ double red[4][MAXQ + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -95,8 +112,8 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
     bxyz[1][tid] = xyz[n_g + b];
     bxyz[2][tid] = xyz[2 * n_g + b];
   }
-  double dth[MAXQ];
-  for (int k = 0; k < MAXQ; ++k) dth[k] = 0.0;
+  double dth[MAXQ + 1];
+  for (int k = 0; k <= MAXQ; ++k) dth[k] = 0.0;
 
   for (long kc = k_lo; kc < k_hi; kc += GT) {
     __syncthreads();
@@ -164,17 +181,18 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
                          bxyz[2][bi] - kxyz[2][kj], m, dth);
         }
   }
-  // deterministic block reduction of the parameter partials
-  for (int k = 0; k < gb.n; ++k) {
+  // deterministic block reduction of the parameter partials (and dL/dd in slot n)
+  const int nout = gb.n + gb.want_d;
+  for (int k = 0; k < nout; ++k) {
     double v = dth[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) red[wave][k] = v;
   }
   __syncthreads();
-  if (tid < gb.n) {
+  if (tid < nout) {
     const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
-    partials[blk * MAXQ + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    partials[blk * (MAXQ + 1) + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
   }
 }
 
@@ -536,8 +554,8 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
                                const double* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, const double* gu1, const double* gu3,
                                const double* gulap, const double* gD1, const double* gD4,
-                               const double* gfield, double* dtheta, void* ws, size_t ws_bytes,
-                               void* stream) {
+                               const double* gfield, double* dtheta, double* dd, void* ws,
+                               size_t ws_bytes, void* stream) {
   XTC_REQUIRE(grid && corr && xi && rho && pivots && dtheta, "xtc_grad: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "xtc_grad: empty grid");
   XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "xtc_grad: bad n_mu");
@@ -551,6 +569,10 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "xtc_grad: pivot index out of range");
   if (bh && gulap) {
     set_error("xtc_grad: the Laplacian channel is defined for the EE form only");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  if (bh && dd) {
+    set_error("xtc_grad: dL/dd is available for the EE form only");
     return XTC_ERR_UNSUPPORTED;
   }
   EECoef cf;
@@ -585,8 +607,10 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   gb.d = corr->d;
   if (!bh) {
     gb.n = corr->n_terms;
+    gb.want_d = dd ? 1 : 0;
     for (int k = 0; k < gb.n; ++k) {
       gb.o[k] = corr->mno[3 * k + 2];
+      gb.c[k] = corr->c[k];
       if (gb.o[k] > gb.omax) gb.omax = gb.o[k];
     }
   }
@@ -679,7 +703,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
       XTC_CHECK_LAUNCH();
     }
     dim3 gridp(cdiv(bn, GT), KSEG);
-    const int stride = bh ? ZS : MAXQ;
+    const int stride = bh ? ZS : MAXQ + 1;
     double* part = L.partials + (long)sb * L.nblk * stride;
     if (bh && bt.n_types == 1)
       hipLaunchKernelGGL(k_grad_pairs_bh<1>, gridp, dim3(256), 0, st, (const double*)L.Pb,
@@ -711,7 +735,10 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
                        (const double*)L.zsum, (const BHParamMap*)L.pmap, n_params, dtheta);
   } else {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
-                       (long)L.nsb * L.nblk, gb.n, MAXQ, dtheta);
+                       (long)L.nsb * L.nblk, gb.n + gb.want_d, MAXQ + 1, L.zsum);
+    XTC_CHECK_LAUNCH();
+    XTC_HIP(hipMemcpyAsync(dtheta, L.zsum, sizeof(double) * gb.n, hipMemcpyDeviceToDevice, st));
+    if (dd) XTC_HIP(hipMemcpyAsync(dd, L.zsum + gb.n, sizeof(double), hipMemcpyDeviceToDevice, st));
   }
   XTC_CHECK_LAUNCH();
   timing_end(tk, st);

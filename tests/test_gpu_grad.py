@@ -77,3 +77,43 @@ def test_adjoint_matches_central_differences_and_autograd(problem):
     note(f"autograd {g_auto} vs central FD {fd}: rel err {err:.2e}")
     # every output is a polynomial of degree <= 2 in c: central differences are exact up to rounding
     assert err < 1e-7
+
+
+@pytest.mark.parametrize("subset", ["all", "u1u3", "D-only"])
+def test_scale_derivative_matches_oracle(problem, subset):
+    """dL/dd for the nonlinear scale d of rbar against the oracle's complex-step
+    derivative of its own contraction, and against Richardson-extrapolated central
+    differences of the device forward pass; dL/dc is unchanged by asking for dL/dd."""
+    import torch
+    from dataclasses import replace
+    from oracle import adjoint
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, cot = problem
+    keys = {"all": list(cot), "u1u3": ["u1", "u3", "field"], "D-only": ["D1", "D4"]}[subset]
+    c_sub = {k: cot[k] for k in keys}
+    ref = adjoint.dL_dd(xyz, w, wl.corr, fr.xi, fr.xigrad, rho[piv], rho, c_sub)
+    grid, xi, xig, rh, dcot = _device(api, problem)
+    dc = {k: dcot[k] for k in keys}
+    g_c, g_d = api.grad(grid, wl.corr, xi, xig, rh, piv, dc, want_d=True)
+    g_only = api.grad(grid, wl.corr, xi, xig, rh, piv, dc)
+    torch.cuda.synchronize()
+    got = float(g_d.cpu()[0])
+    err = abs(got - ref) / abs(ref)
+    note(f"dL/dd {subset}: device {got:.15e}, oracle {ref:.15e}, rel err {err:.2e}")
+    assert err < 1e-10
+    assert torch.equal(g_c, g_only)
+    if subset != "all":
+        return
+    bits = {"u1": 1, "u3": 2, "ulap": 4, "D1": 8, "D4": 16, "field": 32}
+    ch = sum(bits[k] for k in keys)
+
+    def L(d):
+        out = api.kernel_contract(grid, replace(wl.corr, d=d), xi, xig, rh, piv, ch)
+        return sum(float(torch.sum(dc[k] * out[k])) for k in keys)
+
+    d0, h = wl.corr.d, 1e-3
+    fd1 = (L(d0 + h) - L(d0 - h)) / (2 * h)
+    fd2 = (L(d0 + 2 * h) - L(d0 - 2 * h)) / (4 * h)
+    rich = (4.0 * fd1 - fd2) / 3.0
+    note(f"  Richardson central difference {rich:.15e}")
+    assert abs(rich - got) <= 1e-8 * abs(got)

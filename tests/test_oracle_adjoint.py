@@ -52,3 +52,36 @@ def test_adjoint_matches_central_differences(h6_small, form):
         lm = _loss(contract.contract(xyz, w, corr.with_c(cm), xi, xig, G, rho, chans), cot)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[j]) <= 1e-7 * max(1.0, abs(g[j])), (j, fd, g[j])
+
+
+def test_scale_derivative_complex_step_equals_richardson_differences(h2_tiny):
+    """The oracle's dL/dd (complex step through its contraction, every channel) against
+    Richardson-extrapolated central differences of real contractions (O(h^4))."""
+    from dataclasses import replace
+    from oracle import adjoint, contract, fit, orbitals, pivots
+    wl = h2_tiny
+    phi4 = orbitals.eval_orbitals(wl.basis, wl.C_mo, wl.grid_xyz)
+    fp = pivots.select_fused(phi4, wl.grid_w, 10)
+    fr = fit.fit(phi4, wl.grid_w, fp.pivots)
+    rho = orbitals.density(phi4, wl.n_occ)
+    G = rho[fp.pivots]
+    n = len(fp.pivots)
+    rng = np.random.default_rng(3)
+    cot = {"u1": rng.normal(size=(3, n, n)), "u3": rng.normal(size=(n, n)),
+           "ulap": rng.normal(size=(n, n)), "D1": rng.normal(size=(n, n)),
+           "D4": rng.normal(size=(n, n)), "field": rng.normal(size=(3, wl.n_g))}
+    cs = adjoint.dL_dd(wl.grid_xyz, wl.grid_w, wl.corr, fr.xi, fr.xigrad, G, rho, cot)
+
+    def L(d):
+        out = contract.contract(wl.grid_xyz, wl.grid_w, replace(wl.corr, d=d), fr.xi, fr.xigrad,
+                                G, rho, 1 | 2 | 4 | 8 | 16 | 32)
+        return adjoint.loss(out, cot)
+
+    d0, h = wl.corr.d, 1e-3
+    fd1 = (L(d0 + h) - L(d0 - h)) / (2 * h)
+    fd2 = (L(d0 + 2 * h) - L(d0 - 2 * h)) / (4 * h)
+    rich = (4.0 * fd1 - fd2) / 3.0
+    assert abs(rich - cs) <= 1e-10 * abs(cs)
+    # a real d gives real outputs (the complex path leaves the real one unchanged)
+    out = contract.contract(wl.grid_xyz, wl.grid_w, wl.corr, fr.xi, fr.xigrad, G, rho, 1 | 2)
+    assert out["u1"].dtype == np.float64
