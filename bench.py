@@ -45,6 +45,11 @@ def parse():
                    help="also time the four-index assembly of W = -K + dU in orbital panels and the "
                         "xTC one-body pieces (implies --exchange)")
     p.add_argument("--panel", type=int, default=20, help="orbital panel width of the assembly")
+    p.add_argument("--kernel-sample", default=None, metavar="CONFIG",
+                   help="also time the split contraction (u3, D1, D4, field) of CONFIG (e.g. benzene) "
+                        "on a bra shard of --sample-blocks super-blocks against the full ket range, "
+                        "with seeded interpolation vectors of that shape")
+    p.add_argument("--sample-blocks", type=int, default=2)
     p.add_argument("--grad", action="store_true",
                    help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
                         "and the field (D1/D4 cotangents add one recomputation of stage 1)")
@@ -162,6 +167,8 @@ def main():
             if a.assembly:
                 log("timing the CPU oracle sample of the assembly")
                 res["assembly"]["cpu_baseline"] = assembly_cpu_baseline(wl, 1)
+    if a.kernel_sample:
+        res["kernel_sample"] = kernel_sample(a.kernel_sample, a.sample_blocks, log)
     if a.compare_fp64 and prec != L.XTC_FP64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -279,6 +286,55 @@ def assembly_bench(wl, inter, width, log):
                            "launch_ms": round(ap["ms"] / ap["launches"], 3),
                            "launches": ap["launches"]}
     log(f"assembly: prepare {t_prep:.3f} s, panels {t_pan:.3f} s, one-body {t_one:.3f} s")
+    return res
+
+
+def kernel_sample(config, nblk, log):
+    """Stage 1 + stage 2 of the split contraction at another workload's shape on a bra
+    shard of nblk super-blocks of 16,384 points against every ket point: the work one
+    GPU does when the bra index is sharded. The interpolation vectors are seeded N(0,1)
+    rows of the right shape (the kernels' cost does not depend on their values)."""
+    import numpy as np
+    import torch
+
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    from workloads import make_config
+    log(f"building the {config} workload")
+    wl = make_config(config)
+    n_g, n_mu = wl.n_g, wl.n_mu
+    grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    xi = torch.randn((n_mu, n_g), dtype=torch.float64, device="cuda", generator=gen)
+    rho = torch.rand(n_g, dtype=torch.float64, device="cuda", generator=gen)
+    piv = np.sort(np.random.default_rng(7).choice(n_g, n_mu, replace=False))
+    nb = min(n_g, nblk * 16384)
+    ch = L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD
+    log(f"{config}: split contraction over bra points [0, {nb}) of {n_g}, N_mu={n_mu}")
+    torch.cuda.synchronize()
+    with api.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        api.kernel_contract(grid, wl.corr, xi, None, rho, piv, ch, L.XTC_SPLIT_F16, bra=(0, nb))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    tm = kt.result
+    s1 = tm["stage1_kernel"]
+    pairs = float(nb) * n_g
+    per_launch = 8.0 * n_mu * pairs / s1["launches"]
+    ach = per_launch / (s1["ms"] / s1["launches"] * 1e-3) / 1e12
+    res = {"workload": f"{config}: {n_g} grid points, {wl.n_orb} orbitals, N_mu={n_mu}",
+           "bra_points": nb, "ket_points": n_g, "time_s": round(dt, 3),
+           "stage_ms": {k: round(v["ms"], 2) for k, v in tm.items() if v["launches"]},
+           "stage1_full_grid_estimate_s": round(tm["stage1"]["ms"] * 1e-3 * n_g / nb, 1),
+           "roofline": {"bound": "mfma", "kernel": "stage-1 pair kernel (k_stage1_split)",
+                        "achieved": round(ach, 2), "peak": PEAKS["f16"], "unit": "TFLOP/s",
+                        "frac": round(ach / PEAKS["f16"], 4),
+                        "executed_mfma_frac": round(3.0 * ach / PEAKS["f16"], 4), "traffic": None,
+                        "launch_ms": round(s1["ms"] / s1["launches"], 3),
+                        "launches": s1["launches"]}}
+    log(f"{config} sample done in {dt:.2f} s")
+    del xi
     return res
 
 

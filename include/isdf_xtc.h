@@ -248,6 +248,10 @@ xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
  *   E4 = G^T D4 G, E1 = 2 G^T D1 G and their ISDF-free counterparts
  *   E3x = sum_{g,g'} w w' rho rho' |grad_1 u|^2, E4x = sum_g w rho |A_gamma|^2, E1x = 2 E4x.
  * precision: XTC_FP64 or XTC_SPLIT_F16.
+ * [bra_begin, bra_end): the bra points g summed over (non-empty, inside the grid; the ket
+ *   sums always cover the whole grid). (0, n_g) gives the outputs above; disjoint ranges
+ *   give partial sums that add up to them (the bra sharding across devices); field is
+ *   written for the range and zero elsewhere, and escale holds the range's partial sums.
  * ex: NULL, or the exchange intermediates X2, X3 of xTC Terms 2 and 3 to form in the
  *   same pass from the same calG panels (Alg. 2, xTC-correction step; definitions at
  *   xtc_exchange_terms); with ex the workspace query takes n_orb = ex->n_orb and
@@ -256,9 +260,10 @@ xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
 xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                                const double* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, uint32_t channels, int32_t precision,
-                               double* u1, double* u3, double* ulap, double* D1, double* D4,
-                               double* field, double* escale, const xtc_exchange* ex, void* ws,
-                               size_t ws_bytes, void* stream);
+                               int64_t bra_begin, int64_t bra_end, double* u1, double* u3,
+                               double* ulap, double* D1, double* D4, double* field,
+                               double* escale, const xtc_exchange* ex, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Exchange intermediates of xTC Terms 2 and 3 through the low-rank projector
  * (xTC section, "Terms 2 and 3 (non-factorizable)", "Low-rank projector for Terms

@@ -93,8 +93,8 @@ def lib() -> C.CDLL:
                            C.c_size_t, P]
     L.xtc_kernel_contract.restype = st
     L.xtc_kernel_contract.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64,
-                                      C.c_uint32, C.c_int32, P, P, P, P, P, P, D,
-                                      C.POINTER(Exchange), P, C.c_size_t, P]
+                                      C.c_uint32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P,
+                                      P, D, C.POINTER(Exchange), P, C.c_size_t, P]
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, P, P, P, P,
                            P, P, P, P, P, C.c_size_t, P]

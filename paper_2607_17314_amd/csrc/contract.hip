@@ -189,14 +189,22 @@ static xtc_status check_contract_args(const xtc_grid* grid, const xtc_correlator
   return XTC_OK;
 }
 
+__global__ void k_fill_zero(double* __restrict__ x, long n) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) x[t] = 0.0;
+}
+
 extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
                                           int32_t n_mu, const double* xi, const double* xigrad,
                                           const double* rho, const int64_t* pivots,
-                                          uint32_t channels, int32_t precision, double* u1,
+                                          uint32_t channels, int32_t precision, int64_t bra_begin,
+                                          int64_t bra_end, double* u1,
                                           double* u3, double* ulap, double* D1, double* D4,
                                           double* field, double* escale, const xtc_exchange* ex,
                                           void* ws, size_t ws_bytes, void* stream) {
   XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+  XTC_REQUIRE(bra_begin >= 0 && bra_begin < bra_end && bra_end <= grid->n_g,
+              "contract: bra range must be non-empty and inside the grid");
   if (ex) XTC_TRY(check_exchange_args(ex, n_mu));
   XTC_REQUIRE(!(channels & XTC_U1) || u1, "contract: u1 output NULL");
   XTC_REQUIRE(!(channels & XTC_U3) || u3, "contract: u3 output NULL");
@@ -239,9 +247,15 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
     timing_end(tk, st);
   }
   const bool need_h = (channels & (XTC_D1 | XTC_D4)) != 0;
-  for (int sb = 0; sb < C.nsb; ++sb) {
-    const long b0 = (long)sb * C.bp;
-    const long bn = (n_g - b0) < C.bp ? (n_g - b0) : C.bp;
+  if ((channels & XTC_FIELD) && (bra_begin > 0 || bra_end < n_g)) {
+    // the field is written for the bra points of the range only
+    hipLaunchKernelGGL(k_fill_zero, dim3(cdiv(3 * n_g, 256)), dim3(256), 0, st, field, 3 * n_g);
+    XTC_CHECK_LAUNCH();
+  }
+  const int nsb = (int)cdiv(bra_end - bra_begin, C.bp);
+  for (int sb = 0; sb < nsb; ++sb) {
+    const long b0 = bra_begin + (long)sb * C.bp;
+    const long bn = (bra_end - b0) < C.bp ? (bra_end - b0) : C.bp;
     s1.b0 = b0;
     s1.bn = bn;
     size_t tk = timing_begin(TM_STAGE1, st);
@@ -300,11 +314,11 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   }
   if (ex) XTC_TRY(ex_finish(C.ex, ex->X2, ex->X3, false, st));
   if (channels & XTC_ESCALE) {
-    std::vector<double> hs(4 * C.nsb);
-    XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 4 * C.nsb, hipMemcpyDeviceToHost, st));
+    std::vector<double> hs(4 * nsb);
+    XTC_HIP(hipMemcpyAsync(hs.data(), C.sums, sizeof(double) * 4 * nsb, hipMemcpyDeviceToHost, st));
     XTC_HIP(hipStreamSynchronize(st));
     double e3x = 0.0, e4x = 0.0, e3 = 0.0, e4 = 0.0;
-    for (int sb = 0; sb < C.nsb; ++sb) {
+    for (int sb = 0; sb < nsb; ++sb) {
       e3x += hs[4 * sb];
       e4x += hs[4 * sb + 1];
       e3 += hs[4 * sb + 2];

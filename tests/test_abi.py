@@ -57,20 +57,26 @@ def test_host_argument_checks_return_invalid_arg():
     # pivots out of range are rejected before any launch
     piv[:] = [0, 1, 2, 99]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
-                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, None, None, None, None, None,
+                                 piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, None, None, None, None, None,
                                  None, None, None, 0, None)
     assert st == -1 and b"pivot" in lib.xtc_last_error()
     # unknown precision
     piv[:] = [0, 1, 2, 3]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
-                                 piv.ctypes.data_as(L.I64), 2, 7, xyz, None, None, None, None, None,
+                                 piv.ctypes.data_as(L.I64), 2, 7, 0, 10, xyz, None, None, None, None, None,
                                  None, None, None, 0, None)
     assert st == -1
     # a too-small workspace is reported as such, not as a crash
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
-                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, xyz, None, None, None, None,
+                                 piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, xyz, None, None, None, None,
                                  None, None, None, 0, None)
     assert st == -4
+    # an empty or out-of-grid bra range is rejected
+    for b0, b1 in ((5, 5), (0, 11), (-1, 4)):
+        st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
+                                     piv.ctypes.data_as(L.I64), 2, 0, b0, b1, None, xyz, None, None,
+                                     None, None, None, None, None, 0, None)
+        assert st == -1 and b"bra range" in lib.xtc_last_error()
 
 
 def test_exchange_argument_checks_return_invalid_arg():
@@ -105,6 +111,6 @@ def test_exchange_argument_checks_return_invalid_arg():
     piv = np.arange(4, dtype=np.int64)
     exs = L.Exchange(6, xyz, 40, xyz, xyz, None)
     st = lib.xtc_kernel_contract(C.byref(g), C.byref(corr), 4, xyz, xyz, xyz,
-                                 piv.ctypes.data_as(L.I64), 2, 0, xyz, None, None, None, None, None,
+                                 piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, None, None, None, None, None,
                                  None, C.byref(exs), None, 0, None)
     assert st == -1 and b"rank" in lib.xtc_last_error()

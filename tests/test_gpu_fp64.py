@@ -151,3 +151,30 @@ def test_zero_correlator_gives_zeros(api, ragged_case):
                               case.piv, ALL, c=np.zeros(case.wl.corr.c.size))
     for k in ("u1", "u3", "D1", "D4", "field"):
         assert float(out[k].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+def test_contract_bra_ranges_add_up(api, ragged_case, precision):
+    """Partial sums over disjoint bra ranges (the bra sharding) add up to the whole-grid
+    outputs; the field of a range is the whole-grid field there and zero elsewhere."""
+    import torch
+    case = ragged_case
+    grid = _grid(api, case)
+    xi = torch.as_tensor(case.fit.xi).cuda()
+    xig = torch.as_tensor(case.fit.xigrad).cuda()
+    rho = torch.as_tensor(case.rho).cuda()
+    n = grid.n_g
+    cut = 1777
+    full = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL, precision)
+    lo = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL, precision, bra=(0, cut))
+    hi = api.kernel_contract(grid, case.wl.corr, xi, xig, rho, case.piv, ALL, precision, bra=(cut, n))
+    torch.cuda.synchronize()
+    for k in ("u1", "u3", "D1", "D4"):
+        e = float((lo[k] + hi[k] - full[k]).abs().max() / full[k].abs().max())
+        note(f"  {k}: range sum vs whole grid {e:.2e}")
+        assert e < (1e-13 if precision == 0 else 1e-6), k
+    assert torch.equal(lo["field"][:, :cut], full["field"][:, :cut])
+    assert float(lo["field"][:, cut:].abs().max()) == 0.0
+    assert torch.equal(hi["field"][:, cut:], full["field"][:, cut:])
+    es = lo["escale"] + hi["escale"]
+    assert np.allclose(es, full["escale"], rtol=1e-12 if precision == 0 else 1e-6, atol=0.0)
