@@ -328,9 +328,13 @@ xtc_status xtc_one_body(const xtc_assembly* a, int32_t n_occ, double e_nuc, doub
  * + <gD1, D1> + <gD4, D4> + <gfield, field>. Cotangents: device, shapes of the
  * matching outputs, NULL when absent. Kernel tiles are regenerated, never stored;
  * the D cotangents add one recomputation pass of calG.
- * dtheta: device [n_types * n_terms] (output). dd: device [1] or NULL; with the EE
- * form it receives dL/dd for the scale d of rbar = d r / (1 + d r), a nonlinear
- * parameter (XTC_ERR_UNSUPPORTED for the BH form). FP64. Asynchronous. */
+ * dtheta: device [n_types * n_terms] (output). dd: device or NULL; it receives the
+ * derivatives with respect to the nonlinear parameters: for the EE form [1] = dL/dd
+ * for the scale d of rbar = d r / (1 + d r); for the BH form [1 + n_types] =
+ * dL/dd, then dL/db_t for the scale b_t of a_I = b r_I / (1 + b r_I) on the nuclei of
+ * type t (eq. bh-u). Asking for dd leaves dtheta unchanged; for the BH form it runs a
+ * separate kernel variant (more registers) so the dd = NULL path keeps its own.
+ * FP64. Asynchronous. */
 xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                     const double* xi, const double* xigrad, const double* rho,
                     const int64_t* pivots, const double* gu1, const double* gu3,

@@ -105,10 +105,35 @@ def loss(out: dict, cot: dict) -> complex:
                if cot.get(k) is not None)
 
 
+def dL_dnl(xyz, w, corr, xi, xigrad, G, rho, cot: dict, h: float = 1e-30):
+    """Derivatives of L with respect to the nonlinear correlator parameters, by the complex
+    step: L(p + i h) = L(p) + i h L'(p) - h^2 L''(p)/2 + ..., so L'(p) = Im L(p + i h) / h
+    with no subtractive cancellation; the contraction is carried in complex arithmetic.
+    Returns [dL/dd] for the EE form (rbar = d r / (1 + d r)) and
+    [dL/dd, dL/db_0, ..., dL/db_{n_types - 1}] for the BH form (a_I = b r_I / (1 + b r_I))."""
+    from dataclasses import replace
+
+    from .contract import contract
+    ch = 0
+    for k, bit in (("u1", 1), ("u3", 2), ("ulap", 4), ("D1", 8), ("D4", 16), ("field", 32)):
+        if cot.get(k) is not None:
+            ch |= bit
+
+    def step(c):
+        out = contract(xyz, w, c, xi, xigrad, G, rho, ch)
+        return float(np.imag(loss(out, cot)) / h)
+
+    res = [step(replace(corr, d=corr.d + 1j * h))]
+    if corr.form != 0:
+        for t in range(len(corr.b)):
+            b = np.asarray(corr.b, dtype=complex).copy()
+            b[t] += 1j * h
+            res.append(step(replace(corr, b=b)))
+    return np.array(res)
+
+
 def dL_dd(xyz, w, corr, xi, xigrad, G, rho, cot: dict, h: float = 1e-30):
-    """dL/dd for the EE correlator scale d (rbar = d r / (1 + d r)) by the complex step:
-    L(d + i h) = L(d) + i h L'(d) - h^2 L''(d)/2 + ..., so L'(d) = Im L(d + i h) / h with
-    no subtractive cancellation. The contraction is carried with a complex d."""
+    """dL/dd alone (dL_dnl's first entry)."""
     from dataclasses import replace
 
     from .contract import contract

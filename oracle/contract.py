@@ -41,9 +41,9 @@ def contract(xyz, w, corr, xi, xigrad, G, rho, channels: int,
     """All outputs of the docstring above. bra_range = (start, stop) restricts the
     sum over bra points g to that range (used to time a sample of the work)."""
     n_mu, n_g = xi.shape
-    # accumulators take the type of the correlator's d: a complex d carries a complex
-    # step through every sum (the derivative in d, see adjoint.dL_dd)
-    dt = np.result_type(float, corr.d)
+    # accumulators take the type of the correlator's d and b: a complex value carries a
+    # complex step through every sum (the derivatives in d and b, see adjoint.dL_dnl)
+    dt = np.result_type(float, corr.d, np.asarray(corr.b if corr.b is not None else 0.0))
     lap = bool(channels & ULAP)
     need_g = bool(channels & (U1 | D1 | D4))
     wxi = xi * w[None, :]

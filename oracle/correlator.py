@@ -118,8 +118,10 @@ def _bh(corr, X1, X2, D, r):
     e = d * r * t
     zero = r == 0.0
     rs = np.where(zero, 1.0, r)
-    N = np.zeros((3,) + r.shape)
-    S = np.zeros_like(r)
+    # sums take the type of d and b: a complex step in either is carried through
+    dt = np.result_type(float, d, np.asarray(corr.b))
+    N = np.zeros((3,) + r.shape, dt)
+    S = np.zeros(r.shape, dt)
     for I in range(corr.nuc_xyz.shape[0]):
         ty = int(corr.nuc_type[I])
         b = corr.b[ty]

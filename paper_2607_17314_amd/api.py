@@ -325,15 +325,17 @@ class KernelTimer:
 def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None, want_d=False):
     """dL/dc for L = sum over the given cotangents <cot[k], output k> (xtc_grad).
     cot keys: u1, u3, ulap, D1, D4, field (device tensors of the outputs' shapes).
-    Returns a float64 device tensor [n_types * n_terms]; with want_d (EE form) also
-    dL/dd as a float64 device tensor [1]: (dtheta, dd)."""
+    Returns a float64 device tensor [n_types * n_terms]; with want_d also the
+    nonlinear-parameter derivatives as a float64 device tensor, (dtheta, dd):
+    [dL/dd] for the EE form, [dL/dd, dL/db_0, ..., dL/db_{n_types-1}] for the BH form."""
     hc = HostCorrelator(corr, c)
     xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]
     cv = {k: _in(cot.get(k), k) for k in ("u1", "u3", "ulap", "D1", "D4", "field")}
     out = torch.empty(hc.c.size, dtype=torch.float64, device="cuda")
-    dd = torch.empty(1, dtype=torch.float64, device="cuda") if want_d else None
+    n_nl = 1 if int(corr.form) == 0 else 1 + hc.c.shape[0]
+    dd = torch.empty(n_nl, dtype=torch.float64, device="cuda") if want_d else None
     flags = 1 if cv["ulap"] is not None else 0
     ws = _workspace(workspace_bytes(L.XTC_CALL_GRAD, grid.n_g, 0, n_mu, hc.c.size, flags))
     g = grid.c()

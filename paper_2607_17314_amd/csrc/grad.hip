@@ -208,15 +208,16 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
 // Z[t][m][n][o] accumulates the (m, n) half of both sums; the parameter is
 // Z[t][m][n][o] + Z[t][n][m][o]. The (0, 0, o) terms need only the nucleus-free sum
 // Zee[o] = sum W o rbar^{o-1} d t^2 (times 2 per nucleus of the type).
-constexpr int ZS = BH_MAXTYPE * 64 + MAXQ + 1;   // BH partial stride
+// BH partial stride: [types x 64 Z][MAXQ + 1 Zee][dL/dd, dL/db_t per type]
+constexpr int ZS = BH_MAXTYPE * 64 + MAXQ + 1 + 1 + BH_MAXTYPE;
 
-template <int NT>
+template <int NT, bool NL>
 __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __restrict__ T,
                                              const double (*Cs)[BH_NP][BH_NP][BH_NO],
                                              int nn, const double (*TB)[4][GT], int bi,
                                              const double (*TA)[GT], int kj, double dx, double dy,
                                              double dz, const double* m, double* z, double* zee,
-                                             int omax_ee) {
+                                             int omax_ee, double* znl) {
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
   const double t = 1.0 / (1.0 + cf.d * r);
   const double e = cf.d * r * t;
@@ -270,6 +271,21 @@ __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __
   }
   const double wd = W * dedr;
   const double ES[BH_NO] = {0.0, wd, 2.0 * e * wd, 3.0 * e * e * wd};
+  if (NL) {
+    // d: rbar' = r t^2, (d t^2)' = t^2 (1 - 2 rbar); N' = sum_o o rbar^{o-1} rbar' grad F_o,
+    // S' = (d t^2)' (F_1 + 2 rbar F_2 + 3 rbar^2 F_3 + U'_ee) + d t^2 rbar' (2 F_2 + 6 rbar F_3 + U''_ee)
+    const double de_dd = r * t * t;
+    const double d_dedr = t * t * (1.0 - 2.0 * e);
+    double p1p = 0.0;
+    for (int j = cf.n1 - 1; j >= 1; --j) p1p = p1p * e + j * cf.q1[j];
+    const double inner = F[1] + 2.0 * e * F[2] + 3.0 * e * e * F[3] + p1;
+    const double dS = d_dedr * inner + dedr * de_dd * (2.0 * F[2] + 6.0 * e * F[3] + p1p);
+    double vdn = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      vdn += V[c] * de_dd * (GF[1][c] + 2.0 * e * GF[2][c] + 3.0 * e * e * GF[3][c]);
+    znl[0] += vdn + W * dS;
+  }
   // electron-electron (0, 0, o) terms: W o e^{o-1} d t^2
   {
     double ep = 1.0;   // e^{o-1}
@@ -297,12 +313,41 @@ __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __
 #pragma unroll
           for (int n = 0; n < BH_NP; ++n) z[tt * 64 + mm * 16 + n * 4 + o] += u * A2[n];
         }
+      if (NL) {
+        // b of this nucleus' type: a' = a (1 - a) / b, (grad a)' = (1 - 2 a) / b grad a;
+        // dL/db += q sum_o rbar^o (grad F_o)'/grad a + W d t^2 sum_o o rbar^{o-1} F_o'
+        const double b = T->nuc[I][3];
+        const double da1 = a1 * (1.0 - a1) / b, da2 = a2 * (1.0 - a2) / b;
+        const double kg = (1.0 - 2.0 * a1) / b;
+        const double dA2[BH_NP] = {0.0, 1.0, 2.0 * a2, 3.0 * a2 * a2};
+        const double ddA1[BH_NP] = {0.0, 0.0, 2.0, 6.0 * a1};
+        double acc = 0.0;
+#pragma unroll
+        for (int o = 0; o < BH_NO; ++o) {
+          double dF = 0.0, dG = 0.0;
+#pragma unroll
+          for (int mm = 0; mm < BH_NP; ++mm) {
+            double g = 0.0, dg = 0.0;
+#pragma unroll
+            for (int n = 0; n < BH_NP; ++n) {
+              g += Cs[tt][mm][n][o] * A2[n];
+              dg += Cs[tt][mm][n][o] * dA2[n];
+            }
+            dg *= da2;
+            dF += dA1[mm] * da1 * g + A1[mm] * dg;
+            dG += ddA1[mm] * da1 * g + dA1[mm] * dg + kg * dA1[mm] * g;
+          }
+          acc += q * E[o] * dG + ES[o] * dF;
+        }
+        znl[1 + tt] += acc;
+      }
     }
   }
 }
 
-// M tiles exactly as k_grad_pairs (four channels), then the BH per-pair adjoint.
-template <int NT>
+// M tiles exactly as k_grad_pairs (four channels), then the BH per-pair adjoint; NL adds
+// the derivatives with respect to d and the b of each nucleus type.
+template <int NT, bool NL>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int n_rows,
                      const double* __restrict__ xi, const double* __restrict__ rho,
@@ -351,6 +396,9 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
   double zee[MAXQ + 1];
 #pragma unroll
   for (int k = 0; k <= MAXQ; ++k) zee[k] = 0.0;
+  double znl[1 + NT];
+#pragma unroll
+  for (int k = 0; k <= NT; ++k) znl[k] = 0.0;
 
   for (long kc = k_lo; kc < k_hi; kc += GT) {
     __syncthreads();
@@ -417,16 +465,18 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
           double mv[NCH];
 #pragma unroll
           for (int c = 0; c < NCH; ++c) mv[c] = acc[c][i][j][r];
-          pair_grad_bh<NT>(cf, T, Cs, nn, TB, bi, TA, kj, bxyz[0][bi] - kxyz[0][kj],
+          pair_grad_bh<NT, NL>(cf, T, Cs, nn, TB, bi, TA, kj, bxyz[0][bi] - kxyz[0][kj],
                            bxyz[1][bi] - kxyz[1][kj], bxyz[2][bi] - kxyz[2][kj], mv, z, zee,
-                           omax_ee);
+                           omax_ee, znl);
         }
   }
-  // deterministic block reduction: [NT * 64 Z entries][MAXQ + 1 Zee entries]
+  // deterministic block reduction: [NT * 64 Z entries][MAXQ + 1 Zee entries][1 + NT nonlinear]
   __syncthreads();
+  constexpr int NRED = NT * 64 + MAXQ + 1 + (NL ? 1 + NT : 0);
 #pragma unroll
-  for (int k = 0; k < NT * 64 + MAXQ + 1; ++k) {
-    double v = k < NT * 64 ? z[k] : zee[k - NT * 64];
+  for (int k = 0; k < NRED; ++k) {
+    double v = k < NT * 64 ? z[k] : (k < NT * 64 + MAXQ + 1 ? zee[k - NT * 64]
+                                                            : znl[k - NT * 64 - MAXQ - 1]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) red[wave][k] = v;
@@ -434,8 +484,7 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
   __syncthreads();
   const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
   for (int k = tid; k < ZS; k += 256) {
-    const double v = k < NT * 64 + MAXQ + 1
-                         ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
+    const double v = k < NRED ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
     partials[blk * ZS + k] = v;
   }
 }
@@ -571,10 +620,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     set_error("xtc_grad: the Laplacian channel is defined for the EE form only");
     return XTC_ERR_UNSUPPORTED;
   }
-  if (bh && dd) {
-    set_error("xtc_grad: dL/dd is available for the EE form only");
-    return XTC_ERR_UNSUPPORTED;
-  }
+
   EECoef cf;
   BHTable bt;
   int omax_ee = 0;
@@ -705,14 +751,17 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     dim3 gridp(cdiv(bn, GT), KSEG);
     const int stride = bh ? ZS : MAXQ + 1;
     double* part = L.partials + (long)sb * L.nblk * stride;
-    if (bh && bt.n_types == 1)
-      hipLaunchKernelGGL(k_grad_pairs_bh<1>, gridp, dim3(256), 0, st, (const double*)L.Pb,
-                         L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,
-                         grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part);
-    else if (bh)
-      hipLaunchKernelGGL(k_grad_pairs_bh<2>, gridp, dim3(256), 0, st, (const double*)L.Pb,
-                         L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,
-                         grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part);
+    if (bh) {
+#define XTC_LAUNCH_BH(NTV, NLV)                                                                  \
+  hipLaunchKernelGGL((k_grad_pairs_bh<NTV, NLV>), gridp, dim3(256), 0, st, (const double*)L.Pb,    \
+                     L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,        \
+                     grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part)
+      if (bt.n_types == 1 && !dd) XTC_LAUNCH_BH(1, false);
+      else if (bt.n_types == 1) XTC_LAUNCH_BH(1, true);
+      else if (!dd) XTC_LAUNCH_BH(2, false);
+      else XTC_LAUNCH_BH(2, true);
+#undef XTC_LAUNCH_BH
+    }
     else if (L.nch == 4)
       hipLaunchKernelGGL(k_grad_pairs<4>, gridp, dim3(256), 0, st, (const double*)L.Pb, L.rows_pad,
                          L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w, grid->xyz, n_g,
@@ -733,6 +782,9 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     XTC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_bh_params, dim3(cdiv(n_params, 256)), dim3(256), 0, st,
                        (const double*)L.zsum, (const BHParamMap*)L.pmap, n_params, dtheta);
+    if (dd)
+      XTC_HIP(hipMemcpyAsync(dd, L.zsum + bt.n_types * 64 + MAXQ + 1,
+                             sizeof(double) * (1 + bt.n_types), hipMemcpyDeviceToDevice, st));
   } else {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
                        (long)L.nsb * L.nblk, gb.n + gb.want_d, MAXQ + 1, L.zsum);

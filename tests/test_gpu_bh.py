@@ -135,3 +135,56 @@ def test_bh_adjoint_matches_central_differences(bh_small):
         fd = (L(cp) - L(cm)) / (2 * h)
         note(f"  dL/dc[{j}]: adjoint {g[j]:.12e}, central difference {fd:.12e}")
         assert abs(g[j] - fd) <= 1e-7 * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("types", [1, 2])
+def test_bh_nonlinear_derivatives_match_oracle(bh_small, types):
+    """dL/dd and dL/db_t (eq. bh-u) against the oracle's complex-step derivatives of its own
+    contraction; dL/dc is unchanged by asking for them (a separate kernel variant)."""
+    import torch
+    from oracle import adjoint
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, corr, cot = bh_small
+    if types == 2:
+        corr = _two_type(corr)
+    ref = adjoint.dL_dnl(xyz, w, corr, fr.xi, fr.xigrad, rho[piv], rho, cot)
+    grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    dc = {k: t(v) for k, v in cot.items()}
+    g_c, g_nl = api.grad(grid, corr, xi, xig, rh, piv, dc, want_d=True)
+    g_only = api.grad(grid, corr, xi, xig, rh, piv, dc)
+    torch.cuda.synchronize()
+    got = g_nl.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    note(f"BH nonlinear derivatives, {types} type(s): device {got}, oracle {ref}, rel err {err:.2e}")
+    assert got.shape == (1 + types,)
+    assert err < 1e-10
+    assert torch.allclose(g_c, g_only, rtol=1e-13, atol=1e-15 * float(g_only.abs().max()))
+
+
+def test_bh_nonlinear_derivatives_match_richardson_differences(bh_small):
+    """dL/db_0 and dL/dd against Richardson-extrapolated central differences of the
+    device forward pass."""
+    import torch
+    from dataclasses import replace
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, corr, cot = bh_small
+    grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    dc = {k: t(v) for k, v in cot.items()}
+    _, g_nl = api.grad(grid, corr, xi, xig, rh, piv, dc, want_d=True)
+    got = g_nl.cpu().numpy()
+
+    def L(cr):
+        out = api.kernel_contract(grid, cr, xi, xig, rh, piv, CH & ~64)
+        return sum(float(torch.sum(dc[k] * out[k])) for k in ("u1", "u3", "D1", "D4", "field"))
+
+    h = 1e-3
+    for k in range(2):
+        mv = (lambda v: replace(corr, d=corr.d + v)) if k == 0 else \
+             (lambda v: replace(corr, b=np.asarray(corr.b, np.float64) + v))
+        fd1 = (L(mv(h)) - L(mv(-h))) / (2 * h)
+        fd2 = (L(mv(2 * h)) - L(mv(-2 * h))) / (4 * h)
+        rich = (4.0 * fd1 - fd2) / 3.0
+        note(f"  parameter {k}: adjoint {got[k]:.12e}, Richardson difference {rich:.12e}")
+        assert abs(rich - got[k]) <= 1e-8 * np.abs(got).max()

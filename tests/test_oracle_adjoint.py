@@ -85,3 +85,38 @@ def test_scale_derivative_complex_step_equals_richardson_differences(h2_tiny):
     # a real d gives real outputs (the complex path leaves the real one unchanged)
     out = contract.contract(wl.grid_xyz, wl.grid_w, wl.corr, fr.xi, fr.xigrad, G, rho, 1 | 2)
     assert out["u1"].dtype == np.float64
+
+
+def test_bh_nonlinear_derivatives_complex_step_equal_richardson_differences(h6_small):
+    """The oracle's [dL/dd, dL/db_0, dL/db_1] for the BH form (eq. bh-u) on two nucleus
+    types with distinct b: complex step against Richardson-extrapolated central
+    differences of real contractions, each parameter moved on its own."""
+    from dataclasses import replace
+    from workloads import Correlator
+    xyz, w, xi, xig, G, rho = _problem(h6_small, 200, 14, seed=4)
+    base = bh_correlator(h6_small.atom_xyz)
+    n = base.nuc_xyz.shape[0]
+    c = np.random.default_rng(11).uniform(-0.5, 0.5, size=(2, base.n_terms)) / n
+    corr = Correlator(base.form, base.mno, c, base.d, np.array([1.0, 1.3]), base.nuc_xyz,
+                      (np.arange(n) % 2).astype(np.int32))
+    cot = _cotangents(xi.shape[0], xi.shape[1], 35, lap=False)
+    chans = ALL & ~contract.ULAP
+    cs = adjoint.dL_dnl(xyz, w, corr, xi, xig, G, rho, cot)
+    assert cs.shape == (3,)
+
+    def moved(k, v):
+        if k == 0:
+            return replace(corr, d=corr.d + v)
+        b = corr.b.copy()
+        b[k - 1] += v
+        return replace(corr, b=b)
+
+    h = 1e-3
+    for k in range(3):
+        L = lambda v: _loss(contract.contract(xyz, w, moved(k, v), xi, xig, G, rho, chans), cot)
+        fd1 = (L(h) - L(-h)) / (2 * h)
+        fd2 = (L(2 * h) - L(-2 * h)) / (4 * h)
+        rich = (4.0 * fd1 - fd2) / 3.0
+        assert abs(rich - cs[k]) <= 1e-9 * np.abs(cs).max(), (k, rich, cs[k])
+    # the EE form returns dL/dd alone, equal to dL_dd
+    assert adjoint.dL_dnl(xyz, w, h6_small.corr, xi, xig, G, rho, cot).shape == (1,)
