@@ -206,5 +206,34 @@ def make_config(name: str, index: int = 0) -> Workload:
     raise KeyError(name)
 
 
+def nuclear_repulsion(wl: Workload) -> float:
+    """E_nuc = sum_{I<J} Z_I Z_J / |R_I - R_J| (a constant of the Hamiltonian)."""
+    Z, X = wl.atom_Z.astype(np.float64), wl.atom_xyz
+    e = 0.0
+    for i in range(len(Z)):
+        for j in range(i + 1, len(Z)):
+            e += Z[i] * Z[j] / float(np.linalg.norm(X[i] - X[j]))
+    return e
+
+
+def vmc_walkers(wl: Workload, n_w: int, seed: int = 0) -> np.ndarray:
+    """Initial walkers [n_w, 2 n_occ, 3]: electron i sits near nucleus i mod n_atom (both
+    spins), displaced by N(0, 0.7^2) per coordinate (seeded)."""
+    rng = np.random.default_rng(seed)
+    n_el = 2 * wl.n_occ
+    owner = np.arange(n_el) % wl.atom_xyz.shape[0]
+    R = wl.atom_xyz[owner][None, :, :] + 0.7 * rng.normal(size=(n_w, n_el, 3))
+    return np.ascontiguousarray(R)
+
+
+def vmc_draws(n_sweeps: int, n_el: int, n_w: int, seed: int = 0):
+    """Metropolis draws: standard normals [n_sweeps, n_el, n_w, 3] for the proposals and
+    uniforms [n_sweeps, n_el, n_w] on [0, 1) for the acceptance tests (seeded)."""
+    rng = np.random.default_rng(seed)
+    normals = rng.normal(size=(n_sweeps, n_el, n_w, 3))
+    uniforms = rng.random(size=(n_sweeps, n_el, n_w))
+    return np.ascontiguousarray(normals), np.ascontiguousarray(uniforms)
+
+
 __all__ = ["Workload", "Correlator", "make_config", "ee_correlator", "bh_correlator",
-           "FORM_EE", "FORM_BH", "Basis"]
+           "FORM_EE", "FORM_BH", "Basis", "nuclear_repulsion", "vmc_walkers", "vmc_draws"]
