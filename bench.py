@@ -24,7 +24,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS = {"fp64": 78.6, "f16": 2500.0}   # TFLOP/s, dense MFMA (MI355X datasheet)
+PEAKS = {"fp64": 78.6, "f16": 2500.0,   # TFLOP/s, dense MFMA (MI355X datasheet)
+         "fp64_vector": 78.6}            # FP64 vector ALU: 256 CUs x 128 FLOP/clk x 2.4 GHz
 
 
 def parse():
@@ -50,6 +51,11 @@ def parse():
                         "on a bra shard of --sample-blocks super-blocks against the full ket range, "
                         "with seeded interpolation vectors of that shape")
     p.add_argument("--sample-blocks", type=int, default=2)
+    p.add_argument("--vmc", action="store_true",
+                   help="also time one reference-variance VMC optimisation step (sampling, local "
+                        "energies with derivatives, Gauss-Newton) on the workload's determinant")
+    p.add_argument("--walkers", type=int, default=16384)
+    p.add_argument("--vmc-sweeps", type=int, default=20)
     p.add_argument("--grad", action="store_true",
                    help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
                         "and the field (D1/D4 cotangents add one recomputation of stage 1)")
@@ -167,6 +173,11 @@ def main():
             if a.assembly:
                 log("timing the CPU oracle sample of the assembly")
                 res["assembly"]["cpu_baseline"] = assembly_cpu_baseline(wl, 1)
+    if a.vmc:
+        res["vmc"] = vmc_bench(wl, a.walkers, a.vmc_sweeps, log)
+        if not a.no_cpu_baseline:
+            log("timing the CPU oracle sample of the VMC step")
+            res["vmc"]["cpu_baseline"] = vmc_cpu_baseline(wl)
     if a.kernel_sample:
         res["kernel_sample"] = kernel_sample(a.kernel_sample, a.sample_blocks, log)
     if a.compare_fp64 and prec != L.XTC_FP64:
@@ -287,6 +298,107 @@ def assembly_bench(wl, inter, width, log):
                            "launches": ap["launches"]}
     log(f"assembly: prepare {t_prep:.3f} s, panels {t_pan:.3f} s, one-body {t_one:.3f} s")
     return res
+
+
+def _vmc_flops(wl, n_el):
+    """Algorithmic FP64 work of the VMC kernels (exp counted as one operation):
+    per proposal, the AO row (4 per primitive: r^2 term, exp, scale, sum; 3 per AO),
+    the occupied-orbital row (2 n_ao n_occ), the ratio row (2 n_occ^2) and, when accepted,
+    the Sherman-Morrison update (2 n_occ^2); per walker for the local energy, five AO
+    quantities (12 per primitive, 30 per AO) and five orbital rows per electron, two
+    inverses (2 n_occ^3 each), the Slater ratios (8 n_occ per electron) and the Jastrow
+    pair sums (about 40 + 30 n_terms per ordered pair)."""
+    n_prim = int(wl.basis.shell_prim_start[-1])
+    n_ao, n = wl.n_ao, wl.n_occ
+    move = 4 * n_prim + 3 * n_ao + 2 * n_ao * n + 2 * n * n
+    update = 2 * n * n
+    energy = (n_el * (12 * n_prim + 30 * n_ao + 10 * n_ao * n + 8 * n) + 2 * 2 * n ** 3
+              + n_el * (n_el - 1) * (40 + 30 * wl.corr.n_terms))
+    return move, update, energy
+
+
+def vmc_bench(wl, n_w, n_sweeps, log):
+    """One optimisation step of the VMC section at the workload's reference determinant:
+    n_sweeps Metropolis sweeps of every electron of n_w walkers, the local energies with
+    their (c, d) derivatives, and the Gauss-Newton step. Draws come from a seeded device
+    generator before the timed region."""
+    import numpy as np
+    import torch
+
+    from paper_2607_17314_amd import api
+    from workloads import nuclear_repulsion, vmc_walkers
+    sysv = api.VmcSystem.from_workload(wl, nuclear_repulsion(wl))
+    n_el = sysv.n_el
+    R = torch.as_tensor(vmc_walkers(wl, n_w, seed=1), device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    nrm = torch.randn((n_sweeps, n_el, n_w, 3), dtype=torch.float64, device="cuda", generator=g)
+    uni = torch.rand((n_sweeps, n_el, n_w), dtype=torch.float64, device="cuda", generator=g)
+    api.vmc_sample(sysv, R, n_sweeps, 0.6, nrm, uni)          # warm-up and equilibration
+    E, dE = api.vmc_local_energy(sysv, wl.corr, R)
+    api.vmc_gn_step(E, dE, 1e-3, 0.5)
+    torch.cuda.synchronize()
+    with api.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        acc = api.vmc_sample(sysv, R, n_sweeps, 0.6, nrm, uni)
+        E, dE = api.vmc_local_energy(sysv, wl.corr, R)
+        delta, stats = api.vmc_gn_step(E, dE, 1e-3, 0.5)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    tm = kt.result
+    st = stats.cpu().numpy()
+    rate = float(acc.sum()) / (n_w * n_el * n_sweeps)
+    moves = float(n_w) * n_el * n_sweeps
+    f_move, f_upd, f_en = _vmc_flops(wl, n_el)
+    samp_ms, en_ms, gn_ms = tm["vmc_sample"]["ms"], tm["vmc_energy"]["ms"], tm["vmc_gn"]["ms"]
+    samp_flops = moves * (f_move + rate * f_upd)
+    res = {"walkers": n_w, "sweeps": n_sweeps, "electrons": n_el, "n_ao": wl.n_ao,
+           "step_s": round(dt, 4), "sample_ms": round(samp_ms, 2), "energy_ms": round(en_ms, 2),
+           "gn_ms": round(gn_ms, 3), "acceptance": round(rate, 4),
+           "moves_per_s": round(moves / (samp_ms * 1e-3), 1),
+           "local_energies_per_s": round(n_w / (en_ms * 1e-3), 1),
+           "clipped_mean": float(st[2]), "clipped_variance": float(st[3]), "n_clipped": int(st[4])}
+    # the dominant kernel of the step (sampling or energies), FP64 vector ALU roofline
+    if samp_ms >= en_ms:
+        ach = samp_flops / (samp_ms * 1e-3) / 1e12
+        kern, launch_ms = "VMC sampler (k_vmc_sweeps)", samp_ms
+    else:
+        ach = n_w * f_en / (en_ms * 1e-3) / 1e12
+        kern, launch_ms = "VMC local energy (k_vmc_energy)", en_ms
+    res["roofline"] = {"bound": "alu", "kernel": kern, "achieved": round(ach, 3),
+                       "peak": PEAKS["fp64_vector"], "unit": "TFLOP/s",
+                       "frac": round(ach / PEAKS["fp64_vector"], 4), "traffic": None,
+                       "launch_ms": round(launch_ms, 3), "launches": 1}
+    res["energy_tflops"] = round(n_w * f_en / (en_ms * 1e-3) / 1e12, 3)
+    res["sample_tflops"] = round(samp_flops / (samp_ms * 1e-3) / 1e12, 3)
+    log(f"vmc: step {dt:.3f} s (sample {samp_ms:.1f} ms, energies {en_ms:.1f} ms, GN {gn_ms:.2f} ms), "
+        f"acceptance {rate:.3f}")
+    return res
+
+
+def vmc_cpu_baseline(wl, n_w=1024, n_sweeps=2, n_en=256):
+    """The oracle's sampler (n_sweeps sweeps of n_w walkers) and local energies with
+    complex-step derivatives (n_en walkers) on the host."""
+    import numpy as np
+
+    from oracle import vmc
+    from workloads import nuclear_repulsion, vmc_draws, vmc_walkers
+    n_el = 2 * wl.n_occ
+    C_occ = np.ascontiguousarray(wl.C_mo[:, :wl.n_occ])
+    R0 = vmc_walkers(wl, n_w, seed=1)
+    nrm, uni = vmc_draws(n_sweeps, n_el, n_w, seed=2)
+    t0 = time.perf_counter()
+    vmc.metropolis(wl.basis, C_occ, R0, 0.6, nrm, uni)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vmc.local_energy_grad(wl.basis, C_occ, wl.atom_xyz, wl.atom_Z.astype(np.float64),
+                          nuclear_repulsion(wl), wl.corr, R0[:n_en])
+    t_e = time.perf_counter() - t0
+    return {"kind": "oracle", "moves_per_s": round(n_w * n_el * n_sweeps / t_s, 1),
+            "local_energies_per_s": round(n_en / t_e, 2), "unit": "moves/s, local energies/s",
+            "cores": 1, "sample": f"{n_w} walkers x {n_sweeps} sweep(s); {n_en} walkers' "
+                                  f"energies with {wl.corr.n_terms + 1} derivatives (element-wise "
+                                  f"NumPy on small arrays: one thread)"}
 
 
 def kernel_sample(config, nblk, log):

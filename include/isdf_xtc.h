@@ -178,12 +178,12 @@ const char* xtc_version(void);
 /* Call identifiers for xtc_workspace_bytes. */
 enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
        XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7,
-       XTC_CALL_EXCHANGE = 8, XTC_CALL_ASSEMBLY = 9, XTC_CALL_ONE_BODY = 10 };
+       XTC_CALL_EXCHANGE = 8, XTC_CALL_ASSEMBLY = 9, XTC_CALL_ONE_BODY = 10, XTC_CALL_VMC = 11 };
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
  * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT) or
  * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none).
- * n_aux: n_ao (EVAL_ORBITALS), n_params (GRAD), the
+ * n_aux: n_ao (EVAL_ORBITALS, VMC), n_params (GRAD), the
  * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_orb > 0
  * asks for them), else 0. */
 size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
@@ -342,6 +342,67 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
                     const double* gfield, double* dtheta, double* dd, void* ws, size_t ws_bytes,
                     void* stream);
 
+/* ---- Reference-variance VMC optimisation of the correlator (the VMC section) ----
+ * Trial function Psi_T = F Phi_0 with F = prod_{i<j} exp(u(r_i, r_j)) (eq. tau-def) and
+ * Phi_0 the closed-shell reference determinant over the n_occ occupied orbitals:
+ * electrons 0 .. n_occ - 1 spin up, n_occ .. 2 n_occ - 1 spin down,
+ * Phi_0 = det[phi_k(r_i)]_up det[phi_k(r_i)]_down. Hamiltonian: kinetic energy,
+ * electron-nucleus attraction -Z_I / r_iI, electron repulsion 1 / r_ij and e_nuc.
+ * Walkers: device [n_walkers][2 n_occ][3] FP64 (bohr). */
+typedef struct {
+  const xtc_basis* basis;   /* host tables, as for xtc_eval_orbitals */
+  int32_t n_occ;            /* electrons per spin, 1 .. 32 */
+  const double* C_occ;      /* device [n_ao][n_occ]: the occupied orbitals' coefficients */
+  int32_t n_nuc;
+  const double* nuc_xyz;    /* host [n_nuc][3] */
+  const double* nuc_charge; /* host [n_nuc] */
+  double e_nuc;             /* constant added to every local energy */
+} xtc_vmc_system;
+
+/* Metropolis sampling of |Phi_0|^2 (the VMC section samples the reference determinant,
+ * not the trial function, so the draws do not depend on the correlator): n_sweeps
+ * sweeps, each moving electrons 0 .. 2 n_occ - 1 in order with the symmetric proposal
+ * r_i' = r_i + step * eta (product and sum rounded separately) and accepting when
+ * uniform < |Phi_0(R') / Phi_0(R)|^2. The inverse Slater matrices are formed once per
+ * call and kept by Sherman-Morrison updates.
+ * R: device [n_walkers][2 n_occ][3], updated in place. normals: device
+ * [n_sweeps][2 n_occ][n_walkers][3] standard normal draws; uniforms: device
+ * [n_sweeps][2 n_occ][n_walkers] on [0, 1). accepted: device int64 [n_walkers], the
+ * number of accepted moves, or -1 for a walker whose starting determinant is exactly
+ * singular (left unmoved). With n_walkers = 0, R, accepted and the draws may be NULL.
+ * Workspace: xtc_workspace_bytes(XTC_CALL_VMC, 0, 0, 0, n_ao, 0).
+ * Limits: n_occ <= 32; the walker's LDS (4 n_occ^2 + n_ao + 9 n_occ + 64 doubles) within
+ * 160 KB. FP64. Asynchronous after the basis upload. */
+xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* R,
+                          int32_t n_sweeps, double step, const double* normals,
+                          const double* uniforms, int64_t* accepted, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* Local energies E_loc = H Psi_T / Psi_T (eq. Eloc) of the walkers R and, when dE is not
+ * NULL, their derivatives with respect to theta = (c_0 .. c_{n_terms - 1}, d) of the EE
+ * correlator u = sum_k c_k rbar^{o_k}, rbar = d r / (1 + d r):
+ *   lap_i Psi_T / Psi_T = lap_i J + |grad_i J|^2 + 2 grad_i J . grad_i Phi_0 / Phi_0
+ *                         + lap_i Phi_0 / Phi_0,  J = sum_{i<j} u(r_i, r_j).
+ * E: device [n_walkers]; dE: device [n_walkers][n_terms + 1] or NULL. A walker whose
+ * determinant is exactly singular gets NaN. Only the EE form (1 .. 12 terms (0, 0, o))
+ * is accepted; the BH form returns XTC_ERR_UNSUPPORTED. Workspace as xtc_vmc_sample;
+ * LDS per walker 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles within 160 KB. FP64. */
+xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator* corr,
+                                int64_t n_walkers, const double* R, double* E, double* dE,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* One Newton step with Gauss-Newton curvature (eq. gn) on the fixed-batch clipped
+ * variance (eq. var-loss): m = mean E, d = mean |E - m|, Et = clip(E, m - 5 d, m + 5 d),
+ * r_k = Et_k - mean Et, sigma^2 = sum r_k^2 / (N - 1); the clipped energies' derivatives
+ * follow the bounds m +- 5 d as functions of theta (sign(0) = 0 in d's derivative);
+ * C = (1/N) sum_k dr_k dr_k^T + lambda I, delta = -eta C^-1 grad sigma^2 (Cholesky).
+ * E: device [N]; dE: device [N][n_params] (1 .. 64 parameters); delta: device
+ * [n_params]; stats: device [6] = m, d, mean Et, sigma^2, the number of clipped
+ * energies, and 0 (or j + 1 when C's j-th pivot is not positive; delta is then NaN).
+ * N >= 2. No workspace. FP64. Asynchronous. */
+xtc_status xtc_vmc_gn_step(int64_t n_walkers, int32_t n_params, const double* E, const double* dE,
+                           double lambda, double eta, double* delta, double* stats, void* stream);
+
 /* Kernel timing for measurement: HIP events recorded on the call's stream around
  * each launch of the timed stages. mode 1: reset and start collecting; 0: stop and
  * reset; 2: synchronise the recorded events and write, per category c,
@@ -352,9 +413,10 @@ xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_
  * per kernel launch), 9 exchange projections and pair products, 10 exchange X
  * products (operand splitting included), 11 the exchange's stage 1 on the projected
  * rows (split path), 12 the exchange's split X-product kernel alone (one entry per
- * launch), 13 the assembly panel kernel (one entry per launch).
+ * launch), 13 the assembly panel kernel (one entry per launch), 14 VMC sampling,
+ * 15 VMC local energies, 16 the Gauss-Newton step.
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 14
+#define XTC_TIMING_CATEGORIES 17
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

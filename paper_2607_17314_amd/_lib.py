@@ -16,7 +16,7 @@ XTC_SELECT_QR, XTC_SELECT_LEARNED, XTC_SELECT_LEARNED_JUDGED = 0, 1, 2
 XTC_FIT_XI, XTC_FIT_XIGRAD = 1, 2
 XTC_CALL_EVAL_ORBITALS, XTC_CALL_SELECT, XTC_CALL_FIT, XTC_CALL_CONTRACT, XTC_CALL_GRAD = 1, 2, 3, 4, 5
 XTC_CALL_FEATURES, XTC_CALL_MLP_GRAD, XTC_CALL_EXCHANGE = 6, 7, 8
-XTC_CALL_ASSEMBLY, XTC_CALL_ONE_BODY = 9, 10
+XTC_CALL_ASSEMBLY, XTC_CALL_ONE_BODY, XTC_CALL_VMC = 9, 10, 11
 XTC_ASM_K, XTC_ASM_DU, XTC_ASM_W = 1, 2, 4
 
 STATUS_NAMES = {0: "XTC_OK", 1: "XTC_WARN_RANK_DEFICIENT", 2: "XTC_WARN_JITTER",
@@ -53,6 +53,11 @@ class Exchange(C.Structure):
 class Assembly(C.Structure):
     _fields_ = [("n_orb", C.c_int32), ("n_mu", C.c_int32), ("phi4_piv", P), ("u1", P), ("u3", P),
                 ("D1", P), ("D4", P), ("X2", P), ("X3", P)]
+
+
+class VmcSystem(C.Structure):
+    _fields_ = [("basis", C.POINTER(Basis)), ("n_occ", C.c_int32), ("C_occ", P), ("n_nuc", C.c_int32),
+                ("nuc_xyz", D), ("nuc_charge", D), ("e_nuc", C.c_double)]
 
 
 class Mlp(C.Structure):
@@ -109,6 +114,14 @@ def lib() -> C.CDLL:
                                      P, C.c_size_t, P]
     L.xtc_one_body.restype = st
     L.xtc_one_body.argtypes = [C.POINTER(Assembly), C.c_int32, C.c_double, P, P, D, P, C.c_size_t, P]
+    L.xtc_vmc_sample.restype = st
+    L.xtc_vmc_sample.argtypes = [C.POINTER(VmcSystem), C.c_int64, P, C.c_int32, C.c_double, P, P, P,
+                                 P, C.c_size_t, P]
+    L.xtc_vmc_local_energy.restype = st
+    L.xtc_vmc_local_energy.argtypes = [C.POINTER(VmcSystem), C.POINTER(Correlator), C.c_int64, P, P, P,
+                                       P, C.c_size_t, P]
+    L.xtc_vmc_gn_step.restype = st
+    L.xtc_vmc_gn_step.argtypes = [C.c_int64, C.c_int32, P, P, C.c_double, C.c_double, P, P, P]
     L.xtc_timing.restype = st
     L.xtc_timing.argtypes = [C.c_int32, D]
     L.xtc_mlp_features.restype = st
@@ -129,6 +142,8 @@ def lib() -> C.CDLL:
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
             "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing",
             "xtc_exchange_terms", "xtc_assembly_prepare", "xtc_assembly_panel", "xtc_one_body",
-            "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step"]
+            "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step",
+            "xtc_vmc_sample", "xtc_vmc_local_energy", "xtc_vmc_gn_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
-                     "stage1_kernel", "x_pairs", "x_gemm", "x_stage1", "x_mfma", "asm_panel"]
+                     "stage1_kernel", "x_pairs", "x_gemm", "x_stage1", "x_mfma", "asm_panel",
+                     "vmc_sample", "vmc_energy", "vmc_gn"]

@@ -485,3 +485,113 @@ def train_mlp(model: MlpModel, feats, labels, epochs: int = 4, batch: int = 4096
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.4f}")
     return history
+
+
+class VmcSystem:
+    """Reference system of the VMC optimisation (xtc_vmc_system): basis, occupied
+    orbitals (device), nuclei and the constant e_nuc. Holds its host arrays and the
+    library's workspace."""
+
+    def __init__(self, basis, C_occ, nuc_xyz, nuc_charge, e_nuc: float = 0.0):
+        self.hb = _HostBasis(basis)
+        self.C = _dev(np.ascontiguousarray(C_occ, np.float64))
+        self.n_ao, self.n_occ = int(self.C.shape[0]), int(self.C.shape[1])
+        self.nuc = np.ascontiguousarray(nuc_xyz, np.float64).reshape(-1, 3)
+        self.Z = np.ascontiguousarray(nuc_charge, np.float64).reshape(-1)
+        self.e_nuc = float(e_nuc)
+        self.s = L.VmcSystem(C.pointer(self.hb.s), self.n_occ, _ptr(self.C), self.nuc.shape[0],
+                             _dptr(self.nuc), _dptr(self.Z), self.e_nuc)
+        self.ws = _workspace(workspace_bytes(L.XTC_CALL_VMC, 0, 0, 0, self.n_ao))
+
+    @classmethod
+    def from_workload(cls, wl, e_nuc: float = 0.0):
+        return cls(wl.basis, np.ascontiguousarray(wl.C_mo[:, :wl.n_occ]), wl.atom_xyz,
+                   np.asarray(wl.atom_Z, np.float64), e_nuc)
+
+    @property
+    def n_el(self) -> int:
+        return 2 * self.n_occ
+
+
+def vmc_sample(sys: VmcSystem, R, n_sweeps: int, step: float, normals, uniforms):
+    """Metropolis sweeps over |Phi_0|^2 (xtc_vmc_sample); R [n_w, n_el, 3] (device,
+    float64) is updated in place. Returns the accepted-move counts (int64, device)."""
+    if not (isinstance(R, torch.Tensor) and R.is_cuda and R.dtype == torch.float64 and R.is_contiguous()):
+        raise TypeError("R must be a contiguous float64 CUDA tensor")
+    n_w = int(R.shape[0])
+    if tuple(R.shape) != (n_w, sys.n_el, 3):
+        raise ValueError(f"R must be [n_w, {sys.n_el}, 3]")
+    nrm = _in(normals, "normals")
+    uni = _in(uniforms, "uniforms")
+    if n_sweeps > 0 and (tuple(nrm.shape) != (n_sweeps, sys.n_el, n_w, 3) or
+                         tuple(uni.shape) != (n_sweeps, sys.n_el, n_w)):
+        raise ValueError("draws must be [n_sweeps, n_el, n_w, 3] and [n_sweeps, n_el, n_w]")
+    acc = torch.zeros(n_w, dtype=torch.int64, device="cuda")
+    _check("xtc_vmc_sample", L.lib().xtc_vmc_sample(
+        C.byref(sys.s), n_w, _ptr(R), int(n_sweeps), float(step), _ptr(nrm), _ptr(uni), _ptr(acc),
+        _ptr(sys.ws), sys.ws.numel(), _stream()))
+    return acc
+
+
+def vmc_local_energy(sys: VmcSystem, corr, R, want_grad: bool = True, c=None, d=None):
+    """Local energies [n_w] and, with want_grad, dE/dtheta [n_w, n_terms + 1] for
+    theta = (c_0 .. c_{n-1}, d) of the EE correlator (xtc_vmc_local_energy)."""
+    from dataclasses import replace
+    if d is not None:
+        corr = replace(corr, d=float(d))
+    hc = HostCorrelator(corr, c)
+    R = _in(R, "R")
+    n_w = int(R.shape[0])
+    E = torch.empty(n_w, dtype=torch.float64, device="cuda")
+    dE = torch.empty((n_w, corr.n_terms + 1), dtype=torch.float64, device="cuda") if want_grad else None
+    _check("xtc_vmc_local_energy", L.lib().xtc_vmc_local_energy(
+        C.byref(sys.s), C.byref(hc.s), n_w, _ptr(R), _ptr(E), _ptr(dE), _ptr(sys.ws), sys.ws.numel(),
+        _stream()))
+    return (E, dE) if want_grad else E
+
+
+def vmc_gn_step(E, dE, lam: float, eta: float):
+    """Gauss-Newton step on the clipped variance (xtc_vmc_gn_step). Returns
+    (delta [n_params], stats [6] = m, MAD, clipped mean, variance, n_clipped, info)."""
+    E, dE = _in(E, "E"), _in(dE, "dE")
+    n_w, n_p = int(dE.shape[0]), int(dE.shape[1])
+    delta = torch.empty(n_p, dtype=torch.float64, device="cuda")
+    stats = torch.empty(6, dtype=torch.float64, device="cuda")
+    _check("xtc_vmc_gn_step", L.lib().xtc_vmc_gn_step(n_w, n_p, _ptr(E), _ptr(dE), float(lam), float(eta),
+                                                      _ptr(delta), _ptr(stats), _stream()))
+    return delta, stats
+
+
+def vmc_optimize(sys: VmcSystem, corr, R, n_steps: int, n_sweeps: int = 10, step: float = 0.6,
+                 lam: float = 1e-3, eta: float = 0.5, seed: int = 0, log=None):
+    """Reference-variance optimisation loop (the VMC section): per step, n_sweeps of
+    Metropolis over |Phi_0|^2 (draws from a seeded device generator), local energies and
+    their derivatives on the new batch, one Gauss-Newton update of (c, d). lam and eta
+    are held fixed (the paper's adaptive shift and schedule are not specified); a step
+    that would make d non-positive is halved until d > 0 (the scaled distance needs
+    d > 0). Returns the final correlator and the per-step statistics."""
+    from dataclasses import replace
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    n_w = int(R.shape[0])
+    history = []
+    for s in range(n_steps):
+        nrm = torch.randn((n_sweeps, sys.n_el, n_w, 3), dtype=torch.float64, device="cuda", generator=g)
+        uni = torch.rand((n_sweeps, sys.n_el, n_w), dtype=torch.float64, device="cuda", generator=g)
+        acc = vmc_sample(sys, R, n_sweeps, step, nrm, uni)
+        E, dE = vmc_local_energy(sys, corr, R)
+        delta, stats = vmc_gn_step(E, dE, lam, eta)
+        dl = delta.cpu().numpy()
+        st = stats.cpu().numpy()
+        if st[5] != 0.0 or not np.all(np.isfinite(dl)):
+            raise RuntimeError(f"Gauss-Newton step failed (info {st[5]}); raise lam")
+        n = corr.n_terms
+        while corr.d + dl[n] <= 0.0:
+            dl = 0.5 * dl
+        corr = replace(corr, c=corr.c + dl[:n][None, :], d=float(corr.d + dl[n]))
+        rate = float(acc.sum()) / (n_w * sys.n_el * max(n_sweeps, 1))
+        history.append({"mean": float(st[2]), "variance": float(st[3]), "clipped": int(st[4]),
+                        "acceptance": rate, "d": corr.d})
+        if log:
+            log(f"step {s}: <E> {st[2]:.6f} var {st[3]:.6f} clipped {int(st[4])} acc {rate:.3f} d {corr.d:.4f}")
+    return corr, history

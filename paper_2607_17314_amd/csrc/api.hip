@@ -34,6 +34,7 @@ extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, 
     case XTC_CALL_EXCHANGE: return xtc::ws_exchange(n_g, n_orb, n_mu, n_aux, (int)flags);
     case XTC_CALL_ASSEMBLY: return xtc::ws_assembly(n_orb, n_mu, flags);
     case XTC_CALL_ONE_BODY: return xtc::ws_one_body(n_orb, n_mu);
+    case XTC_CALL_VMC: return xtc::ws_vmc(n_aux);
     default: return 0;
   }
 }

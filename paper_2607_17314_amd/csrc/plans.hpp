@@ -17,4 +17,5 @@ size_t ws_fit_residual(int64_t n_g, int n_orb, int n_mu);
 size_t ws_exchange(int64_t n_g, int n_orb, int n_mu, int n_q, int precision);
 size_t ws_assembly(int n_orb, int n_mu, uint32_t outputs);
 size_t ws_one_body(int n_orb, int n_mu);
+size_t ws_vmc(int n_ao);
 }  // namespace xtc

@@ -1,0 +1,785 @@
+// Reference-variance optimisation of the correlator by variational Monte Carlo (the
+// VMC section): Metropolis sampling of the reference determinant |Phi_0|^2, the local
+// energy of the Slater-Jastrow trial function with its parameter derivatives (eq. Eloc),
+// and the Newton step with Gauss-Newton curvature on the clipped variance (eqs. var-loss,
+// gn).
+//
+// Walkers are independent, so the sampler and the local energy give each walker one
+// 64-lane workgroup (a single wave): the wave holds the walker's electrons, its two
+// inverse Slater matrices and the AO row of the current point in LDS, evaluates the AOs
+// lane-parallel over shells and the occupied orbitals lane-parallel over (orbital,
+// AO slice), and keeps the inverses current with Sherman-Morrison updates. No state
+// crosses walkers, so one launch runs every sweep. The Gauss-Newton step is one
+// workgroup of deterministic block reductions over the walkers and a Cholesky solve in
+// LDS.
+#include <cmath>
+#include "common.hpp"
+#include "plans.hpp"
+#include "timing.hpp"
+
+namespace xtc {
+
+constexpr int VMC_MAX_OCC = 32;      // electrons per spin
+constexpr int VMC_MAX_L = 6;
+constexpr int VMC_MAX_TERMS = 12;    // EE terms of the local-energy kernel
+constexpr int VMC_MAX_THETA = 64;    // parameters of the Gauss-Newton step
+constexpr int VMC_GN_THREADS = 1024;
+
+struct VmcBasis {
+  const double* atom_xyz;
+  const int* shell_center;
+  const int* shell_l;
+  const int* shell_prim_start;
+  const int* shell_ao_start;
+  const double* prim_exp;
+  const double* prim_coef;
+  const double* comp;
+  int n_shell, n_ao;
+};
+
+struct VmcDev {
+  VmcBasis b;
+  const double* C;      // [n_ao][n_occ]
+  const double* nuc;    // [n_nuc][4]: x, y, z, Z
+  int n_occ, n_nuc;
+  double e_nuc;
+};
+
+struct EECoefV {
+  int n;
+  double d;
+  int o[VMC_MAX_TERMS];
+  double c[VMC_MAX_TERMS];
+};
+
+// AO values (and, with LAP, gradients and Laplacians) of shell s at the point p, written
+// to chi[a] (and chi[n_ao * q + a], q = 1..4). chi = f P g(s), g = sum c e^{-alpha r^2}:
+// d_x chi = f (i x^{i-1} g + 2 x^{i+1} g') y^j z^k, lap chi = f [g lap P + P (4 l g' + 6 g'
+// + 4 r^2 g'')], primes in s = r^2.
+template <bool LAP>
+__device__ void vmc_shell(const VmcBasis& b, int s, double px, double py, double pz,
+                          double* chi) {
+  const int cen = b.shell_center[s];
+  const int l = b.shell_l[s];
+  const double x = px - b.atom_xyz[3 * cen], y = py - b.atom_xyz[3 * cen + 1],
+               z = pz - b.atom_xyz[3 * cen + 2];
+  const double r2 = x * x + y * y + z * z;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int p = b.shell_prim_start[s]; p < b.shell_prim_start[s + 1]; ++p) {
+    const double al = b.prim_exp[p];
+    const double e = b.prim_coef[p] * exp(-al * r2);
+    g0 += e;
+    if (LAP) {
+      g1 -= al * e;
+      g2 += al * al * e;
+    }
+  }
+  double xp[VMC_MAX_L + 2], yp[VMC_MAX_L + 2], zp[VMC_MAX_L + 2];
+  xp[0] = yp[0] = zp[0] = 1.0;
+  for (int n = 1; n <= l + 1; ++n) {
+    xp[n] = xp[n - 1] * x;
+    yp[n] = yp[n - 1] * y;
+    zp[n] = zp[n - 1] * z;
+  }
+  int a = b.shell_ao_start[s];
+  const int n_ao = b.n_ao;
+  for (int i = l; i >= 0; --i) {
+    for (int j = l - i; j >= 0; --j, ++a) {
+      const int k = l - i - j;
+      const double f = b.comp[a];
+      const double P = xp[i] * yp[j] * zp[k];
+      chi[a] = f * P * g0;
+      if (LAP) {
+        const double dxi = i > 0 ? i * xp[i - 1] : 0.0;
+        const double dyj = j > 0 ? j * yp[j - 1] : 0.0;
+        const double dzk = k > 0 ? k * zp[k - 1] : 0.0;
+        chi[n_ao + a] = f * yp[j] * zp[k] * (dxi * g0 + 2.0 * xp[i + 1] * g1);
+        chi[2 * n_ao + a] = f * xp[i] * zp[k] * (dyj * g0 + 2.0 * yp[j + 1] * g1);
+        chi[3 * n_ao + a] = f * xp[i] * yp[j] * (dzk * g0 + 2.0 * zp[k + 1] * g1);
+        double lapP = 0.0;
+        if (i >= 2) lapP += i * (i - 1) * xp[i - 2] * yp[j] * zp[k];
+        if (j >= 2) lapP += j * (j - 1) * xp[i] * yp[j - 2] * zp[k];
+        if (k >= 2) lapP += k * (k - 1) * xp[i] * yp[j] * zp[k - 2];
+        chi[4 * n_ao + a] = f * (g0 * lapP + P * ((4.0 * l + 6.0) * g1 + 4.0 * r2 * g2));
+      }
+    }
+  }
+}
+
+// All AOs of the point p into chi (lanes over shells); the caller synchronises.
+template <bool LAP>
+__device__ __forceinline__ void vmc_aos(const VmcBasis& b, double px, double py, double pz,
+                                        double* chi) {
+  for (int s = threadIdx.x; s < b.n_shell; s += 64) vmc_shell<LAP>(b, s, px, py, pz, chi);
+}
+
+// out[q * ostride + k] = sum_a chi[q * n_ao + a] C[a][k], q < NQ, k < n_occ: lanes as
+// (k, slice) with P = 64 / n_occ slices; partial sums in part[64 * NQ]; fixed order.
+template <int NQ>
+__device__ __forceinline__ void vmc_orbitals(const VmcDev& v, const double* chi, double* part,
+                                             double* out, int ostride) {
+  const int n = v.n_occ, n_ao = v.b.n_ao;
+  const int P = 64 / n;
+  const int lane = threadIdx.x;
+  const int k = lane / P, sl = lane - k * P;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (k < n) {
+    for (int a = sl; a < n_ao; a += P) {
+      const double cak = v.C[(long)a * n + k];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a] * cak;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) part[q * 64 + lane] = acc[q];
+  __syncthreads();
+  if (lane < n) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int t = 0; t < P; ++t) s += part[q * 64 + lane * P + t];
+      out[q * ostride + lane] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix in the left half
+// of aug [n][2n] (row-major); the inverse ends in the right half. Returns false (uniformly)
+// when a pivot is exactly zero.
+__device__ bool vmc_invert(double* aug, int n, double* fac, int* piv) {
+  const int lane = threadIdx.x;
+  const int w = 2 * n;
+  for (int r = lane; r < n * w; r += 64) {
+    const int i = r / w, c = r - i * w;
+    if (c >= n) aug[r] = (c - n == i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int p = 0; p < n; ++p) {
+    if (lane == 0) {
+      int best = p;
+      double bv = fabs(aug[p * w + p]);
+      for (int r = p + 1; r < n; ++r) {
+        const double v = fabs(aug[r * w + p]);
+        if (v > bv) { bv = v; best = r; }
+      }
+      piv[0] = bv > 0.0 ? best : -1;
+    }
+    __syncthreads();
+    const int pr = piv[0];
+    if (pr < 0) return false;
+    if (pr != p) {
+      for (int c = lane; c < w; c += 64) {
+        const double t = aug[p * w + c];
+        aug[p * w + c] = aug[pr * w + c];
+        aug[pr * w + c] = t;
+      }
+      __syncthreads();
+    }
+    const double inv = 1.0 / aug[p * w + p];
+    __syncthreads();
+    for (int c = lane; c < w; c += 64) aug[p * w + c] *= inv;
+    for (int r = lane; r < n; r += 64) fac[r] = aug[r * w + p];
+    __syncthreads();
+    for (int e = lane; e < n * w; e += 64) {
+      const int r = e / w, c = e - r * w;
+      if (r != p) aug[e] -= fac[r] * aug[p * w + c];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// r + s * e with the product and the sum rounded separately (no fused multiply-add).
+__device__ __forceinline__ double vmc_step(double r, double s, double e) {
+#pragma clang fp contract(off)
+  const double m = s * e;
+  return r + m;
+}
+
+// ---------------------------------------------------------------------------------------
+// Sampler: n_sweeps sweeps of single-electron moves, electrons in index order.
+// LDS (doubles): Ainv [2][n][n], aug [n][2n], chi [n_ao], part [64], phin [n], wv [n],
+// fac [n], R [n_el][3]; then int piv.
+__global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict__ R, long n_w,
+                                                   int n_sweeps, double step,
+                                                   const double* __restrict__ normals,
+                                                   const double* __restrict__ uniforms,
+                                                   long long* __restrict__ accepted) {
+  extern __shared__ double lds[];
+  const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
+  const long w = blockIdx.x;
+  double* Ainv = lds;
+  double* aug = Ainv + 2 * n * n;
+  double* chi = aug + 2 * n * n;
+  double* part = chi + v.b.n_ao;
+  double* phin = part + 64;
+  double* wv = phin + n;
+  double* fac = wv + n;
+  double* Rs = fac + n;
+  int* piv = (int*)(Rs + 3 * n_el);
+  for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  __syncthreads();
+  // inverse Slater matrices of the starting configuration
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int ii = 0; ii < n; ++ii) {
+      const int e = sp * n + ii;
+      vmc_aos<false>(v.b, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+      __syncthreads();
+      vmc_orbitals<1>(v, chi, part, aug + ii * 2 * n, 0);
+    }
+    if (!vmc_invert(aug, n, fac, piv)) {
+      if (lane == 0) accepted[w] = -1;
+      return;   // uniform over the (single-wave) workgroup
+    }
+    for (int e = lane; e < n * n; e += 64) {
+      const int k = e / n, i = e - k * n;
+      Ainv[sp * n * n + e] = aug[k * 2 * n + n + i];
+    }
+    __syncthreads();
+  }
+  long long acc = 0;
+  for (int s = 0; s < n_sweeps; ++s) {
+    for (int e = 0; e < n_el; ++e) {
+      const int sp = e / n, ii = e - sp * n;
+      const long di = ((long)s * n_el + e) * n_w + w;
+      // r' = r + step * eta, rounded as two separate operations
+      const double px = vmc_step(Rs[3 * e], step, normals[3 * di]);
+      const double py = vmc_step(Rs[3 * e + 1], step, normals[3 * di + 1]);
+      const double pz = vmc_step(Rs[3 * e + 2], step, normals[3 * di + 2]);
+      vmc_aos<false>(v.b, px, py, pz, chi);
+      __syncthreads();
+      vmc_orbitals<1>(v, chi, part, phin, 0);
+      double* Ai = Ainv + sp * n * n;
+      // wv[j] = sum_k phi_k(r') Ainv[k][j]; the determinant ratio is wv[ii]
+      if (lane < n) {
+        double t = 0.0;
+        for (int k = 0; k < n; ++k) t += phin[k] * Ai[k * n + lane];
+        wv[lane] = t;
+      }
+      __syncthreads();
+      const double ratio = wv[ii];
+      const double u = uniforms[di];
+      if (u < ratio * ratio) {
+        // Sherman-Morrison for row ii of A replaced by phi(r'):
+        // Ainv[k][j] -= Ainv[k][ii] (wv[j] - delta_{j ii}) / ratio
+        if (lane < n) fac[lane] = Ai[lane * n + ii];
+        __syncthreads();
+        const double rinv = 1.0 / ratio;
+        for (int q = lane; q < n * n; q += 64) {
+          const int k = q / n, j = q - k * n;
+          Ai[q] = (j == ii) ? fac[k] * rinv : Ai[q] - fac[k] * wv[j] * rinv;
+        }
+        if (lane == 0) {
+          Rs[3 * e] = px;
+          Rs[3 * e + 1] = py;
+          Rs[3 * e + 2] = pz;
+        }
+        ++acc;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = lane; e < 3 * n_el; e += 64) R[w * 3 * n_el + e] = Rs[e];
+  if (lane == 0) accepted[w] = acc;
+}
+
+// ---------------------------------------------------------------------------------------
+// Local energy and its parameter derivatives, one walker per workgroup.
+// LDS (doubles): A5 [5][n_el][n], aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64],
+// fac [n], R [n_el][3], red [64]; then int piv.
+__global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
+                                                   const double* __restrict__ R, long n_w,
+                                                   double* __restrict__ E,
+                                                   double* __restrict__ dE) {
+  extern __shared__ double lds[];
+  const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
+  const long w = blockIdx.x;
+  const int nth = cf.n + 1;
+  double* A5 = lds;
+  double* aug = A5 + 5 * n_el * n;
+  double* Ainv = aug + 2 * n * n;
+  double* chi = Ainv + 2 * n * n;
+  double* part = chi + 5 * v.b.n_ao;
+  double* fac = part + 5 * 64;
+  double* Rs = fac + n;
+  double* red = Rs + 3 * n_el;
+  int* piv = (int*)(red + 64);
+  for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  __syncthreads();
+  for (int e = 0; e < n_el; ++e) {
+    vmc_aos<true>(v.b, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+    __syncthreads();
+    vmc_orbitals<5>(v, chi, part, A5 + e * n, n_el * n);
+  }
+  bool ok = true;
+  for (int sp = 0; sp < 2 && ok; ++sp) {
+    for (int q = lane; q < n * n; q += 64) {
+      const int i = q / n, k = q - i * n;
+      aug[i * 2 * n + k] = A5[(sp * n + i) * n + k];
+    }
+    __syncthreads();
+    ok = vmc_invert(aug, n, fac, piv);
+    if (ok) {
+      for (int q = lane; q < n * n; q += 64) {
+        const int k = q / n, i = q - k * n;
+        Ainv[sp * n * n + q] = aug[k * 2 * n + n + i];
+      }
+      __syncthreads();
+    }
+  }
+  if (!ok) {   // exactly singular reference determinant: no local energy
+    if (lane == 0) {
+      E[w] = __builtin_nan("");
+      if (dE)
+        for (int p = 0; p < nth; ++p) dE[w * nth + p] = __builtin_nan("");
+    }
+    return;
+  }
+  // per electron (lane i): Slater ratios, Jastrow sums, potential
+  double ekin = 0.0, pot = 0.0;
+  double dEp[VMC_MAX_TERMS + 1];
+#pragma unroll
+  for (int p = 0; p <= VMC_MAX_TERMS; ++p) dEp[p] = 0.0;
+  if (lane < n_el) {
+    const int i = lane, sp = i / n, ii = i - sp * n;
+    const double* Ai = Ainv + sp * n * n;
+    double Dx = 0.0, Dy = 0.0, Dz = 0.0, S = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double a = Ai[k * n + ii];
+      Dx += A5[(n_el + i) * n + k] * a;
+      Dy += A5[(2 * n_el + i) * n + k] * a;
+      Dz += A5[(3 * n_el + i) * n + k] * a;
+      S += A5[(4 * n_el + i) * n + k] * a;
+    }
+    const double xi = Rs[3 * i], yi = Rs[3 * i + 1], zi = Rs[3 * i + 2];
+    double Gx = 0.0, Gy = 0.0, Gz = 0.0, Lj = 0.0;
+    double gk[VMC_MAX_TERMS + 1][3], lk[VMC_MAX_TERMS + 1];
+#pragma unroll
+    for (int p = 0; p <= VMC_MAX_TERMS; ++p) gk[p][0] = gk[p][1] = gk[p][2] = lk[p] = 0.0;
+    const double d = cf.d;
+    for (int j = 0; j < n_el; ++j) {
+      if (j == i) continue;
+      const double dx = xi - Rs[3 * j], dy = yi - Rs[3 * j + 1], dz = zi - Rs[3 * j + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double rinv = 1.0 / r;
+      if (j > i) pot += rinv;
+      const double t = 1.0 / (1.0 + d * r);
+      const double e = d * r * t;
+      const double t2 = t * t, t3 = t2 * t, t4 = t2 * t2;
+      double up = 0.0, upp = 0.0, upd = 0.0, uppd = 0.0;
+#pragma unroll
+      for (int k = 0; k < VMC_MAX_TERMS; ++k) {
+        if (k < cf.n) {
+          const int o = cf.o[k];
+          // e^{o-1}, e^{o-2} (o >= 1; terms with o = 0 are constant and drop out)
+          double em1 = 1.0, em2 = 1.0;
+          for (int q = 0; q < o - 2; ++q) em2 *= e;
+          em1 = o >= 2 ? em2 * e : 1.0;
+          if (o == 0) continue;
+          // f' = o e^{o-1} d t^2, f'' = o (o-1) e^{o-2} d^2 t^4 - 2 o e^{o-1} d^2 t^3
+          const double fp = o * em1 * d * t2;
+          const double fpp = (o >= 2 ? o * (o - 1) * em2 * d * d * t4 : 0.0) -
+                             2.0 * o * em1 * d * d * t3;
+          // d/dd: [d t^2 e^m]' = t^2 e^m (1 - 2e + m t); [d^2 t^4 e^m]' = d t^4 e^m
+          // (2 - 4e + m t); [d^2 t^3 e^m]' = d t^3 e^m (2 - 3e + m t)
+          const double fpd = o * t2 * em1 * (1.0 - 2.0 * e + (o - 1) * t);
+          const double fppd = (o >= 2 ? o * (o - 1) * d * t4 * em2 * (2.0 - 4.0 * e + (o - 2) * t) : 0.0) -
+                              2.0 * o * d * t3 * em1 * (2.0 - 3.0 * e + (o - 1) * t);
+          const double c = cf.c[k];
+          up += c * fp;
+          upp += c * fpp;
+          upd += c * fpd;
+          uppd += c * fppd;
+          const double s = fp * rinv;
+          gk[k][0] += s * dx;
+          gk[k][1] += s * dy;
+          gk[k][2] += s * dz;
+          lk[k] += fpp + 2.0 * s;
+        }
+      }
+      const double s = up * rinv;
+      Gx += s * dx;
+      Gy += s * dy;
+      Gz += s * dz;
+      Lj += upp + 2.0 * s;
+      const double sd = upd * rinv;
+      gk[VMC_MAX_TERMS][0] += sd * dx;
+      gk[VMC_MAX_TERMS][1] += sd * dy;
+      gk[VMC_MAX_TERMS][2] += sd * dz;
+      lk[VMC_MAX_TERMS] += uppd + 2.0 * sd;
+    }
+    for (int I = 0; I < v.n_nuc; ++I) {
+      const double dx = xi - v.nuc[4 * I], dy = yi - v.nuc[4 * I + 1], dz = zi - v.nuc[4 * I + 2];
+      pot -= v.nuc[4 * I + 3] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    // lap_i Psi / Psi = lap J + |grad J|^2 + 2 grad J . D + S
+    ekin = -0.5 * (Lj + Gx * Gx + Gy * Gy + Gz * Gz + 2.0 * (Gx * Dx + Gy * Dy + Gz * Dz) + S);
+    const double hx = Gx + Dx, hy = Gy + Dy, hz = Gz + Dz;
+#pragma unroll
+    for (int p = 0; p <= VMC_MAX_TERMS; ++p)
+      dEp[p] = -0.5 * (lk[p] + 2.0 * (hx * gk[p][0] + hy * gk[p][1] + hz * gk[p][2]));
+  }
+  // fixed-order sums over the electrons (lanes)
+  auto lane_sum = [&](double x) {
+    red[lane] = x;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+      if (lane < h) red[lane] += red[lane + h];
+      __syncthreads();
+    }
+    const double s = red[0];
+    __syncthreads();
+    return s;
+  };
+  const double Etot = lane_sum(ekin + pot);
+  if (lane == 0) E[w] = Etot + v.e_nuc;
+  if (dE) {
+    for (int p = 0; p < cf.n; ++p) {
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < VMC_MAX_TERMS; ++q)
+        if (q == p) x = dEp[q];
+      const double s = lane_sum(x);
+      if (lane == 0) dE[w * nth + p] = s;
+    }
+    const double s = lane_sum(dEp[VMC_MAX_TERMS]);
+    if (lane == 0) dE[w * nth + cf.n] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Gauss-Newton step (eq. gn) on the clipped variance (eq. var-loss), one workgroup.
+__device__ double gn_block_sum(double x, double* red) {
+  const int t = threadIdx.x;
+  red[t] = x;
+  __syncthreads();
+  for (int h = VMC_GN_THREADS / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+struct GnShared {
+  double red[VMC_GN_THREADS];
+  double dm[VMC_MAX_THETA], dmad[VMC_MAX_THETA], mdt[VMC_MAX_THETA], grad[VMC_MAX_THETA];
+  double C[VMC_MAX_THETA * VMC_MAX_THETA];
+  double x[VMC_MAX_THETA];
+};
+
+__global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restrict__ E,
+                                                           const double* __restrict__ dE, long N,
+                                                           int nth, double lam, double eta,
+                                                           double* __restrict__ delta,
+                                                           double* __restrict__ stats) {
+  __shared__ GnShared sh;
+  const int t = threadIdx.x;
+  const double inv_n = 1.0 / (double)N;
+  double a = 0.0;
+  for (long k = t; k < N; k += VMC_GN_THREADS) a += E[k];
+  const double m = gn_block_sum(a, sh.red) * inv_n;
+  a = 0.0;
+  for (long k = t; k < N; k += VMC_GN_THREADS) a += fabs(E[k] - m);
+  const double mad = gn_block_sum(a, sh.red) * inv_n;
+  const double lo = m - 5.0 * mad, hi = m + 5.0 * mad;
+  a = 0.0;
+  double ncl = 0.0;
+  for (long k = t; k < N; k += VMC_GN_THREADS) {
+    const double e = E[k];
+    a += e < lo ? lo : (e > hi ? hi : e);
+    ncl += (e < lo || e > hi) ? 1.0 : 0.0;
+  }
+  const double mean = gn_block_sum(a, sh.red) * inv_n;
+  const double nclip = gn_block_sum(ncl, sh.red);
+  a = 0.0;
+  for (long k = t; k < N; k += VMC_GN_THREADS) {
+    const double e = E[k];
+    const double r = (e < lo ? lo : (e > hi ? hi : e)) - mean;
+    a += r * r;
+  }
+  const double var = gn_block_sum(a, sh.red) / (double)(N - 1);
+  // derivatives of m and of the MAD, then of the clipped energies
+  for (int p = 0; p < nth; ++p) {
+    a = 0.0;
+    for (long k = t; k < N; k += VMC_GN_THREADS) a += dE[k * nth + p];
+    const double s = gn_block_sum(a, sh.red);
+    if (t == 0) sh.dm[p] = s * inv_n;
+  }
+  __syncthreads();
+  for (int p = 0; p < nth; ++p) {
+    a = 0.0;
+    for (long k = t; k < N; k += VMC_GN_THREADS) {
+      const double df = E[k] - m;
+      const double sg = df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0);
+      a += sg * (dE[k * nth + p] - sh.dm[p]);
+    }
+    const double s = gn_block_sum(a, sh.red);
+    if (t == 0) sh.dmad[p] = s * inv_n;
+  }
+  __syncthreads();
+  auto dclip = [&](long k, int p) {
+    const double e = E[k];
+    if (e < lo) return sh.dm[p] - 5.0 * sh.dmad[p];
+    if (e > hi) return sh.dm[p] + 5.0 * sh.dmad[p];
+    return dE[k * nth + p];
+  };
+  for (int p = 0; p < nth; ++p) {
+    a = 0.0;
+    for (long k = t; k < N; k += VMC_GN_THREADS) a += dclip(k, p);
+    const double s = gn_block_sum(a, sh.red);
+    if (t == 0) sh.mdt[p] = s * inv_n;
+  }
+  __syncthreads();
+  // residual r_k = Et_k - mean, dr_kp = dEt_kp - mean_k(dEt_kp)
+  for (int p = 0; p < nth; ++p) {
+    a = 0.0;
+    for (long k = t; k < N; k += VMC_GN_THREADS) {
+      const double e = E[k];
+      const double r = (e < lo ? lo : (e > hi ? hi : e)) - mean;
+      a += (dclip(k, p) - sh.mdt[p]) * r;
+    }
+    const double s = gn_block_sum(a, sh.red);
+    if (t == 0) sh.grad[p] = 2.0 * s / (double)(N - 1);
+  }
+  for (int p = 0; p < nth; ++p) {
+    for (int q = 0; q <= p; ++q) {
+      a = 0.0;
+      for (long k = t; k < N; k += VMC_GN_THREADS)
+        a += (dclip(k, p) - sh.mdt[p]) * (dclip(k, q) - sh.mdt[q]);
+      const double s = gn_block_sum(a, sh.red);
+      if (t == 0) {
+        const double c = s * inv_n + (p == q ? lam : 0.0);
+        sh.C[p * nth + q] = c;
+        sh.C[q * nth + p] = c;
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    // Cholesky C = L L^T in place (lower), then L y = grad, L^T x = y, delta = -eta x
+    double info = 0.0;
+    for (int j = 0; j < nth && info == 0.0; ++j) {
+      double s = sh.C[j * nth + j];
+      for (int k = 0; k < j; ++k) s -= sh.C[j * nth + k] * sh.C[j * nth + k];
+      if (!(s > 0.0)) {
+        info = j + 1;
+        break;
+      }
+      const double ljj = sqrt(s);
+      sh.C[j * nth + j] = ljj;
+      for (int i = j + 1; i < nth; ++i) {
+        double v = sh.C[i * nth + j];
+        for (int k = 0; k < j; ++k) v -= sh.C[i * nth + k] * sh.C[j * nth + k];
+        sh.C[i * nth + j] = v / ljj;
+      }
+    }
+    if (info == 0.0) {
+      for (int i = 0; i < nth; ++i) {
+        double v = sh.grad[i];
+        for (int k = 0; k < i; ++k) v -= sh.C[i * nth + k] * sh.x[k];
+        sh.x[i] = v / sh.C[i * nth + i];
+      }
+      for (int i = nth - 1; i >= 0; --i) {
+        double v = sh.x[i];
+        for (int k = i + 1; k < nth; ++k) v -= sh.C[k * nth + i] * sh.x[k];
+        sh.x[i] = v / sh.C[i * nth + i];
+      }
+      for (int i = 0; i < nth; ++i) delta[i] = -eta * sh.x[i];
+    } else {
+      for (int i = 0; i < nth; ++i) delta[i] = __builtin_nan("");
+    }
+    stats[0] = m;
+    stats[1] = mad;
+    stats[2] = mean;
+    stats[3] = var;
+    stats[4] = nclip;
+    stats[5] = info;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+struct VmcLayout {
+  double* atom_xyz; int* ints; double* prim; double* comp; double* nuc;
+};
+
+static VmcLayout layout_vmc(Arena& ar, int n_atom, int n_shell, int n_prim, int n_ao, int n_nuc) {
+  VmcLayout L;
+  L.atom_xyz = ar.take<double>(3 * (size_t)n_atom);
+  L.ints = ar.take<int>(4 * (size_t)n_shell + 2);
+  L.prim = ar.take<double>(2 * (size_t)n_prim);
+  L.comp = ar.take<double>(n_ao);
+  L.nuc = ar.take<double>(4 * (size_t)(n_nuc > 0 ? n_nuc : 1));
+  return L;
+}
+
+size_t ws_vmc(int n_ao) {
+  Arena ar(nullptr, 0);
+  layout_vmc(ar, 4096, 4096, 16384, n_ao > 0 ? n_ao : 1, 4096);
+  return ar.used;
+}
+
+static size_t lds_sweeps(int n, int n_ao) {
+  const int n_el = 2 * n;
+  return sizeof(double) * (4 * (size_t)n * n + n_ao + 64 + 3 * (size_t)n + 3 * n_el) + 16;
+}
+
+static size_t lds_energy(int n, int n_ao) {
+  const int n_el = 2 * n;
+  return sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n + 5 * (size_t)n_ao + 5 * 64 +
+                           n + 3 * n_el + 64) + 16;
+}
+
+constexpr size_t VMC_LDS_MAX = 160 * 1024;
+
+// Validates the system and uploads its tables; the stream is synchronised before return.
+static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st, VmcDev* out) {
+  const xtc_basis* basis = sy->basis;
+  XTC_REQUIRE(basis && sy->C_occ, "vmc: null basis or orbital coefficients");
+  XTC_REQUIRE(sy->n_occ >= 1 && sy->n_occ <= VMC_MAX_OCC, "vmc: n_occ must be in 1..32");
+  XTC_REQUIRE(basis->n_shell > 0 && basis->n_atom > 0 && basis->n_atom <= 4096 &&
+                  basis->n_shell <= 4096,
+              "vmc: bad basis sizes");
+  XTC_REQUIRE(basis->atom_xyz && basis->shell_center && basis->shell_l &&
+                  basis->shell_prim_start && basis->prim_exp && basis->prim_coef &&
+                  basis->comp_factor,
+              "vmc: null basis table");
+  XTC_REQUIRE(sy->n_nuc >= 0 && sy->n_nuc <= 4096 && (sy->n_nuc == 0 || (sy->nuc_xyz && sy->nuc_charge)),
+              "vmc: bad nuclei");
+  std::vector<int> ints(4 * basis->n_shell + 2);
+  int n_ao = 0;
+  const int ns = basis->n_shell;
+  for (int s = 0; s < ns; ++s) {
+    const int l = basis->shell_l[s];
+    XTC_REQUIRE(l >= 0 && l <= VMC_MAX_L, "vmc: angular momentum out of range");
+    XTC_REQUIRE(basis->shell_center[s] >= 0 && basis->shell_center[s] < basis->n_atom,
+                "vmc: shell centre out of range");
+    XTC_REQUIRE(basis->shell_prim_start[s + 1] > basis->shell_prim_start[s],
+                "vmc: shell without primitives");
+    ints[s] = basis->shell_center[s];
+    ints[ns + s] = l;
+    ints[2 * ns + s] = basis->shell_prim_start[s];
+    ints[3 * ns + 1 + s] = n_ao;
+    n_ao += (l + 1) * (l + 2) / 2;
+  }
+  ints[2 * ns + ns] = basis->shell_prim_start[ns];
+  ints[3 * ns + 1 + ns] = n_ao;
+  const int n_prim = basis->shell_prim_start[ns];
+  XTC_REQUIRE(basis->shell_prim_start[0] == 0 && n_prim <= 16384, "vmc: bad primitive table");
+  XTC_REQUIRE(n_ao == basis->n_ao, "vmc: n_ao does not match the shells");
+  VmcLayout L = layout_vmc(ar, basis->n_atom, ns, n_prim, n_ao, sy->n_nuc);
+  XTC_TRY(need_ws(ar));
+  std::vector<double> prim(2 * (size_t)n_prim);
+  for (int p = 0; p < n_prim; ++p) {
+    prim[p] = basis->prim_exp[p];
+    prim[n_prim + p] = basis->prim_coef[p];
+  }
+  std::vector<double> nuc(4 * (size_t)(sy->n_nuc > 0 ? sy->n_nuc : 1), 0.0);
+  for (int I = 0; I < sy->n_nuc; ++I) {
+    for (int c = 0; c < 3; ++c) nuc[4 * I + c] = sy->nuc_xyz[3 * I + c];
+    nuc[4 * I + 3] = sy->nuc_charge[I];
+  }
+  XTC_HIP(hipMemcpyAsync(L.atom_xyz, basis->atom_xyz, sizeof(double) * 3 * basis->n_atom,
+                         hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.prim, prim.data(), sizeof(double) * prim.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.comp, basis->comp_factor, sizeof(double) * n_ao, hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.nuc, nuc.data(), sizeof(double) * nuc.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipStreamSynchronize(st));   // host staging vectors end with this call
+  VmcDev v;
+  v.b = VmcBasis{L.atom_xyz, L.ints, L.ints + ns, L.ints + 2 * ns, L.ints + 3 * ns + 1,
+                 L.prim, L.prim + n_prim, L.comp, ns, n_ao};
+  v.C = sy->C_occ;
+  v.nuc = L.nuc;
+  v.n_occ = sy->n_occ;
+  v.n_nuc = sy->n_nuc;
+  v.e_nuc = sy->e_nuc;
+  *out = v;
+  return XTC_OK;
+}
+
+}  // namespace xtc
+
+using namespace xtc;
+
+extern "C" xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* R,
+                                     int32_t n_sweeps, double step, const double* normals,
+                                     const double* uniforms, int64_t* accepted, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  XTC_REQUIRE(sys && (n_walkers == 0 || (R && accepted)), "xtc_vmc_sample: null argument");
+  XTC_REQUIRE(n_walkers >= 0 && n_walkers <= (int64_t)1 << 31, "xtc_vmc_sample: bad n_walkers");
+  XTC_REQUIRE(n_sweeps >= 0, "xtc_vmc_sample: n_sweeps < 0");
+  XTC_REQUIRE(n_sweeps == 0 || (normals && uniforms), "xtc_vmc_sample: null draws");
+  XTC_REQUIRE(std::isfinite(step), "xtc_vmc_sample: step not finite");
+  hipStream_t st = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  VmcDev v;
+  XTC_TRY(vmc_upload(sys, ar, st, &v));
+  const size_t lds = lds_sweeps(v.n_occ, v.b.n_ao);
+  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_sample: n_ao too large for the walker's LDS");
+  if (n_walkers == 0) return XTC_OK;
+  size_t tk = timing_begin(TM_VMC_SAMPLE, st);
+  hipLaunchKernelGGL(k_vmc_sweeps, dim3((unsigned)n_walkers), dim3(64), lds, st, v, R,
+                     (long)n_walkers, n_sweeps, step, normals, uniforms, (long long*)accepted);
+  XTC_CHECK_LAUNCH();
+  timing_end(tk, st);
+  return XTC_OK;
+}
+
+extern "C" xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator* corr,
+                                           int64_t n_walkers, const double* R, double* E,
+                                           double* dE, void* ws, size_t ws_bytes, void* stream) {
+  XTC_REQUIRE(sys && corr && (n_walkers == 0 || (R && E)), "xtc_vmc_local_energy: null argument");
+  XTC_REQUIRE(n_walkers >= 0 && n_walkers <= (int64_t)1 << 31, "xtc_vmc_local_energy: bad n_walkers");
+  if (corr->form != XTC_U_EE) {
+    set_error("xtc_vmc_local_energy: only the EE correlator form has a Laplacian here");
+    return XTC_ERR_UNSUPPORTED;
+  }
+  XTC_REQUIRE(corr->n_terms >= 1 && corr->n_terms <= VMC_MAX_TERMS && corr->mno && corr->c,
+              "xtc_vmc_local_energy: EE correlator needs 1..12 terms");
+  XTC_REQUIRE(corr->d > 0.0 && std::isfinite(corr->d), "xtc_vmc_local_energy: d must be > 0");
+  EECoefV cf;
+  cf.n = corr->n_terms;
+  cf.d = corr->d;
+  for (int k = 0; k < VMC_MAX_TERMS; ++k) {
+    cf.o[k] = k < cf.n ? corr->mno[3 * k + 2] : 0;
+    cf.c[k] = k < cf.n ? corr->c[k] : 0.0;
+    XTC_REQUIRE(k >= cf.n || (corr->mno[3 * k] == 0 && corr->mno[3 * k + 1] == 0 &&
+                              cf.o[k] >= 0 && cf.o[k] <= 64),
+                "xtc_vmc_local_energy: EE terms are (0, 0, o) with 0 <= o <= 64");
+  }
+  hipStream_t st = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  VmcDev v;
+  XTC_TRY(vmc_upload(sys, ar, st, &v));
+  const size_t lds = lds_energy(v.n_occ, v.b.n_ao);
+  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: n_ao too large for the walker's LDS");
+  if (n_walkers == 0) return XTC_OK;
+  size_t tk = timing_begin(TM_VMC_ENERGY, st);
+  hipLaunchKernelGGL(k_vmc_energy, dim3((unsigned)n_walkers), dim3(64), lds, st, v, cf, R,
+                     (long)n_walkers, E, dE);
+  XTC_CHECK_LAUNCH();
+  timing_end(tk, st);
+  return XTC_OK;
+}
+
+extern "C" xtc_status xtc_vmc_gn_step(int64_t n_walkers, int32_t n_params, const double* E,
+                                      const double* dE, double lambda, double eta, double* delta,
+                                      double* stats, void* stream) {
+  XTC_REQUIRE(E && dE && delta && stats, "xtc_vmc_gn_step: null argument");
+  XTC_REQUIRE(n_walkers >= 2, "xtc_vmc_gn_step: need at least two walkers");
+  XTC_REQUIRE(n_params >= 1 && n_params <= VMC_MAX_THETA, "xtc_vmc_gn_step: n_params must be in 1..64");
+  XTC_REQUIRE(lambda >= 0.0 && std::isfinite(lambda) && std::isfinite(eta),
+              "xtc_vmc_gn_step: lambda must be >= 0 and finite, eta finite");
+  hipStream_t st = as_stream(stream);
+  size_t tk = timing_begin(TM_VMC_GN, st);
+  hipLaunchKernelGGL(k_vmc_gn, dim3(1), dim3(VMC_GN_THREADS), 0, st, E, dE, (long)n_walkers,
+                     n_params, lambda, eta, delta, stats);
+  XTC_CHECK_LAUNCH();
+  timing_end(tk, st);
+  return XTC_OK;
+}

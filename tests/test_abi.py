@@ -114,3 +114,51 @@ def test_exchange_argument_checks_return_invalid_arg():
                                  piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, None, None, None, None, None,
                                  None, C.byref(exs), None, 0, None)
     assert st == -1 and b"rank" in lib.xtc_last_error()
+
+
+def test_vmc_argument_checks():
+    """The VMC entry points reject bad sizes, forms and workspaces before any copy or launch."""
+    from paper_2607_17314_amd import _lib as L
+    from workloads import make_config
+    lib = L.lib()
+    wl = make_config("h2_tiny")
+    from paper_2607_17314_amd.api import _HostBasis
+    hb = _HostBasis(wl.basis)
+    fake = C.c_void_p(8)
+    nuc = np.ascontiguousarray(wl.atom_xyz, np.float64)
+    Z = np.ones(2)
+
+    def system(n_occ):
+        return L.VmcSystem(C.pointer(hb.s), n_occ, fake, 2, nuc.ctypes.data_as(L.D),
+                           Z.ctypes.data_as(L.D), 0.7)
+
+    big = lib.xtc_workspace_bytes(L.XTC_CALL_VMC, 0, 0, 0, wl.n_ao, 0)
+    assert big > 0
+    for n_occ in (0, 33):
+        s = system(n_occ)
+        assert lib.xtc_vmc_sample(C.byref(s), 4, fake, 1, 0.5, fake, fake, fake, fake, big, None) == -1
+        assert b"n_occ" in lib.xtc_last_error()
+    s = system(1)
+    assert lib.xtc_vmc_sample(C.byref(s), 4, fake, -1, 0.5, fake, fake, fake, fake, big, None) == -1
+    assert lib.xtc_vmc_sample(C.byref(s), 4, fake, 2, 0.5, None, fake, fake, fake, big, None) == -1
+    # too small a workspace is reported before the basis is copied
+    assert lib.xtc_vmc_sample(C.byref(s), 4, fake, 1, 0.5, fake, fake, fake, fake, 64, None) == -4
+    # the BH form has no local energy here; an EE form with 13 terms is refused
+    mno = np.array([[0, 0, 2]], np.int32)
+    cc = np.array([0.3])
+    bh = L.Correlator(1, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0, None, 0,
+                      None, None)
+    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(bh), 4, fake, fake, None, fake, big, None) == -5
+    mno13 = np.array([[0, 0, k] for k in range(1, 14)], np.int32)
+    c13 = np.zeros(13)
+    ee13 = L.Correlator(0, 13, mno13.ctypes.data_as(L.I32), 1, c13.ctypes.data_as(L.D), 1.0, None, 0,
+                        None, None)
+    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(ee13), 4, fake, fake, None, fake, big, None) == -1
+    ee = L.Correlator(0, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), -1.0, None, 0,
+                      None, None)
+    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(ee), 4, fake, fake, None, fake, big, None) == -1
+    # Gauss-Newton: at least two walkers, 1..64 parameters, lambda >= 0
+    gn = lib.xtc_vmc_gn_step
+    assert gn(1, 3, fake, fake, 0.1, 1.0, fake, fake, None) == -1
+    assert gn(10, 65, fake, fake, 0.1, 1.0, fake, fake, None) == -1
+    assert gn(10, 3, fake, fake, -0.1, 1.0, fake, fake, None) == -1
