@@ -56,6 +56,9 @@ def parse():
                         "energies with derivatives, Gauss-Newton) on the workload's determinant")
     p.add_argument("--walkers", type=int, default=16384)
     p.add_argument("--vmc-sweeps", type=int, default=20)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="copy 1 GiB device to device once before the timed region (the known-size "
+                        "kernel that calibrates the HBM byte counters)")
     p.add_argument("--grad", action="store_true",
                    help="also time the adjoint (xtc_grad) once, with seeded cotangents for u1, u3 "
                         "and the field (D1/D4 cotangents add one recomputation of stage 1)")
@@ -97,6 +100,13 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if a.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB device-to-device copy done")
     for i in range(a.warmup):
         step(prec)
         torch.cuda.synchronize()
@@ -141,7 +151,10 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "stage-1 pair kernel (k_stage1_split)"
                      if prec == L.XTC_SPLIT_F16 else "stage-1 pair kernel (k_stage1_f64)",
                      "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4),
+                     "traffic": (recorded_traffic("stage1_split_h20_hbm_traffic.md")
+                                 if prec == L.XTC_SPLIT_F16 and a.config == "h20" else None),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launch_ms": round(launch_ms, 3), "launches_per_step": launches // a.steps},
     }
     if prec == L.XTC_SPLIT_F16:
@@ -298,6 +311,29 @@ def assembly_bench(wl, inter, width, log):
                            "launches": ap["launches"]}
     log(f"assembly: prepare {t_prep:.3f} s, panels {t_pan:.3f} s, one-body {t_one:.3f} s")
     return res
+
+
+def recorded_traffic(summary: str):
+    """Calibrated HBM bytes per launch from a committed counter summary under profiles/,
+    or None when the summary is missing or the kernel source has changed since (its
+    SHA-1 differs from the one recorded with the counters)."""
+    import hashlib
+    import re
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", summary)).read()
+    except OSError:
+        return None
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    src = re.search(r"^source: (\S+)$", text, re.M)
+    sha = re.search(r"^source_sha1: ([0-9a-f]{40})$", text, re.M)
+    if not (t and src and sha):
+        return None
+    try:
+        now = hashlib.sha1(open(os.path.join(root, src.group(1)), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return int(t.group(1)) if now == sha.group(1) else None
 
 
 def _vmc_flops(wl, n_el):
