@@ -371,8 +371,8 @@ typedef struct {
  * number of accepted moves, or -1 for a walker whose starting determinant is exactly
  * singular (left unmoved). With n_walkers = 0, R, accepted and the draws may be NULL.
  * Workspace: xtc_workspace_bytes(XTC_CALL_VMC, 0, 0, 0, n_ao, 0).
- * Limits: n_occ <= 32; the walker's LDS (4 n_occ^2 + n_ao + 9 n_occ + 64 doubles) within
- * 160 KB. FP64. Asynchronous after the basis upload. */
+ * Limits: n_occ <= 32; the walker's LDS (4 n_occ^2 + n_ao + 17 n_occ + 64 doubles, plus the
+ * basis tables: 4 n_shell + 2 n_prim doubles and 4 n_shell ints) within 160 KB. FP64. Asynchronous after the basis upload. */
 xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* R,
                           int32_t n_sweeps, double step, const double* normals,
                           const double* uniforms, int64_t* accepted, void* ws, size_t ws_bytes,
@@ -386,7 +386,8 @@ xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* 
  * E: device [n_walkers]; dE: device [n_walkers][n_terms + 1] or NULL. A walker whose
  * determinant is exactly singular gets NaN. Only the EE form (1 .. 12 terms (0, 0, o))
  * is accepted; the BH form returns XTC_ERR_UNSUPPORTED. Workspace as xtc_vmc_sample;
- * LDS per walker 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles within 160 KB. FP64. */
+ * LDS per walker 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles plus the basis tables within
+ * 160 KB. FP64. */
 xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator* corr,
                                 int64_t n_walkers, const double* R, double* E, double* dE,
                                 void* ws, size_t ws_bytes, void* stream);

@@ -25,21 +25,20 @@ constexpr int VMC_MAX_TERMS = 12;    // EE terms of the local-energy kernel
 constexpr int VMC_MAX_THETA = 64;    // parameters of the Gauss-Newton step
 constexpr int VMC_GN_THREADS = 1024;
 
+// Basis tables as the kernels hold them (staged into LDS at kernel start): per shell the
+// centre {x, y, z, 0} and {l, first primitive, end primitive, first AO}; per primitive
+// {exponent, coefficient}. The Cartesian component factors are folded into the orbital
+// coefficients (C'[a][k] = comp_a C[a][k]), so the AO rows below omit them.
 struct VmcBasis {
-  const double* atom_xyz;
-  const int* shell_center;
-  const int* shell_l;
-  const int* shell_prim_start;
-  const int* shell_ao_start;
-  const double* prim_exp;
-  const double* prim_coef;
-  const double* comp;
-  int n_shell, n_ao;
+  const double* shd;   // [n_shell][4]
+  const int* shi;      // [n_shell][4]
+  const double* prim;  // [n_prim][2]
+  int n_shell, n_prim, n_ao;
 };
 
 struct VmcDev {
   VmcBasis b;
-  const double* C;      // [n_ao][n_occ]
+  const double* C;      // [n_ao][n_occ], component factors folded in
   const double* nuc;    // [n_nuc][4]: x, y, z, Z
   int n_occ, n_nuc;
   double e_nuc;
@@ -52,65 +51,77 @@ struct EECoefV {
   double c[VMC_MAX_TERMS];
 };
 
-// AO values (and, with LAP, gradients and Laplacians) of shell s at the point p, written
-// to chi[a] (and chi[n_ao * q + a], q = 1..4). chi = f P g(s), g = sum c e^{-alpha r^2}:
-// d_x chi = f (i x^{i-1} g + 2 x^{i+1} g') y^j z^k, lap chi = f [g lap P + P (4 l g' + 6 g'
-// + 4 r^2 g'')], primes in s = r^2.
+// x^n for 0 <= n <= VMC_MAX_L + 1 by a fixed-length predicated product (no register
+// tables indexed by lane-varying exponents).
+__device__ __forceinline__ double vmc_ipow(double x, int n) {
+  double r = 1.0;
+#pragma unroll
+  for (int q = 0; q < VMC_MAX_L + 1; ++q) r = q < n ? r * x : r;
+  return r;
+}
+
+// AO rows (without the component factor) of shell s at the point p, written to chi[a]
+// and, with LAP, chi[n_ao * q + a] for q = 1..4 (gradient, Laplacian). chi = P g(s),
+// P = x^i y^j z^k, g = sum c e^{-alpha r^2}: d_x chi = (i x^{i-1} g + 2 x^{i+1} g') y^j z^k,
+// lap chi = g lap P + P (4 l g' + 6 g' + 4 r^2 g''), primes in s = r^2. Tables in LDS.
 template <bool LAP>
-__device__ void vmc_shell(const VmcBasis& b, int s, double px, double py, double pz,
-                          double* chi) {
-  const int cen = b.shell_center[s];
-  const int l = b.shell_l[s];
-  const double x = px - b.atom_xyz[3 * cen], y = py - b.atom_xyz[3 * cen + 1],
-               z = pz - b.atom_xyz[3 * cen + 2];
+__device__ void vmc_shell(const double* shd, const int* shi, const double* prim, int n_ao, int s,
+                          double px, double py, double pz, double* chi) {
+  const double x = px - shd[4 * s], y = py - shd[4 * s + 1], z = pz - shd[4 * s + 2];
+  const int l = shi[4 * s], p0 = shi[4 * s + 1], p1 = shi[4 * s + 2];
+  int a = shi[4 * s + 3];
   const double r2 = x * x + y * y + z * z;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int p = b.shell_prim_start[s]; p < b.shell_prim_start[s + 1]; ++p) {
-    const double al = b.prim_exp[p];
-    const double e = b.prim_coef[p] * exp(-al * r2);
+  for (int p = p0; p < p1; ++p) {
+    const double al = prim[2 * p];
+    const double e = prim[2 * p + 1] * exp(-al * r2);
     g0 += e;
     if (LAP) {
       g1 -= al * e;
       g2 += al * al * e;
     }
   }
-  double xp[VMC_MAX_L + 2], yp[VMC_MAX_L + 2], zp[VMC_MAX_L + 2];
-  xp[0] = yp[0] = zp[0] = 1.0;
-  for (int n = 1; n <= l + 1; ++n) {
-    xp[n] = xp[n - 1] * x;
-    yp[n] = yp[n - 1] * y;
-    zp[n] = zp[n - 1] * z;
-  }
-  int a = b.shell_ao_start[s];
-  const int n_ao = b.n_ao;
   for (int i = l; i >= 0; --i) {
+    const double xi = vmc_ipow(x, i);
     for (int j = l - i; j >= 0; --j, ++a) {
       const int k = l - i - j;
-      const double f = b.comp[a];
-      const double P = xp[i] * yp[j] * zp[k];
-      chi[a] = f * P * g0;
+      const double yj = vmc_ipow(y, j), zk = vmc_ipow(z, k);
+      const double P = xi * yj * zk;
+      chi[a] = P * g0;
       if (LAP) {
-        const double dxi = i > 0 ? i * xp[i - 1] : 0.0;
-        const double dyj = j > 0 ? j * yp[j - 1] : 0.0;
-        const double dzk = k > 0 ? k * zp[k - 1] : 0.0;
-        chi[n_ao + a] = f * yp[j] * zp[k] * (dxi * g0 + 2.0 * xp[i + 1] * g1);
-        chi[2 * n_ao + a] = f * xp[i] * zp[k] * (dyj * g0 + 2.0 * yp[j + 1] * g1);
-        chi[3 * n_ao + a] = f * xp[i] * yp[j] * (dzk * g0 + 2.0 * zp[k + 1] * g1);
+        const double xm = i > 0 ? vmc_ipow(x, i - 1) : 0.0;
+        const double ym = j > 0 ? vmc_ipow(y, j - 1) : 0.0;
+        const double zm = k > 0 ? vmc_ipow(z, k - 1) : 0.0;
+        chi[n_ao + a] = yj * zk * (i * xm * g0 + 2.0 * xi * x * g1);
+        chi[2 * n_ao + a] = xi * zk * (j * ym * g0 + 2.0 * yj * y * g1);
+        chi[3 * n_ao + a] = xi * yj * (k * zm * g0 + 2.0 * zk * z * g1);
         double lapP = 0.0;
-        if (i >= 2) lapP += i * (i - 1) * xp[i - 2] * yp[j] * zp[k];
-        if (j >= 2) lapP += j * (j - 1) * xp[i] * yp[j - 2] * zp[k];
-        if (k >= 2) lapP += k * (k - 1) * xp[i] * yp[j] * zp[k - 2];
-        chi[4 * n_ao + a] = f * (g0 * lapP + P * ((4.0 * l + 6.0) * g1 + 4.0 * r2 * g2));
+        if (i >= 2) lapP += i * (i - 1) * vmc_ipow(x, i - 2) * yj * zk;
+        if (j >= 2) lapP += j * (j - 1) * xi * vmc_ipow(y, j - 2) * zk;
+        if (k >= 2) lapP += k * (k - 1) * xi * yj * vmc_ipow(z, k - 2);
+        chi[4 * n_ao + a] = g0 * lapP + P * ((4.0 * l + 6.0) * g1 + 4.0 * r2 * g2);
       }
     }
   }
 }
 
+// Copies the basis tables into LDS (the caller synchronises before use).
+__device__ __forceinline__ void vmc_stage(const VmcBasis& b, double* shd, int* shi,
+                                          double* prim) {
+  for (int i = threadIdx.x; i < 4 * b.n_shell; i += 64) {
+    shd[i] = b.shd[i];
+    shi[i] = b.shi[i];
+  }
+  for (int i = threadIdx.x; i < 2 * b.n_prim; i += 64) prim[i] = b.prim[i];
+}
+
 // All AOs of the point p into chi (lanes over shells); the caller synchronises.
 template <bool LAP>
-__device__ __forceinline__ void vmc_aos(const VmcBasis& b, double px, double py, double pz,
+__device__ __forceinline__ void vmc_aos(const VmcBasis& b, const double* shd, const int* shi,
+                                        const double* prim, double px, double py, double pz,
                                         double* chi) {
-  for (int s = threadIdx.x; s < b.n_shell; s += 64) vmc_shell<LAP>(b, s, px, py, pz, chi);
+  for (int s = threadIdx.x; s < b.n_shell; s += 64)
+    vmc_shell<LAP>(shd, shi, prim, b.n_ao, s, px, py, pz, chi);
 }
 
 // out[q * ostride + k] = sum_a chi[q * n_ao + a] C[a][k], q < NQ, k < n_occ: lanes as
@@ -126,7 +137,19 @@ __device__ __forceinline__ void vmc_orbitals(const VmcDev& v, const double* chi,
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
   if (k < n) {
-    for (int a = sl; a < n_ao; a += P) {
+    // eight coefficient loads in flight per batch; the sum keeps the order a = sl, sl + P, ...
+    int a = sl;
+    for (; a + 7 * P < n_ao; a += 8 * P) {
+      double cv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cv[u] = v.C[(long)(a + u * P) * n + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a + u * P] * cv[u];
+      }
+    }
+    for (; a < n_ao; a += P) {
       const double cak = v.C[(long)a * n + k];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a] * cak;
@@ -201,8 +224,9 @@ __device__ __forceinline__ double vmc_step(double r, double s, double e) {
 
 // ---------------------------------------------------------------------------------------
 // Sampler: n_sweeps sweeps of single-electron moves, electrons in index order.
-// LDS (doubles): Ainv [2][n][n], aug [n][2n], chi [n_ao], part [64], phin [n], wv [n],
-// fac [n], R [n_el][3]; then int piv.
+// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], Ainv [2][n][n],
+// aug [n][2n], chi [n_ao], part [64], phin [n], wv [n], fac [n], R [n_el][3], the sweep's
+// draws [n_el][4] (eta_x, eta_y, eta_z, u); then ints: shell records [n_shell][4], piv.
 __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict__ R, long n_w,
                                                    int n_sweeps, double step,
                                                    const double* __restrict__ normals,
@@ -211,7 +235,9 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
   extern __shared__ double lds[];
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   const long w = blockIdx.x;
-  double* Ainv = lds;
+  double* shd = lds;
+  double* prim = shd + 4 * v.b.n_shell;
+  double* Ainv = prim + 2 * v.b.n_prim;
   double* aug = Ainv + 2 * n * n;
   double* chi = aug + 2 * n * n;
   double* part = chi + v.b.n_ao;
@@ -219,14 +245,17 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
   double* wv = phin + n;
   double* fac = wv + n;
   double* Rs = fac + n;
-  int* piv = (int*)(Rs + 3 * n_el);
+  double* dr = Rs + 3 * n_el;
+  int* shi = (int*)(dr + 4 * n_el);
+  int* piv = shi + 4 * v.b.n_shell;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  vmc_stage(v.b, shd, shi, prim);
   __syncthreads();
   // inverse Slater matrices of the starting configuration
   for (int sp = 0; sp < 2; ++sp) {
     for (int ii = 0; ii < n; ++ii) {
       const int e = sp * n + ii;
-      vmc_aos<false>(v.b, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+      vmc_aos<false>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
       __syncthreads();
       vmc_orbitals<1>(v, chi, part, aug + ii * 2 * n, 0);
     }
@@ -241,27 +270,48 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
     __syncthreads();
   }
   long long acc = 0;
+  // A sweep's draws (one record per electron) are loaded one sweep ahead by lanes
+  // 0 .. n_el - 1 (vector loads, straight from HBM) and staged in LDS at the sweep's start.
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+  auto fetch = [&](int s) {
+    if (lane < n_el) {
+      const long di = ((long)s * n_el + lane) * n_w + w;
+      q0 = normals[3 * di];
+      q1 = normals[3 * di + 1];
+      q2 = normals[3 * di + 2];
+      q3 = uniforms[di];
+    }
+  };
+  if (n_sweeps > 0) fetch(0);
   for (int s = 0; s < n_sweeps; ++s) {
+    if (lane < n_el) {
+      dr[4 * lane] = q0;
+      dr[4 * lane + 1] = q1;
+      dr[4 * lane + 2] = q2;
+      dr[4 * lane + 3] = q3;
+    }
+    __syncthreads();
+    if (s + 1 < n_sweeps) fetch(s + 1);
     for (int e = 0; e < n_el; ++e) {
       const int sp = e / n, ii = e - sp * n;
-      const long di = ((long)s * n_el + e) * n_w + w;
+      const double u = dr[4 * e + 3];
       // r' = r + step * eta, rounded as two separate operations
-      const double px = vmc_step(Rs[3 * e], step, normals[3 * di]);
-      const double py = vmc_step(Rs[3 * e + 1], step, normals[3 * di + 1]);
-      const double pz = vmc_step(Rs[3 * e + 2], step, normals[3 * di + 2]);
-      vmc_aos<false>(v.b, px, py, pz, chi);
+      const double px = vmc_step(Rs[3 * e], step, dr[4 * e]);
+      const double py = vmc_step(Rs[3 * e + 1], step, dr[4 * e + 1]);
+      const double pz = vmc_step(Rs[3 * e + 2], step, dr[4 * e + 2]);
+      vmc_aos<false>(v.b, shd, shi, prim, px, py, pz, chi);
       __syncthreads();
       vmc_orbitals<1>(v, chi, part, phin, 0);
       double* Ai = Ainv + sp * n * n;
       // wv[j] = sum_k phi_k(r') Ainv[k][j]; the determinant ratio is wv[ii]
       if (lane < n) {
         double t = 0.0;
+#pragma unroll 8
         for (int k = 0; k < n; ++k) t += phin[k] * Ai[k * n + lane];
         wv[lane] = t;
       }
       __syncthreads();
       const double ratio = wv[ii];
-      const double u = uniforms[di];
       if (u < ratio * ratio) {
         // Sherman-Morrison for row ii of A replaced by phi(r'):
         // Ainv[k][j] -= Ainv[k][ii] (wv[j] - delta_{j ii}) / ratio
@@ -288,8 +338,9 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
 
 // ---------------------------------------------------------------------------------------
 // Local energy and its parameter derivatives, one walker per workgroup.
-// LDS (doubles): A5 [5][n_el][n], aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64],
-// fac [n], R [n_el][3], red [64]; then int piv.
+// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], A5 [5][n_el][n],
+// aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64], fac [n], R [n_el][3], red [64];
+// then ints: shell records [n_shell][4], piv.
 __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
                                                    const double* __restrict__ R, long n_w,
                                                    double* __restrict__ E,
@@ -298,7 +349,9 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   const long w = blockIdx.x;
   const int nth = cf.n + 1;
-  double* A5 = lds;
+  double* shd = lds;
+  double* prim = shd + 4 * v.b.n_shell;
+  double* A5 = prim + 2 * v.b.n_prim;
   double* aug = A5 + 5 * n_el * n;
   double* Ainv = aug + 2 * n * n;
   double* chi = Ainv + 2 * n * n;
@@ -306,11 +359,13 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
   double* fac = part + 5 * 64;
   double* Rs = fac + n;
   double* red = Rs + 3 * n_el;
-  int* piv = (int*)(red + 64);
+  int* shi = (int*)(red + 64);
+  int* piv = shi + 4 * v.b.n_shell;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  vmc_stage(v.b, shd, shi, prim);
   __syncthreads();
   for (int e = 0; e < n_el; ++e) {
-    vmc_aos<true>(v.b, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+    vmc_aos<true>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
     __syncthreads();
     vmc_orbitals<5>(v, chi, part, A5 + e * n, n_el * n);
   }
@@ -603,40 +658,58 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
 }
 
 // ---------------------------------------------------------------------------------------
+// C'[a][k] = comp[a] C[a][k]
+__global__ __launch_bounds__(256) void k_vmc_scale_c(const double* __restrict__ C,
+                                                     const double* __restrict__ comp, long n_ao,
+                                                     int n_occ, double* __restrict__ Cs) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_ao * n_occ) return;
+  Cs[i] = comp[i / n_occ] * C[i];
+}
+
 struct VmcLayout {
-  double* atom_xyz; int* ints; double* prim; double* comp; double* nuc;
+  double* shd; int* shi; double* prim; double* comp; double* nuc; double* Cs;
 };
 
-static VmcLayout layout_vmc(Arena& ar, int n_atom, int n_shell, int n_prim, int n_ao, int n_nuc) {
+static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_occ, int n_nuc) {
   VmcLayout L;
-  L.atom_xyz = ar.take<double>(3 * (size_t)n_atom);
-  L.ints = ar.take<int>(4 * (size_t)n_shell + 2);
+  L.shd = ar.take<double>(4 * (size_t)n_shell);
+  L.shi = ar.take<int>(4 * (size_t)n_shell);
   L.prim = ar.take<double>(2 * (size_t)n_prim);
   L.comp = ar.take<double>(n_ao);
   L.nuc = ar.take<double>(4 * (size_t)(n_nuc > 0 ? n_nuc : 1));
+  L.Cs = ar.take<double>((size_t)n_ao * n_occ);
   return L;
 }
 
 size_t ws_vmc(int n_ao) {
   Arena ar(nullptr, 0);
-  layout_vmc(ar, 4096, 4096, 16384, n_ao > 0 ? n_ao : 1, 4096);
+  const int na = n_ao > 0 ? n_ao : 1;
+  layout_vmc(ar, 4096, 16384, na, VMC_MAX_OCC, 4096);
   return ar.used;
 }
 
-static size_t lds_sweeps(int n, int n_ao) {
-  const int n_el = 2 * n;
-  return sizeof(double) * (4 * (size_t)n * n + n_ao + 64 + 3 * (size_t)n + 3 * n_el) + 16;
+static size_t lds_tables(const VmcBasis& b) {
+  return sizeof(double) * (4 * (size_t)b.n_shell + 2 * (size_t)b.n_prim) +
+         sizeof(int) * 4 * (size_t)b.n_shell;
 }
 
-static size_t lds_energy(int n, int n_ao) {
+static size_t lds_sweeps(const VmcBasis& b, int n) {
   const int n_el = 2 * n;
-  return sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n + 5 * (size_t)n_ao + 5 * 64 +
-                           n + 3 * n_el + 64) + 16;
+  return lds_tables(b) +
+         sizeof(double) * (4 * (size_t)n * n + b.n_ao + 64 + 3 * (size_t)n + 7 * n_el) + 16;
+}
+
+static size_t lds_energy(const VmcBasis& b, int n) {
+  const int n_el = 2 * n;
+  return lds_tables(b) + sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n +
+                                           5 * (size_t)b.n_ao + 5 * 64 + n + 3 * n_el + 64) + 16;
 }
 
 constexpr size_t VMC_LDS_MAX = 160 * 1024;
 
-// Validates the system and uploads its tables; the stream is synchronised before return.
+// Validates the system, uploads its tables and folds the component factors into the
+// orbital coefficients; the stream is synchronised before return (host staging ends).
 static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st, VmcDev* out) {
   const xtc_basis* basis = sy->basis;
   XTC_REQUIRE(basis && sy->C_occ, "vmc: null basis or orbital coefficients");
@@ -650,50 +723,52 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
               "vmc: null basis table");
   XTC_REQUIRE(sy->n_nuc >= 0 && sy->n_nuc <= 4096 && (sy->n_nuc == 0 || (sy->nuc_xyz && sy->nuc_charge)),
               "vmc: bad nuclei");
-  std::vector<int> ints(4 * basis->n_shell + 2);
-  int n_ao = 0;
   const int ns = basis->n_shell;
+  std::vector<double> shd(4 * (size_t)ns, 0.0);
+  std::vector<int> shi(4 * (size_t)ns);
+  int n_ao = 0;
   for (int s = 0; s < ns; ++s) {
     const int l = basis->shell_l[s];
+    const int c = basis->shell_center[s];
     XTC_REQUIRE(l >= 0 && l <= VMC_MAX_L, "vmc: angular momentum out of range");
-    XTC_REQUIRE(basis->shell_center[s] >= 0 && basis->shell_center[s] < basis->n_atom,
-                "vmc: shell centre out of range");
+    XTC_REQUIRE(c >= 0 && c < basis->n_atom, "vmc: shell centre out of range");
     XTC_REQUIRE(basis->shell_prim_start[s + 1] > basis->shell_prim_start[s],
                 "vmc: shell without primitives");
-    ints[s] = basis->shell_center[s];
-    ints[ns + s] = l;
-    ints[2 * ns + s] = basis->shell_prim_start[s];
-    ints[3 * ns + 1 + s] = n_ao;
+    for (int q = 0; q < 3; ++q) shd[4 * s + q] = basis->atom_xyz[3 * c + q];
+    shi[4 * s] = l;
+    shi[4 * s + 1] = basis->shell_prim_start[s];
+    shi[4 * s + 2] = basis->shell_prim_start[s + 1];
+    shi[4 * s + 3] = n_ao;
     n_ao += (l + 1) * (l + 2) / 2;
   }
-  ints[2 * ns + ns] = basis->shell_prim_start[ns];
-  ints[3 * ns + 1 + ns] = n_ao;
   const int n_prim = basis->shell_prim_start[ns];
   XTC_REQUIRE(basis->shell_prim_start[0] == 0 && n_prim <= 16384, "vmc: bad primitive table");
   XTC_REQUIRE(n_ao == basis->n_ao, "vmc: n_ao does not match the shells");
-  VmcLayout L = layout_vmc(ar, basis->n_atom, ns, n_prim, n_ao, sy->n_nuc);
+  VmcLayout L = layout_vmc(ar, ns, n_prim, n_ao, sy->n_occ, sy->n_nuc);
   XTC_TRY(need_ws(ar));
   std::vector<double> prim(2 * (size_t)n_prim);
   for (int p = 0; p < n_prim; ++p) {
-    prim[p] = basis->prim_exp[p];
-    prim[n_prim + p] = basis->prim_coef[p];
+    prim[2 * p] = basis->prim_exp[p];
+    prim[2 * p + 1] = basis->prim_coef[p];
   }
   std::vector<double> nuc(4 * (size_t)(sy->n_nuc > 0 ? sy->n_nuc : 1), 0.0);
   for (int I = 0; I < sy->n_nuc; ++I) {
     for (int c = 0; c < 3; ++c) nuc[4 * I + c] = sy->nuc_xyz[3 * I + c];
     nuc[4 * I + 3] = sy->nuc_charge[I];
   }
-  XTC_HIP(hipMemcpyAsync(L.atom_xyz, basis->atom_xyz, sizeof(double) * 3 * basis->n_atom,
-                         hipMemcpyHostToDevice, st));
-  XTC_HIP(hipMemcpyAsync(L.ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.shd, shd.data(), sizeof(double) * shd.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.shi, shi.data(), sizeof(int) * shi.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.prim, prim.data(), sizeof(double) * prim.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.comp, basis->comp_factor, sizeof(double) * n_ao, hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.nuc, nuc.data(), sizeof(double) * nuc.size(), hipMemcpyHostToDevice, st));
+  const long nc = (long)n_ao * sy->n_occ;
+  hipLaunchKernelGGL(k_vmc_scale_c, dim3(cdiv(nc, 256)), dim3(256), 0, st, sy->C_occ,
+                     (const double*)L.comp, (long)n_ao, sy->n_occ, L.Cs);
+  XTC_CHECK_LAUNCH();
   XTC_HIP(hipStreamSynchronize(st));   // host staging vectors end with this call
   VmcDev v;
-  v.b = VmcBasis{L.atom_xyz, L.ints, L.ints + ns, L.ints + 2 * ns, L.ints + 3 * ns + 1,
-                 L.prim, L.prim + n_prim, L.comp, ns, n_ao};
-  v.C = sy->C_occ;
+  v.b = VmcBasis{L.shd, L.shi, L.prim, ns, n_prim, n_ao};
+  v.C = L.Cs;
   v.nuc = L.nuc;
   v.n_occ = sy->n_occ;
   v.n_nuc = sy->n_nuc;
@@ -719,8 +794,8 @@ extern "C" xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walker
   Arena ar(ws, ws_bytes);
   VmcDev v;
   XTC_TRY(vmc_upload(sys, ar, st, &v));
-  const size_t lds = lds_sweeps(v.n_occ, v.b.n_ao);
-  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_sample: n_ao too large for the walker's LDS");
+  const size_t lds = lds_sweeps(v.b, v.n_occ);
+  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_sample: basis too large for the walker's LDS");
   if (n_walkers == 0) return XTC_OK;
   size_t tk = timing_begin(TM_VMC_SAMPLE, st);
   hipLaunchKernelGGL(k_vmc_sweeps, dim3((unsigned)n_walkers), dim3(64), lds, st, v, R,
@@ -756,8 +831,8 @@ extern "C" xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_
   Arena ar(ws, ws_bytes);
   VmcDev v;
   XTC_TRY(vmc_upload(sys, ar, st, &v));
-  const size_t lds = lds_energy(v.n_occ, v.b.n_ao);
-  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: n_ao too large for the walker's LDS");
+  const size_t lds = lds_energy(v.b, v.n_occ);
+  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: basis too large for the walker's LDS");
   if (n_walkers == 0) return XTC_OK;
   size_t tk = timing_begin(TM_VMC_ENERGY, st);
   hipLaunchKernelGGL(k_vmc_energy, dim3((unsigned)n_walkers), dim3(64), lds, st, v, cf, R,
