@@ -185,20 +185,28 @@ __device__ __forceinline__ void bh_channels(const EECoef& cf, const BHTable* __r
   }
 }
 
-// Same tile and MFMA structure as k_stage1_f64 (four channels), with the BH tables in LDS.
+// Same MFMA structure as k_stage1_f64 (four channels), with the BH tables in LDS and RT
+// rows per workgroup (64 or 128): the generated pair channels, whose nuclear sums dominate
+// the work, are reused by all RT rows, so RT = 128 halves the generation per row. Each
+// wave holds RT/2 rows x 32 bra points per channel.
+constexpr int BH_ROW_TILE = 128;
+
+template <int RT>
 __global__ __launch_bounds__(256) void k_stage1_f64_bh(
     const double* __restrict__ xyz, const double* __restrict__ w, const double* __restrict__ xi,
     const double* __restrict__ rho, const double* __restrict__ rhot, long n_g, int n_mu, long b0,
     long bn, EECoef cf, const BHTable* __restrict__ T, double* __restrict__ panel, long rows_pad,
     long bp) {
   constexpr int KC = 16, NCH = 4;
-  __shared__ double As[64][KC + 1];
+  constexpr int MI = RT / 32;            // 16-row sub-tiles per wave
+  constexpr int NA = RT * KC / 256;      // A elements loaded per thread per chunk
+  __shared__ double As[RT][KC + 1];
   __shared__ double Bs[NCH][KC][65];
   __shared__ double TB[BH_MAXNUC][4][64];
   __shared__ double TK[KC][BH_MAXNUC][BH_NO][BH_NP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long m0 = (long)blockIdx.y * 64;
+  const long m0 = (long)blockIdx.y * RT;
   const long nb0 = (long)blockIdx.x * 64;
   const int gb = tid & 63;
   const int gk = tid >> 6;
@@ -216,19 +224,19 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
     for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
   }
 
-  d4 acc[NCH][2][2];
+  d4 acc[NCH][MI][2];
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
   const int li = lane & 15, lk = lane >> 4;
   for (long k0 = 0; k0 < n_g; k0 += KC) {
-    double ra[4];
+    double ra[NA];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NA; ++j) {
       const int e = tid + 256 * j;
       const int row = e >> 4, kk = e & 15;
       const long g = k0 + kk, rr = m0 + row;
@@ -268,7 +276,7 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NA; ++j) {
       const int e = tid + 256 * j;
       As[e >> 4][e & 15] = ra[j];
     }
@@ -279,28 +287,30 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
-      const double a0 = As[32 * wm + li][4 * s + lk];
-      const double a1 = As[32 * wm + 16 + li][4 * s + lk];
+      double av[MI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) av[i] = As[(RT / 2) * wm + 16 * i + li][4 * s + lk];
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         const double bb0 = Bs[c][4 * s + lk][32 * wn + li];
         const double bb1 = Bs[c][4 * s + lk][32 * wn + 16 + li];
-        acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb0, acc[c][0][0], 0, 0, 0);
-        acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb1, acc[c][0][1], 0, 0, 0);
-        acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb0, acc[c][1][0], 0, 0, 0);
-        acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb1, acc[c][1][1], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          acc[c][i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bb0, acc[c][i][0], 0, 0, 0);
+          acc[c][i][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bb1, acc[c][i][1], 0, 0, 0);
+        }
       }
     }
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const long row = m0 + 32 * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
+          const long row = m0 + (RT / 2) * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
           const long col = nb0 + 32 * wn + 16 * j + li;
           if (row <= n_mu + 1 && col < bn) panel[((long)c * rows_pad + row) * bp + col] = acc[c][i][j][r];
         }
@@ -311,8 +321,9 @@ xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
   const size_t tk = timing_begin(TM_S1_KERNEL, st);
   if (a.bh) {
     XTC_REQUIRE(a.nch == 4, "BH correlator: the Laplacian channel is defined for the EE form only");
-    hipLaunchKernelGGL(k_stage1_f64_bh, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot,
-                       a.n_g, a.n_mu, a.b0, a.bn, cf, a.bh, a.panel, a.rows_pad, a.bp);
+    dim3 gbh(cdiv(a.bn, 64), cdiv(a.n_mu + 2, BH_ROW_TILE));
+    hipLaunchKernelGGL(k_stage1_f64_bh<BH_ROW_TILE>, gbh, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho,
+                       a.rhot, a.n_g, a.n_mu, a.b0, a.bn, cf, a.bh, a.panel, a.rows_pad, a.bp);
   } else if (a.nch == 4)
     hipLaunchKernelGGL(k_stage1_f64<4>, grid, dim3(256), 0, st, a.xyz, a.w, a.xi, a.rho, a.rhot, a.n_g,
                        a.n_mu, a.b0, a.bn, cf, a.panel, a.rows_pad, a.bp);
