@@ -135,6 +135,11 @@ __global__ __launch_bounds__(256) void k_x_transpose(const double* __restrict__ 
 // v_mfma_f64_16x16x4f64), k-tiles of 16 through LDS with the next tile prefetched in
 // registers. The k loop runs over (segment, k-tile) pairs, so the segment, its
 // pointers and coefficient are uniform per tile; a segment's last tile is zero-padded.
+// Launch order: a 1-D grid of 8 x ceil(tiles / 8) workgroups; the hardware deals them
+// round-robin to the 8 XCDs, so workgroup id goes to XCD id % 8, and each XCD takes a
+// contiguous run of output tiles with the M tile fastest. The workgroups that share an
+// N tile (the large, panel-independent operand S) then run together on one XCD and read
+// it through that XCD's L2 instead of each streaming it from HBM.
 struct AsmSegs {
   const double* R[4];
   const double* S[4];
@@ -146,13 +151,16 @@ struct AsmSegs {
 constexpr int AT = 128, AK = 16, ALD = AT + 2;
 
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-void k_asm_panel(AsmSegs sg, long M, long N,
-                                                   double* __restrict__ out, long ldc) {
+void k_asm_panel(AsmSegs sg, long M, long N, double* __restrict__ out, long ldc) {
   __shared__ double As[AK][ALD];
   __shared__ double Bs[AK][ALD];
+  const long n_mt = (M + AT - 1) / AT, n_tiles = n_mt * ((N + AT - 1) / AT);
+  const long per_xcd = (n_tiles + 7) / 8;
+  const long logical = (long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (logical >= n_tiles) return;   // the whole workgroup, before any barrier
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long m0 = (long)blockIdx.y * AT, n0 = (long)blockIdx.x * AT;
+  const long m0 = (logical % n_mt) * AT, n0 = (logical / n_mt) * AT;
   const int tps = (int)((sg.kseg + AK - 1) / AK);   // k-tiles per segment
   const int ntiles = tps * sg.nseg;
   const int ld = (int)sg.ld;                          // n_orb^2 < 2^31
@@ -400,8 +408,9 @@ extern "C" xtc_status xtc_assembly_panel(const xtc_assembly* a, uint32_t outputs
   const int n = a->n_orb;
   const bool has_x = a->X2 || a->X3;
   const long M = (long)(p1 - p0) * n, N = L.nn;
-  XTC_REQUIRE(cdiv(M, AT) <= 65535, "assembly: panel too wide for one launch");
-  dim3 grid(cdiv(N, AT), cdiv(M, AT));
+  const long n_tiles = (long)cdiv(N, AT) * cdiv(M, AT);
+  XTC_REQUIRE(n_tiles <= 0x7fffffffL, "assembly: panel too large for one launch");
+  dim3 grid((unsigned)(8 * ((n_tiles + 7) / 8)));
   struct Out { uint32_t bit; const double* P; double a, b; bool x; double* dst; };
   const Out outs[3] = {{XTC_ASM_K, L.PK, 0.5, 0.0, false, K},
                        {XTC_ASM_DU, L.PU, -1.0, 1.0, has_x, dU},
