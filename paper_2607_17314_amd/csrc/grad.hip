@@ -87,6 +87,99 @@ __device__ __forceinline__ void pair_grad(const EECoef& cf, const GradBasis& gb,
   if (gb.want_d) dth[gb.n] += dd;
 }
 
+// M_c(b, k) = sum_row Pbar[c][row][b] A[row][k] over the workgroup's 64 x 64 pair tile,
+// rows in steps of GK through LDS. With PF the next step's tiles are loaded into registers
+// while the current step's MFMAs run (the pair kernels run one wave per SIMD, so nothing
+// else hides the load latency); kernels without the registers for it load in place.
+template <int NCH, bool PF>
+__device__ __forceinline__ void m_tiles(const double* __restrict__ Pb, long rows_pad, long bp,
+                                        int n_rows, const double* __restrict__ xi,
+                                        const double* __restrict__ rho,
+                                        const double* __restrict__ rhot,
+                                        const double* __restrict__ w, long n_g, int n_mu,
+                                        long bt0, long bn, long kc, long k_hi,
+                                        double (*Gs)[GK][GT + 1], double (*As)[GT + 1],
+                                        d4 (&acc)[NCH][2][2]) {
+  constexpr int NG = NCH * GK * GT / 256, NA = GK * GT / 256;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  double pg[NG], pa[NA];
+  auto fetch = [&](int r0) {
+    // Pbar tile: NCH x GK rows x 64 bra (bra contiguous in memory)
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int e = tid + 256 * q;
+      const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
+      const long row = r0 + rr, b = bt0 + bb;
+      pg[q] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
+    }
+    // A tile: GK rows x 64 ket
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e / GT, kk = e % GT;
+      const long row = r0 + rr, g = kc + kk;
+      double v = 0.0;
+      if (row < n_rows && g < k_hi)
+        v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
+      pa[q] = v;
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+  if (PF) fetch(0);
+  for (int r0 = 0; r0 < n_rows; r0 += GK) {
+    __syncthreads();
+    if (PF) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const int e = tid + 256 * q;
+        Gs[e / (GK * GT)][(e / GT) % GK][e % GT] = pg[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int e = tid + 256 * q;
+        As[e / GT][e % GT] = pa[q];
+      }
+    } else {
+      for (int e = tid; e < NCH * GK * GT; e += 256) {
+        const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
+        const long row = r0 + rr, b = bt0 + bb;
+        Gs[c][rr][bb] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
+      }
+      for (int e = tid; e < GK * GT; e += 256) {
+        const int rr = e / GT, kk = e % GT;
+        const long row = r0 + rr, g = kc + kk;
+        double v = 0.0;
+        if (row < n_rows && g < k_hi)
+          v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
+        As[rr][kk] = v;
+      }
+    }
+    __syncthreads();
+    if (PF && r0 + GK < n_rows) fetch(r0 + GK);
+#pragma unroll
+    for (int s = 0; s < GK / 4; ++s) {
+      const double b0v = As[4 * s + lk][32 * wn + li];
+      const double b1v = As[4 * s + lk][32 * wn + 16 + li];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double a0 = Gs[c][4 * s + lk][32 * wm + li];
+        const double a1 = Gs[c][4 * s + lk][32 * wm + 16 + li];
+        acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[c][0][0], 0, 0, 0);
+        acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[c][0][1], 0, 0, 0);
+        acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[c][1][0], 0, 0, 0);
+        acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[c][1][1], 0, 0, 0);
+      }
+    }
+  }
+}
+
 template <int NCH>
 __global__ __launch_bounds__(256) void k_grad_pairs(
     const double* __restrict__ Pb, long rows_pad, long bp, int n_rows,
@@ -125,45 +218,8 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
       kxyz[2][tid] = xyz[2 * n_g + g];
     }
     d4 acc[NCH][2][2];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < n_rows; r0 += GK) {
-      __syncthreads();
-      // Pbar tile: NCH x 16 rows x 64 bra (bra contiguous in memory)
-      for (int e = tid; e < NCH * GK * GT; e += 256) {
-        const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
-        const long row = r0 + rr, b = bt0 + bb;
-        Gs[c][rr][bb] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
-      }
-      // A tile: 16 rows x 64 ket
-      for (int e = tid; e < GK * GT; e += 256) {
-        const int rr = e / GT, kk = e % GT;
-        const long row = r0 + rr, g = kc + kk;
-        double v = 0.0;
-        if (row < n_rows && g < k_hi)
-          v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
-        As[rr][kk] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < GK / 4; ++s) {
-        const double b0v = As[4 * s + lk][32 * wn + li];
-        const double b1v = As[4 * s + lk][32 * wn + 16 + li];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const double a0 = Gs[c][4 * s + lk][32 * wm + li];
-          const double a1 = Gs[c][4 * s + lk][32 * wm + 16 + li];
-          acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[c][0][0], 0, 0, 0);
-          acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[c][0][1], 0, 0, 0);
-          acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[c][1][0], 0, 0, 0);
-          acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[c][1][1], 0, 0, 0);
-        }
-      }
-    }
+    m_tiles<NCH, NCH == 4>(Pb, rows_pad, bp, n_rows, xi, rho, rhot, w, n_g, n_mu, bt0, bn, kc,
+                           k_hi, Gs, As, acc);
     // epilogue: the 16 pairs this lane holds, D[(l/16) + 4r][l%16] = M[bra][ket]
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -416,43 +472,8 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
       TA[I][kk] = bh_a(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g]);
     }
     d4 acc[NCH][2][2];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < n_rows; r0 += GK) {
-      __syncthreads();
-      for (int e = tid; e < NCH * GK * GT; e += 256) {
-        const int c = e / (GK * GT), rr = (e / GT) % GK, bb = e % GT;
-        const long row = r0 + rr, b = bt0 + bb;
-        Gs[c][rr][bb] = (row < n_rows && b < bn) ? Pb[((long)c * rows_pad + row) * bp + b] : 0.0;
-      }
-      for (int e = tid; e < GK * GT; e += 256) {
-        const int rr = e / GT, kk = e % GT;
-        const long row = r0 + rr, g = kc + kk;
-        double v = 0.0;
-        if (row < n_rows && g < k_hi)
-          v = w[g] * (row < n_mu ? xi[row * n_g + g] : (row == n_mu ? rho[g] : rhot[g]));
-        As[rr][kk] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < GK / 4; ++s) {
-        const double b0v = As[4 * s + lk][32 * wn + li];
-        const double b1v = As[4 * s + lk][32 * wn + 16 + li];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const double a0 = Gs[c][4 * s + lk][32 * wm + li];
-          const double a1 = Gs[c][4 * s + lk][32 * wm + 16 + li];
-          acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[c][0][0], 0, 0, 0);
-          acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[c][0][1], 0, 0, 0);
-          acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[c][1][0], 0, 0, 0);
-          acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[c][1][1], 0, 0, 0);
-        }
-      }
-    }
+    m_tiles<NCH, NT == 1 && !NL>(Pb, rows_pad, bp, n_rows, xi, rho, rhot, w, n_g, n_mu, bt0, bn,
+                                 kc, k_hi, Gs, As, acc);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
