@@ -16,7 +16,13 @@ Local energy (eq. Eloc) with H = -1/2 sum_i lap_i - sum_{i,I} Z_I / r_iI
   S_i = lap_i Phi_0 / Phi_0 = sum_k lap phi_k(r_i) [A^-1]_{k i}
 (Jacobi's formula; A the spin block holding electron i). For the EE form
 u = sum_k c_k rbar^{o_k}, rbar = d r / (1 + d r): grad_i J = sum_{j != i} (u'/r) (r_i - r_j),
-lap_i J = sum_{j != i} (u'' + 2 u' / r).
+lap_i J = sum_{j != i} (u'' + 2 u' / r). For the BH form (eq. bh-u) with
+a = a(r_iI), a' = a(r_jI), e = rbar(r_ij) and P = a^m a'^n + a'^m a^n:
+  grad_i f = c [P_a e^o grad a + P o e^{o-1} grad e],
+  lap_i f = c [P_aa e^o |grad a|^2 + P_a e^o lap a + 2 P_a o e^{o-1} grad a . grad e
+               + P (o (o-1) e^{o-2} |grad e|^2 + o e^{o-1} lap e)],
+P_a, P_aa the derivatives in a; for s = x r / (1 + x r): s' = x t^2, s'' = -2 x^2 t^3,
+grad s = s' rhat, lap s = s'' + 2 s' / r.
 
 Readings (the paper leaves the sampler's details and the schedule to its supporting
 information):
@@ -25,7 +31,8 @@ information):
     uniform draw is below |Phi_0(R') / Phi_0(R)|^2. The draws are inputs.
   * The clip bounds m_s +- 5 d_s are functions of the parameters and are
     differentiated with them (sign(0) = 0 in the MAD's derivative).
-  * Parameters theta = (c_0 .. c_{n_terms - 1}, d) of the EE form.
+  * Parameters theta = (c_0 .. c_{n_terms - 1}, d) of the EE form; for the BH form
+    theta = (c[type][term] type-major, d, b_0 .. b_{n_types - 1}).
 
 Pinned by: the AO Laplacian against central differences; the local energy
 against a finite-difference Laplacian of Psi_T built from values alone; the
@@ -76,10 +83,68 @@ def _radial(corr, r):
     return up, upp
 
 
+def _scaled(x, r):
+    """s = x r / (1 + x r) and its first two derivatives in r."""
+    t = 1.0 / (1.0 + x * r)
+    return x * r * t, x * t * t, -2.0 * x * x * t ** 3
+
+
+def _bh_grad_lap(corr, R):
+    """grad_i J and lap_i J for the BH form (eq. bh-u), summed over nuclei and terms
+    (arrays over walkers x nuclei x terms; types of c, d and b kept)."""
+    n_w, n_el, _ = R.shape
+    dt = np.result_type(float, corr.d, np.asarray(corr.b), corr.c)
+    G = np.zeros((n_w, n_el, 3), dt)
+    L = np.zeros((n_w, n_el), dt)
+    m = corr.mno[:, 0].astype(int)[None, None, :]
+    n = corr.mno[:, 1].astype(int)[None, None, :]
+    o = corr.mno[:, 2].astype(int)[None, None, :]
+    ty = np.asarray(corr.nuc_type, int)
+    b = np.asarray(corr.b)[ty][None, :]                      # [1, I]
+    c = corr.c[ty][None, :, :]                               # [1, I, k]
+    X = corr.nuc_xyz                                         # [I, 3]
+
+    def pw(x, k):          # x^k for integer k >= 0 (0 where k < 0)
+        return np.where(k >= 0, x ** np.maximum(k, 0), 0.0)
+
+    for i in range(n_el):
+        Di = R[:, i, None, :] - X[None, :, :]                # [w, I, 3]
+        ri = np.linalg.norm(Di, axis=2)                      # [w, I]
+        a, a1, a2 = _scaled(b, ri)
+        ga = (a1 / ri)[:, :, None] * Di                      # grad_i a   [w, I, 3]
+        la = a2 + 2.0 * a1 / ri                              # lap_i a    [w, I]
+        A = a[:, :, None]
+        for j in range(n_el):
+            if j == i:
+                continue
+            Dv = R[:, i] - R[:, j]
+            r = np.linalg.norm(Dv, axis=1)
+            e, e1, e2 = _scaled(corr.d, r)
+            ge = (e1 / r)[:, None] * Dv                      # grad_i e  [w, 3]
+            le = e2 + 2.0 * e1 / r
+            aj = _scaled(b, np.linalg.norm(R[:, j, None, :] - X[None, :, :], axis=2))[0]
+            Aj = aj[:, :, None]
+            P = pw(A, m) * pw(Aj, n) + pw(Aj, m) * pw(A, n)
+            Pa = m * pw(A, m - 1) * pw(Aj, n) + n * pw(Aj, m) * pw(A, n - 1)
+            Paa = m * (m - 1) * pw(A, m - 2) * pw(Aj, n) + n * (n - 1) * pw(Aj, m) * pw(A, n - 2)
+            E = e[:, None, None]
+            E0, E1, E2 = pw(E, o), o * pw(E, o - 1), o * (o - 1) * pw(E, o - 2)
+            ga_ge = np.einsum("wic,wc->wi", ga, ge)[:, :, None]
+            ga2 = np.einsum("wic,wic->wi", ga, ga)[:, :, None]
+            ge2 = np.einsum("wc,wc->w", ge, ge)[:, None, None]
+            # gradient: sum over (I, k) of c [Pa E0 grad a + P E1 grad e]
+            wa = (c * Pa * E0).sum(axis=2)                   # [w, I]
+            we = (c * P * E1).sum(axis=(1, 2))               # [w]
+            G[:, i] += np.einsum("wi,wic->wc", wa, ga) + we[:, None] * ge
+            L[:, i] += (c * (Paa * E0 * ga2 + Pa * E0 * la[:, :, None] + 2.0 * Pa * E1 * ga_ge
+                             + P * (E2 * ge2 + E1 * le[:, None, None]))).sum(axis=(1, 2))
+    return G, L
+
+
 def jastrow_grad_lap(corr, R):
-    """grad_i J [n_w, n_el, 3] and lap_i J [n_w, n_el] for the EE form."""
+    """grad_i J [n_w, n_el, 3] and lap_i J [n_w, n_el]."""
     if corr.form != 0:
-        raise NotImplementedError("the local energy is defined here for the EE form")
+        return _bh_grad_lap(corr, R)
     n_w, n_el, _ = R.shape
     dt = np.result_type(float, corr.d, corr.c)
     G = np.zeros((n_w, n_el, 3), dt)
@@ -122,18 +187,25 @@ def local_energy(basis, C_occ, nuc_xyz, nuc_Z, e_nuc, corr, R):
 
 
 def local_energy_grad(basis, C_occ, nuc_xyz, nuc_Z, e_nuc, corr, R, h=1e-30):
-    """E [n_w] and dE/dtheta [n_w, n_terms + 1], theta = (c_0 .. c_{n-1}, d), the
-    derivatives by the complex step Im E(theta + i h e_p) / h."""
+    """E [n_w] and dE/dtheta by the complex step Im E(theta + i h e_p) / h:
+    theta = (c_0 .. c_{n-1}, d) for the EE form and (c[type][term] type-major, d,
+    b_0 .. b_{n_types - 1}) for the BH form."""
     from dataclasses import replace
     E = local_energy(basis, C_occ, nuc_xyz, nuc_Z, e_nuc, corr, R)
-    n = corr.n_terms
-    dE = np.zeros((R.shape[0], n + 1))
-    for p in range(n):
-        c = corr.c.astype(complex)
-        c[0, p] += 1j * h
-        dE[:, p] = np.imag(local_energy(basis, C_occ, nuc_xyz, nuc_Z, e_nuc, replace(corr, c=c), R)) / h
-    dE[:, n] = np.imag(local_energy(basis, C_occ, nuc_xyz, nuc_Z, e_nuc,
-                                    replace(corr, d=corr.d + 1j * h), R)) / h
+    nt, n = corr.c.shape
+    n_b = 0 if corr.form == 0 else len(corr.b)
+    dE = np.zeros((R.shape[0], nt * n + 1 + n_b))
+    f = lambda cr: np.imag(local_energy(basis, C_occ, nuc_xyz, nuc_Z, e_nuc, cr, R)) / h
+    for t in range(nt):
+        for p in range(n):
+            c = corr.c.astype(complex)
+            c[t, p] += 1j * h
+            dE[:, t * n + p] = f(replace(corr, c=c))
+    dE[:, nt * n] = f(replace(corr, d=corr.d + 1j * h))
+    for t in range(n_b):
+        b = np.asarray(corr.b, dtype=complex).copy()
+        b[t] += 1j * h
+        dE[:, nt * n + 1 + t] = f(replace(corr, b=b))
     return E, dE
 
 

@@ -183,3 +183,70 @@ def test_variance_gradient_with_active_clipping_equals_central_differences():
         e[q] = h
         fd = (var(e) - var(-e)) / (2 * h)
         assert fd == pytest.approx(grad[q], rel=1e-6, abs=1e-8)
+
+
+def _bh_two_type(wl):
+    from workloads import Correlator, bh_correlator
+    base = bh_correlator(wl.atom_xyz)
+    n = base.nuc_xyz.shape[0]
+    c = np.random.default_rng(12).uniform(-0.5, 0.5, size=(2, base.n_terms)) / n
+    return Correlator(base.form, base.mno, c, 0.9, np.array([1.1, 0.8]), base.nuc_xyz,
+                      (np.arange(n) % 2).astype(np.int32))
+
+
+def test_bh_local_energy_equals_finite_difference_laplacian_of_psi(h4):
+    """The BH form (eq. bh-u, two nucleus types): E_loc against fourth-order differences of
+    Psi_T values built from u itself (correlator.u_value) and the determinants."""
+    wl = h4
+    corr = _bh_two_type(wl)
+    R = vmc_walkers(wl, 3, seed=15)
+    e_nuc = nuclear_repulsion(wl)
+    Z = wl.atom_Z.astype(float)
+    E = vmc.local_energy(wl.basis, _occ(wl), wl.atom_xyz, Z, e_nuc, corr, R)
+    psi0 = _psi(wl, corr, R)
+
+    def lap_fd(h):
+        tot = np.zeros(R.shape[0])
+        for i in range(R.shape[1]):
+            for c in range(3):
+                Rp, Rm = R.copy(), R.copy()
+                Rp[:, i, c] += h
+                Rm[:, i, c] -= h
+                tot += (_psi(wl, corr, Rp) - 2.0 * psi0 + _psi(wl, corr, Rm)) / (h * h)
+        return tot
+
+    lap = (4.0 * lap_fd(1e-3) - lap_fd(2e-3)) / 3.0
+    E_fd = -0.5 * lap / psi0 + vmc.coulomb(R, wl.atom_xyz, Z, e_nuc)
+    assert np.abs(E_fd - E).max() <= 1e-5 * max(1.0, np.abs(E).max()), (E, E_fd)
+    E0 = vmc.local_energy(wl.basis, _occ(wl), wl.atom_xyz, Z, e_nuc, corr.with_c(0.0 * corr.c), R)
+    assert np.abs(E0 - E).max() > 1e-2
+
+
+def test_bh_parameter_derivatives_equal_richardson_differences(h4):
+    """Complex-step dE/dc[t][k], dE/dd and dE/db_t of the BH form against Richardson
+    differences (a sample of the linear coefficients, every nonlinear parameter)."""
+    from dataclasses import replace
+    wl = h4
+    corr = _bh_two_type(wl)
+    R = vmc_walkers(wl, 4, seed=16)
+    args = (wl.basis, _occ(wl), wl.atom_xyz, wl.atom_Z.astype(float), nuclear_repulsion(wl))
+    E, dE = vmc.local_energy_grad(*args, corr, R)
+    nt, n = corr.c.shape
+    assert dE.shape == (4, nt * n + 1 + nt)
+
+    def moved(p, v):
+        if p < nt * n:
+            c = corr.c.copy()
+            c[p // n, p % n] += v
+            return replace(corr, c=c)
+        if p == nt * n:
+            return replace(corr, d=corr.d + v)
+        b = np.asarray(corr.b, np.float64).copy()
+        b[p - nt * n - 1] += v
+        return replace(corr, b=b)
+
+    for p in (0, 7, 30, n + 5, 2 * n - 1, nt * n, nt * n + 1, nt * n + 2):
+        f = lambda v: vmc.local_energy(*args, moved(p, v), R)
+        h = 1e-3
+        rich = (4.0 * (f(h) - f(-h)) / (2 * h) - (f(2 * h) - f(-2 * h)) / (4 * h)) / 3.0
+        assert np.abs(rich - dE[:, p]).max() <= 1e-8 * max(1.0, np.abs(dE[:, p]).max()), p
