@@ -379,15 +379,18 @@ xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* 
                           void* stream);
 
 /* Local energies E_loc = H Psi_T / Psi_T (eq. Eloc) of the walkers R and, when dE is not
- * NULL, their derivatives with respect to theta = (c_0 .. c_{n_terms - 1}, d) of the EE
- * correlator u = sum_k c_k rbar^{o_k}, rbar = d r / (1 + d r):
+ * NULL, their derivatives in the correlator's parameters: for the EE form
+ * u = sum_k c_k rbar^{o_k}, rbar = d r / (1 + d r), theta = (c_0 .. c_{n_terms - 1}, d);
+ * for the BH form (eq. bh-u) theta = (c[type][term] type-major, d, b_0 .. b_{n_types - 1}):
  *   lap_i Psi_T / Psi_T = lap_i J + |grad_i J|^2 + 2 grad_i J . grad_i Phi_0 / Phi_0
  *                         + lap_i Phi_0 / Phi_0,  J = sum_{i<j} u(r_i, r_j).
- * E: device [n_walkers]; dE: device [n_walkers][n_terms + 1] or NULL. A walker whose
- * determinant is exactly singular gets NaN. Only the EE form (1 .. 12 terms (0, 0, o))
- * is accepted; the BH form returns XTC_ERR_UNSUPPORTED. Workspace as xtc_vmc_sample;
- * LDS per walker 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles plus the basis tables within
- * 160 KB. FP64. */
+ * E: device [n_walkers]; dE: device [n_walkers][number of parameters] or NULL. A walker
+ * whose determinant is exactly singular gets NaN. EE: 1 .. 12 terms (0, 0, o). BH: 1 .. 24
+ * nuclei, 1 .. 2 types, 1 .. 64 terms with m, n <= 3 and o <= 12, at most 128 parameters;
+ * its linear derivatives are sums over electron pairs and nuclei of unit kernels, its d and
+ * b derivatives are carried in forward mode. Workspace as xtc_vmc_sample; LDS per walker
+ * 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles plus the basis tables (BH: plus
+ * 2 n_occ (4 + 9 n_nuc)) within 160 KB. FP64. */
 xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator* corr,
                                 int64_t n_walkers, const double* R, double* E, double* dE,
                                 void* ws, size_t ws_bytes, void* stream);
@@ -397,7 +400,7 @@ xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator*
  * r_k = Et_k - mean Et, sigma^2 = sum r_k^2 / (N - 1); the clipped energies' derivatives
  * follow the bounds m +- 5 d as functions of theta (sign(0) = 0 in d's derivative);
  * C = (1/N) sum_k dr_k dr_k^T + lambda I, delta = -eta C^-1 grad sigma^2 (Cholesky).
- * E: device [N]; dE: device [N][n_params] (1 .. 64 parameters); delta: device
+ * E: device [N]; dE: device [N][n_params] (1 .. 128 parameters); delta: device
  * [n_params]; stats: device [6] = m, d, mean Et, sigma^2, the number of clipped
  * energies, and 0 (or j + 1 when C's j-th pivot is not positive; delta is then NaN).
  * N >= 2. No workspace. FP64. Asynchronous. */

@@ -534,8 +534,9 @@ def vmc_sample(sys: VmcSystem, R, n_sweeps: int, step: float, normals, uniforms)
 
 
 def vmc_local_energy(sys: VmcSystem, corr, R, want_grad: bool = True, c=None, d=None):
-    """Local energies [n_w] and, with want_grad, dE/dtheta [n_w, n_terms + 1] for
-    theta = (c_0 .. c_{n-1}, d) of the EE correlator (xtc_vmc_local_energy)."""
+    """Local energies [n_w] and, with want_grad, dE/dtheta (xtc_vmc_local_energy):
+    EE form [n_w, n_terms + 1], theta = (c_0 .. c_{n-1}, d); BH form
+    [n_w, n_types n_terms + 1 + n_types], theta = (c[type][term], d, b_0 ..)."""
     from dataclasses import replace
     if d is not None:
         corr = replace(corr, d=float(d))
@@ -543,7 +544,8 @@ def vmc_local_energy(sys: VmcSystem, corr, R, want_grad: bool = True, c=None, d=
     R = _in(R, "R")
     n_w = int(R.shape[0])
     E = torch.empty(n_w, dtype=torch.float64, device="cuda")
-    dE = torch.empty((n_w, corr.n_terms + 1), dtype=torch.float64, device="cuda") if want_grad else None
+    n_th = hc.c.size + 1 + (0 if int(corr.form) == 0 else hc.c.shape[0])
+    dE = torch.empty((n_w, n_th), dtype=torch.float64, device="cuda") if want_grad else None
     _check("xtc_vmc_local_energy", L.lib().xtc_vmc_local_energy(
         C.byref(sys.s), C.byref(hc.s), n_w, _ptr(R), _ptr(E), _ptr(dE), _ptr(sys.ws), sys.ws.numel(),
         _stream()))
@@ -568,8 +570,9 @@ def vmc_optimize(sys: VmcSystem, corr, R, n_steps: int, n_sweeps: int = 10, step
     Metropolis over |Phi_0|^2 (draws from a seeded device generator), local energies and
     their derivatives on the new batch, one Gauss-Newton update of (c, d). lam and eta
     are held fixed (the paper's adaptive shift and schedule are not specified); a step
-    that would make d non-positive is halved until d > 0 (the scaled distance needs
-    d > 0). Returns the final correlator and the per-step statistics."""
+    that would make d or a b non-positive is halved until they are positive (the scaled
+    distances need them > 0). EE form: (c, d); BH form: (c, d, b). Returns the final
+    correlator and the per-step statistics."""
     from dataclasses import replace
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -585,10 +588,17 @@ def vmc_optimize(sys: VmcSystem, corr, R, n_steps: int, n_sweeps: int = 10, step
         st = stats.cpu().numpy()
         if st[5] != 0.0 or not np.all(np.isfinite(dl)):
             raise RuntimeError(f"Gauss-Newton step failed (info {st[5]}); raise lam")
-        n = corr.n_terms
-        while corr.d + dl[n] <= 0.0:
+        n = corr.c.size
+        bh = int(corr.form) != 0
+
+        def ok(x):
+            return corr.d + x[n] > 0.0 and (not bh or np.all(np.asarray(corr.b) + x[n + 1:] > 0.0))
+        while not ok(dl):
             dl = 0.5 * dl
-        corr = replace(corr, c=corr.c + dl[:n][None, :], d=float(corr.d + dl[n]))
+        upd = dict(c=corr.c + dl[:n].reshape(corr.c.shape), d=float(corr.d + dl[n]))
+        if bh:
+            upd["b"] = np.asarray(corr.b, np.float64) + dl[n + 1:]
+        corr = replace(corr, **upd)
         rate = float(acc.sum()) / (n_w * sys.n_el * max(n_sweeps, 1))
         history.append({"mean": float(st[2]), "variance": float(st[3]), "clipped": int(st[4]),
                         "acceptance": rate, "d": corr.d})

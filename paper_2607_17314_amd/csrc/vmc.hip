@@ -22,7 +22,7 @@ namespace xtc {
 constexpr int VMC_MAX_OCC = 32;      // electrons per spin
 constexpr int VMC_MAX_L = 6;
 constexpr int VMC_MAX_TERMS = 12;    // EE terms of the local-energy kernel
-constexpr int VMC_MAX_THETA = 64;    // parameters of the Gauss-Newton step
+constexpr int VMC_MAX_THETA = 128;   // parameters of the Gauss-Newton step
 constexpr int VMC_GN_THREADS = 1024;
 
 // Basis tables as the kernels hold them (staged into LDS at kernel start): per shell the
@@ -51,13 +51,17 @@ struct EECoefV {
   double c[VMC_MAX_TERMS];
 };
 
-// x^n for 0 <= n <= VMC_MAX_L + 1 by a fixed-length predicated product (no register
-// tables indexed by lane-varying exponents).
-__device__ __forceinline__ double vmc_ipow(double x, int n) {
+// x^n for 0 <= n <= NMAX by a fixed-length predicated product (no register tables
+// indexed by lane-varying exponents).
+template <int NMAX>
+__device__ __forceinline__ double vmc_ipow_to(double x, int n) {
   double r = 1.0;
 #pragma unroll
-  for (int q = 0; q < VMC_MAX_L + 1; ++q) r = q < n ? r * x : r;
+  for (int q = 0; q < NMAX; ++q) r = q < n ? r * x : r;
   return r;
+}
+__device__ __forceinline__ double vmc_ipow(double x, int n) {   // Cartesian powers, n <= l + 1
+  return vmc_ipow_to<VMC_MAX_L + 1>(x, n);
 }
 
 // AO rows (without the component factor) of shell s at the point p, written to chi[a]
@@ -337,6 +341,51 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
+// The Slater part of a walker's local energy: A5[q][e][k] = (phi_k, d_x, d_y, d_z, lap)
+// of the occupied orbitals at electron e, and the two inverse spin blocks Ainv[sp][k][i].
+// Returns false (uniformly) when a determinant is exactly singular.
+__device__ bool vmc_slater(const VmcDev& v, const double* shd, const int* shi, const double* prim,
+                           const double* Rs, double* A5, double* aug, double* Ainv, double* chi,
+                           double* part, double* fac, int* piv) {
+  const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
+  for (int e = 0; e < n_el; ++e) {
+    vmc_aos<true>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+    __syncthreads();
+    vmc_orbitals<5>(v, chi, part, A5 + e * n, n_el * n);
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int q = lane; q < n * n; q += 64) {
+      const int i = q / n, k = q - i * n;
+      aug[i * 2 * n + k] = A5[(sp * n + i) * n + k];
+    }
+    __syncthreads();
+    if (!vmc_invert(aug, n, fac, piv)) return false;
+    for (int q = lane; q < n * n; q += 64) {
+      const int k = q / n, i = q - k * n;
+      Ainv[sp * n * n + q] = aug[k * 2 * n + n + i];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// D_i = grad_i Phi_0 / Phi_0 and S_i = lap_i Phi_0 / Phi_0 for electron i (Jacobi).
+__device__ __forceinline__ void vmc_ratios(const VmcDev& v, const double* A5, const double* Ainv,
+                                           int i, double& Dx, double& Dy, double& Dz,
+                                           double& S) {
+  const int n = v.n_occ, n_el = 2 * n, sp = i / n, ii = i - sp * n;
+  const double* Ai = Ainv + sp * n * n;
+  Dx = Dy = Dz = S = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double a = Ai[k * n + ii];
+    Dx += A5[(n_el + i) * n + k] * a;
+    Dy += A5[(2 * n_el + i) * n + k] * a;
+    Dz += A5[(3 * n_el + i) * n + k] * a;
+    S += A5[(4 * n_el + i) * n + k] * a;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Local energy and its parameter derivatives, one walker per workgroup.
 // LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], A5 [5][n_el][n],
 // aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64], fac [n], R [n_el][3], red [64];
@@ -364,28 +413,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
   vmc_stage(v.b, shd, shi, prim);
   __syncthreads();
-  for (int e = 0; e < n_el; ++e) {
-    vmc_aos<true>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
-    __syncthreads();
-    vmc_orbitals<5>(v, chi, part, A5 + e * n, n_el * n);
-  }
-  bool ok = true;
-  for (int sp = 0; sp < 2 && ok; ++sp) {
-    for (int q = lane; q < n * n; q += 64) {
-      const int i = q / n, k = q - i * n;
-      aug[i * 2 * n + k] = A5[(sp * n + i) * n + k];
-    }
-    __syncthreads();
-    ok = vmc_invert(aug, n, fac, piv);
-    if (ok) {
-      for (int q = lane; q < n * n; q += 64) {
-        const int k = q / n, i = q - k * n;
-        Ainv[sp * n * n + q] = aug[k * 2 * n + n + i];
-      }
-      __syncthreads();
-    }
-  }
-  if (!ok) {   // exactly singular reference determinant: no local energy
+  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
+    // exactly singular reference determinant: no local energy
     if (lane == 0) {
       E[w] = __builtin_nan("");
       if (dE)
@@ -399,16 +428,9 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
 #pragma unroll
   for (int p = 0; p <= VMC_MAX_TERMS; ++p) dEp[p] = 0.0;
   if (lane < n_el) {
-    const int i = lane, sp = i / n, ii = i - sp * n;
-    const double* Ai = Ainv + sp * n * n;
-    double Dx = 0.0, Dy = 0.0, Dz = 0.0, S = 0.0;
-    for (int k = 0; k < n; ++k) {
-      const double a = Ai[k * n + ii];
-      Dx += A5[(n_el + i) * n + k] * a;
-      Dy += A5[(2 * n_el + i) * n + k] * a;
-      Dz += A5[(3 * n_el + i) * n + k] * a;
-      S += A5[(4 * n_el + i) * n + k] * a;
-    }
+    const int i = lane;
+    double Dx, Dy, Dz, S;
+    vmc_ratios(v, A5, Ainv, i, Dx, Dy, Dz, S);
     const double xi = Rs[3 * i], yi = Rs[3 * i + 1], zi = Rs[3 * i + 2];
     double Gx = 0.0, Gy = 0.0, Gz = 0.0, Lj = 0.0;
     double gk[VMC_MAX_TERMS + 1][3], lk[VMC_MAX_TERMS + 1];
@@ -502,6 +524,272 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
     }
     const double s = lane_sum(dEp[VMC_MAX_TERMS]);
     if (lane == 0) dE[w * nth + cf.n] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Local energy of the BH correlator (eq. bh-u) and its derivatives in every parameter.
+// u(r_i, r_j) = sum_I sum_k c[type I][k] (a_i^m a_j^n + a_j^m a_i^n) e^o with a = a(r_.I),
+// e = rbar(r_ij). For electron i, per (j, I) and with P(a_i) = a_i^m a_j^n + a_j^m a_i^n:
+//   grad_i f = c [P_a e^o grad a_i + P o e^{o-1} grad e],
+//   lap_i f  = c [P_aa e^o |grad a_i|^2 + P_a e^o lap a_i + 2 P_a o e^{o-1} grad a_i . grad e
+//                + P (o (o-1) e^{o-2} |grad e|^2 + o e^{o-1} lap e)],
+// s = x r / (1 + x r): s' = x t^2, s'' = -2 x^2 t^3, grad s = (s'/r) (r - R), lap s = s'' + 2 s'/r;
+// in x: ds = r t^2, ds' = t^2 (1 - 2 s), ds'' = x t^3 (6 s - 4).
+constexpr int VMC_BH_MAXNUC = 24, VMC_BH_MAXTYPE = 2, VMC_BH_MAXTERM = 64, VMC_BH_MAXO = 12;
+constexpr int VMC_BH_TA = 9;   // per (electron, nucleus): a, da/db, ga, dga/db, la, dla/db, r - R
+
+struct VmcBH {
+  const double* nuc;   // [n_nuc][4]: x, y, z, type
+  const double* bt;    // [n_types]
+  const double* c;     // [n_types][n_terms]
+  const int* mno;      // [n_terms][3]
+  int n_nuc, n_types, n_terms;
+  double d;
+};
+
+// value and derivative in one seeded parameter (forward mode)
+struct Dl {
+  double v, d;
+};
+__device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dl operator*(double s, Dl a) { return {s * a.v, s * a.d}; }
+template <class T> __device__ __forceinline__ T vmc_mk(double v, double d);
+template <> __device__ __forceinline__ double vmc_mk<double>(double v, double) { return v; }
+template <> __device__ __forceinline__ Dl vmc_mk<Dl>(double v, double d) { return {v, d}; }
+template <class T> __device__ __forceinline__ T vmc_zero() { return vmc_mk<T>(0.0, 0.0); }
+
+// grad_i J and lap_i J of electron i; with T = Dl the derivatives in the parameter `seed`
+// (0: d, 1 + t: b_t) ride along. TA: the per-(electron, nucleus) table in LDS.
+template <class T>
+__device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* Rs, int n_el,
+                               int i, int seed, T& Gx, T& Gy, T& Gz, T& L) {
+  Gx = Gy = Gz = L = vmc_zero<T>();
+  const double d = bh.d;
+  const int nn = bh.n_nuc;
+  for (int j = 0; j < n_el; ++j) {
+    if (j == i) continue;
+    const double dx = Rs[3 * i] - Rs[3 * j], dy = Rs[3 * i + 1] - Rs[3 * j + 1],
+                 dz = Rs[3 * i + 2] - Rs[3 * j + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz), rinv = 1.0 / r;
+    const double t = 1.0 / (1.0 + d * r), e = d * r * t, e1 = d * t * t, e2 = -2.0 * d * d * t * t * t;
+    const bool sd = seed == 0;
+    const double de = r * t * t, de1 = t * t * (1.0 - 2.0 * e), de2 = d * t * t * t * (6.0 * e - 4.0);
+    const T E = vmc_mk<T>(e, sd ? de : 0.0);
+    const T ge = vmc_mk<T>(e1 * rinv, sd ? de1 * rinv : 0.0);
+    const T le = vmc_mk<T>(e2 + 2.0 * e1 * rinv, sd ? de2 + 2.0 * de1 * rinv : 0.0);
+    T pe[VMC_BH_MAXO + 1];
+    pe[0] = vmc_mk<T>(1.0, 0.0);
+#pragma unroll
+    for (int q = 1; q <= VMC_BH_MAXO; ++q) pe[q] = pe[q - 1] * E;
+    const T ge2 = (r * r) * (ge * ge);
+    for (int I = 0; I < nn; ++I) {
+      const int ty = (int)bh.nuc[4 * I + 3];
+      const bool sb = seed == 1 + ty;
+      const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
+      const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
+      const T A = vmc_mk<T>(ti[0], sb ? ti[1] : 0.0);
+      const T Aj = vmc_mk<T>(tj[0], sb ? tj[1] : 0.0);
+      const T GA = vmc_mk<T>(ti[2], sb ? ti[3] : 0.0);
+      const T LA = vmc_mk<T>(ti[4], sb ? ti[5] : 0.0);
+      const double Dix = ti[6], Diy = ti[7], Diz = ti[8];
+      T pa[4], pj[4];
+      pa[0] = pj[0] = vmc_mk<T>(1.0, 0.0);
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        pa[q] = pa[q - 1] * A;
+        pj[q] = pj[q - 1] * Aj;
+      }
+      T S1 = vmc_zero<T>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
+      const double* cc = bh.c + ty * bh.n_terms;
+      for (int k = 0; k < bh.n_terms; ++k) {
+        const int m = bh.mno[3 * k], n = bh.mno[3 * k + 1], o = bh.mno[3 * k + 2];
+        const double c = cc[k];
+        const T P = pa[m] * pj[n] + pj[m] * pa[n];
+        T Pa = vmc_zero<T>(), Paa = Pa;
+        if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
+        if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
+        if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
+        if (n >= 2) Paa = Paa + (double)(n * (n - 1)) * (pj[m] * pa[n - 2]);
+        const T E0 = pe[o];
+        const T E1 = o >= 1 ? (double)o * pe[o - 1] : vmc_zero<T>();
+        const T E2 = o >= 2 ? (double)(o * (o - 1)) * pe[o - 2] : vmc_zero<T>();
+        S1 = S1 + c * (Pa * E0);
+        S2 = S2 + c * (P * E1);
+        S3 = S3 + c * (Paa * E0);
+        S4 = S4 + c * (Pa * E1);
+        S5 = S5 + c * (P * E2);
+      }
+      // grad a = GA (r_i - R_I), grad e = ge (r_i - r_j)
+      const double dd = Dix * dx + Diy * dy + Diz * dz, di2 = Dix * Dix + Diy * Diy + Diz * Diz;
+      const T ga2 = di2 * (GA * GA), gage = dd * (GA * ge);
+      Gx = Gx + Dix * (S1 * GA) + dx * (S2 * ge);
+      Gy = Gy + Diy * (S1 * GA) + dy * (S2 * ge);
+      Gz = Gz + Diz * (S1 * GA) + dz * (S2 * ge);
+      L = L + S3 * ga2 + S1 * LA + 2.0 * (S4 * gage) + S5 * ge2 + S2 * le;
+    }
+  }
+}
+
+// Pass 2: dE/dc[t][k] = -1/2 sum_i sum_{j != i} sum_{I of type t} [lap_i f + 2 h_i . grad_i f]
+// for the unit kernel f of term k, h_i = grad_i J + grad_i Phi_0 / Phi_0.
+__device__ double vmc_bh_dc(const VmcBH& bh, const double* TA, const double* Rs, const double* H,
+                            int n_el, int p) {
+  const int ty = p / bh.n_terms, k = p - ty * bh.n_terms;
+  const int m = bh.mno[3 * k], n = bh.mno[3 * k + 1], o = bh.mno[3 * k + 2];
+  const double d = bh.d;
+  const int nn = bh.n_nuc;
+  double acc = 0.0;
+  for (int i = 0; i < n_el; ++i) {
+    const double hx = H[4 * i], hy = H[4 * i + 1], hz = H[4 * i + 2];
+    for (int j = 0; j < n_el; ++j) {
+      if (j == i) continue;
+      const double dx = Rs[3 * i] - Rs[3 * j], dy = Rs[3 * i + 1] - Rs[3 * j + 1],
+                   dz = Rs[3 * i + 2] - Rs[3 * j + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz), rinv = 1.0 / r;
+      const double t = 1.0 / (1.0 + d * r), e = d * r * t, e1 = d * t * t,
+                   e2 = -2.0 * d * d * t * t * t;
+      const double ge = e1 * rinv, le = e2 + 2.0 * e1 * rinv, ge2 = e1 * e1;
+      const double E0 = vmc_ipow_to<VMC_BH_MAXO>(e, o),
+                   E1 = o >= 1 ? o * vmc_ipow_to<VMC_BH_MAXO>(e, o - 1) : 0.0,
+                   E2 = o >= 2 ? o * (o - 1) * vmc_ipow_to<VMC_BH_MAXO>(e, o - 2) : 0.0;
+      const double hge = ge * (hx * dx + hy * dy + hz * dz);
+      for (int I = 0; I < nn; ++I) {
+        if ((int)bh.nuc[4 * I + 3] != ty) continue;
+        const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
+        const double a = ti[0], aj = TA[((long)j * nn + I) * VMC_BH_TA];
+        const double ga = ti[2], la = ti[4], Dix = ti[6], Diy = ti[7], Diz = ti[8];
+        const double am = vmc_ipow(a, m), an = vmc_ipow(a, n), jm = vmc_ipow(aj, m),
+                     jn = vmc_ipow(aj, n);
+        const double P = am * jn + jm * an;
+        double Pa = 0.0, Paa = 0.0;
+        if (m >= 1) Pa += m * vmc_ipow(a, m - 1) * jn;
+        if (n >= 1) Pa += n * jm * vmc_ipow(a, n - 1);
+        if (m >= 2) Paa += m * (m - 1) * vmc_ipow(a, m - 2) * jn;
+        if (n >= 2) Paa += n * (n - 1) * jm * vmc_ipow(a, n - 2);
+        const double di2 = Dix * Dix + Diy * Diy + Diz * Diz, dd = Dix * dx + Diy * dy + Diz * dz;
+        const double hga = ga * (hx * Dix + hy * Diy + hz * Diz);
+        const double lap = Paa * E0 * ga * ga * di2 + Pa * E0 * la + 2.0 * Pa * E1 * ga * ge * dd +
+                           P * (E2 * ge2 + E1 * le);
+        acc += lap + 2.0 * (Pa * E0 * hga + P * E1 * hge);
+      }
+    }
+  }
+  return -0.5 * acc;
+}
+
+// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], A5 [5][n_el][n],
+// aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64], fac [n], R [n_el][3], red [64],
+// H [n_el][4] (h_i, then spare), TA [n_el][n_nuc][9]; then ints: shell records
+// [n_shell][4], piv.
+__global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
+                                                      const double* __restrict__ R, long n_w,
+                                                      double* __restrict__ E,
+                                                      double* __restrict__ dE) {
+  extern __shared__ double lds[];
+  const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
+  const long w = blockIdx.x;
+  const int nlin = bh.n_types * bh.n_terms, nth = nlin + 1 + bh.n_types;
+  const int nn = bh.n_nuc;
+  double* shd = lds;
+  double* prim = shd + 4 * v.b.n_shell;
+  double* A5 = prim + 2 * v.b.n_prim;
+  double* aug = A5 + 5 * n_el * n;
+  double* Ainv = aug + 2 * n * n;
+  double* chi = Ainv + 2 * n * n;
+  double* part = chi + 5 * v.b.n_ao;
+  double* fac = part + 5 * 64;
+  double* Rs = fac + n;
+  double* red = Rs + 3 * n_el;
+  double* H = red + 64;
+  double* TA = H + 4 * n_el;
+  int* shi = (int*)(TA + (long)n_el * nn * VMC_BH_TA);
+  int* piv = shi + 4 * v.b.n_shell;
+  for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  vmc_stage(v.b, shd, shi, prim);
+  __syncthreads();
+  // the per-(electron, nucleus) table: a, da/db, (a'/r), d(a'/r)/db, lap a, d lap a/db, r - R
+  for (int q = lane; q < n_el * nn; q += 64) {
+    const int e = q / nn, I = q - e * nn;
+    const double Dx = Rs[3 * e] - bh.nuc[4 * I], Dy = Rs[3 * e + 1] - bh.nuc[4 * I + 1],
+                 Dz = Rs[3 * e + 2] - bh.nuc[4 * I + 2];
+    const double r = sqrt(Dx * Dx + Dy * Dy + Dz * Dz), rinv = 1.0 / r;
+    const double b = bh.bt[(int)bh.nuc[4 * I + 3]];
+    const double t = 1.0 / (1.0 + b * r), a = b * r * t, a1 = b * t * t, a2 = -2.0 * b * b * t * t * t;
+    const double da = r * t * t, da1 = t * t * (1.0 - 2.0 * a), da2 = b * t * t * t * (6.0 * a - 4.0);
+    double* o = TA + (long)q * VMC_BH_TA;
+    o[0] = a;
+    o[1] = da;
+    o[2] = a1 * rinv;
+    o[3] = da1 * rinv;
+    o[4] = a2 + 2.0 * a1 * rinv;
+    o[5] = da2 + 2.0 * da1 * rinv;
+    o[6] = Dx;
+    o[7] = Dy;
+    o[8] = Dz;
+  }
+  __syncthreads();
+  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
+    if (lane == 0) {
+      E[w] = __builtin_nan("");
+      if (dE)
+        for (int p = 0; p < nth; ++p) dE[w * nth + p] = __builtin_nan("");
+    }
+    return;
+  }
+  auto lane_sum = [&](double x) {
+    red[lane] = x;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+      if (lane < h) red[lane] += red[lane + h];
+      __syncthreads();
+    }
+    const double s = red[0];
+    __syncthreads();
+    return s;
+  };
+  // pass 1: local energy; h_i = grad_i J + D_i to LDS
+  double ekin = 0.0, pot = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
+  if (lane < n_el) {
+    const int i = lane;
+    double S, L;
+    vmc_ratios(v, A5, Ainv, i, Dx, Dy, Dz, S);
+    vmc_bh_jastrow<double>(bh, TA, Rs, n_el, i, -1, Gx, Gy, Gz, L);
+    ekin = -0.5 * (L + Gx * Gx + Gy * Gy + Gz * Gz + 2.0 * (Gx * Dx + Gy * Dy + Gz * Dz) + S);
+    const double xi = Rs[3 * i], yi = Rs[3 * i + 1], zi = Rs[3 * i + 2];
+    for (int j = i + 1; j < n_el; ++j) {
+      const double ax = xi - Rs[3 * j], ay = yi - Rs[3 * j + 1], az = zi - Rs[3 * j + 2];
+      pot += 1.0 / sqrt(ax * ax + ay * ay + az * az);
+    }
+    for (int I = 0; I < v.n_nuc; ++I) {
+      const double ax = xi - v.nuc[4 * I], ay = yi - v.nuc[4 * I + 1], az = zi - v.nuc[4 * I + 2];
+      pot -= v.nuc[4 * I + 3] / sqrt(ax * ax + ay * ay + az * az);
+    }
+    H[4 * i] = Gx + Dx;
+    H[4 * i + 1] = Gy + Dy;
+    H[4 * i + 2] = Gz + Dz;
+    H[4 * i + 3] = 0.0;
+  }
+  const double Etot = lane_sum(ekin + pot);
+  if (lane == 0) E[w] = Etot + v.e_nuc;
+  if (!dE) return;   // uniform
+  // pass 2: the linear coefficients, one lane per coefficient
+  for (int p0 = 0; p0 < nlin; p0 += 64) {
+    const int p = p0 + lane;
+    const double g = p < nlin ? vmc_bh_dc(bh, TA, Rs, H, n_el, p) : 0.0;
+    if (p < nlin) dE[w * nth + p] = g;
+  }
+  // pass 3: d and each b_t in forward mode
+  for (int sd = 0; sd <= bh.n_types; ++sd) {
+    double x = 0.0;
+    if (lane < n_el) {
+      Dl gx, gy, gz, l;
+      vmc_bh_jastrow<Dl>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
+      x = -0.5 * (l.d + 2.0 * ((gx.v + Dx) * gx.d + (gy.v + Dy) * gy.d + (gz.v + Dz) * gz.d));
+    }
+    const double s = lane_sum(x);
+    if (lane == 0) dE[w * nth + nlin + sd] = s;
   }
 }
 
@@ -669,6 +957,8 @@ __global__ __launch_bounds__(256) void k_vmc_scale_c(const double* __restrict__ 
 
 struct VmcLayout {
   double* shd; int* shi; double* prim; double* comp; double* nuc; double* Cs;
+  double* bh;    // BH correlator: nuclei [24][4], b [2], c [2][64]
+  int* bh_mno;   // [64][3]
 };
 
 static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_occ, int n_nuc) {
@@ -679,6 +969,8 @@ static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_
   L.comp = ar.take<double>(n_ao);
   L.nuc = ar.take<double>(4 * (size_t)(n_nuc > 0 ? n_nuc : 1));
   L.Cs = ar.take<double>((size_t)n_ao * n_occ);
+  L.bh = ar.take<double>(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM);
+  L.bh_mno = ar.take<int>(3 * VMC_BH_MAXTERM);
   return L;
 }
 
@@ -700,6 +992,13 @@ static size_t lds_sweeps(const VmcBasis& b, int n) {
          sizeof(double) * (4 * (size_t)n * n + b.n_ao + 64 + 3 * (size_t)n + 7 * n_el) + 16;
 }
 
+static size_t lds_energy_bh(const VmcBasis& b, int n, int n_nuc) {
+  const int n_el = 2 * n;
+  return lds_tables(b) + sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n +
+                                           5 * (size_t)b.n_ao + 5 * 64 + n + 3 * n_el + 64 +
+                                           4 * n_el + (size_t)n_el * n_nuc * VMC_BH_TA) + 16;
+}
+
 static size_t lds_energy(const VmcBasis& b, int n) {
   const int n_el = 2 * n;
   return lds_tables(b) + sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n +
@@ -710,7 +1009,8 @@ constexpr size_t VMC_LDS_MAX = 160 * 1024;
 
 // Validates the system, uploads its tables and folds the component factors into the
 // orbital coefficients; the stream is synchronised before return (host staging ends).
-static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st, VmcDev* out) {
+static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st, VmcDev* out,
+                             VmcLayout* lay = nullptr) {
   const xtc_basis* basis = sy->basis;
   XTC_REQUIRE(basis && sy->C_occ, "vmc: null basis or orbital coefficients");
   XTC_REQUIRE(sy->n_occ >= 1 && sy->n_occ <= VMC_MAX_OCC, "vmc: n_occ must be in 1..32");
@@ -774,6 +1074,63 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
   v.n_nuc = sy->n_nuc;
   v.e_nuc = sy->e_nuc;
   *out = v;
+  if (lay) *lay = L;
+  return XTC_OK;
+}
+
+// The BH local energy: validates the correlator, uploads its table and launches
+// k_vmc_energy_bh. dE: [n_walkers][n_types n_terms + 1 + n_types] or NULL.
+static xtc_status vmc_local_energy_bh(const xtc_vmc_system* sys, const xtc_correlator* corr,
+                                      int64_t n_walkers, const double* R, double* E, double* dE,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  XTC_REQUIRE(corr->n_nuc >= 1 && corr->n_nuc <= VMC_BH_MAXNUC && corr->nuc_xyz && corr->nuc_type,
+              "xtc_vmc_local_energy: BH needs 1..24 nuclei");
+  XTC_REQUIRE(corr->n_types >= 1 && corr->n_types <= VMC_BH_MAXTYPE && corr->b && corr->c,
+              "xtc_vmc_local_energy: BH needs 1..2 nucleus types");
+  XTC_REQUIRE(corr->n_terms >= 1 && corr->n_terms <= VMC_BH_MAXTERM && corr->mno,
+              "xtc_vmc_local_energy: BH needs 1..64 terms");
+  XTC_REQUIRE(corr->d > 0.0 && std::isfinite(corr->d), "xtc_vmc_local_energy: d must be > 0");
+  for (int t = 0; t < corr->n_types; ++t)
+    XTC_REQUIRE(corr->b[t] > 0.0 && std::isfinite(corr->b[t]), "xtc_vmc_local_energy: b must be > 0");
+  for (int k = 0; k < corr->n_terms; ++k) {
+    const int m = corr->mno[3 * k], n = corr->mno[3 * k + 1], o = corr->mno[3 * k + 2];
+    XTC_REQUIRE(m >= 0 && m <= 3 && n >= 0 && n <= 3 && o >= 0 && o <= VMC_BH_MAXO,
+                "xtc_vmc_local_energy: BH terms need 0 <= m, n <= 3 and 0 <= o <= 12");
+  }
+  for (int I = 0; I < corr->n_nuc; ++I)
+    XTC_REQUIRE(corr->nuc_type[I] >= 0 && corr->nuc_type[I] < corr->n_types,
+                "xtc_vmc_local_energy: nucleus type out of range");
+  const int nparam = corr->n_types * corr->n_terms + 1 + corr->n_types;
+  XTC_REQUIRE(nparam <= VMC_MAX_THETA, "xtc_vmc_local_energy: more than 128 parameters");
+  hipStream_t st = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  VmcDev v;
+  VmcLayout L;
+  XTC_TRY(vmc_upload(sys, ar, st, &v, &L));
+  const size_t lds = lds_energy_bh(v.b, v.n_occ, corr->n_nuc);
+  XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: system too large for the walker's LDS");
+  std::vector<double> tab(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM, 0.0);
+  for (int I = 0; I < corr->n_nuc; ++I) {
+    for (int c = 0; c < 3; ++c) tab[4 * I + c] = corr->nuc_xyz[3 * I + c];
+    tab[4 * I + 3] = corr->nuc_type[I];
+  }
+  double* bt = tab.data() + 4 * VMC_BH_MAXNUC;
+  double* cc = bt + VMC_BH_MAXTYPE;
+  for (int t = 0; t < corr->n_types; ++t) {
+    bt[t] = corr->b[t];
+    for (int k = 0; k < corr->n_terms; ++k) cc[t * corr->n_terms + k] = corr->c[t * corr->n_terms + k];
+  }
+  XTC_HIP(hipMemcpyAsync(L.bh, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.bh_mno, corr->mno, sizeof(int) * 3 * corr->n_terms, hipMemcpyHostToDevice, st));
+  XTC_HIP(hipStreamSynchronize(st));   // host staging vector ends with this call
+  if (n_walkers == 0) return XTC_OK;
+  VmcBH bh{L.bh, L.bh + 4 * VMC_BH_MAXNUC, L.bh + 4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE, L.bh_mno,
+           corr->n_nuc, corr->n_types, corr->n_terms, corr->d};
+  size_t tk = timing_begin(TM_VMC_ENERGY, st);
+  hipLaunchKernelGGL(k_vmc_energy_bh, dim3((unsigned)n_walkers), dim3(64), lds, st, v, bh, R,
+                     (long)n_walkers, E, dE);
+  XTC_CHECK_LAUNCH();
+  timing_end(tk, st);
   return XTC_OK;
 }
 
@@ -810,10 +1167,9 @@ extern "C" xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_
                                            double* dE, void* ws, size_t ws_bytes, void* stream) {
   XTC_REQUIRE(sys && corr && (n_walkers == 0 || (R && E)), "xtc_vmc_local_energy: null argument");
   XTC_REQUIRE(n_walkers >= 0 && n_walkers <= (int64_t)1 << 31, "xtc_vmc_local_energy: bad n_walkers");
-  if (corr->form != XTC_U_EE) {
-    set_error("xtc_vmc_local_energy: only the EE correlator form has a Laplacian here");
-    return XTC_ERR_UNSUPPORTED;
-  }
+  if (corr->form == XTC_U_BH) return vmc_local_energy_bh(sys, corr, n_walkers, R, E, dE, ws, ws_bytes,
+                                                          stream);
+  XTC_REQUIRE(corr->form == XTC_U_EE, "xtc_vmc_local_energy: unknown correlator form");
   XTC_REQUIRE(corr->n_terms >= 1 && corr->n_terms <= VMC_MAX_TERMS && corr->mno && corr->c,
               "xtc_vmc_local_energy: EE correlator needs 1..12 terms");
   XTC_REQUIRE(corr->d > 0.0 && std::isfinite(corr->d), "xtc_vmc_local_energy: d must be > 0");
@@ -847,7 +1203,7 @@ extern "C" xtc_status xtc_vmc_gn_step(int64_t n_walkers, int32_t n_params, const
                                       double* stats, void* stream) {
   XTC_REQUIRE(E && dE && delta && stats, "xtc_vmc_gn_step: null argument");
   XTC_REQUIRE(n_walkers >= 2, "xtc_vmc_gn_step: need at least two walkers");
-  XTC_REQUIRE(n_params >= 1 && n_params <= VMC_MAX_THETA, "xtc_vmc_gn_step: n_params must be in 1..64");
+  XTC_REQUIRE(n_params >= 1 && n_params <= VMC_MAX_THETA, "xtc_vmc_gn_step: n_params must be in 1..128");
   XTC_REQUIRE(lambda >= 0.0 && std::isfinite(lambda) && std::isfinite(eta),
               "xtc_vmc_gn_step: lambda must be >= 0 and finite, eta finite");
   hipStream_t st = as_stream(stream);

@@ -143,12 +143,21 @@ def test_vmc_argument_checks():
     assert lib.xtc_vmc_sample(C.byref(s), 4, fake, 2, 0.5, None, fake, fake, fake, big, None) == -1
     # too small a workspace is reported before the basis is copied
     assert lib.xtc_vmc_sample(C.byref(s), 4, fake, 1, 0.5, fake, fake, fake, fake, 64, None) == -4
-    # the BH form has no local energy here; an EE form with 13 terms is refused
+    # a BH correlator without nuclei, or with a power beyond the tables, is refused; an EE
+    # form with 13 terms is refused
     mno = np.array([[0, 0, 2]], np.int32)
     cc = np.array([0.3])
-    bh = L.Correlator(1, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0, None, 0,
-                      None, None)
-    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(bh), 4, fake, fake, None, fake, big, None) == -5
+    bb = np.array([1.0])
+    bh = L.Correlator(1, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0,
+                      bb.ctypes.data_as(L.D), 0, None, None)
+    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(bh), 4, fake, fake, None, fake, big, None) == -1
+    assert b"nuclei" in lib.xtc_last_error()
+    nxyz = np.zeros((1, 3))
+    nty = np.zeros(1, np.int32)
+    mno4 = np.array([[4, 0, 1]], np.int32)
+    bh4 = L.Correlator(1, 1, mno4.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0,
+                       bb.ctypes.data_as(L.D), 1, nxyz.ctypes.data_as(L.D), nty.ctypes.data_as(L.I32))
+    assert lib.xtc_vmc_local_energy(C.byref(s), C.byref(bh4), 4, fake, fake, None, fake, big, None) == -1
     mno13 = np.array([[0, 0, k] for k in range(1, 14)], np.int32)
     c13 = np.zeros(13)
     ee13 = L.Correlator(0, 13, mno13.ctypes.data_as(L.I32), 1, c13.ctypes.data_as(L.D), 1.0, None, 0,
@@ -160,5 +169,5 @@ def test_vmc_argument_checks():
     # Gauss-Newton: at least two walkers, 1..64 parameters, lambda >= 0
     gn = lib.xtc_vmc_gn_step
     assert gn(1, 3, fake, fake, 0.1, 1.0, fake, fake, None) == -1
-    assert gn(10, 65, fake, fake, 0.1, 1.0, fake, fake, None) == -1
+    assert gn(10, 129, fake, fake, 0.1, 1.0, fake, fake, None) == -1
     assert gn(10, 3, fake, fake, -0.1, 1.0, fake, fake, None) == -1
