@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--vmc", action="store_true",
                    help="also time one reference-variance VMC optimisation step (sampling, local "
                         "energies with derivatives, Gauss-Newton) on the workload's determinant")
+    p.add_argument("--vmc-bh", action="store_true",
+                   help="with --vmc, also time the step for the 48-term BH correlator on the "
+                        "workload's nuclei (c, d and b per type)")
     p.add_argument("--walkers", type=int, default=16384)
     p.add_argument("--vmc-sweeps", type=int, default=20)
     p.add_argument("--copy-probe", action="store_true",
@@ -191,6 +194,11 @@ def main():
         if not a.no_cpu_baseline:
             log("timing the CPU oracle sample of the VMC step")
             res["vmc"]["cpu_baseline"] = vmc_cpu_baseline(wl)
+        if a.vmc_bh:
+            res["vmc"]["bh"] = vmc_bh_bench(wl, a.walkers, log)
+            if not a.no_cpu_baseline:
+                log("timing the CPU oracle sample of the BH local energies")
+                res["vmc"]["bh"]["cpu_baseline"] = vmc_bh_cpu_baseline(wl)
     if a.kernel_sample:
         res["kernel_sample"] = kernel_sample(a.kernel_sample, a.sample_blocks, log)
     if a.compare_fp64 and prec != L.XTC_FP64:
@@ -410,6 +418,55 @@ def vmc_bench(wl, n_w, n_sweeps, log):
     log(f"vmc: step {dt:.3f} s (sample {samp_ms:.1f} ms, energies {en_ms:.1f} ms, GN {gn_ms:.2f} ms), "
         f"acceptance {rate:.3f}")
     return res
+
+
+def vmc_bh_bench(wl, n_w, log):
+    """Local energies with every (c, d, b) derivative and the Gauss-Newton step for the
+    48-term BH correlator on the workload's nuclei, on n_w equilibrated walkers."""
+    import torch
+
+    from paper_2607_17314_amd import api
+    from workloads import bh_correlator, nuclear_repulsion, vmc_walkers
+    corr = bh_correlator(wl.atom_xyz)
+    sysv = api.VmcSystem.from_workload(wl, nuclear_repulsion(wl))
+    R = torch.as_tensor(vmc_walkers(wl, n_w, seed=1), device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    nrm = torch.randn((20, sysv.n_el, n_w, 3), dtype=torch.float64, device="cuda", generator=g)
+    uni = torch.rand((20, sysv.n_el, n_w), dtype=torch.float64, device="cuda", generator=g)
+    api.vmc_sample(sysv, R, 20, 0.6, nrm, uni)
+    E, dE = api.vmc_local_energy(sysv, corr, R)
+    torch.cuda.synchronize()
+    with api.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        E, dE = api.vmc_local_energy(sysv, corr, R)
+        delta, stats = api.vmc_gn_step(E, dE, 1e-2, 0.5)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    en_ms, gn_ms = kt.result["vmc_energy"]["ms"], kt.result["vmc_gn"]["ms"]
+    st = stats.cpu().numpy()
+    log(f"vmc bh: energies {en_ms:.1f} ms, GN {gn_ms:.2f} ms for {dE.shape[1]} parameters")
+    return {"correlator": f"{corr.n_terms}-term BH, {corr.nuc_xyz.shape[0]} nuclei",
+            "parameters": int(dE.shape[1]), "energy_ms": round(en_ms, 2), "gn_ms": round(gn_ms, 3),
+            "step_s": round(dt, 4), "local_energies_per_s": round(n_w / (en_ms * 1e-3), 1),
+            "clipped_variance": float(st[3])}
+
+
+def vmc_bh_cpu_baseline(wl, n_en=3):
+    """The oracle's BH local energies with complex-step derivatives in every parameter."""
+    import numpy as np
+
+    from oracle import vmc
+    from workloads import bh_correlator, nuclear_repulsion, vmc_walkers
+    corr = bh_correlator(wl.atom_xyz)
+    R = vmc_walkers(wl, n_en, seed=1)
+    t0 = time.perf_counter()
+    vmc.local_energy_grad(wl.basis, np.ascontiguousarray(wl.C_mo[:, :wl.n_occ]), wl.atom_xyz,
+                          wl.atom_Z.astype(np.float64), nuclear_repulsion(wl), corr, R)
+    t = time.perf_counter() - t0
+    return {"kind": "oracle", "local_energies_per_s": round(n_en / t, 3), "cores": 1,
+            "unit": "local energies (with every derivative) per second",
+            "sample": f"{n_en} walkers, complex step over {corr.c.size + 2} parameters"}
 
 
 def vmc_cpu_baseline(wl, n_w=1024, n_sweeps=2, n_en=256):
