@@ -537,13 +537,17 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
 // s = x r / (1 + x r): s' = x t^2, s'' = -2 x^2 t^3, grad s = (s'/r) (r - R), lap s = s'' + 2 s'/r;
 // in x: ds = r t^2, ds' = t^2 (1 - 2 s), ds'' = x t^3 (6 s - 4).
 constexpr int VMC_BH_MAXNUC = 24, VMC_BH_MAXTYPE = 2, VMC_BH_MAXTERM = 64, VMC_BH_MAXO = 12;
-constexpr int VMC_BH_TA = 9;   // per (electron, nucleus): a, da/db, ga, dga/db, la, dla/db, r - R
+// per (electron, nucleus): a, da/db, ga, dga/db, la, dla/db, r - R (3), a^2, a^3
+constexpr int VMC_BH_TA = 11;
+constexpr int VMC_BH_NO = VMC_BH_MAXO + 1;
 
 struct VmcBH {
   const double* nuc;   // [n_nuc][4]: x, y, z, type
   const double* bt;    // [n_types]
   const double* c;     // [n_types][n_terms]
   const int* mno;      // [n_terms][3]
+  const double* cs;    // [n_types][4][4][13]: coefficients summed per (min(m,n), max(m,n), o)
+  const int* on;       // [n_types][4][4]: 1 + the largest o with a coefficient (0: none)
   int n_nuc, n_types, n_terms;
   double d;
 };
@@ -601,25 +605,38 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
         pa[q] = pa[q - 1] * A;
         pj[q] = pj[q - 1] * Aj;
       }
+      // terms grouped by (m <= n): P = a^m a'^n + a'^m a^n is symmetric in (m, n); the sums
+      // over o run in registers (constant indices, a wave-uniform bound per group)
       T S1 = vmc_zero<T>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
-      const double* cc = bh.c + ty * bh.n_terms;
-      for (int k = 0; k < bh.n_terms; ++k) {
-        const int m = bh.mno[3 * k], n = bh.mno[3 * k + 1], o = bh.mno[3 * k + 2];
-        const double c = cc[k];
-        const T P = pa[m] * pj[n] + pj[m] * pa[n];
-        T Pa = vmc_zero<T>(), Paa = Pa;
-        if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
-        if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
-        if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
-        if (n >= 2) Paa = Paa + (double)(n * (n - 1)) * (pj[m] * pa[n - 2]);
-        const T E0 = pe[o];
-        const T E1 = o >= 1 ? (double)o * pe[o - 1] : vmc_zero<T>();
-        const T E2 = o >= 2 ? (double)(o * (o - 1)) * pe[o - 2] : vmc_zero<T>();
-        S1 = S1 + c * (Pa * E0);
-        S2 = S2 + c * (P * E1);
-        S3 = S3 + c * (Paa * E0);
-        S4 = S4 + c * (Pa * E1);
-        S5 = S5 + c * (P * E2);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int n = m; n < 4; ++n) {
+          const int on = bh.on[(ty * 4 + m) * 4 + n];
+          if (on == 0) continue;
+          const double* cw = bh.cs + ((ty * 4 + m) * 4 + n) * VMC_BH_NO;
+          T W0 = vmc_zero<T>(), W1 = W0, W2 = W0;
+#pragma unroll
+          for (int o = 0; o < VMC_BH_NO; ++o) {
+            if (o < on) {   // wave-uniform; constant indices keep pe in registers
+              const double c = cw[o];
+              W0 = W0 + c * pe[o];
+              if (o >= 1) W1 = W1 + (c * o) * pe[o - 1];
+              if (o >= 2) W2 = W2 + (c * (o * (o - 1))) * pe[o - 2];
+            }
+          }
+          const T P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
+          T Pa = vmc_zero<T>(), Paa = Pa;
+          if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
+          if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
+          if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
+          if (n >= 2) Paa = Paa + (double)(n * (n - 1)) * (pj[m] * pa[n - 2]);
+          S1 = S1 + Pa * W0;
+          S2 = S2 + P * W1;
+          S3 = S3 + Paa * W0;
+          S4 = S4 + Pa * W1;
+          S5 = S5 + P * W2;
+        }
       }
       // grad a = GA (r_i - R_I), grad e = ge (r_i - r_j)
       const double dd = Dix * dx + Diy * dy + Diz * dz, di2 = Dix * Dix + Diy * Diy + Diz * Diz;
@@ -658,16 +675,17 @@ __device__ double vmc_bh_dc(const VmcBH& bh, const double* TA, const double* Rs,
       for (int I = 0; I < nn; ++I) {
         if ((int)bh.nuc[4 * I + 3] != ty) continue;
         const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
-        const double a = ti[0], aj = TA[((long)j * nn + I) * VMC_BH_TA];
         const double ga = ti[2], la = ti[4], Dix = ti[6], Diy = ti[7], Diz = ti[8];
-        const double am = vmc_ipow(a, m), an = vmc_ipow(a, n), jm = vmc_ipow(aj, m),
-                     jn = vmc_ipow(aj, n);
+        const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
+        // a^q from the table: q = 0 -> 1, 1 -> [0], 2 -> [9], 3 -> [10]
+        auto apow = [](const double* t, int q) { return q == 0 ? 1.0 : t[q == 1 ? 0 : 7 + q]; };
+        const double am = apow(ti, m), an = apow(ti, n), jm = apow(tj, m), jn = apow(tj, n);
         const double P = am * jn + jm * an;
         double Pa = 0.0, Paa = 0.0;
-        if (m >= 1) Pa += m * vmc_ipow(a, m - 1) * jn;
-        if (n >= 1) Pa += n * jm * vmc_ipow(a, n - 1);
-        if (m >= 2) Paa += m * (m - 1) * vmc_ipow(a, m - 2) * jn;
-        if (n >= 2) Paa += n * (n - 1) * jm * vmc_ipow(a, n - 2);
+        if (m >= 1) Pa += m * apow(ti, m - 1) * jn;
+        if (n >= 1) Pa += n * jm * apow(ti, n - 1);
+        if (m >= 2) Paa += m * (m - 1) * apow(ti, m - 2) * jn;
+        if (n >= 2) Paa += n * (n - 1) * jm * apow(ti, n - 2);
         const double di2 = Dix * Dix + Diy * Diy + Diz * Diz, dd = Dix * dx + Diy * dy + Diz * dz;
         const double hga = ga * (hx * Dix + hy * Diy + hz * Diz);
         const double lap = Paa * E0 * ga * ga * di2 + Pa * E0 * la + 2.0 * Pa * E1 * ga * ge * dd +
@@ -728,6 +746,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
     o[6] = Dx;
     o[7] = Dy;
     o[8] = Dz;
+    o[9] = a * a;
+    o[10] = a * a * a;
   }
   __syncthreads();
   if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
@@ -969,8 +989,9 @@ static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_
   L.comp = ar.take<double>(n_ao);
   L.nuc = ar.take<double>(4 * (size_t)(n_nuc > 0 ? n_nuc : 1));
   L.Cs = ar.take<double>((size_t)n_ao * n_occ);
-  L.bh = ar.take<double>(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM);
-  L.bh_mno = ar.take<int>(3 * VMC_BH_MAXTERM);
+  L.bh = ar.take<double>(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM +
+                         VMC_BH_MAXTYPE * 16 * VMC_BH_NO);
+  L.bh_mno = ar.take<int>(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16);
   return L;
 }
 
@@ -1109,23 +1130,37 @@ static xtc_status vmc_local_energy_bh(const xtc_vmc_system* sys, const xtc_corre
   XTC_TRY(vmc_upload(sys, ar, st, &v, &L));
   const size_t lds = lds_energy_bh(v.b, v.n_occ, corr->n_nuc);
   XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: system too large for the walker's LDS");
-  std::vector<double> tab(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM, 0.0);
+  std::vector<double> tab(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM +
+                              VMC_BH_MAXTYPE * 16 * VMC_BH_NO, 0.0);
+  std::vector<int> itab(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16, 0);
   for (int I = 0; I < corr->n_nuc; ++I) {
     for (int c = 0; c < 3; ++c) tab[4 * I + c] = corr->nuc_xyz[3 * I + c];
     tab[4 * I + 3] = corr->nuc_type[I];
   }
   double* bt = tab.data() + 4 * VMC_BH_MAXNUC;
   double* cc = bt + VMC_BH_MAXTYPE;
+  double* cs = cc + VMC_BH_MAXTYPE * VMC_BH_MAXTERM;
+  int* on = itab.data() + 3 * VMC_BH_MAXTERM;
+  for (int k = 0; k < 3 * corr->n_terms; ++k) itab[k] = corr->mno[k];
   for (int t = 0; t < corr->n_types; ++t) {
     bt[t] = corr->b[t];
-    for (int k = 0; k < corr->n_terms; ++k) cc[t * corr->n_terms + k] = corr->c[t * corr->n_terms + k];
+    for (int k = 0; k < corr->n_terms; ++k) {
+      const double c = corr->c[t * corr->n_terms + k];
+      cc[t * corr->n_terms + k] = c;
+      const int m = corr->mno[3 * k], n = corr->mno[3 * k + 1], o = corr->mno[3 * k + 2];
+      const int lo = m < n ? m : n, hi = m < n ? n : m;
+      cs[((t * 4 + lo) * 4 + hi) * VMC_BH_NO + o] += c;
+      int& top = on[(t * 4 + lo) * 4 + hi];
+      if (o + 1 > top) top = o + 1;
+    }
   }
   XTC_HIP(hipMemcpyAsync(L.bh, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, st));
-  XTC_HIP(hipMemcpyAsync(L.bh_mno, corr->mno, sizeof(int) * 3 * corr->n_terms, hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.bh_mno, itab.data(), sizeof(int) * itab.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipStreamSynchronize(st));   // host staging vector ends with this call
   if (n_walkers == 0) return XTC_OK;
-  VmcBH bh{L.bh, L.bh + 4 * VMC_BH_MAXNUC, L.bh + 4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE, L.bh_mno,
-           corr->n_nuc, corr->n_types, corr->n_terms, corr->d};
+  const double* cdev = L.bh + 4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE;
+  VmcBH bh{L.bh, L.bh + 4 * VMC_BH_MAXNUC, cdev, L.bh_mno, cdev + VMC_BH_MAXTYPE * VMC_BH_MAXTERM,
+           L.bh_mno + 3 * VMC_BH_MAXTERM, corr->n_nuc, corr->n_types, corr->n_terms, corr->d};
   size_t tk = timing_begin(TM_VMC_ENERGY, st);
   hipLaunchKernelGGL(k_vmc_energy_bh, dim3((unsigned)n_walkers), dim3(64), lds, st, v, bh, R,
                      (long)n_walkers, E, dE);
