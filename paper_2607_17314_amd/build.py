@@ -30,6 +30,14 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 
+# Per-file additions. The generic FP64 GEMM keeps its MFMA accumulators in VGPRs:
+# with the default (AGPR) form the compiler copies all of them out of and back into
+# AGPRs around every k-tile's MFMAs; the VGPR form removes those copies (10-20%
+# faster at the fit's shapes, bitwise the same results).
+FILE_FLAGS = {
+    "gemm_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
 
 def _hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
@@ -45,7 +53,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = [hipcc, *FLAGS, "-c", src, "-o", obj]
+        cmd = [hipcc, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msg = "\n".join(line for line in (r.stdout + r.stderr).splitlines()
                         if "packed-fp32-ops" not in line)
