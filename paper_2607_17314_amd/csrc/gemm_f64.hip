@@ -29,8 +29,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long m0 = (long)blockIdx.y * GT;
-  const long n0 = (long)blockIdx.x * GT;
+  // Tile order: the M tile runs fastest, so the workgroups that read the same
+  // column panel of B run at the same time, and consecutive workgroup ids (which
+  // the hardware deals to the 8 XCDs in turn) are spread so that each XCD takes a
+  // contiguous run of tiles and shares those panels in its own L2.
+  const long n_mt = (g.M + GT - 1) / GT, n_tiles = n_mt * ((g.N + GT - 1) / GT);
+  const long per_xcd = (n_tiles + 7) / 8;
+  const long t = (long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= n_tiles) return;   // the whole workgroup, before any barrier
+  const long m0 = (t % n_mt) * GT;
+  const long n0 = (t / n_mt) * GT;
   if (g.lower_only && m0 + GT - 1 < n0) return;
 
   double ra[4], rb[4];
@@ -119,11 +127,13 @@ xtc_status gemm_f64(const GemmArgs& g, hipStream_t st) {
     set_error("gemm_f64: K must be positive");
     return XTC_ERR_INVALID_ARG;
   }
-  dim3 grid(cdiv(g.N, GT), cdiv(g.M, GT));
-  if (grid.y > 65535) {
-    set_error("gemm_f64: M too large for one launch");
+  const long n_tiles = ((g.M + GT - 1) / GT) * ((g.N + GT - 1) / GT);
+  const long n_wg = 8 * ((n_tiles + 7) / 8);
+  if (n_wg > 0x7fffffffL) {
+    set_error("gemm_f64: too many tiles for one launch");
     return XTC_ERR_INVALID_ARG;
   }
+  const dim3 grid((unsigned)n_wg);
   bool ak = (g.a_sk == 1), bk = (g.b_sk == 1);
   if (ak && bk) hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, st, g);
   else if (ak && !bk) hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, st, g);

@@ -538,7 +538,7 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
 // in x: ds = r t^2, ds' = t^2 (1 - 2 s), ds'' = x t^3 (6 s - 4).
 constexpr int VMC_BH_MAXNUC = 24, VMC_BH_MAXTYPE = 2, VMC_BH_MAXTERM = 64, VMC_BH_MAXO = 12;
 // per (electron, nucleus): a, da/db, ga, dga/db, la, dla/db, r - R (3), a^2, a^3
-constexpr int VMC_BH_TA = 11;
+constexpr int VMC_BH_TA = 6;
 constexpr int VMC_BH_NO = VMC_BH_MAXO + 1;
 
 struct VmcBH {
@@ -588,63 +588,75 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
 #pragma unroll
     for (int q = 1; q <= VMC_BH_MAXO; ++q) pe[q] = pe[q - 1] * E;
     const T ge2 = (r * r) * (ge * ge);
-    for (int I = 0; I < nn; ++I) {
-      const int ty = (int)bh.nuc[4 * I + 3];
-      const bool sb = seed == 1 + ty;
-      const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
-      const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
-      const T A = vmc_mk<T>(ti[0], sb ? ti[1] : 0.0);
-      const T Aj = vmc_mk<T>(tj[0], sb ? tj[1] : 0.0);
-      const T GA = vmc_mk<T>(ti[2], sb ? ti[3] : 0.0);
-      const T LA = vmc_mk<T>(ti[4], sb ? ti[5] : 0.0);
-      const double Dix = ti[6], Diy = ti[7], Diz = ti[8];
-      T pa[4], pj[4];
-      pa[0] = pj[0] = vmc_mk<T>(1.0, 0.0);
+    for (int ty = 0; ty < bh.n_types; ++ty) {
+      // the o-sums of each (m <= n) group depend on the pair and the nucleus type only:
+      // W[g] = (sum_o c e^o, sum_o c o e^(o-1), sum_o c o (o-1) e^(o-2)), formed once
+      // per type with constant indices and a wave-uniform bound per group
+      T W[10][3];
 #pragma unroll
-      for (int q = 1; q < 4; ++q) {
-        pa[q] = pa[q - 1] * A;
-        pj[q] = pj[q - 1] * Aj;
-      }
-      // terms grouped by (m <= n): P = a^m a'^n + a'^m a^n is symmetric in (m, n); the sums
-      // over o run in registers (constant indices, a wave-uniform bound per group)
-      T S1 = vmc_zero<T>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
+      for (int m = 0, g = 0; m < 4; ++m) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-#pragma unroll
-        for (int n = m; n < 4; ++n) {
+        for (int n = m; n < 4; ++n, ++g) {
           const int on = bh.on[(ty * 4 + m) * 4 + n];
-          if (on == 0) continue;
           const double* cw = bh.cs + ((ty * 4 + m) * 4 + n) * VMC_BH_NO;
-          T W0 = vmc_zero<T>(), W1 = W0, W2 = W0;
+          W[g][0] = W[g][1] = W[g][2] = vmc_zero<T>();
 #pragma unroll
           for (int o = 0; o < VMC_BH_NO; ++o) {
-            if (o < on) {   // wave-uniform; constant indices keep pe in registers
+            if (o < on) {
               const double c = cw[o];
-              W0 = W0 + c * pe[o];
-              if (o >= 1) W1 = W1 + (c * o) * pe[o - 1];
-              if (o >= 2) W2 = W2 + (c * (o * (o - 1))) * pe[o - 2];
+              W[g][0] = W[g][0] + c * pe[o];
+              if (o >= 1) W[g][1] = W[g][1] + (c * o) * pe[o - 1];
+              if (o >= 2) W[g][2] = W[g][2] + (c * (o * (o - 1))) * pe[o - 2];
             }
           }
-          const T P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
-          T Pa = vmc_zero<T>(), Paa = Pa;
-          if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
-          if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
-          if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
-          if (n >= 2) Paa = Paa + (double)(n * (n - 1)) * (pj[m] * pa[n - 2]);
-          S1 = S1 + Pa * W0;
-          S2 = S2 + P * W1;
-          S3 = S3 + Paa * W0;
-          S4 = S4 + Pa * W1;
-          S5 = S5 + P * W2;
         }
       }
-      // grad a = GA (r_i - R_I), grad e = ge (r_i - r_j)
-      const double dd = Dix * dx + Diy * dy + Diz * dz, di2 = Dix * Dix + Diy * Diy + Diz * Diz;
-      const T ga2 = di2 * (GA * GA), gage = dd * (GA * ge);
-      Gx = Gx + Dix * (S1 * GA) + dx * (S2 * ge);
-      Gy = Gy + Diy * (S1 * GA) + dy * (S2 * ge);
-      Gz = Gz + Diz * (S1 * GA) + dz * (S2 * ge);
-      L = L + S3 * ga2 + S1 * LA + 2.0 * (S4 * gage) + S5 * ge2 + S2 * le;
+      const bool sb = seed == 1 + ty;
+      for (int I = 0; I < nn; ++I) {
+        if ((int)bh.nuc[4 * I + 3] != ty) continue;   // wave-uniform
+        const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
+        const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
+        const T A = vmc_mk<T>(ti[0], sb ? ti[1] : 0.0);
+        const T Aj = vmc_mk<T>(tj[0], sb ? tj[1] : 0.0);
+        const T GA = vmc_mk<T>(ti[2], sb ? ti[3] : 0.0);
+        const T LA = vmc_mk<T>(ti[4], sb ? ti[5] : 0.0);
+        const double Dix = Rs[3 * i] - bh.nuc[4 * I], Diy = Rs[3 * i + 1] - bh.nuc[4 * I + 1],
+                     Diz = Rs[3 * i + 2] - bh.nuc[4 * I + 2];
+        T pa[4], pj[4];
+        pa[0] = pj[0] = vmc_mk<T>(1.0, 0.0);
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          pa[q] = pa[q - 1] * A;
+          pj[q] = pj[q - 1] * Aj;
+        }
+        // P = a^m a'^n + a'^m a^n is symmetric in (m, n), hence the grouping by m <= n
+        T S1 = vmc_zero<T>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
+#pragma unroll
+        for (int m = 0, g = 0; m < 4; ++m) {
+#pragma unroll
+          for (int n = m; n < 4; ++n, ++g) {
+            if (bh.on[(ty * 4 + m) * 4 + n] == 0) continue;   // wave-uniform
+            const T P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
+            T Pa = vmc_zero<T>(), Paa = Pa;
+            if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
+            if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
+            if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
+            if (n >= 2) Paa = Paa + (double)(n * (n - 1)) * (pj[m] * pa[n - 2]);
+            S1 = S1 + Pa * W[g][0];
+            S2 = S2 + P * W[g][1];
+            S3 = S3 + Paa * W[g][0];
+            S4 = S4 + Pa * W[g][1];
+            S5 = S5 + P * W[g][2];
+          }
+        }
+        // grad a = GA (r_i - R_I), grad e = ge (r_i - r_j)
+        const double dd = Dix * dx + Diy * dy + Diz * dz, di2 = Dix * Dix + Diy * Diy + Diz * Diz;
+        const T ga2 = di2 * (GA * GA), gage = dd * (GA * ge);
+        Gx = Gx + Dix * (S1 * GA) + dx * (S2 * ge);
+        Gy = Gy + Diy * (S1 * GA) + dy * (S2 * ge);
+        Gz = Gz + Diz * (S1 * GA) + dz * (S2 * ge);
+        L = L + S3 * ga2 + S1 * LA + 2.0 * (S4 * gage) + S5 * ge2 + S2 * le;
+      }
     }
   }
 }
@@ -672,35 +684,45 @@ __device__ double vmc_bh_dc(const VmcBH& bh, const double* TA, const double* Rs,
                    E1 = o >= 1 ? o * vmc_ipow_to<VMC_BH_MAXO>(e, o - 1) : 0.0,
                    E2 = o >= 2 ? o * (o - 1) * vmc_ipow_to<VMC_BH_MAXO>(e, o - 2) : 0.0;
       const double hge = ge * (hx * dx + hy * dy + hz * dz);
+      // the unit kernel's terms collected by power of e: the pair contributes
+      // E0 Y0 + E1 (2 ge Y1 + (le + 2 h.grad e) Y2) + E2 |grad e|^2 Y2, with the nuclear sums
+      // Y0 = sum_I Paa |grad a|^2 + Pa (lap a + 2 h.grad a), Y1 = sum_I Pa ga (r_i - R_I).(r_i - r_j)
+      // (grad a = ga (r_i - R_I), grad e = ge (r_i - r_j)) and Y2 = sum_I P
+      double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0;
       for (int I = 0; I < nn; ++I) {
         if ((int)bh.nuc[4 * I + 3] != ty) continue;
         const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
-        const double ga = ti[2], la = ti[4], Dix = ti[6], Diy = ti[7], Diz = ti[8];
+        const double ga = ti[2], la = ti[4];
+        const double Dix = Rs[3 * i] - bh.nuc[4 * I], Diy = Rs[3 * i + 1] - bh.nuc[4 * I + 1],
+                     Diz = Rs[3 * i + 2] - bh.nuc[4 * I + 2];
         const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
-        // a^q from the table: q = 0 -> 1, 1 -> [0], 2 -> [9], 3 -> [10]
-        auto apow = [](const double* t, int q) { return q == 0 ? 1.0 : t[q == 1 ? 0 : 7 + q]; };
-        const double am = apow(ti, m), an = apow(ti, n), jm = apow(tj, m), jn = apow(tj, n);
+        const double a_i = ti[0], a_j = tj[0];
+        auto apow = [](double a, int q) { return q == 0 ? 1.0 : q == 1 ? a : q == 2 ? a * a : a * a * a; };
+        const double am = apow(a_i, m), an = apow(a_i, n), jm = apow(a_j, m), jn = apow(a_j, n);
         const double P = am * jn + jm * an;
         double Pa = 0.0, Paa = 0.0;
-        if (m >= 1) Pa += m * apow(ti, m - 1) * jn;
-        if (n >= 1) Pa += n * jm * apow(ti, n - 1);
-        if (m >= 2) Paa += m * (m - 1) * apow(ti, m - 2) * jn;
-        if (n >= 2) Paa += n * (n - 1) * jm * apow(ti, n - 2);
+        if (m >= 1) Pa += m * apow(a_i, m - 1) * jn;
+        if (n >= 1) Pa += n * jm * apow(a_i, n - 1);
+        if (m >= 2) Paa += m * (m - 1) * apow(a_i, m - 2) * jn;
+        if (n >= 2) Paa += n * (n - 1) * jm * apow(a_i, n - 2);
         const double di2 = Dix * Dix + Diy * Diy + Diz * Diz, dd = Dix * dx + Diy * dy + Diz * dz;
         const double hga = ga * (hx * Dix + hy * Diy + hz * Diz);
-        const double lap = Paa * E0 * ga * ga * di2 + Pa * E0 * la + 2.0 * Pa * E1 * ga * ge * dd +
-                           P * (E2 * ge2 + E1 * le);
-        acc += lap + 2.0 * (Pa * E0 * hga + P * E1 * hge);
+        Y0 += Paa * (ga * ga * di2) + Pa * (la + 2.0 * hga);
+        Y1 += Pa * (ga * dd);
+        Y2 += P;
       }
+      acc += E0 * Y0 + E1 * (2.0 * ge * Y1 + (le + 2.0 * hge) * Y2) + E2 * ge2 * Y2;
     }
   }
   return -0.5 * acc;
 }
 
-// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], A5 [5][n_el][n],
-// aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64], fac [n], R [n_el][3], red [64],
-// H [n_el][4] (h_i, then spare), TA [n_el][n_nuc][9]; then ints: shell records
-// [n_shell][4], piv.
+// LDS (doubles): A5 [5][n_el][n], Ainv [2][n][n], fac [n], R [n_el][3], red [64],
+// H [n_el][4] (h_i, then spare), then one region used twice: during the Slater part
+// shell centres [n_shell][4], primitives [n_prim][2], aug [n][2n], chi [5][n_ao],
+// part [5][64] and the ints (shell records [n_shell][4], piv); after it the
+// per-(electron, nucleus) table TA [n_el][n_nuc][6]. Sharing the region keeps a
+// walker's LDS small enough for four workgroups per CU at H20.
 __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
                                                       const double* __restrict__ R, long n_w,
                                                       double* __restrict__ E,
@@ -710,24 +732,33 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
   const long w = blockIdx.x;
   const int nlin = bh.n_types * bh.n_terms, nth = nlin + 1 + bh.n_types;
   const int nn = bh.n_nuc;
-  double* shd = lds;
-  double* prim = shd + 4 * v.b.n_shell;
-  double* A5 = prim + 2 * v.b.n_prim;
-  double* aug = A5 + 5 * n_el * n;
-  double* Ainv = aug + 2 * n * n;
-  double* chi = Ainv + 2 * n * n;
-  double* part = chi + 5 * v.b.n_ao;
-  double* fac = part + 5 * 64;
+  double* A5 = lds;
+  double* Ainv = A5 + 5 * n_el * n;
+  double* fac = Ainv + 2 * n * n;
   double* Rs = fac + n;
   double* red = Rs + 3 * n_el;
   double* H = red + 64;
-  double* TA = H + 4 * n_el;
-  int* shi = (int*)(TA + (long)n_el * nn * VMC_BH_TA);
+  double* shd = H + 4 * n_el;   // the shared region
+  double* prim = shd + 4 * v.b.n_shell;
+  double* aug = prim + 2 * v.b.n_prim;
+  double* chi = aug + 2 * n * n;
+  double* part = chi + 5 * v.b.n_ao;
+  int* shi = (int*)(part + 5 * 64);
   int* piv = shi + 4 * v.b.n_shell;
+  double* TA = shd;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
   vmc_stage(v.b, shd, shi, prim);
   __syncthreads();
-  // the per-(electron, nucleus) table: a, da/db, (a'/r), d(a'/r)/db, lap a, d lap a/db, r - R
+  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
+    if (lane == 0) {
+      E[w] = __builtin_nan("");
+      if (dE)
+        for (int p = 0; p < nth; ++p) dE[w * nth + p] = __builtin_nan("");
+    }
+    return;
+  }
+  __syncthreads();   // the Slater part's tables are dead: TA takes their place
+  // the per-(electron, nucleus) table: a, da/db, (a'/r), d(a'/r)/db, lap a, d lap a/db
   for (int q = lane; q < n_el * nn; q += 64) {
     const int e = q / nn, I = q - e * nn;
     const double Dx = Rs[3 * e] - bh.nuc[4 * I], Dy = Rs[3 * e + 1] - bh.nuc[4 * I + 1],
@@ -743,21 +774,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
     o[3] = da1 * rinv;
     o[4] = a2 + 2.0 * a1 * rinv;
     o[5] = da2 + 2.0 * da1 * rinv;
-    o[6] = Dx;
-    o[7] = Dy;
-    o[8] = Dz;
-    o[9] = a * a;
-    o[10] = a * a * a;
   }
   __syncthreads();
-  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
-    if (lane == 0) {
-      E[w] = __builtin_nan("");
-      if (dE)
-        for (int p = 0; p < nth; ++p) dE[w * nth + p] = __builtin_nan("");
-    }
-    return;
-  }
   auto lane_sum = [&](double x) {
     red[lane] = x;
     __syncthreads();
@@ -1015,9 +1033,12 @@ static size_t lds_sweeps(const VmcBasis& b, int n) {
 
 static size_t lds_energy_bh(const VmcBasis& b, int n, int n_nuc) {
   const int n_el = 2 * n;
-  return lds_tables(b) + sizeof(double) * (5 * (size_t)n_el * n + 4 * (size_t)n * n +
-                                           5 * (size_t)b.n_ao + 5 * 64 + n + 3 * n_el + 64 +
-                                           4 * n_el + (size_t)n_el * n_nuc * VMC_BH_TA) + 16;
+  const size_t keep = sizeof(double) * (5 * (size_t)n_el * n + 2 * (size_t)n * n + n +
+                                        3 * n_el + 64 + 4 * n_el);
+  const size_t slater = lds_tables(b) + sizeof(double) * (2 * (size_t)n * n + 5 * (size_t)b.n_ao +
+                                                          5 * 64) + sizeof(int) * n;
+  const size_t table = sizeof(double) * (size_t)n_el * n_nuc * VMC_BH_TA;
+  return keep + (slater > table ? slater : table) + 16;
 }
 
 static size_t lds_energy(const VmcBasis& b, int n) {
