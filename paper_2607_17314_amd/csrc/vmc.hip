@@ -30,10 +30,10 @@ constexpr int VMC_GN_THREADS = 1024;
 // {exponent, coefficient}. The Cartesian component factors are folded into the orbital
 // coefficients (C'[a][k] = comp_a C[a][k]), so the AO rows below omit them.
 struct VmcBasis {
-  const double* shd;   // [n_shell][4]
-  const int* shi;      // [n_shell][4]
+  const double* cen;   // [n_cent][4]: the distinct shell centres (x, y, z, 0)
+  const int* shi;      // [n_shell][2]: l | centre << 3 | n_prim << 15, first primitive | first AO << 15
   const double* prim;  // [n_prim][2]
-  int n_shell, n_prim, n_ao;
+  int n_shell, n_prim, n_ao, n_cent;
 };
 
 struct VmcDev {
@@ -69,11 +69,13 @@ __device__ __forceinline__ double vmc_ipow(double x, int n) {   // Cartesian pow
 // P = x^i y^j z^k, g = sum c e^{-alpha r^2}: d_x chi = (i x^{i-1} g + 2 x^{i+1} g') y^j z^k,
 // lap chi = g lap P + P (4 l g' + 6 g' + 4 r^2 g''), primes in s = r^2. Tables in LDS.
 template <bool LAP>
-__device__ void vmc_shell(const double* shd, const int* shi, const double* prim, int n_ao, int s,
+__device__ void vmc_shell(const double* cen, const int* shi, const double* prim, int n_ao, int s,
                           double px, double py, double pz, double* chi) {
-  const double x = px - shd[4 * s], y = py - shd[4 * s + 1], z = pz - shd[4 * s + 2];
-  const int l = shi[4 * s], p0 = shi[4 * s + 1], p1 = shi[4 * s + 2];
-  int a = shi[4 * s + 3];
+  const unsigned w0 = (unsigned)shi[2 * s], w1 = (unsigned)shi[2 * s + 1];
+  const int l = (int)(w0 & 7u), c = (int)((w0 >> 3) & 4095u);
+  const int p0 = (int)(w1 & 32767u), p1 = p0 + (int)(w0 >> 15);
+  int a = (int)(w1 >> 15);
+  const double x = px - cen[4 * c], y = py - cen[4 * c + 1], z = pz - cen[4 * c + 2];
   const double r2 = x * x + y * y + z * z;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   for (int p = p0; p < p1; ++p) {
@@ -110,22 +112,20 @@ __device__ void vmc_shell(const double* shd, const int* shi, const double* prim,
 }
 
 // Copies the basis tables into LDS (the caller synchronises before use).
-__device__ __forceinline__ void vmc_stage(const VmcBasis& b, double* shd, int* shi,
+__device__ __forceinline__ void vmc_stage(const VmcBasis& b, double* cen, int* shi,
                                           double* prim) {
-  for (int i = threadIdx.x; i < 4 * b.n_shell; i += 64) {
-    shd[i] = b.shd[i];
-    shi[i] = b.shi[i];
-  }
+  for (int i = threadIdx.x; i < 4 * b.n_cent; i += 64) cen[i] = b.cen[i];
+  for (int i = threadIdx.x; i < 2 * b.n_shell; i += 64) shi[i] = b.shi[i];
   for (int i = threadIdx.x; i < 2 * b.n_prim; i += 64) prim[i] = b.prim[i];
 }
 
 // All AOs of the point p into chi (lanes over shells); the caller synchronises.
 template <bool LAP>
-__device__ __forceinline__ void vmc_aos(const VmcBasis& b, const double* shd, const int* shi,
+__device__ __forceinline__ void vmc_aos(const VmcBasis& b, const double* cen, const int* shi,
                                         const double* prim, double px, double py, double pz,
                                         double* chi) {
   for (int s = threadIdx.x; s < b.n_shell; s += 64)
-    vmc_shell<LAP>(shd, shi, prim, b.n_ao, s, px, py, pz, chi);
+    vmc_shell<LAP>(cen, shi, prim, b.n_ao, s, px, py, pz, chi);
 }
 
 // out[q * ostride + k] = sum_a chi[q * n_ao + a] C[a][k], q < NQ, k < n_occ: lanes as
@@ -228,9 +228,10 @@ __device__ __forceinline__ double vmc_step(double r, double s, double e) {
 
 // ---------------------------------------------------------------------------------------
 // Sampler: n_sweeps sweeps of single-electron moves, electrons in index order.
-// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], Ainv [2][n][n],
-// aug [n][2n], chi [n_ao], part [64], phin [n], wv [n], fac [n], R [n_el][3], the sweep's
-// draws [n_el][4] (eta_x, eta_y, eta_z, u); then ints: shell records [n_shell][4], piv.
+// LDS (doubles): shell centres [n_cent][4], primitives [n_prim][2], Ainv [2][n][n],
+// aug [n][2n] for the starting inverses, whose space then holds the sweep's draws
+// [n_el][4] (eta_x, eta_y, eta_z, u), phin [n], wv [n] and fac [n]; chi [n_ao], part [64]
+// (also the inversion's scratch), R [n_el][3]; then ints: shell records [n_shell][2], piv.
 __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict__ R, long n_w,
                                                    int n_sweeps, double step,
                                                    const double* __restrict__ normals,
@@ -239,31 +240,31 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
   extern __shared__ double lds[];
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   const long w = blockIdx.x;
-  double* shd = lds;
-  double* prim = shd + 4 * v.b.n_shell;
+  double* cen = lds;
+  double* prim = cen + 4 * v.b.n_cent;
   double* Ainv = prim + 2 * v.b.n_prim;
   double* aug = Ainv + 2 * n * n;
-  double* chi = aug + 2 * n * n;
-  double* part = chi + v.b.n_ao;
-  double* phin = part + 64;
+  double* dr = aug;   // after the starting inverses
+  double* phin = dr + 4 * n_el;
   double* wv = phin + n;
   double* fac = wv + n;
-  double* Rs = fac + n;
-  double* dr = Rs + 3 * n_el;
-  int* shi = (int*)(dr + 4 * n_el);
-  int* piv = shi + 4 * v.b.n_shell;
+  double* chi = aug + (2 * n * n > 11 * n ? 2 * n * n : 11 * n);
+  double* part = chi + v.b.n_ao;
+  double* Rs = part + 64;
+  int* shi = (int*)(Rs + 3 * n_el);
+  int* piv = shi + 2 * v.b.n_shell;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
-  vmc_stage(v.b, shd, shi, prim);
+  vmc_stage(v.b, cen, shi, prim);
   __syncthreads();
   // inverse Slater matrices of the starting configuration
   for (int sp = 0; sp < 2; ++sp) {
     for (int ii = 0; ii < n; ++ii) {
       const int e = sp * n + ii;
-      vmc_aos<false>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+      vmc_aos<false>(v.b, cen, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
       __syncthreads();
       vmc_orbitals<1>(v, chi, part, aug + ii * 2 * n, 0);
     }
-    if (!vmc_invert(aug, n, fac, piv)) {
+    if (!vmc_invert(aug, n, part, piv)) {   // part: free between orbital rows
       if (lane == 0) accepted[w] = -1;
       return;   // uniform over the (single-wave) workgroup
     }
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
       const double px = vmc_step(Rs[3 * e], step, dr[4 * e]);
       const double py = vmc_step(Rs[3 * e + 1], step, dr[4 * e + 1]);
       const double pz = vmc_step(Rs[3 * e + 2], step, dr[4 * e + 2]);
-      vmc_aos<false>(v.b, shd, shi, prim, px, py, pz, chi);
+      vmc_aos<false>(v.b, cen, shi, prim, px, py, pz, chi);
       __syncthreads();
       vmc_orbitals<1>(v, chi, part, phin, 0);
       double* Ai = Ainv + sp * n * n;
@@ -344,12 +345,12 @@ __global__ __launch_bounds__(64) void k_vmc_sweeps(VmcDev v, double* __restrict_
 // The Slater part of a walker's local energy: A5[q][e][k] = (phi_k, d_x, d_y, d_z, lap)
 // of the occupied orbitals at electron e, and the two inverse spin blocks Ainv[sp][k][i].
 // Returns false (uniformly) when a determinant is exactly singular.
-__device__ bool vmc_slater(const VmcDev& v, const double* shd, const int* shi, const double* prim,
+__device__ bool vmc_slater(const VmcDev& v, const double* cen, const int* shi, const double* prim,
                            const double* Rs, double* A5, double* aug, double* Ainv, double* chi,
                            double* part, double* fac, int* piv) {
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   for (int e = 0; e < n_el; ++e) {
-    vmc_aos<true>(v.b, shd, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
+    vmc_aos<true>(v.b, cen, shi, prim, Rs[3 * e], Rs[3 * e + 1], Rs[3 * e + 2], chi);
     __syncthreads();
     vmc_orbitals<5>(v, chi, part, A5 + e * n, n_el * n);
   }
@@ -387,9 +388,9 @@ __device__ __forceinline__ void vmc_ratios(const VmcDev& v, const double* A5, co
 
 // ---------------------------------------------------------------------------------------
 // Local energy and its parameter derivatives, one walker per workgroup.
-// LDS (doubles): shell centres [n_shell][4], primitives [n_prim][2], A5 [5][n_el][n],
+// LDS (doubles): shell centres [n_cent][4], primitives [n_prim][2], A5 [5][n_el][n],
 // aug [n][2n], Ainv [2][n][n], chi [5][n_ao], part [5][64], fac [n], R [n_el][3], red [64];
-// then ints: shell records [n_shell][4], piv.
+// then ints: shell records [n_shell][2], piv.
 __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
                                                    const double* __restrict__ R, long n_w,
                                                    double* __restrict__ E,
@@ -398,8 +399,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   const long w = blockIdx.x;
   const int nth = cf.n + 1;
-  double* shd = lds;
-  double* prim = shd + 4 * v.b.n_shell;
+  double* cen = lds;
+  double* prim = cen + 4 * v.b.n_cent;
   double* A5 = prim + 2 * v.b.n_prim;
   double* aug = A5 + 5 * n_el * n;
   double* Ainv = aug + 2 * n * n;
@@ -409,11 +410,11 @@ __global__ __launch_bounds__(64) void k_vmc_energy(VmcDev v, EECoefV cf,
   double* Rs = fac + n;
   double* red = Rs + 3 * n_el;
   int* shi = (int*)(red + 64);
-  int* piv = shi + 4 * v.b.n_shell;
+  int* piv = shi + 2 * v.b.n_shell;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
-  vmc_stage(v.b, shd, shi, prim);
+  vmc_stage(v.b, cen, shi, prim);
   __syncthreads();
-  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
+  if (!vmc_slater(v, cen, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
     // exactly singular reference determinant: no local energy
     if (lane == 0) {
       E[w] = __builtin_nan("");
@@ -719,8 +720,8 @@ __device__ double vmc_bh_dc(const VmcBH& bh, const double* TA, const double* Rs,
 
 // LDS (doubles): A5 [5][n_el][n], Ainv [2][n][n], fac [n], R [n_el][3], red [64],
 // H [n_el][4] (h_i, then spare), then one region used twice: during the Slater part
-// shell centres [n_shell][4], primitives [n_prim][2], aug [n][2n], chi [5][n_ao],
-// part [5][64] and the ints (shell records [n_shell][4], piv); after it the
+// shell centres [n_cent][4], primitives [n_prim][2], aug [n][2n], chi [5][n_ao],
+// part [5][64] and the ints (shell records [n_shell][2], piv); after it the
 // per-(electron, nucleus) table TA [n_el][n_nuc][6]. Sharing the region keeps a
 // walker's LDS small enough for four workgroups per CU at H20.
 __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
@@ -738,18 +739,18 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
   double* Rs = fac + n;
   double* red = Rs + 3 * n_el;
   double* H = red + 64;
-  double* shd = H + 4 * n_el;   // the shared region
-  double* prim = shd + 4 * v.b.n_shell;
+  double* cen = H + 4 * n_el;   // the shared region
+  double* prim = cen + 4 * v.b.n_cent;
   double* aug = prim + 2 * v.b.n_prim;
   double* chi = aug + 2 * n * n;
   double* part = chi + 5 * v.b.n_ao;
   int* shi = (int*)(part + 5 * 64);
-  int* piv = shi + 4 * v.b.n_shell;
-  double* TA = shd;
+  int* piv = shi + 2 * v.b.n_shell;
+  double* TA = cen;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
-  vmc_stage(v.b, shd, shi, prim);
+  vmc_stage(v.b, cen, shi, prim);
   __syncthreads();
-  if (!vmc_slater(v, shd, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
+  if (!vmc_slater(v, cen, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
     if (lane == 0) {
       E[w] = __builtin_nan("");
       if (dE)
@@ -994,15 +995,15 @@ __global__ __launch_bounds__(256) void k_vmc_scale_c(const double* __restrict__ 
 }
 
 struct VmcLayout {
-  double* shd; int* shi; double* prim; double* comp; double* nuc; double* Cs;
+  double* cen; int* shi; double* prim; double* comp; double* nuc; double* Cs;
   double* bh;    // BH correlator: nuclei [24][4], b [2], c [2][64]
   int* bh_mno;   // [64][3]
 };
 
 static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_occ, int n_nuc) {
   VmcLayout L;
-  L.shd = ar.take<double>(4 * (size_t)n_shell);
-  L.shi = ar.take<int>(4 * (size_t)n_shell);
+  L.cen = ar.take<double>(4 * (size_t)n_shell);
+  L.shi = ar.take<int>(2 * (size_t)n_shell);
   L.prim = ar.take<double>(2 * (size_t)n_prim);
   L.comp = ar.take<double>(n_ao);
   L.nuc = ar.take<double>(4 * (size_t)(n_nuc > 0 ? n_nuc : 1));
@@ -1021,14 +1022,15 @@ size_t ws_vmc(int n_ao) {
 }
 
 static size_t lds_tables(const VmcBasis& b) {
-  return sizeof(double) * (4 * (size_t)b.n_shell + 2 * (size_t)b.n_prim) +
-         sizeof(int) * 4 * (size_t)b.n_shell;
+  return sizeof(double) * (4 * (size_t)b.n_cent + 2 * (size_t)b.n_prim) +
+         sizeof(int) * 2 * (size_t)b.n_shell;
 }
 
 static size_t lds_sweeps(const VmcBasis& b, int n) {
   const int n_el = 2 * n;
-  return lds_tables(b) +
-         sizeof(double) * (4 * (size_t)n * n + b.n_ao + 64 + 3 * (size_t)n + 7 * n_el) + 16;
+  const size_t shared = 2 * (size_t)n * n > 11 * (size_t)n ? 2 * (size_t)n * n : 11 * (size_t)n;
+  return lds_tables(b) + sizeof(double) * (2 * (size_t)n * n + shared + b.n_ao + 64 + 3 * n_el) +
+         sizeof(int) * n + 16;
 }
 
 static size_t lds_energy_bh(const VmcBasis& b, int n, int n_nuc) {
@@ -1066,9 +1068,11 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
   XTC_REQUIRE(sy->n_nuc >= 0 && sy->n_nuc <= 4096 && (sy->n_nuc == 0 || (sy->nuc_xyz && sy->nuc_charge)),
               "vmc: bad nuclei");
   const int ns = basis->n_shell;
-  std::vector<double> shd(4 * (size_t)ns, 0.0);
-  std::vector<int> shi(4 * (size_t)ns);
-  int n_ao = 0;
+  // distinct shell centres in order of first use (at most one per shell)
+  std::vector<double> cen;
+  std::vector<int> cid((size_t)basis->n_atom, -1);
+  std::vector<int> shi(2 * (size_t)ns);
+  int n_ao = 0, n_cent = 0;
   for (int s = 0; s < ns; ++s) {
     const int l = basis->shell_l[s];
     const int c = basis->shell_center[s];
@@ -1076,11 +1080,18 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
     XTC_REQUIRE(c >= 0 && c < basis->n_atom, "vmc: shell centre out of range");
     XTC_REQUIRE(basis->shell_prim_start[s + 1] > basis->shell_prim_start[s],
                 "vmc: shell without primitives");
-    for (int q = 0; q < 3; ++q) shd[4 * s + q] = basis->atom_xyz[3 * c + q];
-    shi[4 * s] = l;
-    shi[4 * s + 1] = basis->shell_prim_start[s];
-    shi[4 * s + 2] = basis->shell_prim_start[s + 1];
-    shi[4 * s + 3] = n_ao;
+    if (cid[c] < 0) {
+      cid[c] = n_cent++;
+      for (int q = 0; q < 3; ++q) cen.push_back(basis->atom_xyz[3 * c + q]);
+      cen.push_back(0.0);
+    }
+    // two words per shell: l (3 bits) | centre (12) | primitive count (15), and
+    // first primitive (15) | first AO (17)
+    const unsigned np = (unsigned)(basis->shell_prim_start[s + 1] - basis->shell_prim_start[s]);
+    XTC_REQUIRE(basis->shell_prim_start[s] < 32768 && np < 32768 && n_ao < 131072,
+                "vmc: basis too large for the packed shell records");
+    shi[2 * s] = (int)((unsigned)l | ((unsigned)cid[c] << 3) | (np << 15));
+    shi[2 * s + 1] = (int)((unsigned)basis->shell_prim_start[s] | ((unsigned)n_ao << 15));
     n_ao += (l + 1) * (l + 2) / 2;
   }
   const int n_prim = basis->shell_prim_start[ns];
@@ -1098,7 +1109,7 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
     for (int c = 0; c < 3; ++c) nuc[4 * I + c] = sy->nuc_xyz[3 * I + c];
     nuc[4 * I + 3] = sy->nuc_charge[I];
   }
-  XTC_HIP(hipMemcpyAsync(L.shd, shd.data(), sizeof(double) * shd.size(), hipMemcpyHostToDevice, st));
+  XTC_HIP(hipMemcpyAsync(L.cen, cen.data(), sizeof(double) * cen.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.shi, shi.data(), sizeof(int) * shi.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.prim, prim.data(), sizeof(double) * prim.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.comp, basis->comp_factor, sizeof(double) * n_ao, hipMemcpyHostToDevice, st));
@@ -1109,7 +1120,7 @@ static xtc_status vmc_upload(const xtc_vmc_system* sy, Arena& ar, hipStream_t st
   XTC_CHECK_LAUNCH();
   XTC_HIP(hipStreamSynchronize(st));   // host staging vectors end with this call
   VmcDev v;
-  v.b = VmcBasis{L.shd, L.shi, L.prim, ns, n_prim, n_ao};
+  v.b = VmcBasis{L.cen, L.shi, L.prim, ns, n_prim, n_ao, n_cent};
   v.C = L.Cs;
   v.nuc = L.nuc;
   v.n_occ = sy->n_occ;
