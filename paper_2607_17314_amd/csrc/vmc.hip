@@ -560,17 +560,24 @@ struct Dl {
 __device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
 __device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
 __device__ __forceinline__ Dl operator*(double s, Dl a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, double s) { return {a.v * s, a.d * s}; }
+// the type of a product or sum of a T and a U (a dual when either is one)
+template <class T, class U> struct DlJoin { typedef Dl type; };
+template <> struct DlJoin<double, double> { typedef double type; };
 template <class T> __device__ __forceinline__ T vmc_mk(double v, double d);
 template <> __device__ __forceinline__ double vmc_mk<double>(double v, double) { return v; }
 template <> __device__ __forceinline__ Dl vmc_mk<Dl>(double v, double d) { return {v, d}; }
 template <class T> __device__ __forceinline__ T vmc_zero() { return vmc_mk<T>(0.0, 0.0); }
 
-// grad_i J and lap_i J of electron i; with T = Dl the derivatives in the parameter `seed`
-// (0: d, 1 + t: b_t) ride along. TA: the per-(electron, nucleus) table in LDS.
-template <class T>
+// grad_i J and lap_i J of electron i. The derivative in one parameter `seed` (0: d,
+// 1 + t: b_t) rides along as a dual number: d moves only the pair quantities (e and its
+// derivatives, type TE), b_t only the nuclear ones (a and its derivatives, type TN), so
+// each seed makes just one side dual; TR joins the two. TA: the per-(electron, nucleus)
+// table in LDS.
+template <class TE, class TN, class TR = typename DlJoin<TE, TN>::type>
 __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* Rs, int n_el,
-                               int i, int seed, T& Gx, T& Gy, T& Gz, T& L) {
-  Gx = Gy = Gz = L = vmc_zero<T>();
+                               int i, int seed, TR& Gx, TR& Gy, TR& Gz, TR& L) {
+  Gx = Gy = Gz = L = vmc_zero<TR>();
   const double d = bh.d;
   const int nn = bh.n_nuc;
   for (int j = 0; j < n_el; ++j) {
@@ -581,26 +588,26 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
     const double t = 1.0 / (1.0 + d * r), e = d * r * t, e1 = d * t * t, e2 = -2.0 * d * d * t * t * t;
     const bool sd = seed == 0;
     const double de = r * t * t, de1 = t * t * (1.0 - 2.0 * e), de2 = d * t * t * t * (6.0 * e - 4.0);
-    const T E = vmc_mk<T>(e, sd ? de : 0.0);
-    const T ge = vmc_mk<T>(e1 * rinv, sd ? de1 * rinv : 0.0);
-    const T le = vmc_mk<T>(e2 + 2.0 * e1 * rinv, sd ? de2 + 2.0 * de1 * rinv : 0.0);
-    T pe[VMC_BH_MAXO + 1];
-    pe[0] = vmc_mk<T>(1.0, 0.0);
+    const TE E = vmc_mk<TE>(e, sd ? de : 0.0);
+    const TE ge = vmc_mk<TE>(e1 * rinv, sd ? de1 * rinv : 0.0);
+    const TE le = vmc_mk<TE>(e2 + 2.0 * e1 * rinv, sd ? de2 + 2.0 * de1 * rinv : 0.0);
+    TE pe[VMC_BH_MAXO + 1];
+    pe[0] = vmc_mk<TE>(1.0, 0.0);
 #pragma unroll
     for (int q = 1; q <= VMC_BH_MAXO; ++q) pe[q] = pe[q - 1] * E;
-    const T ge2 = (r * r) * (ge * ge);
+    const TE ge2 = (r * r) * (ge * ge);
     for (int ty = 0; ty < bh.n_types; ++ty) {
       // the o-sums of each (m <= n) group depend on the pair and the nucleus type only:
       // W[g] = (sum_o c e^o, sum_o c o e^(o-1), sum_o c o (o-1) e^(o-2)), formed once
       // per type with constant indices and a wave-uniform bound per group
-      T W[10][3];
+      TE W[10][3];
 #pragma unroll
       for (int m = 0, g = 0; m < 4; ++m) {
 #pragma unroll
         for (int n = m; n < 4; ++n, ++g) {
           const int on = bh.on[(ty * 4 + m) * 4 + n];
           const double* cw = bh.cs + ((ty * 4 + m) * 4 + n) * VMC_BH_NO;
-          W[g][0] = W[g][1] = W[g][2] = vmc_zero<T>();
+          W[g][0] = W[g][1] = W[g][2] = vmc_zero<TE>();
 #pragma unroll
           for (int o = 0; o < VMC_BH_NO; ++o) {
             if (o < on) {
@@ -617,28 +624,28 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
         if ((int)bh.nuc[4 * I + 3] != ty) continue;   // wave-uniform
         const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
         const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
-        const T A = vmc_mk<T>(ti[0], sb ? ti[1] : 0.0);
-        const T Aj = vmc_mk<T>(tj[0], sb ? tj[1] : 0.0);
-        const T GA = vmc_mk<T>(ti[2], sb ? ti[3] : 0.0);
-        const T LA = vmc_mk<T>(ti[4], sb ? ti[5] : 0.0);
+        const TN A = vmc_mk<TN>(ti[0], sb ? ti[1] : 0.0);
+        const TN Aj = vmc_mk<TN>(tj[0], sb ? tj[1] : 0.0);
+        const TN GA = vmc_mk<TN>(ti[2], sb ? ti[3] : 0.0);
+        const TN LA = vmc_mk<TN>(ti[4], sb ? ti[5] : 0.0);
         const double Dix = Rs[3 * i] - bh.nuc[4 * I], Diy = Rs[3 * i + 1] - bh.nuc[4 * I + 1],
                      Diz = Rs[3 * i + 2] - bh.nuc[4 * I + 2];
-        T pa[4], pj[4];
-        pa[0] = pj[0] = vmc_mk<T>(1.0, 0.0);
+        TN pa[4], pj[4];
+        pa[0] = pj[0] = vmc_mk<TN>(1.0, 0.0);
 #pragma unroll
         for (int q = 1; q < 4; ++q) {
           pa[q] = pa[q - 1] * A;
           pj[q] = pj[q - 1] * Aj;
         }
         // P = a^m a'^n + a'^m a^n is symmetric in (m, n), hence the grouping by m <= n
-        T S1 = vmc_zero<T>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
+        TR S1 = vmc_zero<TR>(), S2 = S1, S3 = S1, S4 = S1, S5 = S1;
 #pragma unroll
         for (int m = 0, g = 0; m < 4; ++m) {
 #pragma unroll
           for (int n = m; n < 4; ++n, ++g) {
             if (bh.on[(ty * 4 + m) * 4 + n] == 0) continue;   // wave-uniform
-            const T P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
-            T Pa = vmc_zero<T>(), Paa = Pa;
+            const TN P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
+            TN Pa = vmc_zero<TN>(), Paa = Pa;
             if (m >= 1) Pa = Pa + (double)m * (pa[m - 1] * pj[n]);
             if (n >= 1) Pa = Pa + (double)n * (pj[m] * pa[n - 1]);
             if (m >= 2) Paa = Paa + (double)(m * (m - 1)) * (pa[m - 2] * pj[n]);
@@ -652,7 +659,8 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
         }
         // grad a = GA (r_i - R_I), grad e = ge (r_i - r_j)
         const double dd = Dix * dx + Diy * dy + Diz * dz, di2 = Dix * Dix + Diy * Diy + Diz * Diz;
-        const T ga2 = di2 * (GA * GA), gage = dd * (GA * ge);
+        const TN ga2 = di2 * (GA * GA);
+        const TR gage = dd * (GA * ge);
         Gx = Gx + Dix * (S1 * GA) + dx * (S2 * ge);
         Gy = Gy + Diy * (S1 * GA) + dy * (S2 * ge);
         Gz = Gz + Diz * (S1 * GA) + dz * (S2 * ge);
@@ -794,7 +802,7 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
     const int i = lane;
     double S, L;
     vmc_ratios(v, A5, Ainv, i, Dx, Dy, Dz, S);
-    vmc_bh_jastrow<double>(bh, TA, Rs, n_el, i, -1, Gx, Gy, Gz, L);
+    vmc_bh_jastrow<double, double>(bh, TA, Rs, n_el, i, -1, Gx, Gy, Gz, L);
     ekin = -0.5 * (L + Gx * Gx + Gy * Gy + Gz * Gz + 2.0 * (Gx * Dx + Gy * Dy + Gz * Dz) + S);
     const double xi = Rs[3 * i], yi = Rs[3 * i + 1], zi = Rs[3 * i + 2];
     for (int j = i + 1; j < n_el; ++j) {
@@ -824,7 +832,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
     double x = 0.0;
     if (lane < n_el) {
       Dl gx, gy, gz, l;
-      vmc_bh_jastrow<Dl>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
+      if (sd == 0) vmc_bh_jastrow<Dl, double>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
+      else vmc_bh_jastrow<double, Dl>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
       x = -0.5 * (l.d + 2.0 * ((gx.v + Dx) * gx.d + (gy.v + Dy) * gy.d + (gz.v + Dz) * gz.d));
     }
     const double s = lane_sum(x);
