@@ -561,6 +561,7 @@ __device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b
 __device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
 __device__ __forceinline__ Dl operator*(double s, Dl a) { return {s * a.v, s * a.d}; }
 __device__ __forceinline__ Dl operator*(Dl a, double s) { return {a.v * s, a.d * s}; }
+__device__ __forceinline__ Dl operator+(Dl a, double s) { return {a.v + s, a.d}; }
 // the type of a product or sum of a T and a U (a dual when either is one)
 template <class T, class U> struct DlJoin { typedef Dl type; };
 template <> struct DlJoin<double, double> { typedef double type; };
@@ -591,15 +592,12 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
     const TE E = vmc_mk<TE>(e, sd ? de : 0.0);
     const TE ge = vmc_mk<TE>(e1 * rinv, sd ? de1 * rinv : 0.0);
     const TE le = vmc_mk<TE>(e2 + 2.0 * e1 * rinv, sd ? de2 + 2.0 * de1 * rinv : 0.0);
-    TE pe[VMC_BH_MAXO + 1];
-    pe[0] = vmc_mk<TE>(1.0, 0.0);
-#pragma unroll
-    for (int q = 1; q <= VMC_BH_MAXO; ++q) pe[q] = pe[q - 1] * E;
     const TE ge2 = (r * r) * (ge * ge);
     for (int ty = 0; ty < bh.n_types; ++ty) {
       // the o-sums of each (m <= n) group depend on the pair and the nucleus type only:
-      // W[g] = (sum_o c e^o, sum_o c o e^(o-1), sum_o c o (o-1) e^(o-2)), formed once
-      // per type with constant indices and a wave-uniform bound per group
+      // W[g] = (q(e), q'(e), q''(e)) for q(e) = sum_o c_o e^o, formed once per type by
+      // Horner's rule with its first two derivatives (a rolled loop: the kernel's code
+      // stays small)
       TE W[10][3];
 #pragma unroll
       for (int m = 0, g = 0; m < 4; ++m) {
@@ -607,16 +605,15 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
         for (int n = m; n < 4; ++n, ++g) {
           const int on = bh.on[(ty * 4 + m) * 4 + n];
           const double* cw = bh.cs + ((ty * 4 + m) * 4 + n) * VMC_BH_NO;
-          W[g][0] = W[g][1] = W[g][2] = vmc_zero<TE>();
-#pragma unroll
-          for (int o = 0; o < VMC_BH_NO; ++o) {
-            if (o < on) {
-              const double c = cw[o];
-              W[g][0] = W[g][0] + c * pe[o];
-              if (o >= 1) W[g][1] = W[g][1] + (c * o) * pe[o - 1];
-              if (o >= 2) W[g][2] = W[g][2] + (c * (o * (o - 1))) * pe[o - 2];
-            }
+          TE q0 = vmc_zero<TE>(), q1 = q0, q2 = q0;   // q, q', q''/2
+          for (int o = on - 1; o >= 0; --o) {   // wave-uniform bound
+            q2 = q2 * E + q1;
+            q1 = q1 * E + q0;
+            q0 = q0 * E + cw[o];
           }
+          W[g][0] = q0;
+          W[g][1] = q1;
+          W[g][2] = 2.0 * q2;
         }
       }
       const bool sb = seed == 1 + ty;
