@@ -549,6 +549,8 @@ struct VmcBH {
   const int* mno;      // [n_terms][3]
   const double* cs;    // [n_types][4][4][13]: coefficients summed per (min(m,n), max(m,n), o)
   const int* on;       // [n_types][4][4]: 1 + the largest o with a coefficient (0: none)
+  const int* gst;      // [n_types][11]: start of each (m <= n) group's terms in gtm
+  const int* gtm;      // [n_types][VMC_BH_MAXTERM]: term k | o << 8, grouped by (m <= n)
   int n_nuc, n_types, n_terms;
   double d;
 };
@@ -667,84 +669,119 @@ __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* 
   }
 }
 
+__device__ __forceinline__ double vmc_wave_sum(double x) {   // fixed butterfly order
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 // Pass 2: dE/dc[t][k] = -1/2 sum_i sum_{j != i} sum_{I of type t} [lap_i f + 2 h_i . grad_i f]
-// for the unit kernel f of term k, h_i = grad_i J + grad_i Phi_0 / Phi_0.
-__device__ double vmc_bh_dc(const VmcBH& bh, const double* TA, const double* Rs, const double* H,
-                            int n_el, int p) {
-  const int ty = p / bh.n_terms, k = p - ty * bh.n_terms;
-  const int m = bh.mno[3 * k], n = bh.mno[3 * k + 1], o = bh.mno[3 * k + 2];
+// for the unit kernel f of term k, h_i = grad_i J + grad_i Phi_0 / Phi_0. Lanes over the
+// ordered electron pairs (i, j). Per pair and nucleus type, the nuclear sums of each
+// (m <= n) group, Y0 = sum_I Paa |grad a|^2 + Pa (lap a + 2 h.grad a),
+// Y1 = sum_I Pa ga (r_i - R_I).(r_i - r_j) (grad a = ga (r_i - R_I), grad e = ge (r_i - r_j))
+// and Y2 = sum_I P, serve every term of the group: a term of power o contributes
+// E0 Y0 + E1 (2 ge Y1 + (le + 2 h.grad e) Y2) + E2 |grad e|^2 Y2 with E0 = e^o,
+// E1 = o e^(o-1), E2 = o (o-1) e^(o-2). Each term's pair values are summed over the wave
+// (fixed order) and lane 0 adds them to acc[t][k] in LDS, pair block by pair block.
+__device__ void vmc_bh_dc_pairs(const VmcBH& bh, const double* TA, const double* Rs,
+                                const double* H, int n_el, double* acc) {
+  const int lane = threadIdx.x, nn = bh.n_nuc, np = n_el * (n_el - 1);
   const double d = bh.d;
-  const int nn = bh.n_nuc;
-  double acc = 0.0;
-  for (int i = 0; i < n_el; ++i) {
+  for (int q0 = 0; q0 < np; q0 += 64) {   // wave-uniform
+    const int q = q0 + lane;
+    const bool live = q < np;
+    const int qq = live ? q : 0;
+    const int i = qq / (n_el - 1), jj = qq - i * (n_el - 1), j = jj + (jj >= i ? 1 : 0);
     const double hx = H[4 * i], hy = H[4 * i + 1], hz = H[4 * i + 2];
-    for (int j = 0; j < n_el; ++j) {
-      if (j == i) continue;
-      const double dx = Rs[3 * i] - Rs[3 * j], dy = Rs[3 * i + 1] - Rs[3 * j + 1],
-                   dz = Rs[3 * i + 2] - Rs[3 * j + 2];
-      const double r = sqrt(dx * dx + dy * dy + dz * dz), rinv = 1.0 / r;
-      const double t = 1.0 / (1.0 + d * r), e = d * r * t, e1 = d * t * t,
-                   e2 = -2.0 * d * d * t * t * t;
-      const double ge = e1 * rinv, le = e2 + 2.0 * e1 * rinv, ge2 = e1 * e1;
-      const double E0 = vmc_ipow_to<VMC_BH_MAXO>(e, o),
-                   E1 = o >= 1 ? o * vmc_ipow_to<VMC_BH_MAXO>(e, o - 1) : 0.0,
-                   E2 = o >= 2 ? o * (o - 1) * vmc_ipow_to<VMC_BH_MAXO>(e, o - 2) : 0.0;
-      const double hge = ge * (hx * dx + hy * dy + hz * dz);
-      // the unit kernel's terms collected by power of e: the pair contributes
-      // E0 Y0 + E1 (2 ge Y1 + (le + 2 h.grad e) Y2) + E2 |grad e|^2 Y2, with the nuclear sums
-      // Y0 = sum_I Paa |grad a|^2 + Pa (lap a + 2 h.grad a), Y1 = sum_I Pa ga (r_i - R_I).(r_i - r_j)
-      // (grad a = ga (r_i - R_I), grad e = ge (r_i - r_j)) and Y2 = sum_I P
-      double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0;
+    const double dx = Rs[3 * i] - Rs[3 * j], dy = Rs[3 * i + 1] - Rs[3 * j + 1],
+                 dz = Rs[3 * i + 2] - Rs[3 * j + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz), rinv = 1.0 / r;
+    const double t = 1.0 / (1.0 + d * r), e = d * r * t, e1 = d * t * t,
+                 e2 = -2.0 * d * d * t * t * t;
+    const double ge = e1 * rinv, le = e2 + 2.0 * e1 * rinv, ge2 = e1 * e1;
+    const double hge = ge * (hx * dx + hy * dy + hz * dz);
+    for (int ty = 0; ty < bh.n_types; ++ty) {
+      double Y[10][3];
+#pragma unroll
+      for (int g = 0; g < 10; ++g) Y[g][0] = Y[g][1] = Y[g][2] = 0.0;
       for (int I = 0; I < nn; ++I) {
-        if ((int)bh.nuc[4 * I + 3] != ty) continue;
+        if ((int)bh.nuc[4 * I + 3] != ty) continue;   // wave-uniform
         const double* ti = TA + ((long)i * nn + I) * VMC_BH_TA;
+        const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
         const double ga = ti[2], la = ti[4];
         const double Dix = Rs[3 * i] - bh.nuc[4 * I], Diy = Rs[3 * i + 1] - bh.nuc[4 * I + 1],
                      Diz = Rs[3 * i + 2] - bh.nuc[4 * I + 2];
-        const double* tj = TA + ((long)j * nn + I) * VMC_BH_TA;
-        const double a_i = ti[0], a_j = tj[0];
-        auto apow = [](double a, int q) { return q == 0 ? 1.0 : q == 1 ? a : q == 2 ? a * a : a * a * a; };
-        const double am = apow(a_i, m), an = apow(a_i, n), jm = apow(a_j, m), jn = apow(a_j, n);
-        const double P = am * jn + jm * an;
-        double Pa = 0.0, Paa = 0.0;
-        if (m >= 1) Pa += m * apow(a_i, m - 1) * jn;
-        if (n >= 1) Pa += n * jm * apow(a_i, n - 1);
-        if (m >= 2) Paa += m * (m - 1) * apow(a_i, m - 2) * jn;
-        if (n >= 2) Paa += n * (n - 1) * jm * apow(a_i, n - 2);
         const double di2 = Dix * Dix + Diy * Diy + Diz * Diz, dd = Dix * dx + Diy * dy + Diz * dz;
-        const double hga = ga * (hx * Dix + hy * Diy + hz * Diz);
-        Y0 += Paa * (ga * ga * di2) + Pa * (la + 2.0 * hga);
-        Y1 += Pa * (ga * dd);
-        Y2 += P;
+        const double u0 = ga * ga * di2, u1 = la + 2.0 * ga * (hx * Dix + hy * Diy + hz * Diz),
+                     u2 = ga * dd;
+        double pa[4], pj[4];
+        pa[0] = pj[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          pa[k] = pa[k - 1] * ti[0];
+          pj[k] = pj[k - 1] * tj[0];
+        }
+#pragma unroll
+        for (int m = 0, g = 0; m < 4; ++m) {
+#pragma unroll
+          for (int n = m; n < 4; ++n, ++g) {
+            if (bh.on[(ty * 4 + m) * 4 + n] == 0) continue;   // wave-uniform
+            const double P = m == n ? 2.0 * (pa[m] * pj[m]) : pa[m] * pj[n] + pj[m] * pa[n];
+            double Pa = 0.0, Paa = 0.0;
+            if (m >= 1) Pa += m * (pa[m - 1] * pj[n]);
+            if (n >= 1) Pa += n * (pj[m] * pa[n - 1]);
+            if (m >= 2) Paa += (m * (m - 1)) * (pa[m - 2] * pj[n]);
+            if (n >= 2) Paa += (n * (n - 1)) * (pj[m] * pa[n - 2]);
+            Y[g][0] += Paa * u0 + Pa * u1;
+            Y[g][1] += Pa * u2;
+            Y[g][2] += P;
+          }
+        }
       }
-      acc += E0 * Y0 + E1 * (2.0 * ge * Y1 + (le + 2.0 * hge) * Y2) + E2 * ge2 * Y2;
+#pragma unroll
+      for (int g = 0; g < 10; ++g) {
+        const int x1 = bh.gst[ty * 11 + g + 1];
+        for (int x = bh.gst[ty * 11 + g]; x < x1; ++x) {   // wave-uniform
+          const int ko = bh.gtm[ty * VMC_BH_MAXTERM + x], k = ko & 255, o = ko >> 8;
+          const double eo2 = vmc_ipow_to<VMC_BH_MAXO>(e, o >= 2 ? o - 2 : 0);
+          const double eo1 = o >= 2 ? eo2 * e : 1.0, eo = o >= 2 ? eo1 * e : (o == 1 ? e : 1.0);
+          const double E1 = o >= 1 ? o * eo1 : 0.0, E2 = o >= 2 ? (o * (o - 1)) * eo2 : 0.0;
+          const double val = eo * Y[g][0] + E1 * (2.0 * ge * Y[g][1] + (le + 2.0 * hge) * Y[g][2]) +
+                             E2 * ge2 * Y[g][2];
+          const double sum = vmc_wave_sum(live ? val : 0.0);
+          if (lane == 0) acc[ty * bh.n_terms + k] += sum;
+        }
+      }
     }
   }
-  return -0.5 * acc;
 }
 
 // LDS (doubles): A5 [5][n_el][n], Ainv [2][n][n], fac [n], R [n_el][3], red [64],
-// H [n_el][4] (h_i, then spare), then one region used twice: during the Slater part
+// H [n_el][4] (h_i, then spare), the nuclei [n_nuc][4] (read in every pair's nuclear
+// loop), pass 2's sums [2][64], then one region used twice: during the Slater part
 // shell centres [n_cent][4], primitives [n_prim][2], aug [n][2n], chi [5][n_ao],
 // part [5][64] and the ints (shell records [n_shell][2], piv); after it the
 // per-(electron, nucleus) table TA [n_el][n_nuc][6]. Sharing the region keeps a
 // walker's LDS small enough for four workgroups per CU at H20.
-__global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
+__global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh_in,
                                                       const double* __restrict__ R, long n_w,
                                                       double* __restrict__ E,
                                                       double* __restrict__ dE) {
   extern __shared__ double lds[];
   const int n = v.n_occ, n_el = 2 * n, lane = threadIdx.x;
   const long w = blockIdx.x;
-  const int nlin = bh.n_types * bh.n_terms, nth = nlin + 1 + bh.n_types;
-  const int nn = bh.n_nuc;
+  const int nlin = bh_in.n_types * bh_in.n_terms, nth = nlin + 1 + bh_in.n_types;
+  const int nn = bh_in.n_nuc;
   double* A5 = lds;
   double* Ainv = A5 + 5 * n_el * n;
   double* fac = Ainv + 2 * n * n;
   double* Rs = fac + n;
   double* red = Rs + 3 * n_el;
   double* H = red + 64;
-  double* cen = H + 4 * n_el;   // the shared region
+  double* nuc = H + 4 * n_el;
+  double* acc = nuc + 4 * nn;   // pass 2's sums [n_types][n_terms]
+  double* cen = acc + VMC_BH_MAXTYPE * VMC_BH_MAXTERM;   // the shared region
   double* prim = cen + 4 * v.b.n_cent;
   double* aug = prim + 2 * v.b.n_prim;
   double* chi = aug + 2 * n * n;
@@ -753,6 +790,9 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
   int* piv = shi + 2 * v.b.n_shell;
   double* TA = cen;
   for (int e = lane; e < 3 * n_el; e += 64) Rs[e] = R[w * 3 * n_el + e];
+  for (int e = lane; e < 4 * nn; e += 64) nuc[e] = bh_in.nuc[e];
+  VmcBH bh = bh_in;
+  bh.nuc = nuc;
   vmc_stage(v.b, cen, shi, prim);
   __syncthreads();
   if (!vmc_slater(v, cen, shi, prim, Rs, A5, aug, Ainv, chi, part, fac, piv)) {
@@ -818,12 +858,12 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh,
   const double Etot = lane_sum(ekin + pot);
   if (lane == 0) E[w] = Etot + v.e_nuc;
   if (!dE) return;   // uniform
-  // pass 2: the linear coefficients, one lane per coefficient
-  for (int p0 = 0; p0 < nlin; p0 += 64) {
-    const int p = p0 + lane;
-    const double g = p < nlin ? vmc_bh_dc(bh, TA, Rs, H, n_el, p) : 0.0;
-    if (p < nlin) dE[w * nth + p] = g;
-  }
+  // pass 2: the linear coefficients
+  for (int p = lane; p < nlin; p += 64) acc[p] = 0.0;
+  __syncthreads();
+  vmc_bh_dc_pairs(bh, TA, Rs, H, n_el, acc);
+  __syncthreads();
+  for (int p = lane; p < nlin; p += 64) dE[w * nth + p] = -0.5 * acc[p];
   // pass 3: d and each b_t in forward mode
   for (int sd = 0; sd <= bh.n_types; ++sd) {
     double x = 0.0;
@@ -1016,7 +1056,8 @@ static VmcLayout layout_vmc(Arena& ar, int n_shell, int n_prim, int n_ao, int n_
   L.Cs = ar.take<double>((size_t)n_ao * n_occ);
   L.bh = ar.take<double>(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM +
                          VMC_BH_MAXTYPE * 16 * VMC_BH_NO);
-  L.bh_mno = ar.take<int>(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16);
+  L.bh_mno = ar.take<int>(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16 + VMC_BH_MAXTYPE * 11 +
+                          VMC_BH_MAXTYPE * VMC_BH_MAXTERM);
   return L;
 }
 
@@ -1042,7 +1083,8 @@ static size_t lds_sweeps(const VmcBasis& b, int n) {
 static size_t lds_energy_bh(const VmcBasis& b, int n, int n_nuc) {
   const int n_el = 2 * n;
   const size_t keep = sizeof(double) * (5 * (size_t)n_el * n + 2 * (size_t)n * n + n +
-                                        3 * n_el + 64 + 4 * n_el);
+                                        3 * n_el + 64 + 4 * n_el + 4 * (size_t)n_nuc +
+                                        VMC_BH_MAXTYPE * VMC_BH_MAXTERM);
   const size_t slater = lds_tables(b) + sizeof(double) * (2 * (size_t)n * n + 5 * (size_t)b.n_ao +
                                                           5 * 64) + sizeof(int) * n;
   const size_t table = sizeof(double) * (size_t)n_el * n_nuc * VMC_BH_TA;
@@ -1170,7 +1212,8 @@ static xtc_status vmc_local_energy_bh(const xtc_vmc_system* sys, const xtc_corre
   XTC_REQUIRE(lds <= VMC_LDS_MAX, "xtc_vmc_local_energy: system too large for the walker's LDS");
   std::vector<double> tab(4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE + VMC_BH_MAXTYPE * VMC_BH_MAXTERM +
                               VMC_BH_MAXTYPE * 16 * VMC_BH_NO, 0.0);
-  std::vector<int> itab(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16, 0);
+  std::vector<int> itab(3 * VMC_BH_MAXTERM + VMC_BH_MAXTYPE * 16 + VMC_BH_MAXTYPE * 11 +
+                            VMC_BH_MAXTYPE * VMC_BH_MAXTERM, 0);
   for (int I = 0; I < corr->n_nuc; ++I) {
     for (int c = 0; c < 3; ++c) tab[4 * I + c] = corr->nuc_xyz[3 * I + c];
     tab[4 * I + 3] = corr->nuc_type[I];
@@ -1179,6 +1222,8 @@ static xtc_status vmc_local_energy_bh(const xtc_vmc_system* sys, const xtc_corre
   double* cc = bt + VMC_BH_MAXTYPE;
   double* cs = cc + VMC_BH_MAXTYPE * VMC_BH_MAXTERM;
   int* on = itab.data() + 3 * VMC_BH_MAXTERM;
+  int* gst = on + VMC_BH_MAXTYPE * 16;
+  int* gtm = gst + VMC_BH_MAXTYPE * 11;
   for (int k = 0; k < 3 * corr->n_terms; ++k) itab[k] = corr->mno[k];
   for (int t = 0; t < corr->n_types; ++t) {
     bt[t] = corr->b[t];
@@ -1191,14 +1236,27 @@ static xtc_status vmc_local_energy_bh(const xtc_vmc_system* sys, const xtc_corre
       int& top = on[(t * 4 + lo) * 4 + hi];
       if (o + 1 > top) top = o + 1;
     }
+    // the terms of each (m <= n) group, groups in the kernel's order (0,0), (0,1), ..., (3,3)
+    int x = 0;
+    for (int lo = 0, g = 0; lo < 4; ++lo)
+      for (int hi = lo; hi < 4; ++hi, ++g) {
+        gst[t * 11 + g] = x;
+        for (int k = 0; k < corr->n_terms; ++k) {
+          const int m = corr->mno[3 * k], n = corr->mno[3 * k + 1], o = corr->mno[3 * k + 2];
+          if ((m < n ? m : n) == lo && (m < n ? n : m) == hi) gtm[t * VMC_BH_MAXTERM + x++] = k | (o << 8);
+        }
+      }
+    gst[t * 11 + 10] = x;
   }
   XTC_HIP(hipMemcpyAsync(L.bh, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(L.bh_mno, itab.data(), sizeof(int) * itab.size(), hipMemcpyHostToDevice, st));
   XTC_HIP(hipStreamSynchronize(st));   // host staging vector ends with this call
   if (n_walkers == 0) return XTC_OK;
   const double* cdev = L.bh + 4 * VMC_BH_MAXNUC + VMC_BH_MAXTYPE;
+  const int* on_dev = L.bh_mno + 3 * VMC_BH_MAXTERM;
   VmcBH bh{L.bh, L.bh + 4 * VMC_BH_MAXNUC, cdev, L.bh_mno, cdev + VMC_BH_MAXTYPE * VMC_BH_MAXTERM,
-           L.bh_mno + 3 * VMC_BH_MAXTERM, corr->n_nuc, corr->n_types, corr->n_terms, corr->d};
+           on_dev, on_dev + VMC_BH_MAXTYPE * 16, on_dev + VMC_BH_MAXTYPE * 16 + VMC_BH_MAXTYPE * 11,
+           corr->n_nuc, corr->n_types, corr->n_terms, corr->d};
   size_t tk = timing_begin(TM_VMC_ENERGY, st);
   hipLaunchKernelGGL(k_vmc_energy_bh, dim3((unsigned)n_walkers), dim3(64), lds, st, v, bh, R,
                      (long)n_walkers, E, dE);
