@@ -23,7 +23,8 @@ constexpr int VMC_MAX_OCC = 32;      // electrons per spin
 constexpr int VMC_MAX_L = 6;
 constexpr int VMC_MAX_TERMS = 12;    // EE terms of the local-energy kernel
 constexpr int VMC_MAX_THETA = 128;   // parameters of the Gauss-Newton step
-constexpr int VMC_GN_THREADS = 1024;
+constexpr int VMC_GN_THREADS = 512;
+constexpr int GN_FEW = 16;   // up to this many parameters the GN sums are block reductions
 
 // Basis tables as the kernels hold them (staged into LDS at kernel start): per shell the
 // centre {x, y, z, 0} and {l, first primitive, end primitive, first AO}; per primitive
@@ -931,61 +932,168 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
     a += r * r;
   }
   const double var = gn_block_sum(a, sh.red) / (double)(N - 1);
-  // derivatives of m and of the MAD, then of the clipped energies
-  for (int p = 0; p < nth; ++p) {
-    a = 0.0;
-    for (long k = t; k < N; k += VMC_GN_THREADS) a += dE[k * nth + p];
-    const double s = gn_block_sum(a, sh.red);
-    if (t == 0) sh.dm[p] = s * inv_n;
-  }
-  __syncthreads();
-  for (int p = 0; p < nth; ++p) {
-    a = 0.0;
-    for (long k = t; k < N; k += VMC_GN_THREADS) {
-      const double df = E[k] - m;
-      const double sg = df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0);
-      a += sg * (dE[k * nth + p] - sh.dm[p]);
-    }
-    const double s = gn_block_sum(a, sh.red);
-    if (t == 0) sh.dmad[p] = s * inv_n;
-  }
-  __syncthreads();
-  auto dclip = [&](long k, int p) {
-    const double e = E[k];
-    if (e < lo) return sh.dm[p] - 5.0 * sh.dmad[p];
-    if (e > hi) return sh.dm[p] + 5.0 * sh.dmad[p];
-    return dE[k * nth + p];
-  };
-  for (int p = 0; p < nth; ++p) {
-    a = 0.0;
-    for (long k = t; k < N; k += VMC_GN_THREADS) a += dclip(k, p);
-    const double s = gn_block_sum(a, sh.red);
-    if (t == 0) sh.mdt[p] = s * inv_n;
-  }
-  __syncthreads();
-  // residual r_k = Et_k - mean, dr_kp = dEt_kp - mean_k(dEt_kp)
-  for (int p = 0; p < nth; ++p) {
-    a = 0.0;
-    for (long k = t; k < N; k += VMC_GN_THREADS) {
-      const double e = E[k];
-      const double r = (e < lo ? lo : (e > hi ? hi : e)) - mean;
-      a += (dclip(k, p) - sh.mdt[p]) * r;
-    }
-    const double s = gn_block_sum(a, sh.red);
-    if (t == 0) sh.grad[p] = 2.0 * s / (double)(N - 1);
-  }
-  for (int p = 0; p < nth; ++p) {
-    for (int q = 0; q <= p; ++q) {
+  if (nth <= GN_FEW) {
+    // few parameters: each sum is one block reduction over the walkers
+    // derivatives of m and of the MAD, then of the clipped energies
+    for (int p = 0; p < nth; ++p) {
       a = 0.0;
-      for (long k = t; k < N; k += VMC_GN_THREADS)
-        a += (dclip(k, p) - sh.mdt[p]) * (dclip(k, q) - sh.mdt[q]);
+      for (long k = t; k < N; k += VMC_GN_THREADS) a += dE[k * nth + p];
       const double s = gn_block_sum(a, sh.red);
-      if (t == 0) {
-        const double c = s * inv_n + (p == q ? lam : 0.0);
-        sh.C[p * nth + q] = c;
-        sh.C[q * nth + p] = c;
+      if (t == 0) sh.dm[p] = s * inv_n;
+    }
+    __syncthreads();
+    for (int p = 0; p < nth; ++p) {
+      a = 0.0;
+      for (long k = t; k < N; k += VMC_GN_THREADS) {
+        const double df = E[k] - m;
+        const double sg = df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0);
+        a += sg * (dE[k * nth + p] - sh.dm[p]);
+      }
+      const double s = gn_block_sum(a, sh.red);
+      if (t == 0) sh.dmad[p] = s * inv_n;
+    }
+    __syncthreads();
+    auto dclip = [&](long k, int p) {
+      const double e = E[k];
+      if (e < lo) return sh.dm[p] - 5.0 * sh.dmad[p];
+      if (e > hi) return sh.dm[p] + 5.0 * sh.dmad[p];
+      return dE[k * nth + p];
+    };
+    for (int p = 0; p < nth; ++p) {
+      a = 0.0;
+      for (long k = t; k < N; k += VMC_GN_THREADS) a += dclip(k, p);
+      const double s = gn_block_sum(a, sh.red);
+      if (t == 0) sh.mdt[p] = s * inv_n;
+    }
+    __syncthreads();
+    // residual r_k = Et_k - mean, dr_kp = dEt_kp - mean_k(dEt_kp)
+    for (int p = 0; p < nth; ++p) {
+      a = 0.0;
+      for (long k = t; k < N; k += VMC_GN_THREADS) {
+        const double e = E[k];
+        const double r = (e < lo ? lo : (e > hi ? hi : e)) - mean;
+        a += (dclip(k, p) - sh.mdt[p]) * r;
+      }
+      const double s = gn_block_sum(a, sh.red);
+      if (t == 0) sh.grad[p] = 2.0 * s / (double)(N - 1);
+    }
+    for (int p = 0; p < nth; ++p) {
+      for (int q = 0; q <= p; ++q) {
+        a = 0.0;
+        for (long k = t; k < N; k += VMC_GN_THREADS)
+          a += (dclip(k, p) - sh.mdt[p]) * (dclip(k, q) - sh.mdt[q]);
+        const double s = gn_block_sum(a, sh.red);
+        if (t == 0) {
+          const double c = s * inv_n + (p == q ? lam : 0.0);
+          sh.C[p * nth + q] = c;
+          sh.C[q * nth + p] = c;
+        }
       }
     }
+  } else {
+    // The parameter sums run in walker order over tiles of tk walkers: a tile's dE rows are
+    // staged in the space of C (not needed until the end) and its energies in red; one
+    // thread per parameter column, and up to GN_PAIRS entries (p, q) of C per thread.
+    constexpr int GN_PAIRS = (VMC_MAX_THETA * (VMC_MAX_THETA + 1) / 2 + VMC_GN_THREADS - 1) /
+                             VMC_GN_THREADS;
+    const int tk = VMC_MAX_THETA * VMC_MAX_THETA / nth < VMC_GN_THREADS
+                       ? VMC_MAX_THETA * VMC_MAX_THETA / nth : VMC_GN_THREADS;
+    double* tile = sh.C;
+    double* te = sh.red;
+    auto stage = [&](long k0, int nk) {
+      __syncthreads();   // the previous tile's readers are done
+      for (int e = t; e < nk * nth; e += VMC_GN_THREADS) tile[e] = dE[k0 * nth + e];
+      for (int e = t; e < nk; e += VMC_GN_THREADS) te[e] = E[k0 + e];
+      __syncthreads();
+    };
+    auto tile_len = [&](long k0) { return (int)(N - k0 < tk ? N - k0 : tk); };
+    // Column sums over the walkers: thread t takes column t % nth and the walkers of
+    // segment t / nth (every S-th walker of each tile, S = threads / nth); the S partial
+    // sums of a column are then added in segment order (fixed).
+    const int S = VMC_GN_THREADS / nth, ccol = t % nth, cseg = t / nth;
+    auto combine = [&](double a) {   // returns the column total on threads t < nth
+      __syncthreads();
+      te[t] = cseg < S ? a : 0.0;
+      __syncthreads();
+      double tot = 0.0;
+      if (t < nth)
+        for (int g = 0; g < S; ++g) tot += te[g * nth + t];
+      return tot;
+    };
+    auto colsum = [&](auto f) {
+      double a = 0.0;
+      for (long k0 = 0; k0 < N; k0 += tk) {
+        const int nk = tile_len(k0);
+        stage(k0, nk);
+        if (cseg < S)
+          for (int kk = cseg; kk < nk; kk += S) a += f(kk, tile[kk * nth + ccol]);
+      }
+      return combine(a);
+    };
+    // derivatives of m and of the MAD, then of the clipped energies
+    double a1 = colsum([&](int, double x) { return x; });
+    if (t < nth) sh.dm[t] = a1 * inv_n;
+    a1 = colsum([&](int kk, double x) {   // sh.dm is visible after the first tile's barrier
+      const double df = te[kk] - m;
+      return (df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0)) * (x - sh.dm[ccol]);
+    });
+    if (t < nth) sh.dmad[t] = a1 * inv_n;
+    a1 = colsum([&](int kk, double x) {
+      const double e = te[kk];
+      return e < lo ? sh.dm[ccol] - 5.0 * sh.dmad[ccol]
+                    : (e > hi ? sh.dm[ccol] + 5.0 * sh.dmad[ccol] : x);
+    });
+    if (t < nth) sh.mdt[t] = a1 * inv_n;
+    // residual r_k = Et_k - mean and dr_kp = dEt_kp - mean_k(dEt_kp): the gradient and C
+    const int npair = nth * (nth + 1) / 2;
+    const int nu = t < npair ? (npair - t + VMC_GN_THREADS - 1) / VMC_GN_THREADS : 0;
+    double cacc[GN_PAIRS];
+    int cpq[GN_PAIRS];   // p | q << 8 of this thread's entries t + u VMC_GN_THREADS (q <= p)
+  #pragma unroll
+    for (int u = 0; u < GN_PAIRS; ++u) {
+      const int x = t + u * VMC_GN_THREADS;
+      int pp = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+      while ((pp + 1) * (pp + 2) / 2 <= x) ++pp;
+      while (pp * (pp + 1) / 2 > x) --pp;
+      cacc[u] = 0.0;
+      cpq[u] = x < npair ? pp | ((x - pp * (pp + 1) / 2) << 8) : 0;
+    }
+    a1 = 0.0;
+    for (long k0 = 0; k0 < N; k0 += tk) {
+      const int nk = tile_len(k0);
+      stage(k0, nk);
+      for (int e = t; e < nk * nth; e += VMC_GN_THREADS) {   // centred clipped derivatives
+        const int kk = e / nth, p = e - kk * nth;
+        const double ev = te[kk];
+        const double v = ev < lo ? sh.dm[p] - 5.0 * sh.dmad[p]
+                                 : (ev > hi ? sh.dm[p] + 5.0 * sh.dmad[p] : tile[e]);
+        tile[e] = v - sh.mdt[p];
+      }
+      __syncthreads();
+      if (cseg < S)
+        for (int kk = cseg; kk < nk; kk += S) {
+          const double e0 = te[kk];
+          a1 += tile[kk * nth + ccol] * ((e0 < lo ? lo : (e0 > hi ? hi : e0)) - mean);
+        }
+      if (nu > 0)
+        for (int kk = 0; kk < nk; ++kk) {
+          const double* row = tile + kk * nth;
+  #pragma unroll
+          for (int u = 0; u < GN_PAIRS; ++u)   // the first test is block-uniform
+            if (u * VMC_GN_THREADS < npair && u < nu) cacc[u] += row[cpq[u] & 255] * row[cpq[u] >> 8];
+        }
+    }
+    a1 = combine(a1);
+    if (t < nth) sh.grad[t] = 2.0 * a1 / (double)(N - 1);
+    __syncthreads();   // the tile space becomes C
+  #pragma unroll
+    for (int u = 0; u < GN_PAIRS; ++u)
+      if (t + u * VMC_GN_THREADS < npair) {
+        const int pp = cpq[u] & 255, qq = cpq[u] >> 8;
+        const double c = cacc[u] * inv_n + (pp == qq ? lam : 0.0);
+        sh.C[pp * nth + qq] = c;
+        sh.C[qq * nth + pp] = c;
+      }
   }
   __syncthreads();
   if (t == 0) {
