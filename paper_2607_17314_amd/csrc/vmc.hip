@@ -65,33 +65,17 @@ __device__ __forceinline__ double vmc_ipow(double x, int n) {   // Cartesian pow
   return vmc_ipow_to<VMC_MAX_L + 1>(x, n);
 }
 
-// AO rows (without the component factor) of shell s at the point p, written to chi[a]
-// and, with LAP, chi[n_ao * q + a] for q = 1..4 (gradient, Laplacian). chi = P g(s),
-// P = x^i y^j z^k, g = sum c e^{-alpha r^2}: d_x chi = (i x^{i-1} g + 2 x^{i+1} g') y^j z^k,
-// lap chi = g lap P + P (4 l g' + 6 g' + 4 r^2 g''), primes in s = r^2. Tables in LDS.
-template <bool LAP>
-__device__ void vmc_shell(const double* cen, const int* shi, const double* prim, int n_ao, int s,
-                          double px, double py, double pz, double* chi) {
-  const unsigned w0 = (unsigned)shi[2 * s], w1 = (unsigned)shi[2 * s + 1];
-  const int l = (int)(w0 & 7u), c = (int)((w0 >> 3) & 4095u);
-  const int p0 = (int)(w1 & 32767u), p1 = p0 + (int)(w0 >> 15);
-  int a = (int)(w1 >> 15);
-  const double x = px - cen[4 * c], y = py - cen[4 * c + 1], z = pz - cen[4 * c + 2];
-  const double r2 = x * x + y * y + z * z;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int p = p0; p < p1; ++p) {
-    const double al = prim[2 * p];
-    const double e = prim[2 * p + 1] * exp(-al * r2);
-    g0 += e;
-    if (LAP) {
-      g1 -= al * e;
-      g2 += al * al * e;
-    }
-  }
-  for (int i = l; i >= 0; --i) {
+// The Cartesian functions of one shell of angular momentum L (compile time, so every
+// power below is a fixed product, the same left-to-right product as at run time).
+template <int L, bool LAP>
+__device__ __forceinline__ void vmc_shell_l(double x, double y, double z, double r2, double g0,
+                                            double g1, double g2, int n_ao, int a, double* chi) {
+#pragma unroll
+  for (int i = L; i >= 0; --i) {
     const double xi = vmc_ipow(x, i);
-    for (int j = l - i; j >= 0; --j, ++a) {
-      const int k = l - i - j;
+#pragma unroll
+    for (int j = L - i; j >= 0; --j, ++a) {
+      const int k = L - i - j;
       const double yj = vmc_ipow(y, j), zk = vmc_ipow(z, k);
       const double P = xi * yj * zk;
       chi[a] = P * g0;
@@ -106,9 +90,43 @@ __device__ void vmc_shell(const double* cen, const int* shi, const double* prim,
         if (i >= 2) lapP += i * (i - 1) * vmc_ipow(x, i - 2) * yj * zk;
         if (j >= 2) lapP += j * (j - 1) * xi * vmc_ipow(y, j - 2) * zk;
         if (k >= 2) lapP += k * (k - 1) * xi * yj * vmc_ipow(z, k - 2);
-        chi[4 * n_ao + a] = g0 * lapP + P * ((4.0 * l + 6.0) * g1 + 4.0 * r2 * g2);
+        chi[4 * n_ao + a] = g0 * lapP + P * ((4.0 * L + 6.0) * g1 + 4.0 * r2 * g2);
       }
     }
+  }
+}
+
+// AO rows (without the component factor) of shell s at the point p, written to chi[a]
+// and, with LAP, chi[n_ao * q + a] for q = 1..4 (gradient, Laplacian). chi = P g(s),
+// P = x^i y^j z^k, g = sum c e^{-alpha r^2}: d_x chi = (i x^{i-1} g + 2 x^{i+1} g') y^j z^k,
+// lap chi = g lap P + P (4 l g' + 6 g' + 4 r^2 g''), primes in s = r^2. Tables in LDS.
+template <bool LAP>
+__device__ void vmc_shell(const double* cen, const int* shi, const double* prim, int n_ao, int s,
+                          double px, double py, double pz, double* chi) {
+  const unsigned w0 = (unsigned)shi[2 * s], w1 = (unsigned)shi[2 * s + 1];
+  const int l = (int)(w0 & 7u), c = (int)((w0 >> 3) & 4095u);
+  const int p0 = (int)(w1 & 32767u), p1 = p0 + (int)(w0 >> 15);
+  const int a = (int)(w1 >> 15);
+  const double x = px - cen[4 * c], y = py - cen[4 * c + 1], z = pz - cen[4 * c + 2];
+  const double r2 = x * x + y * y + z * z;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    const double al = prim[2 * p];
+    const double e = prim[2 * p + 1] * exp(-al * r2);
+    g0 += e;
+    if (LAP) {
+      g1 -= al * e;
+      g2 += al * al * e;
+    }
+  }
+  switch (l) {   // one straight-line body per angular momentum
+    case 0: vmc_shell_l<0, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    case 1: vmc_shell_l<1, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    case 2: vmc_shell_l<2, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    case 3: vmc_shell_l<3, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    case 4: vmc_shell_l<4, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    case 5: vmc_shell_l<5, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
+    default: vmc_shell_l<6, LAP>(x, y, z, r2, g0, g1, g2, n_ao, a, chi); break;
   }
 }
 
