@@ -39,7 +39,7 @@ struct VmcBasis {
 
 struct VmcDev {
   VmcBasis b;
-  const double* C;      // [n_ao][n_occ], component factors folded in
+  const double* C;      // [n_occ][n_ao] (orbital-major), component factors folded in
   const double* nuc;    // [n_nuc][4]: x, y, z, Z
   int n_occ, n_nuc;
   double e_nuc;
@@ -148,7 +148,10 @@ __device__ __forceinline__ void vmc_aos(const VmcBasis& b, const double* cen, co
 }
 
 // out[q * ostride + k] = sum_a chi[q * n_ao + a] C[a][k], q < NQ, k < n_occ: lanes as
-// (k, slice) with P = 64 / n_occ slices; partial sums in part[64 * NQ]; fixed order.
+// (k, slice) with P = 64 / n_occ slices; slice sl sums the contiguous AOs
+// [sl B, sl B + B), B = ceil(n_ao / P), in order (the coefficients orbital-major, so both
+// operands of a batch of eight are read at fixed offsets from one base); partial sums in
+// part[64 * NQ], added in slice order.
 template <int NQ>
 __device__ __forceinline__ void vmc_orbitals(const VmcDev& v, const double* chi, double* part,
                                              double* out, int ostride) {
@@ -160,20 +163,22 @@ __device__ __forceinline__ void vmc_orbitals(const VmcDev& v, const double* chi,
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
   if (k < n) {
-    // eight coefficient loads in flight per batch; the sum keeps the order a = sl, sl + P, ...
-    int a = sl;
-    for (; a + 7 * P < n_ao; a += 8 * P) {
+    const int B = (n_ao + P - 1) / P;
+    const int a0 = sl * B, a1 = a0 + B < n_ao ? a0 + B : n_ao;
+    const double* ck = v.C + (long)k * n_ao;
+    int a = a0;
+    for (; a + 8 <= a1; a += 8) {
       double cv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) cv[u] = v.C[(long)(a + u * P) * n + k];
+      for (int u = 0; u < 8; ++u) cv[u] = ck[a + u];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a + u * P] * cv[u];
+        for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a + u] * cv[u];
       }
     }
-    for (; a < n_ao; a += P) {
-      const double cak = v.C[(long)a * n + k];
+    for (; a < a1; ++a) {
+      const double cak = ck[a];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) acc[q] += chi[q * n_ao + a] * cak;
     }
@@ -1157,13 +1162,14 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
 }
 
 // ---------------------------------------------------------------------------------------
-// C'[a][k] = comp[a] C[a][k]
+// C'[k][a] = comp[a] C[a][k] (stored orbital-major)
 __global__ __launch_bounds__(256) void k_vmc_scale_c(const double* __restrict__ C,
                                                      const double* __restrict__ comp, long n_ao,
                                                      int n_occ, double* __restrict__ Cs) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n_ao * n_occ) return;
-  Cs[i] = comp[i / n_occ] * C[i];
+  const long a = i / n_occ, k = i - a * n_occ;
+  Cs[k * n_ao + a] = comp[a] * C[i];   // orbital-major
 }
 
 struct VmcLayout {
