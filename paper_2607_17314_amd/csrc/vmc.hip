@@ -596,18 +596,18 @@ template <> __device__ __forceinline__ double vmc_mk<double>(double v, double) {
 template <> __device__ __forceinline__ Dl vmc_mk<Dl>(double v, double d) { return {v, d}; }
 template <class T> __device__ __forceinline__ T vmc_zero() { return vmc_mk<T>(0.0, 0.0); }
 
-// grad_i J and lap_i J of electron i. The derivative in one parameter `seed` (0: d,
+// The partners j = j0, j0 + js, ... of electron i: their share of grad_i J and lap_i J. The derivative in one parameter `seed` (0: d,
 // 1 + t: b_t) rides along as a dual number: d moves only the pair quantities (e and its
 // derivatives, type TE), b_t only the nuclear ones (a and its derivatives, type TN), so
 // each seed makes just one side dual; TR joins the two. TA: the per-(electron, nucleus)
 // table in LDS.
 template <class TE, class TN, class TR = typename DlJoin<TE, TN>::type>
 __device__ void vmc_bh_jastrow(const VmcBH& bh, const double* TA, const double* Rs, int n_el,
-                               int i, int seed, TR& Gx, TR& Gy, TR& Gz, TR& L) {
+                               int i, int seed, int j0, int js, TR& Gx, TR& Gy, TR& Gz, TR& L) {
   Gx = Gy = Gz = L = vmc_zero<TR>();
   const double d = bh.d;
   const int nn = bh.n_nuc;
-  for (int j = 0; j < n_el; ++j) {
+  for (int j = j0; j < n_el; j += js) {   // the partners j0, j0 + js, ...
     if (j == i) continue;
     const double dx = Rs[3 * i] - Rs[3 * j], dy = Rs[3 * i + 1] - Rs[3 * j + 1],
                  dz = Rs[3 * i + 2] - Rs[3 * j + 2];
@@ -783,7 +783,8 @@ __device__ void vmc_bh_dc_pairs(const VmcBH& bh, const double* TA, const double*
 
 // LDS (doubles): A5 [5][n_el][n], Ainv [2][n][n], fac [n], R [n_el][3], red [64],
 // H [n_el][4] (h_i, then spare), the nuclei [n_nuc][4] (read in every pair's nuclear
-// loop), pass 2's sums [2][64], then one region used twice: during the Slater part
+// loop), pass 2's sums [2][64], the partner-group partial sums [64][8], then one region
+// used twice: during the Slater part
 // shell centres [n_cent][4], primitives [n_prim][2], aug [n][2n], chi [5][n_ao],
 // part [5][64] and the ints (shell records [n_shell][2], piv); after it the
 // per-(electron, nucleus) table TA [n_el][n_nuc][6]. Sharing the region keeps a
@@ -805,7 +806,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh_in,
   double* H = red + 64;
   double* nuc = H + 4 * n_el;
   double* acc = nuc + 4 * nn;   // pass 2's sums [n_types][n_terms]
-  double* cen = acc + VMC_BH_MAXTYPE * VMC_BH_MAXTERM;   // the shared region
+  double* PJ = acc + VMC_BH_MAXTYPE * VMC_BH_MAXTERM;   // partner-group partial sums [64][8]
+  double* cen = PJ + 64 * 8;    // the shared region
   double* prim = cen + 4 * v.b.n_cent;
   double* aug = prim + 2 * v.b.n_prim;
   double* chi = aug + 2 * n * n;
@@ -857,13 +859,33 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh_in,
     __syncthreads();
     return s;
   };
+  // Passes 1 and 3 put the lanes over (electron i, partner group gj): the partners of i
+  // are split into NG strided groups, each lane sums its group, and lane i adds the
+  // groups' partial sums in order.
+  const int NG = 64 / n_el, gi = lane % n_el, gj = lane / n_el;
   // pass 1: local energy; h_i = grad_i J + D_i to LDS
+  if (gj < NG) {
+    double gx, gy, gz, l;
+    vmc_bh_jastrow<double, double>(bh, TA, Rs, n_el, gi, -1, gj, NG, gx, gy, gz, l);
+    double* o = PJ + 8 * (gj * n_el + gi);
+    o[0] = gx;
+    o[1] = gy;
+    o[2] = gz;
+    o[3] = l;
+  }
+  __syncthreads();
   double ekin = 0.0, pot = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
   if (lane < n_el) {
     const int i = lane;
-    double S, L;
+    double S, L = 0.0;
     vmc_ratios(v, A5, Ainv, i, Dx, Dy, Dz, S);
-    vmc_bh_jastrow<double, double>(bh, TA, Rs, n_el, i, -1, Gx, Gy, Gz, L);
+    for (int g = 0; g < NG; ++g) {
+      const double* o = PJ + 8 * (g * n_el + i);
+      Gx += o[0];
+      Gy += o[1];
+      Gz += o[2];
+      L += o[3];
+    }
     ekin = -0.5 * (L + Gx * Gx + Gy * Gy + Gz * Gz + 2.0 * (Gx * Dx + Gy * Dy + Gz * Dz) + S);
     const double xi = Rs[3 * i], yi = Rs[3 * i + 1], zi = Rs[3 * i + 2];
     for (int j = i + 1; j < n_el; ++j) {
@@ -890,11 +912,31 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh_in,
   for (int p = lane; p < nlin; p += 64) dE[w * nth + p] = -0.5 * acc[p];
   // pass 3: d and each b_t in forward mode
   for (int sd = 0; sd <= bh.n_types; ++sd) {
+    if (gj < NG) {
+      Dl gx, gy, gz, l;
+      if (sd == 0) vmc_bh_jastrow<Dl, double>(bh, TA, Rs, n_el, gi, sd, gj, NG, gx, gy, gz, l);
+      else vmc_bh_jastrow<double, Dl>(bh, TA, Rs, n_el, gi, sd, gj, NG, gx, gy, gz, l);
+      double* o = PJ + 8 * (gj * n_el + gi);
+      o[0] = gx.v;
+      o[1] = gx.d;
+      o[2] = gy.v;
+      o[3] = gy.d;
+      o[4] = gz.v;
+      o[5] = gz.d;
+      o[6] = l.v;
+      o[7] = l.d;
+    }
+    __syncthreads();
     double x = 0.0;
     if (lane < n_el) {
-      Dl gx, gy, gz, l;
-      if (sd == 0) vmc_bh_jastrow<Dl, double>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
-      else vmc_bh_jastrow<double, Dl>(bh, TA, Rs, n_el, lane, sd, gx, gy, gz, l);
+      Dl gx = {0.0, 0.0}, gy = gx, gz = gx, l = gx;
+      for (int g = 0; g < NG; ++g) {
+        const double* o = PJ + 8 * (g * n_el + lane);
+        gx = gx + Dl{o[0], o[1]};
+        gy = gy + Dl{o[2], o[3]};
+        gz = gz + Dl{o[4], o[5]};
+        l = l + Dl{o[6], o[7]};
+      }
       x = -0.5 * (l.d + 2.0 * ((gx.v + Dx) * gx.d + (gy.v + Dy) * gy.d + (gz.v + Dz) * gz.d));
     }
     const double s = lane_sum(x);
@@ -1216,7 +1258,7 @@ static size_t lds_energy_bh(const VmcBasis& b, int n, int n_nuc) {
   const int n_el = 2 * n;
   const size_t keep = sizeof(double) * (5 * (size_t)n_el * n + 2 * (size_t)n * n + n +
                                         3 * n_el + 64 + 4 * n_el + 4 * (size_t)n_nuc +
-                                        VMC_BH_MAXTYPE * VMC_BH_MAXTERM);
+                                        VMC_BH_MAXTYPE * VMC_BH_MAXTERM + 64 * 8);
   const size_t slater = lds_tables(b) + sizeof(double) * (2 * (size_t)n * n + 5 * (size_t)b.n_ao +
                                                           5 * 64) + sizeof(int) * n;
   const size_t table = sizeof(double) * (size_t)n_el * n_nuc * VMC_BH_TA;
