@@ -1058,9 +1058,11 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
   } else {
     // The parameter sums run in walker order over tiles of tk walkers: a tile's dE rows are
     // staged in the space of C (not needed until the end) and its energies in red; one
-    // thread per parameter column, and up to GN_PAIRS entries (p, q) of C per thread.
-    constexpr int GN_PAIRS = (VMC_MAX_THETA * (VMC_MAX_THETA + 1) / 2 + VMC_GN_THREADS - 1) /
-                             VMC_GN_THREADS;
+    // thread per parameter column, and up to GN_BLK blocks of C per thread, a block being the
+    // four entries (p, q0 .. q0 + 3), q0 a multiple of 4 not above p (one read of row p
+    // serves four products).
+    constexpr int GN_NBLK = VMC_MAX_THETA * (VMC_MAX_THETA / 4 + 1) / 2 + VMC_MAX_THETA;
+    constexpr int GN_BLK = (GN_NBLK + VMC_GN_THREADS - 1) / VMC_GN_THREADS;
     const int tk = VMC_MAX_THETA * VMC_MAX_THETA / nth < VMC_GN_THREADS
                        ? VMC_MAX_THETA * VMC_MAX_THETA / nth : VMC_GN_THREADS;
     double* tile = sh.C;
@@ -1110,18 +1112,19 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
     });
     if (t < nth) sh.mdt[t] = a1 * inv_n;
     // residual r_k = Et_k - mean and dr_kp = dEt_kp - mean_k(dEt_kp): the gradient and C
-    const int npair = nth * (nth + 1) / 2;
-    const int nu = t < npair ? (npair - t + VMC_GN_THREADS - 1) / VMC_GN_THREADS : 0;
-    double cacc[GN_PAIRS];
-    int cpq[GN_PAIRS];   // p | q << 8 of this thread's entries t + u VMC_GN_THREADS (q <= p)
+    int nblk = 0;   // blocks (p, q0), p-major
+    for (int pp = 0; pp < nth; ++pp) nblk += pp / 4 + 1;
+    const int nu = t < nblk ? (nblk - t + VMC_GN_THREADS - 1) / VMC_GN_THREADS : 0;
+    double cacc[GN_BLK][4];
+    int cp[GN_BLK], cq[GN_BLK];   // row p and first column q0 of this thread's blocks
   #pragma unroll
-    for (int u = 0; u < GN_PAIRS; ++u) {
+    for (int u = 0; u < GN_BLK; ++u) {
       const int x = t + u * VMC_GN_THREADS;
-      int pp = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-      while ((pp + 1) * (pp + 2) / 2 <= x) ++pp;
-      while (pp * (pp + 1) / 2 > x) --pp;
-      cacc[u] = 0.0;
-      cpq[u] = x < npair ? pp | ((x - pp * (pp + 1) / 2) << 8) : 0;
+      int pp = 0, first = 0;
+      while (pp < nth && first + pp / 4 + 1 <= x) first += pp++ / 4 + 1;
+      cp[u] = x < nblk ? pp : 0;
+      cq[u] = x < nblk ? 4 * (x - first) : 0;
+      cacc[u][0] = cacc[u][1] = cacc[u][2] = cacc[u][3] = 0.0;
     }
     a1 = 0.0;
     for (long k0 = 0; k0 < N; k0 += tk) {
@@ -1144,20 +1147,31 @@ __global__ __launch_bounds__(VMC_GN_THREADS) void k_vmc_gn(const double* __restr
         for (int kk = 0; kk < nk; ++kk) {
           const double* row = tile + kk * nth;
   #pragma unroll
-          for (int u = 0; u < GN_PAIRS; ++u)   // the first test is block-uniform
-            if (u * VMC_GN_THREADS < npair && u < nu) cacc[u] += row[cpq[u] & 255] * row[cpq[u] >> 8];
+          for (int u = 0; u < GN_BLK; ++u)   // the first test is block-uniform
+            if (u * VMC_GN_THREADS < nblk && u < nu) {
+              const double a = row[cp[u]];
+  #pragma unroll
+              for (int jq = 0; jq < 4; ++jq) {   // columns past the row's end are clamped, then dropped
+                const int q = cq[u] + jq < nth ? cq[u] + jq : nth - 1;
+                cacc[u][jq] += a * row[q];
+              }
+            }
         }
     }
     a1 = combine(a1);
     if (t < nth) sh.grad[t] = 2.0 * a1 / (double)(N - 1);
     __syncthreads();   // the tile space becomes C
   #pragma unroll
-    for (int u = 0; u < GN_PAIRS; ++u)
-      if (t + u * VMC_GN_THREADS < npair) {
-        const int pp = cpq[u] & 255, qq = cpq[u] >> 8;
-        const double c = cacc[u] * inv_n + (pp == qq ? lam : 0.0);
-        sh.C[pp * nth + qq] = c;
-        sh.C[qq * nth + pp] = c;
+    for (int u = 0; u < GN_BLK; ++u)
+      if (t + u * VMC_GN_THREADS < nblk) {
+  #pragma unroll
+        for (int jq = 0; jq < 4; ++jq) {
+          const int pp = cp[u], qq = cq[u] + jq;
+          if (qq > pp) continue;   // q <= p < nth
+          const double c = cacc[u][jq] * inv_n + (pp == qq ? lam : 0.0);
+          sh.C[pp * nth + qq] = c;
+          sh.C[qq * nth + pp] = c;
+        }
       }
   }
   __syncthreads();
