@@ -10,7 +10,8 @@
 // lane-parallel over shells and the occupied orbitals lane-parallel over (orbital,
 // AO slice), and keeps the inverses current with Sherman-Morrison updates. No state
 // crosses walkers, so one launch runs every sweep. The Gauss-Newton step is one
-// workgroup of deterministic block reductions over the walkers and a Cholesky solve in
+// workgroup: its sums over the walkers are block reductions for a few parameters and
+// walker tiles staged in LDS for more, all in a fixed order, then a Cholesky solve in
 // LDS.
 #include <cmath>
 #include "common.hpp"
@@ -945,7 +946,8 @@ __global__ __launch_bounds__(64) void k_vmc_energy_bh(VmcDev v, VmcBH bh_in,
 }
 
 // ---------------------------------------------------------------------------------------
-// Gauss-Newton step (eq. gn) on the clipped variance (eq. var-loss), one workgroup.
+// Gauss-Newton step (eq. gn) on the clipped variance (eq. var-loss), one workgroup of
+// VMC_GN_THREADS threads.
 __device__ double gn_block_sum(double x, double* red) {
   const int t = threadIdx.x;
   red[t] = x;
