@@ -371,8 +371,11 @@ typedef struct {
  * number of accepted moves, or -1 for a walker whose starting determinant is exactly
  * singular (left unmoved). With n_walkers = 0, R, accepted and the draws may be NULL.
  * Workspace: xtc_workspace_bytes(XTC_CALL_VMC, 0, 0, 0, n_ao, 0).
- * Limits: n_occ <= 32; the walker's LDS (4 n_occ^2 + n_ao + 17 n_occ + 64 doubles, plus the
- * basis tables: 4 n_shell + 2 n_prim doubles and 4 n_shell ints) within 160 KB. FP64. Asynchronous after the basis upload. */
+ * Limits: n_occ <= 32; per shell fewer than 32768 primitives, each starting below 32768,
+ * and n_ao < 131072 (packed shell records); the walker's LDS within 160 KB: with n = n_occ,
+ * 2 n^2 + max(2 n^2, 11 n) + n_ao + 6 n + 64 doubles and n ints, plus the basis tables
+ * (4 per distinct shell centre + 2 n_prim doubles, 2 n_shell ints). FP64. Asynchronous
+ * after the basis upload. */
 xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* R,
                           int32_t n_sweeps, double step, const double* normals,
                           const double* uniforms, int64_t* accepted, void* ws, size_t ws_bytes,
@@ -389,8 +392,10 @@ xtc_status xtc_vmc_sample(const xtc_vmc_system* sys, int64_t n_walkers, double* 
  * nuclei, 1 .. 2 types, 1 .. 64 terms with m, n <= 3 and o <= 12, at most 128 parameters;
  * its linear derivatives are sums over electron pairs and nuclei of unit kernels, its d and
  * b derivatives are carried in forward mode. Workspace as xtc_vmc_sample; LDS per walker
- * 14 n_occ^2 + 5 n_ao + 7 n_occ + 384 doubles plus the basis tables (BH: plus
- * 2 n_occ (4 + 9 n_nuc)) within 160 KB. FP64. */
+ * within 160 KB, with n = n_occ and T the basis tables (as for xtc_vmc_sample): EE
+ * 14 n^2 + 5 n_ao + 7 n + 384 doubles plus T; BH 12 n^2 + 15 n + 4 n_nuc + 704 doubles
+ * plus the larger of (T + 2 n^2 + 5 n_ao + 320 doubles + n ints) and 12 n n_nuc doubles.
+ * FP64. */
 xtc_status xtc_vmc_local_energy(const xtc_vmc_system* sys, const xtc_correlator* corr,
                                 int64_t n_walkers, const double* R, double* E, double* dE,
                                 void* ws, size_t ws_bytes, void* stream);
