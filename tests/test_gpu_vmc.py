@@ -162,6 +162,14 @@ def test_bh_local_energy_and_derivatives_match_oracle(h4, types):
     assert dE.shape == (23, 48 * types + 1 + types)
 
 
+def test_bh_local_energy_six_electrons_two_types(h6_small):
+    """Six electrons: ten partner groups of the lanes (60 of 64 working) and 30 electron
+    pairs in one partial pair block; two nucleus types (99 parameters)."""
+    from paper_2607_17314_amd import api
+    E, dE = _energy_case(api, h6_small, 11, seed=43, corr=_bh_corr(h6_small, 2))
+    assert dE.shape == (11, 48 * 2 + 1 + 2)
+
+
 def test_bh_local_energy_matches_oracle_at_h20_shape(h20):
     """20 electrons, 20 nuclei, 48 terms, 50 parameters (3 walkers: the oracle's complex step
     runs 51 contractions)."""
