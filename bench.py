@@ -6,7 +6,14 @@ interpolation-point selection, ISDF fit of xi and xi~, and the grid-pair
 contraction with every channel (u1, u3, D1, D4, field, energy-scale sums),
 with inputs resident in HBM. Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--precision split|fp64] [--compare-fp64]
+  python bench.py [--steps K] [--warmup W] [--precision split|fp64] [--no-fp64-form]
+
+After the timed region (not timed with it) the metric's comparison runs: one whole
+step of the plain FP64 GPU form on the same inputs, its time-to-V, the speedup and the
+per-block error of the timed form against it (gate 1e-6); and the CPU oracle on a
+bounded bra sample with its own orbitals, stored pivots and fit, whose outputs the
+device reproduces on the same inputs (gates 1e-6 split, 1e-10 FP64). A failed gate
+exits with status 1 after the JSON line.
 
 The roofline object is for the dominant kernel, the stage-1 pair kernel: its
 algorithmic flops per launch (8 per row per grid pair, rows = the N_mu
@@ -35,8 +42,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--config", default="h20")
     p.add_argument("--precision", default="split", choices=["fp64", "split"])
-    p.add_argument("--compare-fp64", action="store_true",
-                   help="also time the plain FP64 form and report its time-to-V and the error")
+    p.add_argument("--no-fp64-form", action="store_true",
+                   help="skip the plain FP64 form (by default one whole FP64 step runs after the "
+                        "timed region: its time-to-V, the speedup and the per-block error gate)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bra", type=int, default=1024, help="bra points in the CPU-oracle sample")
     p.add_argument("--exchange", action="store_true",
@@ -201,23 +209,62 @@ def main():
                 res["vmc"]["bh"]["cpu_baseline"] = vmc_bh_cpu_baseline(wl)
     if a.kernel_sample:
         res["kernel_sample"] = kernel_sample(a.kernel_sample, a.sample_blocks, log)
-    if a.compare_fp64 and prec != L.XTC_FP64:
+    gate_ok = True
+    if not a.no_fp64_form and prec != L.XTC_FP64:
+        # the metric's comparison: the plain FP64 GPU form, one whole step (same inputs, so
+        # the same pivots), and the per-block error of the timed form against it
+        log("plain FP64 form: one whole step")
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ref, _ = step(L.XTC_FP64)
-        torch.cuda.synchronize()
-        res["fp64_time_to_V_s"] = round(time.perf_counter() - t0, 4)
-        errs = {}
-        for k in ("u1", "u3", "D1", "D4", "field"):
-            r = ref[k]
-            errs[k] = float((out[k] - r).abs().max() / r.abs().max())
-        errs["escale"] = float(np.max(np.abs(out["escale"] - ref["escale"]) / np.abs(ref["escale"])))
+        with api.KernelTimer() as kt64:
+            t0 = time.perf_counter()
+            ref, piv64 = step(L.XTC_FP64)
+            torch.cuda.synchronize()
+            t64 = time.perf_counter() - t0
+        errs = block_errors(out, ref)
+        gate_ok = bool(np.array_equal(piv, piv64)) and max(errs.values()) <= GATE
+        res["fp64_form"] = {"time_to_V_s": round(t64, 4),
+                            "stage_ms": {k: round(v["ms"], 2) for k, v in kt64.result.items()
+                                         if v["launches"]}}
+        res["speedup_vs_fp64_form"] = round(t64 / dt, 3)
         res["max_rel_err_vs_fp64"] = errs
-        res["speedup_vs_fp64_form"] = round(res["fp64_time_to_V_s"] / dt, 3)
+        res["accuracy_gate"] = {"bound": GATE, "per": "output block, max|got - ref| / max|ref|",
+                                "pass": gate_ok}
+        log(f"FP64 form {t64:.2f} s ({t64 / dt:.2f}x the timed form); worst block error "
+            f"{max(errs.values()):.2e}")
+        del ref
     if not a.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        res["cpu_baseline"] = cpu_baseline(wl, n_mu, a.cpu_bra)
+        res["cpu_baseline"], oerr = cpu_baseline(wl, n_mu, a.cpu_bra, a.config, grid, piv, log)
+        if oerr is not None:
+            res["max_rel_err_vs_oracle"] = oerr
+            ok = max(oerr["split"].values()) <= GATE and max(oerr["fp64"].values()) <= 1e-10
+            res["oracle_gate"] = {"bounds": {"split": GATE, "fp64": 1e-10}, "pass": ok}
+            gate_ok = gate_ok and ok
     print(json.dumps(res), flush=True)
+    if not gate_ok:
+        print("accuracy gate failed", file=sys.stderr, flush=True)
+        sys.exit(1)
+
+
+GATE = 1e-6   # the mixed path's bound per output block (max |got - ref| / max |ref|)
+
+
+def block_errors(out, ref, cols=None):
+    """max |got - ref| / max |ref| for every output block (the field on cols, if given) and
+    the largest relative error of the energy-scale scalars."""
+    import numpy as np
+    errs = {}
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        g, r = out[k], ref[k]
+        if not isinstance(g, np.ndarray):
+            g = g.cpu().numpy()
+        if not isinstance(r, np.ndarray):
+            r = r.cpu().numpy()
+        if k == "field" and cols is not None:
+            g, r = g[:, cols[0]:cols[1]], r[:, cols[0]:cols[1]]
+        errs[k] = float(np.abs(g - r).max() / np.abs(r).max())
+    errs["escale"] = float(np.max(np.abs(out["escale"] - ref["escale"]) / np.abs(ref["escale"])))
+    return errs
 
 
 def exchange_bench(wl, grid, C_mo, chans, prec, log):
@@ -591,26 +638,82 @@ def assembly_cpu_baseline(wl, n_p=1):
             "sample": f"W panel of {n_p} of {n} orbitals, N_mu={n_mu}; {dt:.1f} s"}
 
 
-def cpu_baseline(wl, n_mu, n_bra):
-    """The FP64 CPU oracle's contraction on a bounded sample: n_bra bra points
-    against every ket point, N_mu interpolation vectors of the workload's shape."""
+def read_pivots(config):
+    """The oracle's fused pivots of a workload, stored under tests/golden/ by the committed
+    script there (fused order: scalar pivots, then gradient-only pivots), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{config}_pivots.txt")
+    if not os.path.exists(path):
+        return None
+    sc, gr = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            ch, _, g, _ = line.split()
+            (sc if ch == "s" else gr).append(int(g))
+    ss = set(sc)
+    return sc + [g for g in gr if g not in ss]
+
+
+def cpu_baseline(wl, n_mu, n_bra, config, grid, gpu_piv, log):
+    """The FP64 CPU oracle's contraction on a bounded sample (n_bra bra points against every
+    ket point, all channels) on the oracle's own inputs: its orbitals, its stored fused
+    pivots and its fit of xi (all columns) and xi~ (the sample's columns). The same inputs go
+    to the device (split and FP64) on the same bra range, and the per-block errors against
+    the oracle are returned. Workloads without stored pivots use seeded N(0, 1) rows of the
+    right shape and no error check."""
     import numpy as np
+    import torch
 
     from oracle import contract as oc
-    rng = np.random.default_rng(0)
-    xi = rng.standard_normal((n_mu, wl.n_g))
-    xig = rng.standard_normal((3, n_mu, wl.n_g))
-    rho = rng.random(wl.n_g)
-    G = rho[:n_mu]
+    from oracle import fit as ofit
+    from oracle import orbitals as oorb
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
     cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    piv = read_pivots(config)
+    chans = 1 | 2 | 8 | 16 | 32 | 64
+    if piv is None:
+        rng = np.random.default_rng(0)
+        xi = rng.standard_normal((n_mu, wl.n_g))
+        xig = rng.standard_normal((3, n_mu, wl.n_g))
+        rho = rng.random(wl.n_g)
+        pv = np.arange(n_mu)
+        kind = "seeded N(0,1) interpolation vectors"
+    else:
+        pv = np.asarray(piv, np.int64)
+        log("  oracle orbitals and fit on the stored pivots (not timed)")
+        phi4 = oorb.eval_orbitals(wl.basis, wl.C_mo, wl.grid_xyz)
+        rho = oorb.density(phi4, wl.n_occ)
+        fr = ofit.fit(phi4, wl.grid_w, pv, grad_cols=np.arange(n_bra))
+        del phi4
+        xi = fr.xi
+        xig = np.zeros((3, n_mu, wl.n_g))        # untouched pages stay unmapped
+        xig[:, :, :n_bra] = fr.xigrad
+        kind = "the oracle's xi and xi~ on its own fused pivots"
     t0 = time.perf_counter()
-    oc.contract(wl.grid_xyz, wl.grid_w, wl.corr, xi, xig, G, rho, 1 | 2 | 8 | 16 | 32,
-                bra_range=(0, n_bra))
+    ref = oc.contract(wl.grid_xyz, wl.grid_w, wl.corr, xi, xig, rho[pv], rho, chans,
+                      bra_range=(0, n_bra))
     dt = time.perf_counter() - t0
     flops = 8.0 * (n_mu + 1) * n_bra * wl.n_g
-    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"stage 1 + stage 2 of {n_bra} bra points x {wl.n_g} ket points, N_mu={n_mu}, "
-                      f"all channels; {dt:.1f} s"}
+    res = {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"stage 1 + stage 2 of {n_bra} bra points x {wl.n_g} ket points, N_mu={n_mu}, "
+                     f"all channels, {kind}; {dt:.1f} s"}
+    if piv is None:
+        return res, None
+    res["gpu_pivots_equal_oracle"] = bool(np.array_equal(np.asarray(gpu_piv), pv))
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    xi_d, rho_d = t(xi), t(rho)
+    xig_d = torch.zeros((3, n_mu, wl.n_g), dtype=torch.float64, device="cuda")
+    xig_d[:, :, :n_bra] = t(fr.xigrad)
+    errs = {}
+    for name, prec in (("split", L.XTC_SPLIT_F16), ("fp64", L.XTC_FP64)):
+        out = api.kernel_contract(grid, wl.corr, xi_d, xig_d, rho_d, pv, chans, prec, bra=(0, n_bra))
+        torch.cuda.synchronize()
+        errs[name] = block_errors(out, ref, cols=(0, n_bra))
+        log(f"  {name} vs oracle on the sample: worst block {max(errs[name].values()):.2e}")
+    del xig_d, xi_d
+    return res, errs
 
 
 if __name__ == "__main__":

@@ -19,6 +19,11 @@
  *    status is an error (outputs undefined); a positive status is a warning
  *    (outputs valid, see the code). xtc_last_error() returns a thread-local
  *    message for the last failing call on the calling thread.
+ *  - Weights: every call that takes an xtc_grid and a workspace first checks on
+ *    the device that the weights are finite and non-negative (one small kernel
+ *    writing an integer flag into the first bytes of ws), synchronises the stream
+ *    to read the flag, and returns XTC_ERR_INVALID_ARG before any other launch if
+ *    one is not.
  *  - Determinism: reductions use fixed trees and no floating-point atomics,
  *    so repeated calls on the same inputs give bitwise-identical results.
  *  - Units: bohr for coordinates, hartree-scale quantities in FP64.
@@ -256,7 +261,7 @@ xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
  *   same pass from the same calG panels (Alg. 2, xTC-correction step; definitions at
  *   xtc_exchange_terms); with ex the workspace query takes n_orb = ex->n_orb and
  *   n_aux = ex->n_q.
- * Synchronising only if escale != NULL. */
+ * Asynchronous after the weight check; synchronising if escale != NULL. */
 xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                                const double* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, uint32_t channels, int32_t precision,
@@ -334,10 +339,14 @@ xtc_status xtc_one_body(const xtc_assembly* a, int32_t n_occ, double e_nuc, doub
  * dL/dd, then dL/db_t for the scale b_t of a_I = b r_I / (1 + b r_I) on the nuclei of
  * type t (eq. bh-u). Asking for dd leaves dtheta unchanged; for the BH form it runs a
  * separate kernel variant (more registers) so the dd = NULL path keeps its own.
- * FP64. Asynchronous. */
+ * [bra_begin, bra_end): the bra points of the outputs being differentiated, as for
+ * xtc_kernel_contract (non-empty, inside the grid): the derivative of the range's partial
+ * sums, so disjoint ranges give derivatives that add up to the whole grid's (0, n_g).
+ * FP64. Asynchronous after the weight check (see the conventions). */
 xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                     const double* xi, const double* xigrad, const double* rho,
-                    const int64_t* pivots, const double* gu1, const double* gu3,
+                    const int64_t* pivots, int64_t bra_begin, int64_t bra_end,
+                    const double* gu1, const double* gu3,
                     const double* gulap, const double* gD1, const double* gD4,
                     const double* gfield, double* dtheta, double* dd, void* ws, size_t ws_bytes,
                     void* stream);

@@ -30,16 +30,20 @@ def _unit(corr, j):
     return corr.with_c(c)
 
 
-def dL_dc(xyz, w, corr, xi, xigrad, G, rho, cot: dict, bra_block: int = 128, ket_block: int = 2048):
+def dL_dc(xyz, w, corr, xi, xigrad, G, rho, cot: dict, bra_block: int = 128, ket_block: int = 2048,
+          bra_range=None, params=None):
+    """dL/dc_j for j in params (default every coefficient). bra_range = (start, stop): the
+    outputs are the partial sums over those bra points (the ket sums cover the whole grid)."""
     n_mu, n_g = xi.shape
+    lo, hi = (0, n_g) if bra_range is None else bra_range
     wxi = xi * w[None, :]
     wrho = w * rho
     lap = cot.get("ulap") is not None
     need_calG = any(cot.get(k) is not None for k in ("u1", "D1", "D4"))
-    units = [_unit(corr, j) for j in range(corr.c.size)]
+    units = [_unit(corr, j) for j in (range(corr.c.size) if params is None else params)]
 
     def block(b0):
-        b1 = min(n_g, b0 + bra_block)
+        b1 = min(hi, b0 + bra_block)
         nb = b1 - b0
         P = len(units)
         calG = np.zeros((3, n_mu, nb))
@@ -64,12 +68,12 @@ def dL_dc(xyz, w, corr, xi, xigrad, G, rho, cot: dict, bra_block: int = 128, ket
                     dTL[j] += wxi[:, k0:k1] @ Kj["lap"].T
         return calG, dcalG, dT3, dTL, dfld
 
-    starts = list(range(0, n_g, bra_block))
+    starts = list(range(lo, hi, bra_block))
     grad = np.zeros(len(units))
     workers = max(1, min(len(starts), int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))))
     with threadpool_limits(1 if workers > 1 else None), ThreadPoolExecutor(workers) as ex:
         for b0, (calG, dcalG, dT3, dTL, dfld) in zip(starts, ex.map(block, starts)):
-            b1 = min(n_g, b0 + bra_block)
+            b1 = min(hi, b0 + bra_block)
             wb = w[b0:b1]
             wt = wb * (G @ xi[:, b0:b1])
             H = np.einsum("l,clg->gc", G, calG)

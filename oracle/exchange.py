@@ -83,26 +83,16 @@ def x_terms_direct(phi, piv, xi, cG, w, gamma):
 
 
 def x_terms(phi, piv, xi, cG, w, LQ):
-    """X2, X3 through the low-rank projector (the form the GPU computes): the per-point
-    pair products T2_{qs}(g) = sum_{c,a} R^c_{qa} R^c_{sa} and
-    T3^c_{qs}(g) = sum_a (R^c_{qa} Q_{sa} + Q_{qa} R^c_{sa}), then the grid sums."""
-    C = pivot_tensor(phi, piv)
-    P = np.einsum("tsn,ta->san", C, LQ)                       # P[s, a, nu]
-    n_orb, n_q, n_mu = P.shape
-    n_g = xi.shape[1]
-    Pm = P.reshape(n_orb * n_q, n_mu)
-    Q = (Pm @ xi).reshape(n_orb, n_q, n_g).transpose(2, 0, 1)            # Q[g, s, a]
-    X2 = np.zeros((n_orb * n_orb, n_mu))
-    X3 = np.zeros((n_orb * n_orb, n_mu))
-    T2 = np.zeros((n_g, n_orb, n_orb))
-    for c in range(3):
-        R = (Pm @ cG[c]).reshape(n_orb, n_q, n_g).transpose(2, 0, 1)     # R^c[g, s, a]
-        Rt = R.transpose(0, 2, 1)
-        T2 += R @ Rt                                                     # [g, q, s]
-        T3 = R @ Q.transpose(0, 2, 1) + Q @ Rt                           # T3^c[g, q, s]
-        X3 += (T3.reshape(n_g, -1) * w[:, None]).T @ cG[c].T
-    X2 += (T2.reshape(n_g, -1) * w[:, None]).T @ xi.T
-    return dict(X2=X2.reshape(n_orb, n_orb, n_mu), X3=X3.reshape(n_orb, n_orb, n_mu))
+    """X2, X3 through the low-rank projector, the formulas of the module docstring written
+    as einsums over P, R^c and Q (no per-point pair products, no blocking)."""
+    C = pivot_tensor(phi, piv)                                          # C[t, s, nu]
+    P = np.einsum("tsn,ta->san", C, LQ)                                 # P[s, a, nu]
+    R = np.einsum("san,cng->csag", P, cG, optimize=True)                # R^c[s, a](g)
+    Q = np.einsum("san,ng->sag", P, xi, optimize=True)                  # Q[s, a](g)
+    X2 = np.einsum("g,mg,csag,cqag->qsm", w, xi, R, R, optimize=True)
+    X3 = (np.einsum("g,cmg,sag,cqag->qsm", w, cG, Q, R, optimize=True)
+          + np.einsum("g,cmg,csag,qag->qsm", w, cG, R, Q, optimize=True))
+    return dict(X2=X2, X3=X3)
 
 
 def terms23_isdf(phi, piv, X2, X3):

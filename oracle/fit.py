@@ -38,12 +38,14 @@ def gram(phi4, piv):
     return A, Ac, G
 
 
-def rhs(phi4, piv):
-    """(B [N_mu, N_g], B_c [3, N_mu, N_g])."""
+def rhs(phi4, piv, scalar: bool = True, grad: bool = True, cols=None):
+    """(B [N_mu, N_g], B_c [3, N_mu, N_g]); a part not asked for is None. cols: the grid
+    columns to form (default all)."""
     Pm = phi4[:, :, piv]
-    P = Pm[0].T @ phi4[0]
-    B = P * P
-    Bc = np.stack([P * (Pm[1 + c].T @ phi4[1 + c]) for c in range(3)])
+    ph = phi4 if cols is None else phi4[:, :, np.asarray(cols)]
+    P = Pm[0].T @ ph[0]
+    B = P * P if scalar else None
+    Bc = np.stack([P * (Pm[1 + c].T @ ph[1 + c]) for c in range(3)]) if grad else None
     return B, Bc
 
 
@@ -79,22 +81,36 @@ def pair_norms(phi4):
     return n2 * n2, n2[None, :] * g2
 
 
-def fit(phi4, w, piv, with_grad: bool = True) -> FitResult:
+def fit(phi4, w, piv, with_grad: bool = True, cols=None, grad_cols=None) -> FitResult:
+    """xi and xi~ from the normal equations. The system of every grid point (one column of
+    B) is solved on its own with the same factor of A, so the fit is column-separable:
+    cols (grid indices, default all) selects the columns of xi and grad_cols (default
+    cols) those of xi~, giving exactly those columns of the full solution; the residuals
+    then cover the selected columns only."""
     piv = np.asarray(piv)
     A, Ac, _ = gram(phi4, piv)
-    B, Bc = rhs(phi4, piv)
-    D, Dc = pair_norms(phi4)
-    w2 = w * w
+    B, Bc = rhs(phi4, piv, grad=with_grad and grad_cols is None, cols=cols)
     jit = np.full(4, -1)
     res = np.zeros(4)
     rel = np.zeros(4)
+    D, Dcol = pair_norms(phi4 if cols is None else phi4[:, :, np.asarray(cols)])
+    w_c = w if cols is None else w[np.asarray(cols)]
     cf, jit[0] = chol_with_jitter(A)
     xi = cho_solve(cf, B)
+    w2 = w_c * w_c
     res[0] = float(np.sum(w2 * (D - np.einsum("mg,mg->g", xi, B))))
     rel[0] = res[0] / float(np.sum(w2 * D))
+    del B
     xig = None
     if with_grad:
-        xig = np.empty((3,) + B.shape)
+        if Bc is None:
+            Bc = rhs(phi4, piv, scalar=False, cols=grad_cols)[1]
+            _, Dc = pair_norms(phi4[:, :, np.asarray(grad_cols)])
+            wg = w[np.asarray(grad_cols)]
+        else:
+            Dc, wg = Dcol, w_c
+        w2 = wg * wg
+        xig = np.empty(Bc.shape)
         for c in range(3):
             cf, jit[1 + c] = chol_with_jitter(Ac[c])
             xig[c] = cho_solve(cf, Bc[c])

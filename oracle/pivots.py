@@ -1,29 +1,37 @@
-"""Weight-scaled, fixed-rank pivoted Cholesky and pivot fusion.
+"""Weight-scaled, fixed-rank pivoted Cholesky and pivot fusion (ISDF section,
+pivot selection, Alg. 1; the matrix-free pivot search of the numerical notes).
 
-Follows the ISDF section (pivot selection by pivoted Cholesky, Alg. 1) and the
-matrix-free pivot search of the numerical-implementation notes:
-  scalar channel   d_g = w_g^2 (sum_p phi_p(g)^2)^2,
-                   s_g = w_g w_* (sum_p phi_p(g) phi_p(*))^2;
-  gradient channel d_g = w_g^2 (sum_p phi_p(g)^2)(sum_{p,c} d_c phi_p(g)^2),
-                   s_g = w_g w_* (sum_p phi_p(g) phi_p(*)) (sum_{p,c} d_c phi_p(g) d_c phi_p(*)).
-Each step: g* = argmax_g d_g, L_{g,mu} = (s_g - sum_{lambda<mu} L_{g,lambda} L_{g*,lambda}) / sqrt(d_{g*}),
-d_g <- max(d_g - L_{g,mu}^2, 0).
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+What is factorised. For one channel, let m_g be the weighted pair-product
+vector of grid point g: the scalar channel's m_g has the entries
+w_g phi_p(g) phi_q(g) over all ordered pairs (p, q); the gradient channel's has
+w_g phi_p(g) d_c phi_q(g) over (p, c, q). The pair matrix S_{gh} = m_g . m_h is
+positive semidefinite, and the method never forms it: its entries follow from
+orbital dot products,
+  scalar    S_{gh} = w_g w_h (Phi_g . Phi_h)^2,
+  gradient  S_{gh} = w_g w_h (Phi_g . Phi_h) (sum_c dPhi_g^c . dPhi_h^c),
+with Phi_g the vector of orbital values at g. Selecting interpolation points is
+the greedy (diagonally pivoted) Cholesky factorisation of S: after k pivots
+S ~ L^T L with L [k][N_g], and the residual diagonal d_g = S_gg - sum_k L_kg^2 is
+the squared norm of m_g outside the span of the selected vectors, so each new
+pivot is the point the current points represent worst. The next row of L is the
+residual (Schur-complement) column of S at that pivot, normalised by the square
+root of its diagonal entry.
 
 Readings where the paper is silent (also listed in the design notes):
   * ties in the argmax go to the lowest grid index;
-  * the selected point's own residual is set to its exact-arithmetic value 0
-    after its update (the update gives d_{g*} - d_{g*});
+  * the selected point's own residual is set to its exact-arithmetic value 0;
   * the fixed-rank loop stops early, reporting rank deficiency, once
-    max_g d_g <= 1e-14 * max_g D_g (the division by sqrt(d_{g*}) would
-    otherwise divide by zero after the clamp);
+    max_g d_g <= 1e-14 * max_g S_gg (the normalisation would divide by ~0);
   * fusion "fill-to-target": the gradient channel runs to ceil(N_mu / 2)
     pivots, then the scalar channel is extended one pivot at a time until the
     union holds N_mu points; the fused order is the scalar pivots in selection
     order followed by the gradient-only pivots in theirs.
 
 Pinned by: equality with LAPACK's column-pivoted QR (scipy.linalg.qr with
-pivoting) on an explicit weighted pair matrix for tiny inputs, the projection
-residual identity sum_g d_g = ||M_w - P_S M_w||_F^2, monotone pivot values and
+pivoting) of the explicit matrix [m_g] on tiny inputs, the projection residual
+identity sum_g d_g = ||M - P_S M||_F^2, non-increasing pivot values, and
 termination exactly at the numerical rank.
 """
 from __future__ import annotations
@@ -36,6 +44,7 @@ RANK_TOL = 1e-14
 
 
 def diagonal(phi4: np.ndarray, w: np.ndarray, channel: str) -> np.ndarray:
+    """S_gg for every grid point."""
     n2 = np.einsum("pg,pg->g", phi4[0], phi4[0])
     if channel == "scalar":
         return w * w * n2 * n2
@@ -44,6 +53,7 @@ def diagonal(phi4: np.ndarray, w: np.ndarray, channel: str) -> np.ndarray:
 
 
 def column(phi4: np.ndarray, w: np.ndarray, gstar: int, channel: str) -> np.ndarray:
+    """S_{g, g*} for every grid point g."""
     a = phi4[0].T @ phi4[0][:, gstar]
     if channel == "scalar":
         return w * w[gstar] * a * a
@@ -53,21 +63,28 @@ def column(phi4: np.ndarray, w: np.ndarray, gstar: int, channel: str) -> np.ndar
 
 @dataclass
 class CholeskyState:
-    """Incremental state of one channel's pivoted Cholesky (Alg. 1)."""
+    """Incremental state of one channel's pivoted Cholesky (Alg. 1). The factor's
+    rows live in a preallocated array that doubles when full."""
     phi4: np.ndarray
     w: np.ndarray
     channel: str
     d: np.ndarray = None
     d0max: float = 0.0
-    L: list = field(default_factory=list)
     pivots: list = field(default_factory=list)
     pivot_values: list = field(default_factory=list)
     gaps: list = field(default_factory=list)
     deficient: bool = False
+    _rows: np.ndarray = None
 
     def __post_init__(self):
         self.d = diagonal(self.phi4, self.w, self.channel)
         self.d0max = float(self.d.max()) if self.d.size else 0.0
+        self._rows = np.empty((16, self.d.size))
+
+    @property
+    def L(self) -> np.ndarray:
+        """The Cholesky factor's rows [k][N_g] (S ~ L^T L)."""
+        return self._rows[: len(self.pivots)]
 
     def step(self) -> bool:
         """One pivot; returns False (and marks rank deficiency) if none is left."""
@@ -76,17 +93,24 @@ class CholeskyState:
         if not dmax > RANK_TOL * self.d0max:
             self.deficient = True
             return False
-        rest = np.delete(self.d, gstar)
-        second = float(rest.max()) if rest.size else 0.0
+        keep = self.d[gstar]
+        self.d[gstar] = -np.inf
+        second = max(float(self.d.max()), 0.0) if self.d.size > 1 else 0.0
+        self.d[gstar] = keep
         self.gaps.append((dmax - second) / dmax)
-        s = column(self.phi4, self.w, gstar, self.channel)
-        if self.L:
-            Lm = np.asarray(self.L)
-            s = s - Lm.T @ Lm[:, gstar]
-        col = s / np.sqrt(dmax)
-        self.d = np.maximum(self.d - col * col, 0.0)
+        k = len(self.pivots)
+        # residual column of S at g*: S[:, g*] minus what the current factor explains
+        resid = column(self.phi4, self.w, gstar, self.channel)
+        if k:
+            resid = resid - self.L.T @ self.L[:, gstar]
+        row = resid / np.sqrt(dmax)
+        if k == self._rows.shape[0]:
+            grown = np.empty((2 * k, self.d.size))
+            grown[:k] = self._rows
+            self._rows = grown
+        self._rows[k] = row
+        self.d = np.maximum(self.d - row * row, 0.0)
         self.d[gstar] = 0.0
-        self.L.append(col)
         self.pivots.append(gstar)
         self.pivot_values.append(dmax)
         return True

@@ -101,8 +101,8 @@ def lib() -> C.CDLL:
                                       C.c_uint32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P,
                                       P, D, C.POINTER(Exchange), P, C.c_size_t, P]
     L.xtc_grad.restype = st
-    L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, P, P, P, P,
-                           P, P, P, P, P, C.c_size_t, P]
+    L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, C.c_int64,
+                           C.c_int64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
     L.xtc_exchange_terms.restype = st
     L.xtc_exchange_terms.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P,
                                      C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int64, C.c_int64,

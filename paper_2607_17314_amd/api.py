@@ -322,12 +322,15 @@ class KernelTimer:
         return False
 
 
-def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None, want_d=False):
+def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None, want_d=False,
+         bra=None):
     """dL/dc for L = sum over the given cotangents <cot[k], output k> (xtc_grad).
     cot keys: u1, u3, ulap, D1, D4, field (device tensors of the outputs' shapes).
     Returns a float64 device tensor [n_types * n_terms]; with want_d also the
     nonlinear-parameter derivatives as a float64 device tensor, (dtheta, dd):
-    [dL/dd] for the EE form, [dL/dd, dL/db_0, ..., dL/db_{n_types-1}] for the BH form."""
+    [dL/dd] for the EE form, [dL/dd, dL/db_0, ..., dL/db_{n_types-1}] for the BH form.
+    bra = (begin, end): the outputs are the partial sums over those bra points (as in
+    kernel_contract); default the whole grid."""
     hc = HostCorrelator(corr, c)
     xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
     piv = np.ascontiguousarray(pivots, np.int64)
@@ -339,9 +342,10 @@ def grad(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, cot: dict, c=None, wan
     flags = 1 if cv["ulap"] is not None else 0
     ws = _workspace(workspace_bytes(L.XTC_CALL_GRAD, grid.n_g, 0, n_mu, hc.c.size, flags))
     g = grid.c()
+    b0, b1 = (0, grid.n_g) if bra is None else bra
     _check("xtc_grad", L.lib().xtc_grad(
         C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
-        _ptr(cv["u1"]), _ptr(cv["u3"]), _ptr(cv["ulap"]), _ptr(cv["D1"]), _ptr(cv["D4"]),
+        int(b0), int(b1), _ptr(cv["u1"]), _ptr(cv["u3"]), _ptr(cv["ulap"]), _ptr(cv["D1"]), _ptr(cv["D4"]),
         _ptr(cv["field"]), _ptr(out), _ptr(dd), _ptr(ws), ws.numel(), _stream()))
     return (out, dd) if want_d else out
 

@@ -5,6 +5,44 @@
 namespace xtc {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+__global__ void k_flag_clear(int* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+// flag |= 1 if any weight is not in [0, inf)
+__global__ __launch_bounds__(256) void k_check_w(const double* __restrict__ w, long n,
+                                                 int* __restrict__ flag) {
+  int bad = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const double v = w[i];
+    if (!(v >= 0.0 && v <= 1.7976931348623157e308)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+xtc_status check_weights(const xtc_grid* grid, void* ws, size_t ws_bytes, hipStream_t st,
+                         const char* who) {
+  if (!ws || ws_bytes < sizeof(int)) {
+    set_error(std::string(who) + ": workspace too small for the weight check");
+    return XTC_ERR_NO_WORKSPACE;
+  }
+  int* flag = (int*)ws;
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, st, flag);
+  XTC_CHECK_LAUNCH();
+  const long n = grid->n_g;
+  const long blocks = n < 256L * 1024 ? (long)cdiv(n, 256) : 1024;
+  hipLaunchKernelGGL(k_check_w, dim3((unsigned)blocks), dim3(256), 0, st, grid->w, n, flag);
+  XTC_CHECK_LAUNCH();
+  int h = 0;
+  XTC_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  XTC_HIP(hipStreamSynchronize(st));
+  if (h) {
+    set_error(std::string(who) + ": quadrature weights must be finite and non-negative");
+    return XTC_ERR_INVALID_ARG;
+  }
+  return XTC_OK;
+}
 }  // namespace xtc
 
 extern "C" const char* xtc_last_error(void) { return xtc::g_last_error.c_str(); }

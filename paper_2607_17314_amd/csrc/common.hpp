@@ -93,6 +93,13 @@ struct GemmArgs {
 
 xtc_status gemm_f64(const GemmArgs& g, hipStream_t st);
 
+// Rejects quadrature weights that are negative, NaN or infinite (XTC_ERR_INVALID_ARG):
+// one small kernel over grid->w with an integer flag in the first bytes of the caller's
+// workspace, then a synchronisation of the stream to read the flag. Called before any
+// other launch of the calls that take a grid.
+xtc_status check_weights(const xtc_grid* grid, void* ws, size_t ws_bytes, hipStream_t st,
+                         const char* who);
+
 // Deterministic FP64 sum of x[0..n) (fixed two-level tree); result to *out (device).
 xtc_status reduce_sum_f64(const double* x, long n, double* out, double* scratch, hipStream_t st);
 

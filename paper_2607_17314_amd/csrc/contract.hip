@@ -224,6 +224,7 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, ex ? ex->n_orb : 0,
                            ex ? ex->n_q : 0);
   XTC_TRY(need_ws(ar));
+  XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_kernel_contract"));
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   if (ex) XTC_TRY(ex_prepare(C.ex, ex->phi_piv, ex->lq, grid->xyz, grid->w, xi, n_g, st));

@@ -499,6 +499,7 @@ extern "C" xtc_status xtc_exchange_terms(const xtc_grid* grid, const xtc_correla
   Arena ar(ws, ws_bytes);
   ExLayout L = layout_ex(ar, n_g, n_mu, n_orb, n_q, precision);
   XTC_TRY(need_ws(ar));
+  XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_exchange_terms"));
   if (bra_end == bra_begin) {
     XTC_TRY(ex_finish(L.W, X2, X3, true, st));
     XTC_HIP(hipStreamSynchronize(st));

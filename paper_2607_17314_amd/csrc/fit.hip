@@ -385,6 +385,7 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
   Arena ar(ws, ws_bytes);
   FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
   XTC_TRY(need_ws(ar));
+  XTC_TRY(check_weights(grid, ws, ws_bytes, st, "isdf_fit"));
   size_t tk = timing_begin(TM_FIT, st);
   XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_gather_piv, dim3(cdiv(4L * n_orb * n_mu, 256)), dim3(256), 0, st, phi4,

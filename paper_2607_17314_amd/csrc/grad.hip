@@ -622,12 +622,15 @@ using namespace xtc;
 
 extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                                const double* xi, const double* xigrad, const double* rho,
-                               const int64_t* pivots, const double* gu1, const double* gu3,
+                               const int64_t* pivots, int64_t bra_begin, int64_t bra_end,
+                               const double* gu1, const double* gu3,
                                const double* gulap, const double* gD1, const double* gD4,
                                const double* gfield, double* dtheta, double* dd, void* ws,
                                size_t ws_bytes, void* stream) {
   XTC_REQUIRE(grid && corr && xi && rho && pivots && dtheta, "xtc_grad: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "xtc_grad: empty grid");
+  XTC_REQUIRE(bra_begin >= 0 && bra_begin < bra_end && bra_end <= grid->n_g,
+              "xtc_grad: bra range must be non-empty and inside the grid");
   XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "xtc_grad: bad n_mu");
   XTC_REQUIRE(!gu1 || xigrad, "xtc_grad: the u1 cotangent needs xigrad");
   XTC_REQUIRE(corr->n_terms > 0 && corr->mno && corr->c && corr->d > 0.0,
@@ -686,6 +689,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   Arena ar(ws, ws_bytes);
   GradLayout L = layout_grad(ar, n_g, n_mu, n_params, gulap ? 1u : 0u);
   XTC_TRY(need_ws(ar));
+  XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_grad"));
   if (bh) {
     XTC_HIP(hipMemcpyAsync(L.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
     XTC_HIP(hipMemcpyAsync(L.pmap, pmap.data(), sizeof(BHParamMap) * pmap.size(),
@@ -714,9 +718,11 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   const bool need_fwd = gD1 || gD4;
   Stage1Args s1{grid->xyz, grid->w, xi, rho, L.rhot, n_g, n_mu, 0, 0, L.F, L.rows_pad, L.bp, 4};
   if (bh) s1.bh = L.bh;
-  for (int sb = 0; sb < L.nsb; ++sb) {
-    const long b0 = (long)sb * L.bp;
-    const long bn = (n_g - b0) < L.bp ? (n_g - b0) : L.bp;
+  // bra super-blocks of the range; the ket sums always cover the whole grid
+  const int nsb = (int)cdiv(bra_end - bra_begin, L.bp);
+  for (int sb = 0; sb < nsb; ++sb) {
+    const long b0 = bra_begin + (long)sb * L.bp;
+    const long bn = (bra_end - b0) < L.bp ? (bra_end - b0) : L.bp;
     if (need_fwd) {
       s1.b0 = b0;
       s1.bn = bn;
@@ -799,7 +805,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
   }
   if (bh) {
     hipLaunchKernelGGL(k_sum_partials, dim3(cdiv(ZS, 256)), dim3(256), 0, st,
-                       (const double*)L.partials, (long)L.nsb * L.nblk, ZS, ZS, L.zsum);
+                       (const double*)L.partials, (long)nsb * L.nblk, ZS, ZS, L.zsum);
     XTC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_bh_params, dim3(cdiv(n_params, 256)), dim3(256), 0, st,
                        (const double*)L.zsum, (const BHParamMap*)L.pmap, n_params, dtheta);
@@ -808,7 +814,7 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
                              sizeof(double) * (1 + bt.n_types), hipMemcpyDeviceToDevice, st));
   } else {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)L.partials,
-                       (long)L.nsb * L.nblk, gb.n + gb.want_d, MAXQ + 1, L.zsum);
+                       (long)nsb * L.nblk, gb.n + gb.want_d, MAXQ + 1, L.zsum);
     XTC_CHECK_LAUNCH();
     XTC_HIP(hipMemcpyAsync(dtheta, L.zsum, sizeof(double) * gb.n, hipMemcpyDeviceToDevice, st));
     if (dd) XTC_HIP(hipMemcpyAsync(dd, L.zsum + gb.n, sizeof(double), hipMemcpyDeviceToDevice, st));

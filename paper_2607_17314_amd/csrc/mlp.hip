@@ -346,6 +346,7 @@ extern "C" xtc_status xtc_mlp_features(const double* phi4, const xtc_grid* grid,
   Arena ar(ws, ws_bytes);
   double* nuc = ar.take<double>(3 * (size_t)n_nuc);
   XTC_TRY(need_ws(ar));
+  XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_mlp_features"));
   XTC_HIP(hipMemcpyAsync(nuc, nuc_xyz, sizeof(double) * 3 * n_nuc, hipMemcpyHostToDevice, st));
   XTC_HIP(hipStreamSynchronize(st));
   hipLaunchKernelGGL(k_features, dim3(cdiv(grid->n_g, 256)), dim3(256), 0, st, phi4, grid->xyz,

@@ -352,6 +352,7 @@ extern "C" xtc_status isdf_select_points(const double* phi4, const xtc_grid* gri
   XTC_REQUIRE(mode == XTC_SELECT_QR || mlp, "isdf_select_points: learned modes need an mlp");
   if (info)
     for (int i = 0; i < 8; ++i) info[i] = 0.0;
+  XTC_TRY(check_weights(grid, ws, ws_bytes, as_stream(stream), "isdf_select_points"));
   Arena ar(ws, ws_bytes);
   size_t tk = timing_begin(TM_SELECT, as_stream(stream));
   xtc_status s = mode == XTC_SELECT_QR

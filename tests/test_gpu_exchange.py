@@ -262,3 +262,34 @@ def test_full_size_fused_pass_equals_standalone(h20_fitted):
         assert torch.equal(fused[k], alone[k]), k
         assert torch.equal(fused[k], fused[k].transpose(0, 1)), k
         assert bool(torch.isfinite(fused[k]).all()), k
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (2, 1e-6)])
+def test_exchange_matches_literal_direct_form(h6_small, precision, tol):
+    """X2, X3 against the paper's literal Y, Z, Lt, Ch form (x_terms_direct, no projector)
+    on a small case: 700 points, 40 interpolation points, 40 orbital functions, a
+    non-diagonal reference density of rank 7."""
+    from oracle import exchange, fit, orbitals, pivots
+    from paper_2607_17314_amd import api
+    wl = h6_small
+    phi4 = orbitals.eval_orbitals(wl.basis, wl.C_mo, wl.grid_xyz)
+    idx = np.sort(np.random.default_rng(24).choice(wl.n_g, 700, replace=False))
+    xyz, w, phi4 = np.ascontiguousarray(wl.grid_xyz[:, idx]), wl.grid_w[idx].copy(), phi4[:, :, idx]
+    fp = pivots.select_fused(phi4, w, 40)
+    fr = fit.fit(phi4, w, fp.pivots)
+    n_fun = 40
+    mix = np.random.default_rng(25).normal(size=(n_fun, phi4.shape[1])) / np.sqrt(phi4.shape[1])
+    phi = mix @ phi4[0]
+    rng = np.random.default_rng(26)
+    V = np.linalg.qr(rng.normal(size=(n_fun, n_fun)))[0][:, :7]
+    gamma = (V * rng.uniform(0.5, 1.0, 7)) @ V.T
+    cG = exchange.calG(xyz, w, wl.corr, fr.xi)
+    ref = exchange.x_terms_direct(phi, fp.pivots, fr.xi, cG, w, gamma)
+    LQ = exchange.density_projector(gamma)
+    note(f"exchange vs literal form: n_g={len(w)} n_mu={len(fp.pivots)} n_orb={n_fun} "
+         f"n_q={LQ.shape[1]} precision={precision}")
+    got = _run(api, wl, xyz, w, fr.xi, phi[:, fp.pivots], LQ, precision)
+    for k in ("X2", "X3"):
+        e = rel_err(got[k], ref[k])
+        note(f"  {k}: rel max err {e:.2e}")
+        assert e < tol, k

@@ -117,3 +117,23 @@ def test_scale_derivative_matches_oracle(problem, subset):
     rich = (4.0 * fd1 - fd2) / 3.0
     note(f"  Richardson central difference {rich:.15e}")
     assert abs(rich - got) <= 1e-8 * abs(got)
+
+
+def test_adjoint_bra_ranges_add_up_and_match_oracle(problem):
+    """xtc_grad on a bra range is the derivative of that range's partial sums: two disjoint
+    ranges add up to the whole grid's derivative, and one range matches the oracle's."""
+    from oracle import adjoint
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, cot = problem
+    grid, xi, xig, rh, dcot = _device(api, problem)
+    n_g = len(w)
+    cut = 517
+    whole = api.grad(grid, wl.corr, xi, xig, rh, piv, dcot).cpu().numpy()
+    a = api.grad(grid, wl.corr, xi, xig, rh, piv, dcot, bra=(0, cut)).cpu().numpy()
+    b = api.grad(grid, wl.corr, xi, xig, rh, piv, dcot, bra=(cut, n_g)).cpu().numpy()
+    e = np.abs(a + b - whole).max() / np.abs(whole).max()
+    ref = adjoint.dL_dc(xyz, w, wl.corr, fr.xi, fr.xigrad, rho[piv], rho, cot, bra_range=(cut, n_g))
+    eo = np.abs(b - ref).max() / np.abs(ref).max()
+    note(f"adjoint bra ranges: sum vs whole {e:.2e}, range vs oracle {eo:.2e}")
+    assert e < 1e-12
+    assert eo < 1e-10

@@ -76,3 +76,18 @@ def test_jitter_retry_on_singular_gram(tiny):
     rho = np.einsum("pg,qg->pqg", phi, phi)
     a = np.einsum("mg,pqm->pqg", fr.xi, rho[:, :, piv])
     assert np.abs(a - rho).max() < 1e-6 * np.abs(rho).max()
+
+
+def test_column_restricted_fit_equals_full_columns(h6_small):
+    """The fit is column-separable: solving only some grid columns gives exactly those
+    columns of the full solution (xi and xi~ restricted separately)."""
+    phi4 = orbitals.eval_orbitals(h6_small.basis, h6_small.C_mo, h6_small.grid_xyz)
+    fp = pivots.select_fused(phi4, h6_small.grid_w, 80)
+    full = fit.fit(phi4, h6_small.grid_w, fp.pivots)
+    cols = np.arange(1000, 1700)
+    gcols = np.arange(4000, 4123)
+    part = fit.fit(phi4, h6_small.grid_w, fp.pivots, cols=cols, grad_cols=gcols)
+    assert np.allclose(part.xi, full.xi[:, cols], rtol=0, atol=1e-12 * np.abs(full.xi).max())
+    assert np.allclose(part.xigrad, full.xigrad[:, :, gcols], rtol=0,
+                       atol=1e-12 * np.abs(full.xigrad).max())
+    assert np.array_equal(part.jitter, full.jitter)
