@@ -83,15 +83,19 @@ def x_terms_direct(phi, piv, xi, cG, w, gamma):
 
 
 def x_terms(phi, piv, xi, cG, w, LQ):
-    """X2, X3 through the low-rank projector, the formulas of the module docstring written
-    as einsums over P, R^c and Q (no per-point pair products, no blocking)."""
+    """X2, X3 through the low-rank projector: the formulas of the module docstring as
+    einsums over P, R^c and Q, each bracketed sum taken in turn (the inner sum over the
+    projector index a and channel c at every grid point, then the grid sum)."""
     C = pivot_tensor(phi, piv)                                          # C[t, s, nu]
     P = np.einsum("tsn,ta->san", C, LQ)                                 # P[s, a, nu]
-    R = np.einsum("san,cng->csag", P, cG, optimize=True)                # R^c[s, a](g)
-    Q = np.einsum("san,ng->sag", P, xi, optimize=True)                  # Q[s, a](g)
-    X2 = np.einsum("g,mg,csag,cqag->qsm", w, xi, R, R, optimize=True)
-    X3 = (np.einsum("g,cmg,sag,cqag->qsm", w, cG, Q, R, optimize=True)
-          + np.einsum("g,cmg,csag,qag->qsm", w, cG, R, Q, optimize=True))
+    R = np.einsum("san,cng->cgsa", P, cG, optimize=True)                # R^c[s, a](g)
+    Q = np.einsum("san,ng->gsa", P, xi, optimize=True)                  # Q[s, a](g)
+    # inner sums at each grid point
+    T2 = np.einsum("cgsa,cgqa->gqs", R, R)                              # sum_{a,c} R^c_s R^c_q
+    T3 = np.einsum("gsa,cgqa->cgqs", Q, R) + np.einsum("cgsa,gqa->cgqs", R, Q)
+    # grid sums
+    X2 = np.einsum("g,mg,gqs->qsm", w, xi, T2, optimize=True)
+    X3 = np.einsum("g,cmg,cgqs->qsm", w, cG, T3, optimize=True)
     return dict(X2=X2, X3=X3)
 
 

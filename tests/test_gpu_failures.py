@@ -1,7 +1,7 @@
 """Failure and warning paths of the boundary, forced from the host with valid launches:
 rejected weights (negative, NaN, infinite) before any stage runs; Alg. 1's stop at the
 pair rank (XTC_WARN_RANK_DEFICIENT); the auxiliary fit's Tikhonov retry
-(XTC_WARN_JITTER on duplicated pivots) and its failure (XTC_ERR_NOT_SPD when every
+(XTC_WARN_JITTER when every orbital vanishes at one pivot) and its failure (XTC_ERR_NOT_SPD when every
 orbital vanishes at the pivots, so that the Gram matrix and every shift are zero).
 The oracle takes the same decisions on the same inputs."""
 import numpy as np
@@ -77,10 +77,34 @@ def test_rank_deficiency_is_reported(tiny):
     assert np.array_equal(piv, ref.pivots)
 
 
-def test_duplicated_pivots_take_the_tikhonov_retry(tiny):
-    """A duplicated pivot makes the Gram matrix exactly singular; a shift restores
-    positive definiteness (XTC_WARN_JITTER) and the fit still reproduces the pair products
-    as well as the pivots without the duplicate."""
+def test_orbital_free_pivot_takes_the_tikhonov_retry(tiny):
+    """All orbitals vanishing at one pivot give its Gram row and column exactly zero, so the
+    unshifted Cholesky fails in every system and the first shift (k = 0) restores positive
+    definiteness: XTC_WARN_JITTER with k = 0 for the scalar and the three gradient systems,
+    the oracle's choice too; the fit then reproduces the pair products as well as the other
+    pivots alone do."""
+    from oracle import fit
+    from paper_2607_17314_amd import _lib as L
+    api, wl, t = tiny["api"], tiny["wl"], tiny["t"]
+    grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+    piv = np.asarray(tiny["piv"])
+    phi4 = tiny["phi4"].copy()
+    phi4[:, :, piv[2]] = 0.0
+    xi, xig, info, st = api.fit(t(phi4), grid, piv)
+    ref = fit.fit(phi4, wl.grid_w, piv)
+    note(f"orbital-free pivot: status {st}, shift indices {info[:4]} (oracle {ref.jitter}), "
+         f"residuals {info[4:]} (oracle {ref.resid_rel})")
+    assert st == L.XTC_WARN_JITTER
+    assert np.array_equal(info[:4], [0, 0, 0, 0]) and np.array_equal(ref.jitter, [0, 0, 0, 0])
+    assert np.all(np.abs(info[4:] - ref.resid_rel) <= 1e-9 + 1e-9 * np.abs(ref.resid_rel))
+    assert bool(np.isfinite(xi.cpu().numpy()).all() and np.isfinite(xig.cpu().numpy()).all())
+
+
+def test_duplicated_pivot_is_singular_only_up_to_rounding(tiny):
+    """A duplicated pivot makes the Gram matrix singular in exact arithmetic; in floating
+    point the last Cholesky pivot is a rounding-level number of either sign, so some systems
+    may need a shift (XTC_WARN_JITTER) and others not. Either way the fit reproduces the
+    pair products as well as the pivots without the duplicate."""
     from oracle import fit
     from paper_2607_17314_amd import _lib as L
     api, wl, t = tiny["api"], tiny["wl"], tiny["t"]
@@ -89,13 +113,10 @@ def test_duplicated_pivots_take_the_tikhonov_retry(tiny):
     dup = np.concatenate([piv, piv[2:3]])
     xi, xig, info, st = api.fit(t(tiny["phi4"]), grid, dup)
     note(f"duplicated pivot: status {st}, shift indices {info[:4]}, residuals {info[4:]}")
-    assert st == L.XTC_WARN_JITTER
-    assert np.all(info[:4] >= 0)
-    ref = fit.fit(tiny["phi4"], wl.grid_w, dup)
-    assert np.all(ref.jitter >= 0)
+    assert st in (L.XTC_OK, L.XTC_WARN_JITTER)
+    assert (st == L.XTC_WARN_JITTER) == bool(np.any(info[:4] >= 0))
     base = fit.fit(tiny["phi4"], wl.grid_w, piv)
     assert np.all(np.abs(info[4:] - base.resid_rel) <= 1e-6 + 1e-6 * np.abs(base.resid_rel))
-    assert bool(np.isfinite(xi.cpu().numpy()).all() and np.isfinite(xig.cpu().numpy()).all())
 
 
 def test_vanishing_orbitals_fail_with_not_spd(tiny):
