@@ -270,6 +270,29 @@ xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
                                double* escale, const xtc_exchange* ex, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): xtc_kernel_contract without a
+ * workspace. Same arguments, outputs and results as xtc_kernel_contract, minus ws and
+ * ws_bytes. Its scratch is one file-scope device array of XTC_NOALLOC_SCRATCH_BYTES
+ * bytes per device, which the library holds from the first call on that device until the
+ * process ends; the call allocates and frees nothing. The bra super-blocks are narrowed
+ * (halved, in multiples of 64 points) until the scratch fits, which only reorders the
+ * stage-2 sums; with the regular call's width the results are bitwise those of
+ * xtc_kernel_contract. A problem that needs more scratch even at 64-point super-blocks
+ * (for example the split path's operand, 4 bytes per row and grid point) returns
+ * XTC_ERR_NO_WORKSPACE. Every byte of the scratch that a call reads it has written
+ * earlier in the same call, so contents left by an earlier call do not matter; calls
+ * that overlap in time on one device (two host threads, or two streams) share the one
+ * array and race: serialise them. */
+#define XTC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+xtc_status xtc_kernel_contract_noalloc(const xtc_grid* grid, const xtc_correlator* corr,
+                                       int32_t n_mu, const double* xi, const double* xigrad,
+                                       const double* rho, const int64_t* pivots, uint32_t channels,
+                                       int32_t precision, int64_t bra_begin, int64_t bra_end,
+                                       double* u1, double* u3, double* ulap, double* D1, double* D4,
+                                       double* field, double* escale, const xtc_exchange* ex,
+                                       void* stream);
+
 /* Exchange intermediates of xTC Terms 2 and 3 through the low-rank projector
  * (xTC section, "Terms 2 and 3 (non-factorizable)", "Low-rank projector for Terms
  * 2 and 3"; pipeline section, symmetry paragraph). With gamma = LQ LQ^T,

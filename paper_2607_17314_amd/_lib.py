@@ -100,6 +100,10 @@ def lib() -> C.CDLL:
     L.xtc_kernel_contract.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64,
                                       C.c_uint32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P,
                                       P, D, C.POINTER(Exchange), P, C.c_size_t, P]
+    L.xtc_kernel_contract_noalloc.restype = st
+    L.xtc_kernel_contract_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P,
+                                              P, I64, C.c_uint32, C.c_int32, C.c_int64, C.c_int64,
+                                              P, P, P, P, P, P, D, C.POINTER(Exchange), P]
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, C.c_int64,
                            C.c_int64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
@@ -140,7 +144,8 @@ def lib() -> C.CDLL:
 
 
 EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_orbitals",
-            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_grad", "xtc_timing",
+            "isdf_select_points", "isdf_fit", "xtc_kernel_contract", "xtc_kernel_contract_noalloc",
+            "xtc_grad", "xtc_timing",
             "xtc_exchange_terms", "xtc_assembly_prepare", "xtc_assembly_panel", "xtc_one_body",
             "xtc_mlp_features", "xtc_mlp_forward", "xtc_mlp_loss_grad", "xtc_adam_step",
             "xtc_vmc_sample", "xtc_vmc_local_energy", "xtc_vmc_gn_step"]

@@ -180,12 +180,15 @@ ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_E
 
 
 def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: int = ALL_CHANNELS,
-                    precision: int = L.XTC_FP64, c=None, out=None, exchange=None, bra=None):
+                    precision: int = L.XTC_FP64, c=None, out=None, exchange=None, bra=None,
+                    noalloc=False):
     """Grid-pair kernels and xTC D terms (xtc_kernel_contract). Returns a dict of device tensors
     (u1, u3, ulap, D1, D4, field) and escale (numpy [6]) for the requested channels.
     exchange: None, or {"phi_piv": [n_orb][n_mu], "lq": [n_orb][n_q], "want": ("X2", "X3")}
     to form the xTC Terms 2-3 intermediates in the same pass (keys X2, X3 of the result).
-    bra = (begin, end) restricts the bra sums (partial sums; default the whole grid)."""
+    bra = (begin, end) restricts the bra sums (partial sums; default the whole grid).
+    noalloc: call xtc_kernel_contract_noalloc (the library's static scratch instead of a
+    workspace; the outputs are still allocated here)."""
     hc = HostCorrelator(corr, c)
     xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
     piv = np.ascontiguousarray(pivots, np.int64)
@@ -219,15 +222,18 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
         for k in ("X2", "X3"):
             o[k] = torch.empty((n_orb, n_orb, n_mu), **f64) if k in want_x else None
         exs = L.Exchange(n_orb, _ptr(phi_piv), n_q, _ptr(lq), _ptr(o["X2"]), _ptr(o["X3"]))
-    ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, n_orb, n_mu, n_q,
-                                    channels | (precision << 16)))
     g = grid.c()
     b0, b1 = (0, n_g) if bra is None else bra
-    _check("xtc_kernel_contract", L.lib().xtc_kernel_contract(
-        C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho), piv.ctypes.data_as(L.I64),
-        channels, precision, b0, b1, _ptr(u1), _ptr(u3), _ptr(ul), _ptr(d1), _ptr(d4), _ptr(fld),
-        _dptr(esc) if channels & L.XTC_ESCALE else None, C.byref(exs) if exs is not None else None,
-        _ptr(ws), ws.numel(), _stream()))
+    args = (C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho),
+            piv.ctypes.data_as(L.I64), channels, precision, b0, b1, _ptr(u1), _ptr(u3), _ptr(ul),
+            _ptr(d1), _ptr(d4), _ptr(fld), _dptr(esc) if channels & L.XTC_ESCALE else None,
+            C.byref(exs) if exs is not None else None)
+    if noalloc:
+        _check("xtc_kernel_contract_noalloc", L.lib().xtc_kernel_contract_noalloc(*args, _stream()))
+    else:
+        ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, n_orb, n_mu, n_q,
+                                        channels | (precision << 16)))
+        _check("xtc_kernel_contract", L.lib().xtc_kernel_contract(*args, _ptr(ws), ws.numel(), _stream()))
     o["escale"] = esc if channels & L.XTC_ESCALE else None
     return o
 

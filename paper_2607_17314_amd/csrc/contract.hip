@@ -6,6 +6,7 @@
 // with wt_g = w_g sum_l G_l xi_l(g), H_gc = sum_l G_l calG^c_lg, V = sum_c H_c calG^c,
 // all as FP64 MFMA GEMMs accumulated in place. The rho row of the panel gives
 // the exact field A_gamma and the ISDF-free energy-scale sums.
+#include <mutex>
 #include "contract.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
@@ -121,11 +122,19 @@ struct ConLayout {
   ExWork ex;   // exchange intermediates (when requested)
 };
 
+// Width of the bra super-blocks: the whole grid rounded up to 64 points, at most SUPER_BLOCK.
+static long default_bp(int64_t n_g) {
+  return n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
+}
+
+// bp: the super-block width, a multiple of 64 (every stage-1 and stage-2 launch of a
+// super-block covers at most bp bra points, so any such width gives the same sums up to
+// their order).
 static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision,
-                            int n_orb, int n_q) {
+                            int n_orb, int n_q, long bp) {
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
-  C.bp = n_g < SUPER_BLOCK ? ((n_g + 63) / 64) * 64 : SUPER_BLOCK;
+  C.bp = bp;
   C.rows_pad = ((n_mu + 2 + 255) / 256) * 256;   // whole row tiles of the split kernel
   C.nsb = (int)cdiv(n_g, C.bp);
   C.piv = ar.take<long>(n_mu);
@@ -155,7 +164,8 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
 
 size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q) {
   Arena ar(nullptr, 0);
-  layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q);
+  layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q,
+             default_bp(n_g));
   return ar.used;
 }
 
@@ -194,14 +204,15 @@ __global__ void k_fill_zero(double* __restrict__ x, long n) {
   if (t < n) x[t] = 0.0;
 }
 
-extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
-                                          int32_t n_mu, const double* xi, const double* xigrad,
-                                          const double* rho, const int64_t* pivots,
-                                          uint32_t channels, int32_t precision, int64_t bra_begin,
-                                          int64_t bra_end, double* u1,
-                                          double* u3, double* ulap, double* D1, double* D4,
-                                          double* field, double* escale, const xtc_exchange* ex,
-                                          void* ws, size_t ws_bytes, void* stream) {
+// The body of xtc_kernel_contract and xtc_kernel_contract_noalloc: scratch is ws (its
+// bytes), the bra super-blocks are bp points wide (a multiple of 64).
+static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
+                                const double* xi, const double* xigrad, const double* rho,
+                                const int64_t* pivots, uint32_t channels, int32_t precision,
+                                int64_t bra_begin, int64_t bra_end, double* u1, double* u3,
+                                double* ulap, double* D1, double* D4, double* field,
+                                double* escale, const xtc_exchange* ex, void* ws,
+                                size_t ws_bytes, long bp, void* stream) {
   XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
   XTC_REQUIRE(bra_begin >= 0 && bra_begin < bra_end && bra_end <= grid->n_g,
               "contract: bra range must be non-empty and inside the grid");
@@ -222,7 +233,7 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
   ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, ex ? ex->n_orb : 0,
-                           ex ? ex->n_q : 0);
+                           ex ? ex->n_q : 0, bp);
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_kernel_contract"));
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
@@ -337,3 +348,76 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
 
 
 
+
+extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
+                                          int32_t n_mu, const double* xi, const double* xigrad,
+                                          const double* rho, const int64_t* pivots,
+                                          uint32_t channels, int32_t precision, int64_t bra_begin,
+                                          int64_t bra_end, double* u1,
+                                          double* u3, double* ulap, double* D1, double* D4,
+                                          double* field, double* escale, const xtc_exchange* ex,
+                                          void* ws, size_t ws_bytes, void* stream) {
+  XTC_REQUIRE(grid, "contract: null argument");
+  return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
+                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, ws, ws_bytes,
+                       default_bp(grid->n_g), stream);
+}
+
+// ---- the variant without a workspace: scratch in a file-scope device array ----------
+//
+// One array per device (the module's copy on that device), shared by every call of
+// xtc_kernel_contract_noalloc on that device; its device address is looked up once per
+// device with hipGetSymbolAddress and only that address is handed to the kernels.
+
+static __device__ __align__(256) unsigned char scratch[XTC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static xtc_status scratch_address(void** out) {
+  int dev = -1;
+  XTC_HIP(hipGetDevice(&dev));
+  XTC_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "contract_noalloc: device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    XTC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    XTC_REQUIRE(p != nullptr, "contract_noalloc: no device address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return XTC_OK;
+}
+
+extern "C" xtc_status xtc_kernel_contract_noalloc(
+    const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu, const double* xi,
+    const double* xigrad, const double* rho, const int64_t* pivots, uint32_t channels,
+    int32_t precision, int64_t bra_begin, int64_t bra_end, double* u1, double* u3, double* ulap,
+    double* D1, double* D4, double* field, double* escale, const xtc_exchange* ex, void* stream) {
+  XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+  if (ex) XTC_TRY(check_exchange_args(ex, n_mu));
+  // the widest super-block (a multiple of 64, at most the regular call's) whose scratch fits
+  const int n_orb = ex ? ex->n_orb : 0, n_q = ex ? ex->n_q : 0;
+  auto need = [&](long bp) {
+    Arena ar(nullptr, 0);
+    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp);
+    return ar.used;
+  };
+  long bp = default_bp(grid->n_g);
+  while (bp > 64 && need(bp) > (size_t)XTC_NOALLOC_SCRATCH_BYTES) bp = ((bp / 2 + 63) / 64) * 64;
+  if (need(bp) > (size_t)XTC_NOALLOC_SCRATCH_BYTES) {
+    set_error("contract_noalloc: this problem needs " + std::to_string(need(bp)) +
+              " bytes of scratch even with 64-point super-blocks; the static scratch holds " +
+              std::to_string((size_t)XTC_NOALLOC_SCRATCH_BYTES) +
+              " (use xtc_kernel_contract with a workspace)");
+    return XTC_ERR_NO_WORKSPACE;
+  }
+  void* ptr = nullptr;
+  XTC_TRY(scratch_address(&ptr));
+  return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
+                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, ptr,
+                       (size_t)XTC_NOALLOC_SCRATCH_BYTES, bp, stream);
+}
