@@ -51,9 +51,11 @@ enum {
   XTC_ERR_UNSUPPORTED = -5
 };
 
-/* Arithmetic of the grid-pair contraction (xtc_kernel_contract, xtc_grad). */
+/* Arithmetic of the grid-pair contraction (xtc_kernel_contract, xtc_grad), and the
+ * storage type of the interpolation vectors xi (isdf_fit's xi_prec, xtc_xi_source). */
 enum {
   XTC_FP64 = 0,      /* FP64 kernels and FP64 MFMA throughout */
+  XTC_FP32 = 1,      /* storage of xi only: FP32 (half the memory; the split path reads it) */
   XTC_SPLIT_F16 = 2  /* stage 1 as FP16 hi+lo split products on MFMA with FP32
                         accumulation and FP64 compensation across ket chunks;
                         stage 2, Gram/Cholesky and energy-scale sums in FP64 */
@@ -85,7 +87,14 @@ enum {
 };
 
 /* Fit outputs of isdf_fit (bit mask). */
-enum { XTC_FIT_XI = 1, XTC_FIT_XIGRAD = 2 };
+enum { XTC_FIT_XI = 1, XTC_FIT_XIGRAD = 2, XTC_FIT_KEEP_CHOL = 4 };
+
+/* Doubles of one system's kept factor (isdf_fit with XTC_FIT_KEEP_CHOL): the lower
+ * Cholesky factor L of A + shift I, row-major n_mu x n_mu (its strict upper triangle
+ * unspecified), then the inverses of its 64 x 64 diagonal blocks [ceil(n_mu / 64)][64][64]
+ * (the last block zero-padded), as the blocked triangular solves use them. */
+#define XTC_CHOL_SYSTEM_DOUBLES(n_mu) \
+  ((size_t)(n_mu) * (size_t)(n_mu) + (size_t)4096 * (size_t)(((n_mu) + 63) / 64))
 
 /* Integration grid. */
 typedef struct {
@@ -185,12 +194,17 @@ enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
        XTC_CALL_CONTRACT = 4, XTC_CALL_GRAD = 5, XTC_CALL_FEATURES = 6, XTC_CALL_MLP_GRAD = 7,
        XTC_CALL_EXCHANGE = 8, XTC_CALL_ASSEMBLY = 9, XTC_CALL_ONE_BODY = 10, XTC_CALL_VMC = 11 };
 
+/* Flag of the contraction's workspace query: xi~ formed per bra super-block. */
+#define XTC_WS_XIGRAD_BLOCKS (1u << 24)
+
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
- * precision in bits 16..23) or the select mode (SELECT) or the fit mask (FIT) or
+ * precision in bits 16..23 and, for CONTRACT, XTC_WS_XIGRAD_BLOCKS) or the select mode
+ * (SELECT) or the fit mask (FIT) or
  * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none).
  * n_aux: n_ao (EVAL_ORBITALS, VMC), n_params (GRAD), the
- * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_orb > 0
- * asks for them), else 0. */
+ * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_aux > 0
+ * asks for them), else 0. n_orb: the orbitals (also for CONTRACT with exchange outputs or
+ * XTC_WS_XIGRAD_BLOCKS). */
 size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, int32_t n_mu,
                            int32_t n_aux, uint32_t flags);
 
@@ -230,22 +244,46 @@ xtc_status isdf_select_points(const double* phi4, const xtc_grid* grid, int32_t 
  * scalar A = G o G, G = Phi_mu^T Phi_mu; B = P o P, P = Phi_mu^T Phi; A xi = B.
  * gradient A_c = (dPhi_mu^T dPhi_mu)_c o G; B_c = P o (dPhi_mu^T dPhi)_c; A_c xi~^c = B_c.
  * Solved by FP64 Cholesky with the adaptive Tikhonov retry (no shift, then
- * 1e-14 * 10^k * mean(diag A), k = 0..8) and blocked triangular solves.
- * pivots: host [n_mu]. xi: device [n_mu][n_g] (if what & XTC_FIT_XI).
- * xigrad: device [3][n_mu][n_g] (if what & XTC_FIT_XIGRAD).
+ * 1e-14 * 10^k * mean(diag A), k = 0..8) and blocked triangular solves, in FP64 whatever
+ * the storage type of xi. The grid is processed in chunks, each column on its own (the
+ * fit is column-separable).
+ * what: XTC_FIT_XI (xi), XTC_FIT_XIGRAD (xi~), XTC_FIT_KEEP_CHOL (the four factors to
+ * chol, also those of systems whose solution is not asked for; the contraction forms xi~
+ * per bra block from them when it is given no xigrad).
+ * pivots: host [n_mu]. xi_prec: XTC_FP64 or XTC_FP32, the type of xi: device [n_mu][n_g]
+ * (XTC_FP32: each element the rounding of the FP64 solution).
+ * xigrad: device double [3][n_mu][n_g] (if what & XTC_FIT_XIGRAD).
+ * chol: device double [4][XTC_CHOL_SYSTEM_DOUBLES(n_mu)] (if what & XTC_FIT_KEEP_CHOL):
+ * scalar, x, y, z.
  * info: host [8] or NULL: {shift index k per system (-1 none) x4, relative weighted
- * residual sum_g w^2 (|m_g|^2 - xi(g).B(g)) / sum_g w^2 |m_g|^2 x4} (scalar, x, y, z).
+ * residual sum_g w^2 (|m_g|^2 - xi(g).B(g)) / sum_g w^2 |m_g|^2 x4} (scalar, x, y, z; the
+ * residual of a system is reported when its solution is asked for, else 0).
  * Returns XTC_WARN_JITTER if any shift was used. Synchronising. */
 xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
-                    const int64_t* pivots, int32_t n_mu, uint32_t what, double* xi,
-                    double* xigrad, double* info, void* ws, size_t ws_bytes, void* stream);
+                    const int64_t* pivots, int32_t n_mu, uint32_t what, int32_t xi_prec,
+                    void* xi, double* xigrad, double* chol, double* info, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Where xtc_kernel_contract takes xi and xi~ from, when not from the defaults (FP64 xi and
+ * a stored xigrad): xi in FP32 (split path only), and xi~ formed per bra super-block
+ * (xigrad = NULL with XTC_U1) from the orbitals and the fit's kept factors, with the fit's
+ * own right-hand-side products and blocked solves for the block's columns (so the same
+ * values as a stored xigrad, bit for bit, without its [3][n_mu][n_g] of memory). */
+typedef struct {
+  int32_t xi_prec;     /* XTC_FP64 or XTC_FP32: the element type of xi */
+  const double* phi4;  /* device [4][n_orb][n_g], or NULL when xigrad is given */
+  int32_t n_orb;
+  const double* chol;  /* device: isdf_fit's kept factors [4][XTC_CHOL_SYSTEM_DOUBLES(n_mu)],
+                          or NULL when xigrad is given */
+} xtc_xi_source;
 
 /* Grid-pair kernels and xTC D terms, with the kernel tiles generated on the fly
  * (K-kernel section, eqs. K1-isdf and K3-isdf; xTC section Terms 1 and 4, with
  * calG^c_{mu,g} = sum_g' w_g' xi_mu(g') d_c u(g,g'), H_{g,c} = sum_l G_l calG^c_{l,g},
  * V_{nu,g} = sum_c H_{g,c} calG^c_{nu,g}, wt_g = w_g sum_l G_l xi_l(g), and
  * G_nu = rho_gamma(r_nu)). grad acts on the bra point g.
- * xi: device [n_mu][n_g]; xigrad: device [3][n_mu][n_g] (needed for XTC_U1).
+ * xi: device [n_mu][n_g] (FP64, or FP32 per src); xigrad: device [3][n_mu][n_g] (needed
+ * for XTC_U1 unless src provides the factors).
  * rho: device [n_g] (rho_gamma). pivots: host [n_mu] (G is gathered from rho).
  * Outputs (device, FP64, overwritten; NULL when the channel is off):
  *   u1 [3][n_mu][n_mu], u3, ulap, D1, D4 [n_mu][n_mu], field [3][n_g].
@@ -260,15 +298,18 @@ xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
  * ex: NULL, or the exchange intermediates X2, X3 of xTC Terms 2 and 3 to form in the
  *   same pass from the same calG panels (Alg. 2, xTC-correction step; definitions at
  *   xtc_exchange_terms); with ex the workspace query takes n_orb = ex->n_orb and
- *   n_aux = ex->n_q.
+ *   n_aux = ex->n_q (FP64 xi only).
+ * src: NULL (xi FP64; XTC_U1 needs xigrad), or the xi storage type and, for xigrad = NULL,
+ *   the orbitals and kept factors (see xtc_xi_source); then the workspace query takes
+ *   n_orb = src->n_orb and flags bit 24 (XTC_WS_XIGRAD_BLOCKS).
  * Asynchronous after the weight check; synchronising if escale != NULL. */
 xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
-                               const double* xi, const double* xigrad, const double* rho,
+                               const void* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, uint32_t channels, int32_t precision,
                                int64_t bra_begin, int64_t bra_end, double* u1, double* u3,
                                double* ulap, double* D1, double* D4, double* field,
-                               double* escale, const xtc_exchange* ex, void* ws, size_t ws_bytes,
-                               void* stream);
+                               double* escale, const xtc_exchange* ex, const xtc_xi_source* src,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): xtc_kernel_contract without a
@@ -286,12 +327,12 @@ xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
  * array and race: serialise them. */
 #define XTC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 xtc_status xtc_kernel_contract_noalloc(const xtc_grid* grid, const xtc_correlator* corr,
-                                       int32_t n_mu, const double* xi, const double* xigrad,
+                                       int32_t n_mu, const void* xi, const double* xigrad,
                                        const double* rho, const int64_t* pivots, uint32_t channels,
                                        int32_t precision, int64_t bra_begin, int64_t bra_end,
                                        double* u1, double* u3, double* ulap, double* D1, double* D4,
                                        double* field, double* escale, const xtc_exchange* ex,
-                                       void* stream);
+                                       const xtc_xi_source* src, void* stream);
 
 /* Exchange intermediates of xTC Terms 2 and 3 through the low-rank projector
  * (xTC section, "Terms 2 and 3 (non-factorizable)", "Low-rank projector for Terms

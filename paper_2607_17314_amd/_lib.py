@@ -9,11 +9,17 @@ LIB_PATH = os.path.join(_HERE, "libisdfxtc.so")
 
 XTC_OK, XTC_WARN_RANK_DEFICIENT, XTC_WARN_JITTER, XTC_WARN_FALLBACK = 0, 1, 2, 3
 XTC_ERR_INVALID_ARG, XTC_ERR_NOT_SPD, XTC_ERR_HIP, XTC_ERR_NO_WORKSPACE, XTC_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
-XTC_FP64, XTC_SPLIT_F16 = 0, 2
+XTC_FP64, XTC_FP32, XTC_SPLIT_F16 = 0, 1, 2
 XTC_U_EE, XTC_U_BH = 0, 1
 XTC_U1, XTC_U3, XTC_ULAP, XTC_D1, XTC_D4, XTC_FIELD, XTC_ESCALE = 1, 2, 4, 8, 16, 32, 64
 XTC_SELECT_QR, XTC_SELECT_LEARNED, XTC_SELECT_LEARNED_JUDGED = 0, 1, 2
-XTC_FIT_XI, XTC_FIT_XIGRAD = 1, 2
+XTC_FIT_XI, XTC_FIT_XIGRAD, XTC_FIT_KEEP_CHOL = 1, 2, 4
+XTC_WS_XIGRAD_BLOCKS = 1 << 24
+
+
+def chol_system_doubles(n_mu: int) -> int:
+    """XTC_CHOL_SYSTEM_DOUBLES: one system's kept factor and inverted diagonal blocks."""
+    return n_mu * n_mu + 4096 * ((n_mu + 63) // 64)
 XTC_CALL_EVAL_ORBITALS, XTC_CALL_SELECT, XTC_CALL_FIT, XTC_CALL_CONTRACT, XTC_CALL_GRAD = 1, 2, 3, 4, 5
 XTC_CALL_FEATURES, XTC_CALL_MLP_GRAD, XTC_CALL_EXCHANGE = 6, 7, 8
 XTC_CALL_ASSEMBLY, XTC_CALL_ONE_BODY, XTC_CALL_VMC = 9, 10, 11
@@ -48,6 +54,10 @@ class Correlator(C.Structure):
 class Exchange(C.Structure):
     _fields_ = [("n_orb", C.c_int32), ("phi_piv", P), ("n_q", C.c_int32), ("lq", P), ("X2", P),
                 ("X3", P)]
+
+
+class XiSource(C.Structure):
+    _fields_ = [("xi_prec", C.c_int32), ("phi4", P), ("n_orb", C.c_int32), ("chol", P)]
 
 
 class Assembly(C.Structure):
@@ -94,16 +104,18 @@ def lib() -> C.CDLL:
     L.isdf_select_points.argtypes = [P, C.POINTER(Grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      C.POINTER(Mlp), C.c_double, I64, I32, D, P, C.c_size_t, P]
     L.isdf_fit.restype = st
-    L.isdf_fit.argtypes = [P, C.POINTER(Grid), C.c_int32, I64, C.c_int32, C.c_uint32, P, P, D, P,
-                           C.c_size_t, P]
+    L.isdf_fit.argtypes = [P, C.POINTER(Grid), C.c_int32, I64, C.c_int32, C.c_uint32, C.c_int32, P,
+                           P, P, D, P, C.c_size_t, P]
     L.xtc_kernel_contract.restype = st
     L.xtc_kernel_contract.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64,
                                       C.c_uint32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P,
-                                      P, D, C.POINTER(Exchange), P, C.c_size_t, P]
+                                      P, D, C.POINTER(Exchange), C.POINTER(XiSource), P, C.c_size_t,
+                                      P]
     L.xtc_kernel_contract_noalloc.restype = st
     L.xtc_kernel_contract_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P,
                                               P, I64, C.c_uint32, C.c_int32, C.c_int64, C.c_int64,
-                                              P, P, P, P, P, P, D, C.POINTER(Exchange), P]
+                                              P, P, P, P, P, P, D, C.POINTER(Exchange),
+                                              C.POINTER(XiSource), P]
     L.xtc_grad.restype = st
     L.xtc_grad.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64, C.c_int64,
                            C.c_int64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]

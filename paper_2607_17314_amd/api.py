@@ -159,21 +159,50 @@ def select_points(phi4, grid: DeviceGrid, n_mu: int, n_occ: int = 0, mode: int =
 
 
 def fit(phi4, grid: DeviceGrid, pivots, what: int = L.XTC_FIT_XI | L.XTC_FIT_XIGRAD):
-    """xi [n_mu, n_g] and xigrad [3, n_mu, n_g] (isdf_fit). Returns (xi, xigrad, info, status)."""
+    """xi [n_mu, n_g] and xigrad [3, n_mu, n_g] in FP64 (isdf_fit). Returns (xi, xigrad, info,
+    status)."""
+    xi, xig, info, _, st = fit_ex(phi4, grid, pivots, xi=bool(what & L.XTC_FIT_XI),
+                                  xigrad=bool(what & L.XTC_FIT_XIGRAD))
+    return xi, xig, info, st
+
+
+def fit_ex(phi4, grid: DeviceGrid, pivots, xi_prec: int = L.XTC_FP64, xi: bool = True,
+           xigrad: bool = True, keep_chol: bool = False):
+    """isdf_fit with every option: xi in FP64 or FP32 (xi_prec), xi~ (FP64), and the kept
+    factors [4, XTC_CHOL_SYSTEM_DOUBLES(n_mu)] (FP64) from which the contraction forms xi~
+    per bra block. Returns (xi, xigrad, info, chol, status), None for what was not asked."""
     phi4 = _in(phi4, "phi4")
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]
     n_orb = int(phi4.shape[1])
-    xi = torch.empty((n_mu, grid.n_g), dtype=torch.float64, device="cuda") if what & L.XTC_FIT_XI else None
-    xig = (torch.empty((3, n_mu, grid.n_g), dtype=torch.float64, device="cuda")
-           if what & L.XTC_FIT_XIGRAD else None)
+    what = ((L.XTC_FIT_XI if xi else 0) | (L.XTC_FIT_XIGRAD if xigrad else 0)
+            | (L.XTC_FIT_KEEP_CHOL if keep_chol else 0))
+    dt = torch.float32 if xi_prec == L.XTC_FP32 else torch.float64
+    x = torch.empty((n_mu, grid.n_g), dtype=dt, device="cuda") if xi else None
+    xig = torch.empty((3, n_mu, grid.n_g), dtype=torch.float64, device="cuda") if xigrad else None
+    chol = (torch.empty((4, L.chol_system_doubles(n_mu)), dtype=torch.float64, device="cuda")
+            if keep_chol else None)
     info = np.zeros(8, np.float64)
     ws = _workspace(workspace_bytes(L.XTC_CALL_FIT, grid.n_g, n_orb, n_mu, 0, what))
     g = grid.c()
     st = _check("isdf_fit", L.lib().isdf_fit(
-        _ptr(phi4), C.byref(g), n_orb, piv.ctypes.data_as(L.I64), n_mu, what, _ptr(xi), _ptr(xig),
-        _dptr(info), _ptr(ws), ws.numel(), _stream()))
-    return xi, xig, info, st
+        _ptr(phi4), C.byref(g), n_orb, piv.ctypes.data_as(L.I64), n_mu, what, int(xi_prec), _ptr(x),
+        _ptr(xig), _ptr(chol), _dptr(info), _ptr(ws), ws.numel(), _stream()))
+    return x, xig, info, chol, st
+
+
+@dataclass
+class XiSource:
+    """How the contraction reads xi and xi~ (xtc_xi_source): xi_prec is the element type of
+    xi; phi4 [4, n_orb, n_g] and the kept factors chol (from fit_ex(keep_chol=True)) let it
+    form xi~ per bra block when xigrad is None."""
+    phi4: torch.Tensor = None
+    chol: torch.Tensor = None
+    xi_prec: int = L.XTC_FP64
+
+    def c(self):
+        n_orb = int(self.phi4.shape[1]) if self.phi4 is not None else 0
+        return L.XiSource(int(self.xi_prec), _ptr(self.phi4), n_orb, _ptr(self.chol))
 
 
 ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_ESCALE
@@ -181,16 +210,21 @@ ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_E
 
 def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: int = ALL_CHANNELS,
                     precision: int = L.XTC_FP64, c=None, out=None, exchange=None, bra=None,
-                    noalloc=False):
+                    noalloc=False, src: XiSource = None):
     """Grid-pair kernels and xTC D terms (xtc_kernel_contract). Returns a dict of device tensors
     (u1, u3, ulap, D1, D4, field) and escale (numpy [6]) for the requested channels.
     exchange: None, or {"phi_piv": [n_orb][n_mu], "lq": [n_orb][n_q], "want": ("X2", "X3")}
     to form the xTC Terms 2-3 intermediates in the same pass (keys X2, X3 of the result).
     bra = (begin, end) restricts the bra sums (partial sums; default the whole grid).
     noalloc: call xtc_kernel_contract_noalloc (the library's static scratch instead of a
-    workspace; the outputs are still allocated here)."""
+    workspace; the outputs are still allocated here).
+    src: an XiSource for xi in FP32 and/or xi~ formed per bra block (xigrad None)."""
     hc = HostCorrelator(corr, c)
-    xi, xigrad, rho = _in(xi, "xi"), _in(xigrad, "xigrad"), _in(rho, "rho")
+    xi_dt = torch.float32 if src is not None and src.xi_prec == L.XTC_FP32 else torch.float64
+    xi, xigrad, rho = _in(xi, "xi", xi_dt), _in(xigrad, "xigrad"), _in(rho, "rho")
+    if src is not None:
+        src = XiSource(_in(src.phi4, "phi4"), _in(src.chol, "chol"), src.xi_prec)
+    srcs = src.c() if src is not None else None
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]
     n_g = grid.n_g
@@ -227,12 +261,15 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
     args = (C.byref(g), C.byref(hc.s), n_mu, _ptr(xi), _ptr(xigrad), _ptr(rho),
             piv.ctypes.data_as(L.I64), channels, precision, b0, b1, _ptr(u1), _ptr(u3), _ptr(ul),
             _ptr(d1), _ptr(d4), _ptr(fld), _dptr(esc) if channels & L.XTC_ESCALE else None,
-            C.byref(exs) if exs is not None else None)
+            C.byref(exs) if exs is not None else None, C.byref(srcs) if srcs is not None else None)
     if noalloc:
         _check("xtc_kernel_contract_noalloc", L.lib().xtc_kernel_contract_noalloc(*args, _stream()))
     else:
-        ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, n_orb, n_mu, n_q,
-                                        channels | (precision << 16)))
+        flags = channels | (precision << 16)
+        if src is not None and xigrad is None and channels & L.XTC_U1:
+            flags |= L.XTC_WS_XIGRAD_BLOCKS
+            n_orb = int(src.phi4.shape[1])
+        ws = _workspace(workspace_bytes(L.XTC_CALL_CONTRACT, n_g, n_orb, n_mu, n_q, flags))
         _check("xtc_kernel_contract", L.lib().xtc_kernel_contract(*args, _ptr(ws), ws.numel(), _stream()))
     o["escale"] = esc if channels & L.XTC_ESCALE else None
     return o

@@ -89,6 +89,7 @@ struct GemmArgs {
   const double* E = nullptr; long e_sm = 0, e_sn = 0;
   bool lower_only = false;    // skip tiles strictly above the diagonal (m < n)
   const double* sn = nullptr; // per-column scale of the product: alpha * sn[n] * (A B)[m, n]
+  const float* A32 = nullptr; // split GEMM only: A in FP32 (then A is nullptr)
 };
 
 xtc_status gemm_f64(const GemmArgs& g, hipStream_t st);

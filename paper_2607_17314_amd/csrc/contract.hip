@@ -13,6 +13,7 @@
 #include "gemm_split.hpp"
 #include "bh.hpp"
 #include "exchange.hpp"
+#include "fit.hpp"
 
 namespace xtc {
 
@@ -118,6 +119,8 @@ struct ConLayout {
   long* piv; double* G; double* rhot; double* panel; double* V; double* wt; double* H; double* e3x;
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
   void* gsplit; size_t gsplit_bytes; BHTable* bh;
+  // xi~ per bra super-block: the orbitals at the pivots, xi~ of the block, solve scratch
+  double* phimu; double* xigb; double* fitP; double* fitR;
   long bp; long rows_pad; int nsb; int nch;
   ExWork ex;   // exchange intermediates (when requested)
 };
@@ -131,7 +134,7 @@ static long default_bp(int64_t n_g) {
 // super-block covers at most bp bra points, so any such width gives the same sums up to
 // their order).
 static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision,
-                            int n_orb, int n_q, long bp) {
+                            int n_orb, int n_q, long bp, bool xig_blocks) {
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = bp;
@@ -157,30 +160,62 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
   C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   C.bh = ar.take<BHTable>(1);
+  C.phimu = C.xigb = C.fitP = C.fitR = nullptr;
+  if (xig_blocks && (channels & XTC_U1)) {
+    C.phimu = ar.take<double>(4 * (size_t)n_orb * n_mu);
+    C.xigb = ar.take<double>(3 * (size_t)n_mu * C.bp);
+    C.fitP = ar.take<double>((size_t)n_mu * C.bp);
+    C.fitR = ar.take<double>((size_t)n_mu * C.bp);
+  }
   C.ex = ExWork{};
-  if (n_orb > 0) ex_layout(ar, n_g, C.bp, n_mu, n_orb, n_q, precision, &C.ex);
+  if (n_q > 0) ex_layout(ar, n_g, C.bp, n_mu, n_orb, n_q, precision, &C.ex);
   return C;
 }
 
 size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q) {
   Arena ar(nullptr, 0);
   layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q,
-             default_bp(n_g));
+             default_bp(n_g), (flags & XTC_WS_XIGRAD_BLOCKS) != 0);
   return ar.used;
+}
+
+// rhot[g] = sum_mu G[mu] xi[mu][g] for xi stored in FP32, summed in FP64 in mu order
+__global__ __launch_bounds__(256) void k_rhot_f32(const double* __restrict__ G,
+                                                  const float* __restrict__ xi, int n_mu, long n_g,
+                                                  double* __restrict__ rhot) {
+  const long g = (long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= n_g) return;
+  double s = 0.0;
+  for (int m = 0; m < n_mu; ++m) s += G[m] * (double)xi[(long)m * n_g + g];
+  rhot[g] = s;
 }
 
 }  // namespace xtc
 
 using namespace xtc;
 
+static bool xig_on_the_fly(uint32_t channels, const double* xigrad) {
+  return (channels & XTC_U1) && !xigrad;
+}
+
 static xtc_status check_contract_args(const xtc_grid* grid, const xtc_correlator* corr,
-                                      int32_t n_mu, const double* xi, const double* xigrad,
+                                      int32_t n_mu, const void* xi, const double* xigrad,
                                       const double* rho, const int64_t* pivots,
-                                      uint32_t channels, int32_t precision) {
+                                      uint32_t channels, int32_t precision,
+                                      const xtc_exchange* ex, const xtc_xi_source* src) {
   XTC_REQUIRE(grid && corr && xi && rho && pivots, "contract: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->xyz && grid->w, "contract: empty grid");
   XTC_REQUIRE(n_mu > 0 && n_mu <= grid->n_g, "contract: bad n_mu");
-  XTC_REQUIRE(!(channels & XTC_U1) || xigrad, "contract: XTC_U1 needs xigrad");
+  XTC_REQUIRE(!xig_on_the_fly(channels, xigrad) || (src && src->phi4 && src->chol && src->n_orb > 0),
+              "contract: XTC_U1 needs xigrad, or the orbitals and kept factors in src");
+  if (src) {
+    XTC_REQUIRE(src->xi_prec == XTC_FP64 || src->xi_prec == XTC_FP32,
+                "contract: src->xi_prec must be FP64 or FP32");
+    if (src->xi_prec == XTC_FP32 && (precision != XTC_SPLIT_F16 || ex)) {
+      set_error("contract: FP32 xi is read by the split path without exchange outputs only");
+      return XTC_ERR_UNSUPPORTED;
+    }
+  }
   XTC_REQUIRE((channels & ~127u) == 0, "contract: unknown channel bits");
   XTC_REQUIRE(precision == XTC_FP64 || precision == XTC_SPLIT_F16, "contract: bad precision");
   XTC_REQUIRE(corr->n_terms > 0 && corr->mno && corr->c && corr->d > 0.0,
@@ -207,13 +242,18 @@ __global__ void k_fill_zero(double* __restrict__ x, long n) {
 // The body of xtc_kernel_contract and xtc_kernel_contract_noalloc: scratch is ws (its
 // bytes), the bra super-blocks are bp points wide (a multiple of 64).
 static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
-                                const double* xi, const double* xigrad, const double* rho,
+                                const void* xi_any, const double* xigrad, const double* rho,
                                 const int64_t* pivots, uint32_t channels, int32_t precision,
                                 int64_t bra_begin, int64_t bra_end, double* u1, double* u3,
                                 double* ulap, double* D1, double* D4, double* field,
-                                double* escale, const xtc_exchange* ex, void* ws,
-                                size_t ws_bytes, long bp, void* stream) {
-  XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+                                double* escale, const xtc_exchange* ex, const xtc_xi_source* src,
+                                void* ws, size_t ws_bytes, long bp, void* stream) {
+  XTC_TRY(check_contract_args(grid, corr, n_mu, xi_any, xigrad, rho, pivots, channels, precision,
+                              ex, src));
+  // xi in FP64 (xi) or FP32 (xi32, split path only); xi~ stored or formed per block
+  const float* xi32 = (src && src->xi_prec == XTC_FP32) ? (const float*)xi_any : nullptr;
+  const double* xi = xi32 ? nullptr : (const double*)xi_any;
+  const bool fly = xig_on_the_fly(channels, xigrad);
   XTC_REQUIRE(bra_begin >= 0 && bra_begin < bra_end && bra_end <= grid->n_g,
               "contract: bra range must be non-empty and inside the grid");
   if (ex) XTC_TRY(check_exchange_args(ex, n_mu));
@@ -232,8 +272,8 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   hipStream_t st = as_stream(stream);
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
-  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, ex ? ex->n_orb : 0,
-                           ex ? ex->n_q : 0, bp);
+  const int n_orb_l = ex ? ex->n_orb : (fly ? src->n_orb : 0);
+  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, n_orb_l, ex ? ex->n_q : 0, bp, fly);
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_kernel_contract"));
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
@@ -242,16 +282,24 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
                      (const long*)C.piv, n_mu, C.G);
   XTC_CHECK_LAUNCH();
-  {
-    GemmArgs g{};   // ISDF density rhot = G^T xi
+  if (xi32) {   // ISDF density rhot = G^T xi
+    hipLaunchKernelGGL(k_rhot_f32, dim3(cdiv(n_g, 256)), dim3(256), 0, st, (const double*)C.G,
+                       xi32, n_mu, n_g, C.rhot);
+    XTC_CHECK_LAUNCH();
+  } else {
+    GemmArgs g{};
     g.M = 1; g.N = n_g; g.K = n_mu;
     g.A = C.G; g.a_sm = 1; g.a_sk = 1;
     g.B = xi; g.b_sk = n_g; g.b_sn = 1;
     g.C = C.rhot; g.c_sm = n_g; g.c_sn = 1;
     XTC_TRY(gemm_f64(g, st));
   }
+  if (fly)   // the orbitals and their gradients at the pivots, for xi~ per block
+    XTC_TRY(gather_pivot_rows(src->phi4, n_g, 4 * src->n_orb, (const long*)C.piv, n_mu, C.phimu,
+                              st));
   Stage1Args s1{grid->xyz, grid->w, xi, rho, C.rhot, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp,
                 C.nch};
+  s1.xi32 = xi32;
   if (bh) s1.bh = C.bh;
   if (precision == XTC_SPLIT_F16) {
     size_t tk = timing_begin(TM_SPLIT_PREP, st);
@@ -277,10 +325,11 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
     size_t tk2 = timing_begin(TM_STAGE2, st);
     const double beta = sb == 0 ? 0.0 : 1.0;
     auto nt = [&](const double* A, long a_sm, const double* s, const double* B, double* out,
-                  double bet) {
+                  double bet, const float* A32 = nullptr) {
       GemmArgs g{};
       g.M = n_mu; g.N = n_mu; g.K = bn;
       g.A = A; g.a_sm = a_sm; g.a_sk = 1;
+      g.A32 = A32;
       g.s = s;
       g.B = B; g.b_sk = 1; g.b_sn = C.bp;
       g.C = out; g.c_sm = n_mu; g.c_sn = 1;
@@ -288,15 +337,30 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
       return precision == XTC_SPLIT_F16 ? gemm_split_nt(g, C.gsplit, C.gsplit_bytes, st)
                                         : gemm_f64(g, st);
     };
+    // (w xi) T^T for a panel channel, xi in FP64 or FP32
+    auto nt_xi = [&](const double* B, double* out, double bet) {
+      return xi32 ? nt(nullptr, n_g, grid->w + b0, B, out, bet, xi32 + b0)
+                  : nt(xi + b0, n_g, grid->w + b0, B, out, bet);
+    };
     const double* wb = grid->w + b0;
     if (channels & XTC_U1)
-      for (int c = 0; c < 3; ++c)
-        XTC_TRY(nt(xigrad + (long)c * n_mu * n_g + b0, n_g, wb, C.panel + (long)c * C.rows_pad * C.bp,
-                   u1 + (long)c * n_mu * n_mu, beta));
-    if (channels & XTC_U3)
-      XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 3L * C.rows_pad * C.bp, u3, beta));
-    if (channels & XTC_ULAP)
-      XTC_TRY(nt(xi + b0, n_g, wb, C.panel + 4L * C.rows_pad * C.bp, ulap, beta));
+      for (int c = 0; c < 3; ++c) {
+        const double* xg = xigrad + (long)c * n_mu * n_g + b0;
+        long ld = n_g;
+        if (fly) {   // xi~^c of this block's columns from the kept factor of system 1 + c
+          const size_t sysd = XTC_CHOL_SYSTEM_DOUBLES(n_mu);
+          double* out = C.xigb + (long)c * n_mu * C.bp;
+          XTC_TRY(fit_columns(src->phi4, n_g, src->n_orb, C.phimu, n_mu, 1 + c,
+                              src->chol + (1 + c) * sysd, b0, bn, out, C.bp, C.fitP, C.fitR, C.bp,
+                              st));
+          xg = out;
+          ld = C.bp;
+        }
+        XTC_TRY(nt(xg, ld, wb, C.panel + (long)c * C.rows_pad * C.bp, u1 + (long)c * n_mu * n_mu,
+                   beta));
+      }
+    if (channels & XTC_U3) XTC_TRY(nt_xi(C.panel + 3L * C.rows_pad * C.bp, u3, beta));
+    if (channels & XTC_ULAP) XTC_TRY(nt_xi(C.panel + 4L * C.rows_pad * C.bp, ulap, beta));
     hipLaunchKernelGGL(k_point_vectors, dim3(cdiv(bn, 256)), dim3(256), 0, st,
                        (const double*)C.rhot, grid->w, rho, n_g, n_mu, b0, bn,
                        (const double*)C.panel, C.rows_pad, C.bp, need_h ? 1 : 0, C.wt, C.H, C.e3x,
@@ -312,7 +376,7 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
                          (const double*)C.panel, C.rows_pad, C.bp, n_mu, bn, (const double*)C.H,
                          C.V);
       XTC_CHECK_LAUNCH();
-      XTC_TRY(nt(xi + b0, n_g, wb, C.V, D1, beta));
+      XTC_TRY(nt_xi(C.V, D1, beta));
     }
     XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 4 * sb, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 4 * sb + 1, C.red, st));
@@ -350,16 +414,17 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
 
 
 extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr,
-                                          int32_t n_mu, const double* xi, const double* xigrad,
+                                          int32_t n_mu, const void* xi, const double* xigrad,
                                           const double* rho, const int64_t* pivots,
                                           uint32_t channels, int32_t precision, int64_t bra_begin,
                                           int64_t bra_end, double* u1,
                                           double* u3, double* ulap, double* D1, double* D4,
                                           double* field, double* escale, const xtc_exchange* ex,
-                                          void* ws, size_t ws_bytes, void* stream) {
+                                          const xtc_xi_source* src, void* ws, size_t ws_bytes,
+                                          void* stream) {
   XTC_REQUIRE(grid, "contract: null argument");
   return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
-                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, ws, ws_bytes,
+                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, src, ws, ws_bytes,
                        default_bp(grid->n_g), stream);
 }
 
@@ -393,17 +458,20 @@ static xtc_status scratch_address(void** out) {
 }
 
 extern "C" xtc_status xtc_kernel_contract_noalloc(
-    const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu, const double* xi,
+    const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu, const void* xi,
     const double* xigrad, const double* rho, const int64_t* pivots, uint32_t channels,
     int32_t precision, int64_t bra_begin, int64_t bra_end, double* u1, double* u3, double* ulap,
-    double* D1, double* D4, double* field, double* escale, const xtc_exchange* ex, void* stream) {
-  XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision));
+    double* D1, double* D4, double* field, double* escale, const xtc_exchange* ex,
+    const xtc_xi_source* src, void* stream) {
+  XTC_TRY(check_contract_args(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, ex,
+                              src));
   if (ex) XTC_TRY(check_exchange_args(ex, n_mu));
   // the widest super-block (a multiple of 64, at most the regular call's) whose scratch fits
-  const int n_orb = ex ? ex->n_orb : 0, n_q = ex ? ex->n_q : 0;
+  const bool fly = xig_on_the_fly(channels, xigrad);
+  const int n_orb = ex ? ex->n_orb : (fly ? src->n_orb : 0), n_q = ex ? ex->n_q : 0;
   auto need = [&](long bp) {
     Arena ar(nullptr, 0);
-    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp);
+    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp, fly);
     return ar.used;
   };
   long bp = default_bp(grid->n_g);
@@ -418,6 +486,6 @@ extern "C" xtc_status xtc_kernel_contract_noalloc(
   void* ptr = nullptr;
   XTC_TRY(scratch_address(&ptr));
   return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
-                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, ptr,
+                       bra_end, u1, u3, ulap, D1, D4, field, escale, ex, src, ptr,
                        (size_t)XTC_NOALLOC_SCRATCH_BYTES, bp, stream);
 }

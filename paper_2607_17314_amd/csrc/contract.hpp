@@ -33,6 +33,7 @@ struct Stage1Args {
   int nch;
   const BHTable* bh = nullptr;   // device table of a BH correlator (FP64 path), or nullptr for EE
   bool rho_rows = true;          // false: the density rows n_mu, n_mu + 1 may be left unset
+  const float* xi32 = nullptr;   // split path: xi in FP32 (then xi is nullptr)
 };
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);

@@ -12,6 +12,7 @@
 // The fit is column-separable in g, so the grid is processed in chunks and the
 // workspace does not grow with n_g beyond one chunk.
 #include "common.hpp"
+#include "fit.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
 
@@ -212,65 +213,105 @@ static xtc_status cholesky(FitLayout& F, long n, hipStream_t st, int* failed) {
   return XTC_OK;
 }
 
-// Solve A X = R for a chunk (R: [n][cn], ld = chunk) with the factor in F.A;
-// X goes to out (row stride ldo). Also records the residual sums of the chunk.
-static xtc_status solve_chunk(FitLayout& F, long n, long cn, double* out, long ldo,
+// A lower Cholesky factor L (row-major n x n, lower triangle used) with the inverses of
+// its NB x NB diagonal blocks, as the blocked solves below use it.
+struct Factor {
+  const double* L; const double* linv; long n; int nblk;
+};
+
+// Forward substitution L Y = R for the columns of a chunk (R: [n][cn], row stride ldr, used
+// as scratch); Y goes to out (row stride ldo).
+static xtc_status solve_chunk(const Factor& f, long cn, double* R, long ldr, double* out, long ldo,
                               hipStream_t st) {
+  const long n = f.n;
   // forward: Y_i = Linv_ii (R_i - L_i,<i Y_<i), Y stored in out
-  for (int b = 0; b < F.nblk; ++b) {
+  for (int b = 0; b < f.nblk; ++b) {
     long i0 = (long)b * NB;
     long nb = (n - i0) < NB ? (n - i0) : NB;
     if (i0 > 0) {
       GemmArgs g{};
       g.M = nb; g.N = cn; g.K = i0;
-      g.A = F.A + i0 * n; g.a_sm = n; g.a_sk = 1;
+      g.A = f.L + i0 * n; g.a_sm = n; g.a_sk = 1;
       g.B = out; g.b_sk = ldo; g.b_sn = 1;
-      g.C = F.R + i0 * F.chunk; g.c_sm = F.chunk; g.c_sn = 1;
+      g.C = R + i0 * ldr; g.c_sm = ldr; g.c_sn = 1;
       g.alpha = -1.0; g.beta = 1.0;
       XTC_TRY(gemm_f64(g, st));
     }
     GemmArgs d{};
     d.M = nb; d.N = cn; d.K = nb;
-    d.A = F.linv + (long)b * NB * NB; d.a_sm = NB; d.a_sk = 1;
-    d.B = F.R + i0 * F.chunk; d.b_sk = F.chunk; d.b_sn = 1;
+    d.A = f.linv + (long)b * NB * NB; d.a_sm = NB; d.a_sk = 1;
+    d.B = R + i0 * ldr; d.b_sk = ldr; d.b_sn = 1;
     d.C = out + i0 * ldo; d.c_sm = ldo; d.c_sn = 1;
     XTC_TRY(gemm_f64(d, st));
   }
   return XTC_OK;
 }
 
-static xtc_status back_chunk(FitLayout& F, long n, long cn, double* out, long ldo,
+// Back substitution L^T X = Y in place in out (row stride ldo); R [n][cn] (row stride ldr)
+// is scratch.
+static xtc_status back_chunk(const Factor& f, long cn, double* R, long ldr, double* out, long ldo,
                              hipStream_t st) {
-  for (int b = F.nblk - 1; b >= 0; --b) {
+  const long n = f.n;
+  for (int b = f.nblk - 1; b >= 0; --b) {
     long i0 = (long)b * NB;
     long nb = (n - i0) < NB ? (n - i0) : NB;
     long i1 = i0 + nb;
     if (i1 < n) {
       GemmArgs g{};   // R_i = Y_i - L_{>i,i}^T X_{>i}
       g.M = nb; g.N = cn; g.K = n - i1;
-      g.A = F.A + i1 * n + i0; g.a_sm = 1; g.a_sk = n;
+      g.A = f.L + i1 * n + i0; g.a_sm = 1; g.a_sk = n;
       g.B = out + i1 * ldo; g.b_sk = ldo; g.b_sn = 1;
-      g.C = F.R + i0 * F.chunk; g.c_sm = F.chunk; g.c_sn = 1;
+      g.C = R + i0 * ldr; g.c_sm = ldr; g.c_sn = 1;
       g.alpha = -1.0; g.beta = 1.0;   // R_i holds a copy of Y_i (below)
       hipLaunchKernelGGL(k_copy_rows, dim3(cdiv(nb * cn, 256)), dim3(256), 0, st,
-                         (const double*)(out + i0 * ldo), ldo, F.R + i0 * F.chunk, F.chunk,
-                         (int)nb, cn);
+                         (const double*)(out + i0 * ldo), ldo, R + i0 * ldr, ldr, (int)nb, cn);
       XTC_CHECK_LAUNCH();
       XTC_TRY(gemm_f64(g, st));
     } else {
       hipLaunchKernelGGL(k_copy_rows, dim3(cdiv(nb * cn, 256)), dim3(256), 0, st,
-                         (const double*)(out + i0 * ldo), ldo, F.R + i0 * F.chunk, F.chunk,
-                         (int)nb, cn);
+                         (const double*)(out + i0 * ldo), ldo, R + i0 * ldr, ldr, (int)nb, cn);
       XTC_CHECK_LAUNCH();
     }
     GemmArgs d{};   // X_i = Linv_ii^T R_i
     d.M = nb; d.N = cn; d.K = nb;
-    d.A = F.linv + (long)b * NB * NB; d.a_sm = 1; d.a_sk = NB;
-    d.B = F.R + i0 * F.chunk; d.b_sk = F.chunk; d.b_sn = 1;
+    d.A = f.linv + (long)b * NB * NB; d.a_sm = 1; d.a_sk = NB;
+    d.B = R + i0 * ldr; d.b_sk = ldr; d.b_sn = 1;
     d.C = out + i0 * ldo; d.c_sm = ldo; d.c_sn = 1;
     XTC_TRY(gemm_f64(d, st));
   }
   return XTC_OK;
+}
+
+static Factor factor_of(const FitLayout& F, long n) { return Factor{F.A, F.linv, n, F.nblk}; }
+
+// The right-hand side of one system for grid points [g0, g0 + cn) into R (row stride ldr),
+// with P (row stride ldr) as scratch: B = P o P (scalar, comp -1) or (dPhi_mu^T dPhi)_c o P,
+// P = Phi_mu^T Phi. phimu: [4][n_orb][n_mu], the orbitals and gradients at the pivots.
+static xtc_status rhs_chunk(const double* phi4, long n_g, int n_orb, const double* phimu, long n,
+                            int comp, long g0, long cn, double* P, double* R, long ldr,
+                            hipStream_t st) {
+  GemmArgs p{};   // P = Phi_mu^T Phi (chunk)
+  p.M = n; p.N = cn; p.K = n_orb;
+  p.A = phimu; p.a_sm = 1; p.a_sk = n;
+  p.B = phi4 + g0; p.b_sk = n_g; p.b_sn = 1;
+  p.C = P; p.c_sm = ldr; p.c_sn = 1;
+  XTC_TRY(gemm_f64(p, st));
+  GemmArgs r{};   // B = P o P or (dPhi_mu^T dPhi)_c o P
+  r.M = n; r.N = cn; r.K = n_orb;
+  const double* ph = phimu + (long)(comp < 0 ? 0 : (1 + comp)) * n_orb * n;
+  r.A = ph; r.a_sm = 1; r.a_sk = n;
+  r.B = phi4 + (long)(comp < 0 ? 0 : (1 + comp)) * n_orb * n_g + g0; r.b_sk = n_g; r.b_sn = 1;
+  r.C = R; r.c_sm = ldr; r.c_sn = 1;
+  r.epi = EPI_MUL_E; r.E = P; r.e_sm = ldr; r.e_sn = 1;
+  return gemm_f64(r, st);
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, long lds, float* __restrict__ dst,
+                         long ldd, long rows, long cols) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= rows * cols) return;
+  const long r = t / cols, c = t % cols;
+  dst[r * ldd + c] = (float)src[r * lds + c];
 }
 
 // Cholesky of F.A with the adaptive Tikhonov retry; F.Asave receives the unshifted A.
@@ -338,7 +379,7 @@ xtc_status fit_scalar_residual(const double* phi4, const xtc_grid* grid, int n_o
     r.C = F.R; r.c_sm = F.chunk; r.c_sn = 1;
     r.epi = EPI_SQUARE;
     XTC_TRY(gemm_f64(r, st));
-    XTC_TRY(solve_chunk(F, n, cn, F.P, F.chunk, st));   // Y = L^-1 B into F.P
+    XTC_TRY(solve_chunk(factor_of(F, n), cn, F.R, F.chunk, F.P, F.chunk, st));   // Y = L^-1 B into F.P
     hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g, n_orb, -1,
                        g0, cn, (const double*)F.P, F.chunk, n_mu, F.rtmp, F.mtmp);
     XTC_CHECK_LAUNCH();
@@ -364,20 +405,54 @@ size_t ws_fit_residual(int64_t n_g, int n_orb, int n_mu) {
   return ar.used;
 }
 
+// Copies the factor of one system (L, then the inverted diagonal blocks) to dst.
+static xtc_status keep_factor(const FitLayout& F, long n, double* dst, hipStream_t st) {
+  XTC_HIP(hipMemcpyAsync(dst, F.A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+  XTC_HIP(hipMemcpyAsync(dst + n * n, F.linv, sizeof(double) * F.nblk * NB * NB,
+                         hipMemcpyDeviceToDevice, st));
+  return XTC_OK;
+}
+
+// xi (sys 0) or xi~^c (sys 1 + c) at grid points [g0, g0 + cn) from a factor kept by
+// isdf_fit (XTC_FIT_KEEP_CHOL): the same right-hand-side GEMMs and blocked solves as the
+// fit, so the columns equal the fit's bit for bit. phimu: [4][n_orb][n_mu] at the pivots;
+// out [n_mu][cn] (row stride ldo); P, R: scratch [n_mu][cn] (row stride ldr).
+xtc_status fit_columns(const double* phi4, long n_g, int n_orb, const double* phimu, int n_mu,
+                       int sys, const double* chol_sys, long g0, long cn, double* out, long ldo,
+                       double* P, double* R, long ldr, hipStream_t st) {
+  const long n = n_mu;
+  const Factor f{chol_sys, chol_sys + n * n, n, (int)cdiv(n, NB)};
+  XTC_TRY(rhs_chunk(phi4, n_g, n_orb, phimu, n, sys - 1, g0, cn, P, R, ldr, st));
+  XTC_TRY(solve_chunk(f, cn, R, ldr, out, ldo, st));
+  return back_chunk(f, cn, R, ldr, out, ldo, st);
+}
+
+xtc_status gather_pivot_rows(const double* phi4, long n_g, int rows, const long* piv, int n_mu,
+                             double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_piv, dim3(cdiv((long)rows * n_mu, 256)), dim3(256), 0, st, phi4, n_g,
+                     rows, piv, n_mu, out);
+  XTC_CHECK_LAUNCH();
+  return XTC_OK;
+}
+
 }  // namespace xtc
 
 using namespace xtc;
 
 extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
-                               const int64_t* pivots, int32_t n_mu, uint32_t what, double* xi,
-                               double* xigrad, double* info, void* ws, size_t ws_bytes,
-                               void* stream) {
+                               const int64_t* pivots, int32_t n_mu, uint32_t what,
+                               int32_t xi_prec, void* xi, double* xigrad, double* chol,
+                               double* info, void* ws, size_t ws_bytes, void* stream) {
   XTC_REQUIRE(phi4 && grid && pivots, "isdf_fit: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->w, "isdf_fit: empty grid");
   XTC_REQUIRE(n_orb > 0 && n_mu > 0 && n_mu <= grid->n_g, "isdf_fit: bad sizes");
   XTC_REQUIRE(!(what & XTC_FIT_XI) || xi, "isdf_fit: xi requested but NULL");
   XTC_REQUIRE(!(what & XTC_FIT_XIGRAD) || xigrad, "isdf_fit: xigrad requested but NULL");
-  XTC_REQUIRE(what & (XTC_FIT_XI | XTC_FIT_XIGRAD), "isdf_fit: nothing requested");
+  XTC_REQUIRE(!(what & XTC_FIT_KEEP_CHOL) || chol, "isdf_fit: factors requested but chol NULL");
+  XTC_REQUIRE(what & (XTC_FIT_XI | XTC_FIT_XIGRAD | XTC_FIT_KEEP_CHOL),
+              "isdf_fit: nothing requested");
+  XTC_REQUIRE((what & ~7u) == 0, "isdf_fit: unknown bits in what");
+  XTC_REQUIRE(xi_prec == XTC_FP64 || xi_prec == XTC_FP32, "isdf_fit: xi_prec must be FP64 or FP32");
   const long n_g = grid->n_g;
   for (int m = 0; m < n_mu; ++m)
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < n_g, "isdf_fit: pivot index out of range");
@@ -392,6 +467,7 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
                      n_g, 4 * n_orb, (const long*)F.piv, n_mu, F.phimu);
   XTC_CHECK_LAUNCH();
   const long n = n_mu;
+  const size_t sys_doubles = XTC_CHOL_SYSTEM_DOUBLES(n_mu);
   // G = Phi_mu^T Phi_mu
   {
     GemmArgs g{};
@@ -403,11 +479,11 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
   }
   double jit[4] = {-1, -1, -1, -1}, rel[4] = {0, 0, 0, 0};
   bool any_jitter = false;
+  const bool keep = (what & XTC_FIT_KEEP_CHOL) != 0;
   for (int sys = 0; sys < 4; ++sys) {
     const int comp = sys - 1;   // -1 scalar, 0..2 gradient component
-    if (sys == 0 && !(what & XTC_FIT_XI)) continue;
-    if (sys > 0 && !(what & XTC_FIT_XIGRAD)) continue;
-    double* out = sys == 0 ? xi : xigrad + (long)comp * n * n_g;
+    const bool solve = sys == 0 ? (what & XTC_FIT_XI) != 0 : (what & XTC_FIT_XIGRAD) != 0;
+    if (!solve && !keep) continue;
     // Gram of this system
     {
       GemmArgs g{};
@@ -425,32 +501,28 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
       jit[sys] = k;
       any_jitter = true;
     }
-    // chunks over the grid
+    if (keep) XTC_TRY(keep_factor(F, n, chol + sys * sys_doubles, st));
+    if (!solve) continue;
+    // the FP64 solution of a chunk goes straight into the output, or (FP32 xi) into P first
+    const bool f32 = sys == 0 && xi_prec == XTC_FP32;
     for (int c = 0; c < F.nchunks; ++c) {
       long g0 = (long)c * F.chunk;
       long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
-      GemmArgs p{};   // P = Phi_mu^T Phi (chunk)
-      p.M = n; p.N = cn; p.K = n_orb;
-      p.A = F.phimu; p.a_sm = 1; p.a_sk = n;
-      p.B = phi4 + g0; p.b_sk = n_g; p.b_sn = 1;
-      p.C = F.P; p.c_sm = F.chunk; p.c_sn = 1;
-      XTC_TRY(gemm_f64(p, st));
-      GemmArgs r{};   // B = P o P or (dPhi_mu^T dPhi)_c o P
-      r.M = n; r.N = cn; r.K = n_orb;
-      const double* ph = F.phimu + (long)(sys == 0 ? 0 : (1 + comp)) * n_orb * n;
-      r.A = ph; r.a_sm = 1; r.a_sk = n;
-      r.B = phi4 + (long)(sys == 0 ? 0 : (1 + comp)) * n_orb * n_g + g0; r.b_sk = n_g; r.b_sn = 1;
-      r.C = F.R; r.c_sm = F.chunk; r.c_sn = 1;
-      r.epi = EPI_MUL_E; r.E = F.P; r.e_sm = F.chunk; r.e_sn = 1;
-      XTC_TRY(gemm_f64(r, st));
-      XTC_TRY(solve_chunk(F, n, cn, out + g0, n_g, st));
+      double* out = f32 ? F.P : (sys == 0 ? (double*)xi : xigrad + (long)comp * n * n_g) + g0;
+      const long ldo = f32 ? F.chunk : n_g;
+      XTC_TRY(rhs_chunk(phi4, n_g, n_orb, F.phimu, n, comp, g0, cn, F.P, F.R, F.chunk, st));
+      XTC_TRY(solve_chunk(factor_of(F, n), cn, F.R, F.chunk, out, ldo, st));
       hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g,
-                         n_orb, comp, g0, cn, (const double*)(out + g0), n_g, n_mu, F.rtmp,
-                         F.mtmp);
+                         n_orb, comp, g0, cn, (const double*)out, ldo, n_mu, F.rtmp, F.mtmp);
       XTC_CHECK_LAUNCH();
       XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
       XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
-      XTC_TRY(back_chunk(F, n, cn, out + g0, n_g, st));
+      XTC_TRY(back_chunk(factor_of(F, n), cn, F.R, F.chunk, out, ldo, st));
+      if (f32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n * cn, 256)), dim3(256), 0, st, (const double*)out,
+                           ldo, (float*)xi + g0, n_g, n, cn);
+        XTC_CHECK_LAUNCH();
+      }
     }
     std::vector<double> hs(2 * F.nchunks);
     XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks,

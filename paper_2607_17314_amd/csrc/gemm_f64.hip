@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 }
 
 xtc_status gemm_f64(const GemmArgs& g, hipStream_t st) {
+  XTC_REQUIRE(g.A32 == nullptr, "gemm_f64: FP32 operands are for the split GEMM only");
   if (g.M <= 0 || g.N <= 0) return XTC_OK;
   if (g.K <= 0) {
     set_error("gemm_f64: K must be positive");

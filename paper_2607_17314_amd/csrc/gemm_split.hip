@@ -49,9 +49,11 @@ size_t gemm_split_scratch_bytes(long M, long N, long K) {
   return gemm_split_seg_scratch_bytes(M, N, K, 1);
 }
 
-// One operand over its segments: value(r, k) = X[seg][r sm + k sk] s[seg][k].
+// One operand over its segments: value(r, k) = X[seg][r sm + k sk] s[seg][k], X in FP64
+// or (Xf set) FP32.
 struct SegOperand {
   const double* X[SPLIT_MAXSEG];
+  const float* Xf[SPLIT_MAXSEG];
   const double* s[SPLIT_MAXSEG];
   long sm, sk;
   long K;
@@ -59,7 +61,8 @@ struct SegOperand {
 };
 
 __device__ inline double seg_value(const SegOperand& o, int seg, long r, long k) {
-  double v = o.X[seg][r * o.sm + k * o.sk];
+  const long i = r * o.sm + k * o.sk;
+  double v = o.Xf[seg] ? (double)o.Xf[seg][i] : o.X[seg][i];
   if (o.s[seg]) v *= o.s[seg][k];
   return v;
 }
@@ -262,12 +265,13 @@ xtc_status gemm_split_seg(long M, long N, long K, const SplitSeg* seg, int nseg,
   XTC_REQUIRE(a.sk == 1 || a.sm == 1, "split GEMM: A needs k or m contiguous");
   XTC_REQUIRE(b.sk == 1, "split GEMM: B needs k contiguous");
   for (int i = 0; i < nseg; ++i) {
-    XTC_REQUIRE(seg[i].A && seg[i].B, "split GEMM: null segment operand");
+    XTC_REQUIRE((seg[i].A != nullptr) != (seg[i].Af != nullptr) && seg[i].B,
+                "split GEMM: null segment operand");
     XTC_REQUIRE(seg[i].a_sm == a.sm && seg[i].a_sk == a.sk && seg[i].b_sn == b.sm &&
                     seg[i].b_sk == b.sk,
                 "split GEMM: segments need one layout");
-    a.X[i] = seg[i].A; a.s[i] = seg[i].s;
-    b.X[i] = seg[i].B; b.s[i] = nullptr;
+    a.X[i] = seg[i].A; a.Xf[i] = seg[i].Af; a.s[i] = seg[i].s;
+    b.X[i] = seg[i].B; b.Xf[i] = nullptr; b.s[i] = nullptr;
   }
   if (M <= 0 || N <= 0) return XTC_OK;
   const long Mp = round_up(M, ST), Np = round_up(N, ST);
@@ -294,7 +298,7 @@ xtc_status gemm_split_nt(const GemmArgs& g, void* scratch, size_t bytes, hipStre
   XTC_REQUIRE(g.alpha == 1.0 && (g.beta == 0.0 || g.beta == 1.0) && g.D == nullptr &&
                   g.epi == EPI_NONE && g.sn == nullptr && !g.lower_only,
               "split GEMM: only C = A s B^T or C += A s B^T");
-  SplitSeg sg{g.A, g.a_sm, g.a_sk, g.s, g.B, g.b_sn, g.b_sk};
+  SplitSeg sg{g.A, g.a_sm, g.a_sk, g.s, g.B, g.b_sn, g.b_sk, g.A32};
   return gemm_split_seg(g.M, g.N, g.K, &sg, 1, g.C, g.c_sm, g.beta == 1.0, scratch, bytes, st);
 }
 

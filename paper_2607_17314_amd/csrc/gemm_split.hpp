@@ -14,6 +14,7 @@ struct SplitSeg {
   const double* A; long a_sm, a_sk;
   const double* s;
   const double* B; long b_sn, b_sk;
+  const float* Af = nullptr;   // A in FP32 instead (then A is nullptr)
 };
 
 // C (+)= sum_seg A_seg diag(s_seg) B_seg^T over nseg (1..4) segments of K each, one

@@ -85,23 +85,23 @@ size_t rho_row_scratch_bytes(long bp);
 
 // --- preparation --------------------------------------------------------------
 
-__device__ __forceinline__ double a_value(const double* __restrict__ w, const double* __restrict__ xi,
-                                          const double* __restrict__ rho, long n_g, int n_mu,
-                                          long row, long g) {
-  (void)rho;
+// w xi in FP64 from xi stored in FP64 or FP32 (T)
+template <class T>
+__device__ __forceinline__ double a_value(const double* __restrict__ w, const T* __restrict__ xi,
+                                          long n_g, int n_mu, long row, long g) {
   if (g >= n_g || row >= n_mu) return 0.0;
-  return w[g] * xi[row * n_g + g];
+  return w[g] * (double)xi[row * n_g + g];
 }
 
 // one block per row: exponent s with max |A_row| 2^s in [2^14, 2^15)
+template <class T>
 __global__ __launch_bounds__(256) void k_row_scale(const double* __restrict__ w,
-                                                   const double* __restrict__ xi,
-                                                   const double* __restrict__ rho, long n_g,
+                                                   const T* __restrict__ xi, long n_g,
                                                    int n_mu, int* __restrict__ sA) {
   __shared__ double red[256];
   const long row = blockIdx.x;
   double m = 0.0;
-  for (long g = threadIdx.x; g < n_g; g += 256) m = fmax(m, fabs(a_value(w, xi, rho, n_g, n_mu, row, g)));
+  for (long g = threadIdx.x; g < n_g; g += 256) m = fmax(m, fabs(a_value(w, xi, n_g, n_mu, row, g)));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(256) void k_row_scale(const double* __restrict__ w,
 }
 
 // one thread per (row block, k-step, lane): 8 consecutive ket values, split
+template <class T>
 __global__ __launch_bounds__(256) void k_split_A(const double* __restrict__ w,
-                                                 const double* __restrict__ xi,
-                                                 const double* __restrict__ rho, long n_g,
+                                                 const T* __restrict__ xi, long n_g,
                                                  int n_mu, const int* __restrict__ sA, long nks,
                                                  long nrb, h8* __restrict__ At) {
   const long t = (long)blockIdx.x * 256 + threadIdx.x;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_split_A(const double* __restrict__ w,
   h8 hi, lo;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const double v = a_value(w, xi, rho, n_g, n_mu, row, k0 + e) * sc;
+    const double v = a_value(w, xi, n_g, n_mu, row, k0 + e) * sc;
     const float vf = (float)v;
     const _Float16 h = (_Float16)vf;
     hi[e] = h;
@@ -164,12 +164,20 @@ __global__ __launch_bounds__(256) void k_split_coords(const double* __restrict__
 xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st) {
   SplitLayout S = split_layout(scratch, a.n_g, a.n_mu);
   XTC_HIP(hipMemsetAsync(S.sA, 0, sizeof(int) * S.rows_pad, st));
-  hipLaunchKernelGGL(k_row_scale, dim3(a.n_mu), dim3(256), 0, st, a.w, a.xi, a.rho, a.n_g,
-                     a.n_mu, S.sA);
-  XTC_CHECK_LAUNCH();
   const long nrb = S.rows_pad / 32;
-  hipLaunchKernelGGL(k_split_A, dim3(cdiv(nrb * S.nks * 64, 256)), dim3(256), 0, st, a.w, a.xi,
-                     a.rho, a.n_g, a.n_mu, (const int*)S.sA, S.nks, nrb, S.A);
+  if (a.xi32) {
+    hipLaunchKernelGGL(k_row_scale<float>, dim3(a.n_mu), dim3(256), 0, st, a.w, a.xi32, a.n_g,
+                       a.n_mu, S.sA);
+    XTC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_split_A<float>, dim3(cdiv(nrb * S.nks * 64, 256)), dim3(256), 0, st, a.w,
+                       a.xi32, a.n_g, a.n_mu, (const int*)S.sA, S.nks, nrb, S.A);
+  } else {
+    hipLaunchKernelGGL(k_row_scale<double>, dim3(a.n_mu), dim3(256), 0, st, a.w, a.xi, a.n_g,
+                       a.n_mu, S.sA);
+    XTC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_split_A<double>, dim3(cdiv(nrb * S.nks * 64, 256)), dim3(256), 0, st, a.w,
+                       a.xi, a.n_g, a.n_mu, (const int*)S.sA, S.nks, nrb, S.A);
+  }
   XTC_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_split_coords, dim3(cdiv(S.n_g_pad, 256)), dim3(256), 0, st, a.xyz, a.n_g,
                      S.n_g_pad, S.kc);

@@ -46,7 +46,8 @@ def test_host_argument_checks_return_invalid_arg():
     g = L.Grid(0, None, None)
     assert lib.xtc_eval_orbitals(None, None, None, 1, 0, None, None, None, 0, None) == -1
     assert b"null" in lib.xtc_last_error()
-    assert lib.isdf_fit(None, C.byref(g), 1, None, 1, 1, None, None, None, None, 0, None) == -1
+    assert lib.isdf_fit(None, C.byref(g), 1, None, 1, 1, 0, None, None, None, None, None, 0,
+                        None) == -1
     piv = np.zeros(4, np.int64)
     xyz = C.c_void_p(8)
     g2 = L.Grid(10, xyz, xyz)
@@ -58,24 +59,24 @@ def test_host_argument_checks_return_invalid_arg():
     piv[:] = [0, 1, 2, 99]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, None, None, None, None, None,
-                                 None, None, None, 0, None)
+                                 None, None, None, None, 0, None)
     assert st == -1 and b"pivot" in lib.xtc_last_error()
     # unknown precision
     piv[:] = [0, 1, 2, 3]
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 7, 0, 10, xyz, None, None, None, None, None,
-                                 None, None, None, 0, None)
+                                 None, None, None, None, 0, None)
     assert st == -1
     # a too-small workspace is reported as such, not as a crash
     st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, xyz, None, None, None, None,
-                                 None, None, None, 0, None)
+                                 None, None, None, None, 0, None)
     assert st == -4
     # an empty or out-of-grid bra range is rejected
     for b0, b1 in ((5, 5), (0, 11), (-1, 4)):
         st = lib.xtc_kernel_contract(C.byref(g2), C.byref(corr), 4, xyz, xyz, xyz,
                                      piv.ctypes.data_as(L.I64), 2, 0, b0, b1, None, xyz, None, None,
-                                     None, None, None, None, None, 0, None)
+                                     None, None, None, None, None, None, 0, None)
         assert st == -1 and b"bra range" in lib.xtc_last_error()
 
 
@@ -112,7 +113,7 @@ def test_exchange_argument_checks_return_invalid_arg():
     exs = L.Exchange(6, xyz, 40, xyz, xyz, None)
     st = lib.xtc_kernel_contract(C.byref(g), C.byref(corr), 4, xyz, xyz, xyz,
                                  piv.ctypes.data_as(L.I64), 2, 0, 0, 10, xyz, None, None, None, None, None,
-                                 None, C.byref(exs), None, 0, None)
+                                 None, C.byref(exs), None, None, 0, None)
     assert st == -1 and b"rank" in lib.xtc_last_error()
 
 
@@ -171,3 +172,33 @@ def test_vmc_argument_checks():
     assert gn(1, 3, fake, fake, 0.1, 1.0, fake, fake, None) == -1
     assert gn(10, 129, fake, fake, 0.1, 1.0, fake, fake, None) == -1
     assert gn(10, 3, fake, fake, -0.1, 1.0, fake, fake, None) == -1
+
+
+def test_xi_source_argument_checks():
+    """xi~ formed per block needs the orbitals and kept factors; FP32 xi is for the split
+    path only; the fit rejects an unknown xi type and factors requested without storage."""
+    from paper_2607_17314_amd import _lib as L
+    lib = L.lib()
+    xyz = C.c_void_p(8)
+    g = L.Grid(10, xyz, xyz)
+    mno = np.array([[0, 0, 2]], np.int32)
+    cc = np.array([0.3])
+    corr = L.Correlator(0, 1, mno.ctypes.data_as(L.I32), 1, cc.ctypes.data_as(L.D), 1.0, None, 0,
+                        None, None)
+    piv = np.arange(4, dtype=np.int64)
+    u1 = L.XTC_U1
+    st = lib.xtc_kernel_contract(C.byref(g), C.byref(corr), 4, xyz, None, xyz,
+                                 piv.ctypes.data_as(L.I64), u1, 0, 0, 10, xyz, None, None, None,
+                                 None, None, None, None, None, None, 0, None)
+    assert st == -1 and b"xigrad" in lib.xtc_last_error()
+    src = L.XiSource(L.XTC_FP32, xyz, 6, xyz)
+    st = lib.xtc_kernel_contract(C.byref(g), C.byref(corr), 4, xyz, None, xyz,
+                                 piv.ctypes.data_as(L.I64), u1, L.XTC_FP64, 0, 10, xyz, None, None,
+                                 None, None, None, None, None, C.byref(src), None, 0, None)
+    assert st == L.XTC_ERR_UNSUPPORTED and b"FP32" in lib.xtc_last_error()
+    assert lib.isdf_fit(xyz, C.byref(g), 2, piv.ctypes.data_as(L.I64), 4, L.XTC_FIT_XI, 5, xyz,
+                        None, None, None, None, 0, None) == -1
+    assert lib.isdf_fit(xyz, C.byref(g), 2, piv.ctypes.data_as(L.I64), 4, L.XTC_FIT_KEEP_CHOL, 0,
+                        None, None, None, None, None, 0, None) == -1
+    assert b"chol" in lib.xtc_last_error()
+    assert L.chol_system_doubles(65) == 65 * 65 + 2 * 4096
