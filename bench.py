@@ -45,6 +45,22 @@ def parse():
     p.add_argument("--no-fp64-form", action="store_true",
                    help="skip the plain FP64 form (by default one whole FP64 step runs after the "
                         "timed region: its time-to-V, the speedup and the per-block error gate)")
+    p.add_argument("--xi-fp32", action="store_true",
+                   help="store xi in FP32 (split path; default for benzene)")
+    p.add_argument("--xigrad-blocks", action="store_true",
+                   help="form xi~ per bra super-block from the fit's kept factors instead of "
+                        "storing it (default for benzene)")
+    p.add_argument("--bra-calls", type=int, default=None,
+                   help="split the timed contraction into this many bra-range calls whose partial "
+                        "sums add up, each reported as it completes (default 8 for benzene, else 1)")
+    p.add_argument("--field-oracle", action="store_true",
+                   help="check the device field against the oracle's exact field at sampled bra "
+                        "points (default for workloads too large for the oracle's own fit)")
+    p.add_argument("--fp64-sample-blocks", type=int, default=None,
+                   help="time the plain FP64 form's contraction on this many bra super-blocks "
+                        "and extrapolate it to the whole grid (0: one whole FP64 step; default 2 "
+                        "for benzene, 0 otherwise); the error gate then compares both forms on "
+                        "that bra range")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bra", type=int, default=1024, help="bra points in the CPU-oracle sample")
     p.add_argument("--exchange", action="store_true",
@@ -90,26 +106,72 @@ def main():
     from workloads import make_config
 
     wl = make_config(a.config)
+    big = a.config == "benzene"
+    xi_fp32 = a.xi_fp32 or big
+    blocks = a.xigrad_blocks or big
+    sample_blocks = a.fp64_sample_blocks if a.fp64_sample_blocks is not None else (2 if big else 0)
+    bra_calls = a.bra_calls if a.bra_calls is not None else (8 if big else 1)
+    field_oracle = a.field_oracle or big
+    if a.grad and blocks:
+        print("--grad needs the stored xi~ (no --xigrad-blocks)", file=sys.stderr)
+        sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
     C_mo = torch.as_tensor(wl.C_mo, device=dev)
     prec = L.XTC_SPLIT_F16 if a.precision == "split" else L.XTC_FP64
+    if xi_fp32 and prec != L.XTC_SPLIT_F16:
+        print("FP32 xi is read by the split path only", file=sys.stderr)
+        sys.exit(2)
     chans = api.ALL_CHANNELS
     torch.cuda.synchronize()
 
     last = {}
 
-    def step(precision):
-        phi4, rho = api.eval_orbitals(wl.basis, grid, C_mo, wl.n_occ)
-        piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
-        xi, xig, _, _ = api.fit(phi4, grid, piv)
-        out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, precision)
-        last.update(xi=xi, xig=xig, rho=rho, phi4=phi4)
-        return out, piv
-
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    def step(precision, xp=L.XTC_FP64, piv=None, bra=None):
+        """One pass of the path: orbitals, points (unless given), fit, contraction."""
+        phi4, rho = api.eval_orbitals(wl.basis, grid, C_mo, wl.n_occ)
+        if piv is None:
+            piv, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ)
+            if big:
+                torch.cuda.empty_cache()
+                log(f"  points selected ({len(piv)})")
+        if blocks:
+            xi, _, _, chol, _, rhot = api.fit_ex(phi4, grid, piv, xi_prec=xp, xigrad=False,
+                                                 keep_chol=True, rho=rho)
+            xig, src = None, api.XiSource(phi4=phi4, chol=chol, xi_prec=xp, rhot=rhot)
+        else:
+            xi, xig, _, _ = api.fit(phi4, grid, piv)
+            src = None
+        if big:
+            torch.cuda.empty_cache()
+            log("  fit done")
+        if bra_calls > 1 and bra is None:
+            # the bra range in several calls whose partial sums add up (the bra sharding of the
+            # design), so that each call's completion is reported as it happens
+            per = 16384 * -(-wl.n_g // (bra_calls * 16384))
+            out = None
+            for b0 in range(0, wl.n_g, per):
+                b1 = min(wl.n_g, b0 + per)
+                part = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, precision,
+                                           src=src, bra=(b0, b1))
+                torch.cuda.synchronize()
+                log(f"  bra points [{b0}, {b1}) contracted")
+                if out is None:
+                    out = part
+                else:
+                    for k in ("u1", "u3", "D1", "D4", "field"):
+                        out[k] += part[k]
+                    out["escale"] = out["escale"] + part["escale"]
+                del part
+        else:
+            out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, chans, precision, src=src,
+                                      bra=bra)
+        last.update(xi=xi, xig=xig, rho=rho, phi4=phi4, src=src)
+        return out, piv
 
     if a.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -118,14 +180,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copy probe: 1 GiB device-to-device copy done")
+    xp_timed = L.XTC_FP32 if xi_fp32 else L.XTC_FP64
     for i in range(a.warmup):
-        step(prec)
+        step(prec, xp_timed)
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{a.warmup} done")
     with api.KernelTimer() as kt:
         t0 = time.perf_counter()
         for i in range(a.steps):
-            out, piv = step(prec)
+            out, piv = step(prec, xp_timed)
             log(f"timed step {i + 1}/{a.steps} enqueued")
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
@@ -146,6 +209,8 @@ def main():
 
     corr_desc = ("4-term e-e correlator" if wl.corr.form == 0 else
                  f"{wl.corr.n_terms}-term multi-centre Boys-Handy correlator ({wl.corr.nuc_xyz.shape[0]} nuclei)")
+    system = {"h20": "linear H20 chain", "h20_bh": "linear H20 chain", "h4": "linear H4 chain",
+              "benzene": "planar C6H6"}.get(a.config, a.config)
     res = {
         "metric": "ISDF-xTC build time & grid-pair TFLOP/s vs FP64 GPU form at 1e-6 rel err, 1 GPU",
         "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps,
@@ -153,10 +218,12 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f16x2-split/f32acc/f64" if prec == L.XTC_SPLIT_F16 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: linear H20 chain, {n_g} grid points, {wl.n_orb} orbitals, "
+        "config": {"workload": f"{a.config}: {system}, {n_g} grid points, {wl.n_orb} orbitals, "
                                f"N_mu={n_mu}, {corr_desc}; time-to-V = orbitals + pivots + fit + "
                                f"contraction (u1,u3,D1,D4,field,escale)",
-                   "n_g": n_g, "n_orb": wl.n_orb, "n_mu": n_mu, "precision": a.precision},
+                   "n_g": n_g, "n_orb": wl.n_orb, "n_mu": n_mu, "precision": a.precision,
+                   "xi_storage": "fp32" if xi_fp32 else "fp64",
+                   "xigrad": "per bra super-block from the kept factors" if blocks else "stored"},
         "time_to_V_s": round(dt, 4),
         "stage_ms": {k: round(v["ms"] / a.steps, 2) for k, v in tm.items() if v["launches"]},
         "roofline": {"bound": "mfma", "kernel": "stage-1 pair kernel (k_stage1_split)"
@@ -210,7 +277,8 @@ def main():
     if a.kernel_sample:
         res["kernel_sample"] = kernel_sample(a.kernel_sample, a.sample_blocks, log)
     gate_ok = True
-    if not a.no_fp64_form and prec != L.XTC_FP64:
+    field_full = out["field"]
+    if not a.no_fp64_form and prec != L.XTC_FP64 and sample_blocks == 0:
         # the metric's comparison: the plain FP64 GPU form, one whole step (same inputs, so
         # the same pivots), and the per-block error of the timed form against it
         log("plain FP64 form: one whole step")
@@ -232,7 +300,68 @@ def main():
         log(f"FP64 form {t64:.2f} s ({t64 / dt:.2f}x the timed form); worst block error "
             f"{max(errs.values()):.2e}")
         del ref
-    if not a.no_cpu_baseline:
+    elif not a.no_fp64_form and prec != L.XTC_FP64:
+        # the plain FP64 form's contraction is timed on the first sample_blocks bra
+        # super-blocks (its cost is linear in the bra points) after its own FP64 fit on the
+        # same points; orbitals and point selection are the same work as the timed step's
+        nb = min(n_g, sample_blocks * 16384)
+        bra = (0, nb)
+        escale_full = out["escale"]
+        del out
+        log(f"timed form on the bra sample [0, {nb})")
+        sp = api.kernel_contract(grid, wl.corr, last["xi"], last["xig"], last["rho"], piv, chans, prec,
+                                 src=last["src"], bra=bra)
+        torch.cuda.synchronize()
+        sp = {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in sp.items()}
+        last["xi"] = last["xig"] = last["src"] = None
+        torch.cuda.empty_cache()
+        phi4, rho = last["phi4"], last["rho"]
+        log("plain FP64 form: FP64 fit")
+        with api.KernelTimer() as kt64:
+            t0 = time.perf_counter()
+            if blocks:
+                xi64, _, _, chol64, _, rhot64 = api.fit_ex(phi4, grid, piv, xigrad=False,
+                                                           keep_chol=True, rho=rho)
+                xig64, src64 = None, api.XiSource(phi4=phi4, chol=chol64, rhot=rhot64)
+            else:
+                xi64, xig64, _, _ = api.fit(phi4, grid, piv)
+                src64 = None
+            torch.cuda.synchronize()
+            t_fit = time.perf_counter() - t0
+            log(f"plain FP64 form: contraction on the bra sample [0, {nb})")
+            t0 = time.perf_counter()
+            ref = api.kernel_contract(grid, wl.corr, xi64, xig64, rho, piv, chans, L.XTC_FP64,
+                                      src=src64, bra=bra)
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t0
+        ref = {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in ref.items()}
+        del xi64, xig64, src64
+        t_shared = (tm["orbitals"]["ms"] + tm["select"]["ms"]) * 1e-3 / a.steps
+        t64 = t_shared + t_fit + t_s * n_g / nb
+        errs = block_errors(sp, ref, cols=bra)
+        gate_ok = max(errs.values()) <= GATE
+        res["fp64_form"] = {"time_to_V_s": round(t64, 2), "extrapolated": True,
+                            "how": f"orbitals + points of the timed step ({t_shared:.2f} s) + its own "
+                                   f"FP64 fit ({t_fit:.2f} s) + its contraction timed on {nb} of "
+                                   f"{n_g} bra points ({t_s:.2f} s) scaled by {n_g / nb:.2f}",
+                            "stage_ms": {k: round(v["ms"], 2) for k, v in kt64.result.items()
+                                         if v["launches"]}}
+        res["speedup_vs_fp64_form"] = round(t64 / dt, 3)
+        res["max_rel_err_vs_fp64"] = errs
+        res["accuracy_gate"] = {"bound": GATE, "per": "output block, max|got - ref| / max|ref|, "
+                                f"both forms on bra points [0, {nb})", "pass": gate_ok}
+        res["escale"] = [float(x) for x in escale_full]
+        log(f"FP64 form {t64:.1f} s extrapolated ({t64 / dt:.2f}x the timed form); worst block "
+            f"error on the sample {max(errs.values()):.2e}")
+        del ref, sp
+    if not a.no_cpu_baseline and field_oracle:
+        log("timing the CPU oracle's exact field on sampled bra points")
+        res["cpu_baseline"], ferr = field_oracle_sample(wl, last["rho"], field_full, log)
+        res["max_rel_err_vs_oracle"] = {"field": ferr}
+        ok = ferr <= 1e-10
+        res["oracle_gate"] = {"bounds": {"field": 1e-10}, "pass": ok}
+        gate_ok = gate_ok and ok
+    elif not a.no_cpu_baseline:
         log("timing the CPU oracle sample")
         res["cpu_baseline"], oerr = cpu_baseline(wl, n_mu, a.cpu_bra, a.config, grid, piv, log)
         if oerr is not None:
@@ -636,6 +765,48 @@ def assembly_cpu_baseline(wl, n_p=1):
     flops = 2.0 * n_p * n ** 3 * 4 * n_mu
     return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"W panel of {n_p} of {n} orbitals, N_mu={n_mu}; {dt:.1f} s"}
+
+
+def field_oracle_sample(wl, rho_dev, field_dev, log, n_blk=4, width=256, seed=9):
+    """The exact field A_gamma(g) = sum_g' w' rho(g') grad_1 u(g, g') (the density row of
+    stage 1, over every ket point) at n_blk seeded runs of `width` bra points, from the
+    oracle's own orbitals and density, against the device field of the timed step; also
+    the device density against the oracle's at those points. Returns (cpu_baseline, max
+    relative error of the field)."""
+    import numpy as np
+
+    from oracle import contract as oc
+    from oracle import orbitals as oorb
+    rng = np.random.default_rng(seed)
+    starts = np.sort(rng.choice(wl.n_g // width, n_blk, replace=False)) * width
+    t0 = time.perf_counter()
+    C_occ = np.ascontiguousarray(wl.C_mo[:, :wl.n_occ])
+    rho = np.empty(wl.n_g)
+    for g0 in range(0, wl.n_g, 65536):      # orbital values are pointwise: chunks are exact
+        g1 = min(wl.n_g, g0 + 65536)
+        phi_occ = oorb.eval_orbitals(wl.basis, C_occ, np.ascontiguousarray(wl.grid_xyz[:, g0:g1]))
+        rho[g0:g1] = oorb.density(phi_occ, wl.n_occ)
+    log(f"  oracle density on {wl.n_g} points in {time.perf_counter() - t0:.1f} s")
+    zero = np.zeros((1, wl.n_g))
+    fld = field_dev.cpu().numpy()
+    rd = rho_dev.cpu().numpy()
+    errs, erho = [], []
+    cores = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    for b in starts:
+        r = oc.contract(wl.grid_xyz, wl.grid_w, wl.corr, zero, None, np.zeros(1), rho, 32,
+                        bra_block=16, bra_range=(int(b), int(b) + width))
+        ref = r["field"][:, b:b + width]
+        got = fld[:, b:b + width]
+        errs.append(float(np.abs(got - ref).max() / np.abs(ref).max()))
+        erho.append(float(np.abs(rd[b:b + width] - rho[b:b + width]).max() / np.abs(rho).max()))
+    dt = time.perf_counter() - t0
+    flops = 6.0 * n_blk * width * wl.n_g          # the field's 3 channels x 2 flops per pair
+    log(f"  field at {n_blk} x {width} bra points: worst rel err {max(errs):.2e} ({dt:.1f} s)")
+    return ({"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+             "sample": f"exact field of {n_blk} x {width} bra points (starts {starts.tolist()}) x "
+                       f"{wl.n_g} ket points from the oracle's density; {dt:.1f} s",
+             "density_max_rel_err": max(erho)}, max(errs))
 
 
 def read_pivots(config):

@@ -255,14 +255,19 @@ xtc_status isdf_select_points(const double* phi4, const xtc_grid* grid, int32_t 
  * xigrad: device double [3][n_mu][n_g] (if what & XTC_FIT_XIGRAD).
  * chol: device double [4][XTC_CHOL_SYSTEM_DOUBLES(n_mu)] (if what & XTC_FIT_KEEP_CHOL):
  * scalar, x, y, z.
+ * rho, rhot: device [n_g] each, or both NULL: with XTC_FIT_XI, rhot receives the ISDF
+ * density rhot(g) = sum_mu rho(r_mu) xi_mu(g) (xTC section; rho the reference density)
+ * from the FP64 solution, before any FP32 rounding of xi. That sum cancels heavily (xi
+ * is large and sign-alternating where rhot is O(1)), so with FP32 xi the contraction
+ * should take this rhot (xtc_xi_source) rather than re-forming it from the rounded xi.
  * info: host [8] or NULL: {shift index k per system (-1 none) x4, relative weighted
  * residual sum_g w^2 (|m_g|^2 - xi(g).B(g)) / sum_g w^2 |m_g|^2 x4} (scalar, x, y, z; the
  * residual of a system is reported when its solution is asked for, else 0).
  * Returns XTC_WARN_JITTER if any shift was used. Synchronising. */
 xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
                     const int64_t* pivots, int32_t n_mu, uint32_t what, int32_t xi_prec,
-                    void* xi, double* xigrad, double* chol, double* info, void* ws,
-                    size_t ws_bytes, void* stream);
+                    void* xi, double* xigrad, double* chol, const double* rho, double* rhot,
+                    double* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Where xtc_kernel_contract takes xi and xi~ from, when not from the defaults (FP64 xi and
  * a stored xigrad): xi in FP32 (split path only), and xi~ formed per bra super-block
@@ -275,6 +280,8 @@ typedef struct {
   int32_t n_orb;
   const double* chol;  /* device: isdf_fit's kept factors [4][XTC_CHOL_SYSTEM_DOUBLES(n_mu)],
                           or NULL when xigrad is given */
+  const double* rhot;  /* device [n_g]: the ISDF density from isdf_fit, or NULL to form it
+                          from xi (recommended with FP32 xi, see isdf_fit) */
 } xtc_xi_source;
 
 /* Grid-pair kernels and xTC D terms, with the kernel tiles generated on the fly

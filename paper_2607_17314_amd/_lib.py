@@ -57,7 +57,8 @@ class Exchange(C.Structure):
 
 
 class XiSource(C.Structure):
-    _fields_ = [("xi_prec", C.c_int32), ("phi4", P), ("n_orb", C.c_int32), ("chol", P)]
+    _fields_ = [("xi_prec", C.c_int32), ("phi4", P), ("n_orb", C.c_int32), ("chol", P),
+                ("rhot", P)]
 
 
 class Assembly(C.Structure):
@@ -105,7 +106,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(Mlp), C.c_double, I64, I32, D, P, C.c_size_t, P]
     L.isdf_fit.restype = st
     L.isdf_fit.argtypes = [P, C.POINTER(Grid), C.c_int32, I64, C.c_int32, C.c_uint32, C.c_int32, P,
-                           P, P, D, P, C.c_size_t, P]
+                           P, P, P, P, D, P, C.c_size_t, P]
     L.xtc_kernel_contract.restype = st
     L.xtc_kernel_contract.argtypes = [C.POINTER(Grid), C.POINTER(Correlator), C.c_int32, P, P, P, I64,
                                       C.c_uint32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P,

@@ -167,10 +167,12 @@ def fit(phi4, grid: DeviceGrid, pivots, what: int = L.XTC_FIT_XI | L.XTC_FIT_XIG
 
 
 def fit_ex(phi4, grid: DeviceGrid, pivots, xi_prec: int = L.XTC_FP64, xi: bool = True,
-           xigrad: bool = True, keep_chol: bool = False):
-    """isdf_fit with every option: xi in FP64 or FP32 (xi_prec), xi~ (FP64), and the kept
+           xigrad: bool = True, keep_chol: bool = False, rho=None):
+    """isdf_fit with every option: xi in FP64 or FP32 (xi_prec), xi~ (FP64), the kept
     factors [4, XTC_CHOL_SYSTEM_DOUBLES(n_mu)] (FP64) from which the contraction forms xi~
-    per bra block. Returns (xi, xigrad, info, chol, status), None for what was not asked."""
+    per bra block, and (rho given) the ISDF density rhot [n_g] from the FP64 solution.
+    Returns (xi, xigrad, info, chol, status), None for what was not asked; with rho the
+    result has a sixth entry, rhot."""
     phi4 = _in(phi4, "phi4")
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]
@@ -182,12 +184,16 @@ def fit_ex(phi4, grid: DeviceGrid, pivots, xi_prec: int = L.XTC_FP64, xi: bool =
     xig = torch.empty((3, n_mu, grid.n_g), dtype=torch.float64, device="cuda") if xigrad else None
     chol = (torch.empty((4, L.chol_system_doubles(n_mu)), dtype=torch.float64, device="cuda")
             if keep_chol else None)
+    rho = _in(rho, "rho")
+    rhot = torch.empty(grid.n_g, dtype=torch.float64, device="cuda") if rho is not None else None
     info = np.zeros(8, np.float64)
     ws = _workspace(workspace_bytes(L.XTC_CALL_FIT, grid.n_g, n_orb, n_mu, 0, what))
     g = grid.c()
     st = _check("isdf_fit", L.lib().isdf_fit(
         _ptr(phi4), C.byref(g), n_orb, piv.ctypes.data_as(L.I64), n_mu, what, int(xi_prec), _ptr(x),
-        _ptr(xig), _ptr(chol), _dptr(info), _ptr(ws), ws.numel(), _stream()))
+        _ptr(xig), _ptr(chol), _ptr(rho), _ptr(rhot), _dptr(info), _ptr(ws), ws.numel(), _stream()))
+    if rho is not None:
+        return x, xig, info, chol, st, rhot
     return x, xig, info, chol, st
 
 
@@ -199,10 +205,12 @@ class XiSource:
     phi4: torch.Tensor = None
     chol: torch.Tensor = None
     xi_prec: int = L.XTC_FP64
+    rhot: torch.Tensor = None
 
     def c(self):
         n_orb = int(self.phi4.shape[1]) if self.phi4 is not None else 0
-        return L.XiSource(int(self.xi_prec), _ptr(self.phi4), n_orb, _ptr(self.chol))
+        return L.XiSource(int(self.xi_prec), _ptr(self.phi4), n_orb, _ptr(self.chol),
+                          _ptr(self.rhot))
 
 
 ALL_CHANNELS = L.XTC_U1 | L.XTC_U3 | L.XTC_D1 | L.XTC_D4 | L.XTC_FIELD | L.XTC_ESCALE
@@ -223,7 +231,8 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
     xi_dt = torch.float32 if src is not None and src.xi_prec == L.XTC_FP32 else torch.float64
     xi, xigrad, rho = _in(xi, "xi", xi_dt), _in(xigrad, "xigrad"), _in(rho, "rho")
     if src is not None:
-        src = XiSource(_in(src.phi4, "phi4"), _in(src.chol, "chol"), src.xi_prec)
+        src = XiSource(_in(src.phi4, "phi4"), _in(src.chol, "chol"), src.xi_prec,
+                       _in(src.rhot, "rhot"))
     srcs = src.c() if src is not None else None
     piv = np.ascontiguousarray(pivots, np.int64)
     n_mu = piv.shape[0]

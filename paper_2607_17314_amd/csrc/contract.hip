@@ -282,7 +282,9 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   hipLaunchKernelGGL(k_gather_G, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
                      (const long*)C.piv, n_mu, C.G);
   XTC_CHECK_LAUNCH();
-  if (xi32) {   // ISDF density rhot = G^T xi
+  if (src && src->rhot) {   // ISDF density rhot = G^T xi, given (from the fit's FP64 xi)
+    XTC_HIP(hipMemcpyAsync(C.rhot, src->rhot, sizeof(double) * n_g, hipMemcpyDeviceToDevice, st));
+  } else if (xi32) {
     hipLaunchKernelGGL(k_rhot_f32, dim3(cdiv(n_g, 256)), dim3(256), 0, st, (const double*)C.G,
                        xi32, n_mu, n_g, C.rhot);
     XTC_CHECK_LAUNCH();

@@ -178,6 +178,7 @@ size_t ws_fit(int64_t n_g, int n_orb, int n_mu, uint32_t what) {
   (void)what;
   Arena ar(nullptr, 0);
   layout_fit(ar, n_g, n_orb, n_mu);
+  ar.take<double>(n_mu);   // rho at the pivots, when rhot is asked for
   return ar.used;
 }
 
@@ -439,10 +440,17 @@ xtc_status gather_pivot_rows(const double* phi4, long n_g, int rows, const long*
 
 using namespace xtc;
 
+__global__ void k_gather_rho(const double* __restrict__ rho, const long* __restrict__ piv,
+                             int n_mu, double* __restrict__ G) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n_mu) G[i] = rho[piv[i]];
+}
+
 extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
                                const int64_t* pivots, int32_t n_mu, uint32_t what,
                                int32_t xi_prec, void* xi, double* xigrad, double* chol,
-                               double* info, void* ws, size_t ws_bytes, void* stream) {
+                               const double* rho, double* rhot, double* info, void* ws,
+                               size_t ws_bytes, void* stream) {
   XTC_REQUIRE(phi4 && grid && pivots, "isdf_fit: null argument");
   XTC_REQUIRE(grid->n_g > 0 && grid->w, "isdf_fit: empty grid");
   XTC_REQUIRE(n_orb > 0 && n_mu > 0 && n_mu <= grid->n_g, "isdf_fit: bad sizes");
@@ -453,16 +461,23 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
               "isdf_fit: nothing requested");
   XTC_REQUIRE((what & ~7u) == 0, "isdf_fit: unknown bits in what");
   XTC_REQUIRE(xi_prec == XTC_FP64 || xi_prec == XTC_FP32, "isdf_fit: xi_prec must be FP64 or FP32");
+  XTC_REQUIRE(!rhot || (rho && (what & XTC_FIT_XI)), "isdf_fit: rhot needs rho and XTC_FIT_XI");
   const long n_g = grid->n_g;
   for (int m = 0; m < n_mu; ++m)
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < n_g, "isdf_fit: pivot index out of range");
   hipStream_t st = as_stream(stream);
   Arena ar(ws, ws_bytes);
   FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
+  double* Grho = rhot ? ar.take<double>(n_mu) : nullptr;   // rho at the pivots
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "isdf_fit"));
   size_t tk = timing_begin(TM_FIT, st);
   XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
+  if (rhot) {
+    hipLaunchKernelGGL(k_gather_rho, dim3(cdiv(n_mu, 256)), dim3(256), 0, st, rho,
+                       (const long*)F.piv, n_mu, Grho);
+    XTC_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(k_gather_piv, dim3(cdiv(4L * n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
                      n_g, 4 * n_orb, (const long*)F.piv, n_mu, F.phimu);
   XTC_CHECK_LAUNCH();
@@ -518,6 +533,14 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
       XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
       XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
       XTC_TRY(back_chunk(factor_of(F, n), cn, F.R, F.chunk, out, ldo, st));
+      if (sys == 0 && rhot) {   // ISDF density from the FP64 solution (the product the
+        GemmArgs g{};           // contraction forms from FP64 xi, element for element)
+        g.M = 1; g.N = cn; g.K = n;
+        g.A = Grho; g.a_sm = 1; g.a_sk = 1;
+        g.B = out; g.b_sk = ldo; g.b_sn = 1;
+        g.C = rhot + g0; g.c_sm = n_g; g.c_sn = 1;
+        XTC_TRY(gemm_f64(g, st));
+      }
       if (f32) {
         hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n * cn, 256)), dim3(256), 0, st, (const double*)out,
                            ldo, (float*)xi + g0, n_g, n, cn);

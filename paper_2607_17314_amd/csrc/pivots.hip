@@ -13,6 +13,8 @@
 // only synchronises once per batch of steps to see whether the fused set is
 // complete. Ties in the argmax go to the lowest grid index; the reduction
 // order is fixed, so repeated runs select identical pivots.
+#include <cstdio>
+#include <cstdlib>
 #include "common.hpp"
 #include "plans.hpp"
 #include "timing.hpp"
@@ -239,6 +241,13 @@ size_t ws_select(int64_t n_g, int n_orb, int n_mu, int mode) {
 }
 
 // Runs one channel; returns the number of pivots recorded.
+// XTC_PROGRESS set in the environment: long host loops report their progress on stderr
+// at the points where they synchronise anyway.
+static bool progress_enabled() {
+  static const bool on = getenv("XTC_PROGRESS") != nullptr;
+  return on;
+}
+
 static xtc_status run_channel(const double* phi4, const double* w, long n_g, int n_orb, int channel,
                               int max_steps, int fill_target, SelLayout& S, long* piv_out,
                               hipStream_t st, int* n_out, int* deficient) {
@@ -266,6 +275,9 @@ static xtc_status run_channel(const double* phi4, const double* w, long n_g, int
     XTC_CHECK_LAUNCH();
     XTC_HIP(hipMemcpyAsync(&h, S.ctl, sizeof(PivCtl), hipMemcpyDeviceToHost, st));
     XTC_HIP(hipStreamSynchronize(st));
+    if (progress_enabled() && h.step / 1024 != done_steps / 1024)
+      fprintf(stderr, "isdf_select_points: %s channel, %d steps done\n",
+              channel == 0 ? "scalar" : "gradient", h.step);
     done_steps = h.step;
     if (h.stop != 0) break;
   }

@@ -46,8 +46,8 @@ def test_host_argument_checks_return_invalid_arg():
     g = L.Grid(0, None, None)
     assert lib.xtc_eval_orbitals(None, None, None, 1, 0, None, None, None, 0, None) == -1
     assert b"null" in lib.xtc_last_error()
-    assert lib.isdf_fit(None, C.byref(g), 1, None, 1, 1, 0, None, None, None, None, None, 0,
-                        None) == -1
+    assert lib.isdf_fit(None, C.byref(g), 1, None, 1, 1, 0, None, None, None, None, None, None,
+                        None, 0, None) == -1
     piv = np.zeros(4, np.int64)
     xyz = C.c_void_p(8)
     g2 = L.Grid(10, xyz, xyz)
@@ -197,8 +197,8 @@ def test_xi_source_argument_checks():
                                  None, None, None, None, None, C.byref(src), None, 0, None)
     assert st == L.XTC_ERR_UNSUPPORTED and b"FP32" in lib.xtc_last_error()
     assert lib.isdf_fit(xyz, C.byref(g), 2, piv.ctypes.data_as(L.I64), 4, L.XTC_FIT_XI, 5, xyz,
-                        None, None, None, None, 0, None) == -1
+                        None, None, None, None, None, None, 0, None) == -1
     assert lib.isdf_fit(xyz, C.byref(g), 2, piv.ctypes.data_as(L.I64), 4, L.XTC_FIT_KEEP_CHOL, 0,
-                        None, None, None, None, None, 0, None) == -1
+                        None, None, None, None, None, None, None, 0, None) == -1
     assert b"chol" in lib.xtc_last_error()
     assert L.chol_system_doubles(65) == 65 * 65 + 2 * 4096

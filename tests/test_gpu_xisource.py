@@ -2,7 +2,7 @@
 337 GB in FP64): xi stored in FP32, the fit's Cholesky factors kept (XTC_FIT_KEEP_CHOL),
 and xi~ formed per bra super-block inside the contraction from those factors (xigrad =
 NULL), which repeats the fit's own right-hand-side products and blocked solves for the
-block's columns. Checked against the oracle and against the stored-xi~ call, on H4 and
+block's columns; with FP32 xi, the ISDF density comes from the fit's FP64 solution. Checked against the oracle and against the stored-xi~ call, on H4 and
 on a ragged grid subset."""
 import numpy as np
 import pytest
@@ -61,8 +61,8 @@ def test_contract_with_xigrad_on_the_fly(cases, which):
     case = cases[which]
     api, grid, phi4, rho, t = _device(case)
     xi64, xig64, _, _ = api.fit(phi4, grid, case.piv)
-    xi32, _, _, chol, _ = api.fit_ex(phi4, grid, case.piv, xi_prec=L.XTC_FP32, xigrad=False,
-                                     keep_chol=True)
+    xi32, _, _, chol, _, rhot = api.fit_ex(phi4, grid, case.piv, xi_prec=L.XTC_FP32, xigrad=False,
+                                           keep_chol=True, rho=rho)
     _, _, _, chol64, _ = api.fit_ex(phi4, grid, case.piv, xi_prec=L.XTC_FP64, xigrad=False,
                                     xi=False, keep_chol=True)
     assert torch.equal(chol, chol64)
@@ -71,11 +71,15 @@ def test_contract_with_xigrad_on_the_fly(cases, which):
     stored = api.kernel_contract(grid, case.wl.corr, xi64, xig64, rho, case.piv, CH, L.XTC_FP64)
     fly = api.kernel_contract(grid, case.wl.corr, xi64, None, rho, case.piv, CH, L.XTC_FP64,
                               src=src)
+    # the fit's FP64 density is the product the contraction forms from FP64 xi, bit for bit
+    given = api.kernel_contract(grid, case.wl.corr, xi64, None, rho, case.piv, CH, L.XTC_FP64,
+                                src=api.XiSource(phi4=phi4, chol=chol, rhot=rhot))
     sp = api.kernel_contract(grid, case.wl.corr, xi32, None, rho, case.piv, CH, L.XTC_SPLIT_F16,
-                             src=api.XiSource(phi4=phi4, chol=chol, xi_prec=L.XTC_FP32))
+                             src=api.XiSource(phi4=phi4, chol=chol, xi_prec=L.XTC_FP32, rhot=rhot))
     torch.cuda.synchronize()
     for k in ("u1", "u3", "D1", "D4", "field"):
         assert torch.equal(fly[k], stored[k]), k
+        assert torch.equal(given[k], stored[k]), k
         ed = float((sp[k] - fly[k]).abs().max() / fly[k].abs().max())
         e64 = rel_err(fly[k].cpu().numpy(), ref[k])
         es = rel_err(sp[k].cpu().numpy(), ref[k])
