@@ -146,12 +146,13 @@ typedef struct {
   const float* params;     /* device, 8h + h + h*h + h + h + 1 floats */
   const float* feat_shift; /* device [8]: feature z-score shift */
   const float* feat_scale; /* device [8]: feature z-score scale */
-  double kappa;            /* candidates kept = ceil(kappa * n_mu), clamped to n_g */
+  double kappa;            /* candidates by score = ceil(kappa * n_mu), clamped to n_g */
   int32_t n_nuc;           /* nuclei for the distance features */
   const double* nuc_xyz;   /* host [n_nuc][3] */
   int32_t judge;           /* 0: reference residual from the fit below; 1: run the QR
                               selection and use its residual (validation) */
   double ref_a, ref_b;     /* judge 0: log R_ref = ref_a + ref_b log(n_mu / n_orb) */
+  int32_t stride;          /* coverage: every stride-th grid point is a candidate too (0: none) */
 } xtc_mlp;
 
 /* Exchange intermediates requested from xtc_kernel_contract (xTC Terms 2 and 3,
@@ -200,7 +201,8 @@ enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
  * precision in bits 16..23 and, for CONTRACT, XTC_WS_XIGRAD_BLOCKS) or the select mode
  * (SELECT) or the fit mask (FIT) or
- * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none).
+ * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none); for
+ * SELECT in a learned mode, flags = mode | (mlp->stride << 8) and n_aux = ceil(100 kappa).
  * n_aux: n_ao (EVAL_ORBITALS, VMC), n_params (GRAD), the
  * projector rank n_q (EXCHANGE, and CONTRACT with exchange outputs, where n_aux > 0
  * asks for them), else 0. n_orb: the orbitals (also for CONTRACT with exchange outputs or
@@ -218,11 +220,13 @@ xtc_status xtc_eval_orbitals(const xtc_basis* basis, const xtc_grid* grid, const
                              void* ws, size_t ws_bytes, void* stream);
 
 /* Interpolation-point selection (ISDF section, pivot selection and fusion; Alg. 1).
- * Learned modes (not in the paper): score every point with the MLP, keep the
- * ceil(kappa n_mu) best (ties to the lowest index), run the same fused pivoting
- * restricted to those candidates; XTC_SELECT_LEARNED_JUDGED then computes the
- * weighted scalar-channel fit residual R of the proposal over the whole grid and
- * falls back to the QR selection (XTC_WARN_FALLBACK) when R > fallback_factor R_ref.
+ * Learned modes (not in the paper): score every point with the MLP; the candidates are
+ * the ceil(kappa n_mu) best (ties to the lowest index) and every mlp->stride-th grid
+ * point (coverage of the whole grid); the same fused pivoting runs restricted to the
+ * candidates; XTC_SELECT_LEARNED_JUDGED then computes R, the mean of the four relative
+ * weighted fit residuals (scalar and the three gradient components, as isdf_fit reports
+ * them) of the proposal over the whole grid, and falls back to the QR selection
+ * (XTC_WARN_FALLBACK) when R > fallback_factor R_ref.
  * QR mode: matrix-free weight-scaled pivoted Cholesky, FP64, on the scalar channel
  * d_g = w_g^2 (sum_p phi_p^2)^2 and the gradient channel
  * d_g = w_g^2 (sum_p phi_p^2)(sum_{p,c} (d_c phi_p)^2); ties go to the lowest index;

@@ -120,3 +120,18 @@ def top_candidates(scores, k):
     """Indices of the k largest scores, ties to the lowest index, in ascending index order."""
     order = np.lexsort((np.arange(scores.shape[0]), -scores))
     return np.sort(order[:k])
+
+
+def candidates(scores, k, stride):
+    """The learned proposal's candidate set: the k largest scores (ties to the lowest index)
+    and every stride-th grid point (coverage; stride 0: none), in ascending index order."""
+    top = top_candidates(scores, k)
+    if stride <= 0:
+        return top
+    return np.union1d(top, np.arange(0, scores.shape[0], stride))
+
+
+def judge_residual(resid_rel):
+    """The judge's residual: the mean of the four relative fit residuals (scalar, x, y, z)."""
+    r = np.asarray(resid_rel, np.float64)
+    return 0.25 * ((r[0] + r[1]) + (r[2] + r[3]))

@@ -74,7 +74,8 @@ class VmcSystem(C.Structure):
 class Mlp(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("params", P), ("feat_shift", P),
                 ("feat_scale", P), ("kappa", C.c_double), ("n_nuc", C.c_int32), ("nuc_xyz", D),
-                ("judge", C.c_int32), ("ref_a", C.c_double), ("ref_b", C.c_double)]
+                ("judge", C.c_int32), ("ref_a", C.c_double), ("ref_b", C.c_double),
+                ("stride", C.c_int32)]
 
 
 _lib = None

@@ -148,7 +148,8 @@ def select_points(phi4, grid: DeviceGrid, n_mu: int, n_occ: int = 0, mode: int =
     n_out = C.c_int32(0)
     info = np.zeros(8, np.float64)
     kap = int(np.ceil(mlp.kappa * 100)) if mlp is not None else 0
-    ws = _workspace(workspace_bytes(L.XTC_CALL_SELECT, grid.n_g, n_orb, n_mu, kap, mode))
+    flags = mode | ((mlp.stride << 8) if mlp is not None else 0)
+    ws = _workspace(workspace_bytes(L.XTC_CALL_SELECT, grid.n_g, n_orb, n_mu, kap, flags))
     g = grid.c()
     ms = mlp.c() if mlp is not None else None
     mp = C.byref(ms) if ms is not None else None
@@ -445,7 +446,7 @@ class MlpModel:
     statistics, the nuclei for the distance features and the judge settings."""
 
     def __init__(self, params, shift, scale, hidden=64, kappa=3.0, nuclei=None, judge=0,
-                 ref_a=0.0, ref_b=0.0):
+                 ref_a=0.0, ref_b=0.0, stride=0):
         self.params = _dev(params, torch.float32)
         self.shift = _dev(shift, torch.float32)
         self.scale = _dev(scale, torch.float32)
@@ -455,11 +456,12 @@ class MlpModel:
                                         np.float64).reshape(-1, 3)
         self.judge = int(judge)
         self.ref_a, self.ref_b = float(ref_a), float(ref_b)
+        self.stride = int(stride)
 
     def c(self):
         return L.Mlp(8, self.hidden, self.params.data_ptr(), self.shift.data_ptr(),
                      self.scale.data_ptr(), self.kappa, self.nuc.shape[0], _dptr(self.nuc),
-                     self.judge, self.ref_a, self.ref_b)
+                     self.judge, self.ref_a, self.ref_b, self.stride)
 
     def with_nuclei(self, nuclei):
         m = MlpModel.__new__(MlpModel)

@@ -54,12 +54,14 @@ extern "C" size_t xtc_workspace_bytes(int32_t call, int64_t n_g, int32_t n_orb, 
   switch (call) {
     case XTC_CALL_EVAL_ORBITALS: return xtc::ws_eval_orbitals(n_g, n_orb, n_aux);
     case XTC_CALL_SELECT: {
-      // learned modes: n_aux = ceil(100 kappa); the judge may run the full-grid QR
-      // selection and two residual fits after the candidate-restricted selection
-      size_t base = xtc::ws_select(n_g, n_orb, n_mu, (int)flags);
-      if (flags == XTC_SELECT_QR) return base;
+      // learned modes: n_aux = ceil(100 kappa), flags = mode | stride << 8; the judge may
+      // run the full-grid QR selection and two residual fits after the candidate-restricted
+      // selection
+      const int mode = (int)(flags & 0xff);
+      size_t base = xtc::ws_select(n_g, n_orb, n_mu, mode);
+      if (mode == XTC_SELECT_QR) return base;
       const double kappa = n_aux > 0 ? n_aux / 100.0 : 3.0;
-      size_t learned = xtc::ws_learned(n_g, n_orb, n_mu, kappa);
+      size_t learned = xtc::ws_learned(n_g, n_orb, n_mu, kappa, (long)(flags >> 8));
       size_t fr = xtc::ws_fit_residual(n_g, n_orb, n_mu);
       size_t tail = base > fr ? base : fr;
       return learned + tail + 4096;

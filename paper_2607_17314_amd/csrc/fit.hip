@@ -346,56 +346,63 @@ static xtc_status chol_jitter(FitLayout& F, long n, hipStream_t st, int* k_used)
   return XTC_ERR_NOT_SPD;
 }
 
-// Relative weighted scalar-channel fit residual of a pivot set (the judge of the
-// learned selection): Gram, Cholesky, forward solve and column norms only; xi is
-// not formed. Uses (and releases) arena space after ar.used.
-xtc_status fit_scalar_residual(const double* phi4, const xtc_grid* grid, int n_orb,
-                               const int64_t* pivots, int n_mu, Arena& ar, hipStream_t st,
-                               double* rel) {
+// Relative weighted fit residuals of a pivot set in the four systems (scalar, x, y, z; the
+// judge of the learned selection): per system the Gram, its Cholesky with the retry, and per
+// grid chunk the right-hand side, the forward solve and the residual sums; xi is not formed.
+// Uses (and releases) arena space after ar.used.
+xtc_status fit_residuals(const double* phi4, const xtc_grid* grid, int n_orb,
+                         const int64_t* pivots, int n_mu, Arena& ar, hipStream_t st, double* rel) {
   const size_t mark = ar.used;
   const long n_g = grid->n_g;
   FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
   XTC_TRY(need_ws(ar));
   XTC_HIP(hipMemcpyAsync(F.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_gather_piv, dim3(cdiv((long)n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
-                     n_g, n_orb, (const long*)F.piv, n_mu, F.phimu);
+  hipLaunchKernelGGL(k_gather_piv, dim3(cdiv(4L * n_orb * n_mu, 256)), dim3(256), 0, st, phi4,
+                     n_g, 4 * n_orb, (const long*)F.piv, n_mu, F.phimu);
   XTC_CHECK_LAUNCH();
   const long n = n_mu;
-  GemmArgs g{};
-  g.M = n; g.N = n; g.K = n_orb;
-  g.A = F.phimu; g.a_sm = 1; g.a_sk = n;
-  g.B = F.phimu; g.b_sk = n; g.b_sn = 1;
-  g.C = F.A; g.c_sm = n; g.c_sn = 1;
-  g.epi = EPI_SQUARE;
-  XTC_TRY(gemm_f64(g, st));
-  int k = -1;
-  XTC_TRY(chol_jitter(F, n, st, &k));
-  for (int c = 0; c < F.nchunks; ++c) {
-    const long g0 = (long)c * F.chunk;
-    const long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
-    GemmArgs r{};   // B = (Phi_mu^T Phi)^2
-    r.M = n; r.N = cn; r.K = n_orb;
-    r.A = F.phimu; r.a_sm = 1; r.a_sk = n;
-    r.B = phi4 + g0; r.b_sk = n_g; r.b_sn = 1;
-    r.C = F.R; r.c_sm = F.chunk; r.c_sn = 1;
-    r.epi = EPI_SQUARE;
-    XTC_TRY(gemm_f64(r, st));
-    XTC_TRY(solve_chunk(factor_of(F, n), cn, F.R, F.chunk, F.P, F.chunk, st));   // Y = L^-1 B into F.P
-    hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g, n_orb, -1,
-                       g0, cn, (const double*)F.P, F.chunk, n_mu, F.rtmp, F.mtmp);
-    XTC_CHECK_LAUNCH();
-    XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
-    XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
+  {
+    GemmArgs g{};   // G = Phi_mu^T Phi_mu
+    g.M = n; g.N = n; g.K = n_orb;
+    g.A = F.phimu; g.a_sm = 1; g.a_sk = n;
+    g.B = F.phimu; g.b_sk = n; g.b_sn = 1;
+    g.C = F.G; g.c_sm = n; g.c_sn = 1;
+    XTC_TRY(gemm_f64(g, st));
   }
-  std::vector<double> hs(2 * F.nchunks);
-  XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks, hipMemcpyDeviceToHost, st));
-  XTC_HIP(hipStreamSynchronize(st));
-  double rs = 0.0, ms = 0.0;
-  for (int c = 0; c < F.nchunks; ++c) {
-    rs += hs[2 * c];
-    ms += hs[2 * c + 1];
+  for (int sys = 0; sys < 4; ++sys) {
+    const int comp = sys - 1;
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = n_orb;
+    const double* ph = F.phimu + (long)sys * n_orb * n;
+    g.A = ph; g.a_sm = 1; g.a_sk = n;
+    g.B = ph; g.b_sk = n; g.b_sn = 1;
+    g.C = F.A; g.c_sm = n; g.c_sn = 1;
+    g.epi = EPI_MUL_E; g.E = F.G; g.e_sm = n; g.e_sn = 1;
+    XTC_TRY(gemm_f64(g, st));
+    int k = -1;
+    XTC_TRY(chol_jitter(F, n, st, &k));
+    for (int c = 0; c < F.nchunks; ++c) {
+      const long g0 = (long)c * F.chunk;
+      const long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
+      XTC_TRY(rhs_chunk(phi4, n_g, n_orb, F.phimu, n, comp, g0, cn, F.P, F.R, F.chunk, st));
+      XTC_TRY(solve_chunk(factor_of(F, n), cn, F.R, F.chunk, F.P, F.chunk, st));  // Y into F.P
+      hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g, n_orb,
+                         comp, g0, cn, (const double*)F.P, F.chunk, n_mu, F.rtmp, F.mtmp);
+      XTC_CHECK_LAUNCH();
+      XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
+      XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
+    }
+    std::vector<double> hs(2 * F.nchunks);
+    XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks,
+                           hipMemcpyDeviceToHost, st));
+    XTC_HIP(hipStreamSynchronize(st));
+    double rs = 0.0, ms = 0.0;
+    for (int c = 0; c < F.nchunks; ++c) {
+      rs += hs[2 * c];
+      ms += hs[2 * c + 1];
+    }
+    rel[sys] = ms > 0.0 ? rs / ms : 0.0;
   }
-  *rel = ms > 0.0 ? rs / ms : 0.0;
   ar.used = mark;
   return XTC_OK;
 }

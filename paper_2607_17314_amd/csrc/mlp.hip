@@ -293,21 +293,31 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* tot) {
   return incl - v;
 }
 
+// candidates: the top K by score (ties to the lowest index) and every stride-th point
 __global__ __launch_bounds__(256) void k_sel_flags(const float* __restrict__ s, long n,
                                                    const SelState* st,
                                                    const unsigned* __restrict__ eq_off,
-                                                   unsigned char* __restrict__ sel,
+                                                   long stride, unsigned char* __restrict__ sel,
                                                    unsigned* __restrict__ sel_cnt) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   const unsigned key = i < n ? fkey(s[i]) : 0u;
   const unsigned eq = (i < n && key == st->thr) ? 1u : 0u;
   unsigned tot;
   const unsigned r = block_excl_scan(eq, &tot) + eq_off[blockIdx.x];
-  const unsigned f = (i < n) && (key > st->thr || (eq && (long)r < st->need_eq));
+  const unsigned f = (i < n) && (key > st->thr || (eq && (long)r < st->need_eq) ||
+                                 (stride > 0 && i % stride == 0));
   if (i < n) sel[i] = (unsigned char)f;
   unsigned tot2;
   block_excl_scan(f, &tot2);
   if (threadIdx.x == 0) sel_cnt[blockIdx.x] = tot2;
+}
+
+// total of the per-block counts (before their exclusive scan) into st->cnt
+__global__ void k_sum_counts(SelState* st, const unsigned* __restrict__ bc, int nb) {
+  if (threadIdx.x) return;
+  unsigned long long t = 0;
+  for (int b = 0; b < nb; ++b) t += bc[b];
+  st->cnt = t;
 }
 
 __global__ __launch_bounds__(256) void k_scatter_sel(const unsigned char* __restrict__ sel, long n,
@@ -422,6 +432,7 @@ struct LearnLayout {
   long* cand; double* sub; double* wsub; double* nuc; int nb; long K;
 };
 
+// K: the largest candidate count (the top K by score plus the coverage points)
 static LearnLayout layout_learn(Arena& ar, int64_t n_g, int n_orb, long K) {
   LearnLayout L;
   L.K = K;
@@ -439,8 +450,10 @@ static LearnLayout layout_learn(Arena& ar, int64_t n_g, int n_orb, long K) {
   return L;
 }
 
-// top-K by score; candidate indices ascending in L.cand
-static xtc_status top_k(LearnLayout& L, long n, hipStream_t st) {
+// top-K by score and every stride-th point; candidate indices ascending in L.cand, their
+// number returned in *count
+static xtc_status top_k(LearnLayout& L, long n, long K, long stride, hipStream_t st,
+                        long* count) {
   SelState init{};
   init.lo = 0u;
   init.hi = 0xffffffffu;
@@ -449,7 +462,7 @@ static xtc_status top_k(LearnLayout& L, long n, hipStream_t st) {
   for (int it = 0; it < 32; ++it) {
     hipLaunchKernelGGL(k_count_ge, dim3(nbc), dim3(256), 0, st, (const float*)L.logits, n,
                        (const SelState*)L.sst, 1, 0u, L.bc);
-    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(1), 0, st, L.sst, (const unsigned*)L.bc, nbc, L.K);
+    hipLaunchKernelGGL(k_bisect, dim3(1), dim3(1), 0, st, L.sst, (const unsigned*)L.bc, nbc, K);
   }
   XTC_CHECK_LAUNCH();
   // count(key > thr): one more pass at thr + 1, read on the device
@@ -462,16 +475,21 @@ static xtc_status top_k(LearnLayout& L, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_count_ge, dim3(nbc), dim3(256), 0, st, (const float*)L.logits, n,
                        (const SelState*)L.sst, 0, h.lo + 1u, L.bc);
   }
-  hipLaunchKernelGGL(k_finish_thr, dim3(1), dim3(1), 0, st, L.sst, (const unsigned*)L.bc, nbc, L.K);
+  hipLaunchKernelGGL(k_finish_thr, dim3(1), dim3(1), 0, st, L.sst, (const unsigned*)L.bc, nbc, K);
   hipLaunchKernelGGL(k_eq_counts, dim3(L.nb), dim3(256), 0, st, (const float*)L.logits, n,
                      (const SelState*)L.sst, L.bc2);
   hipLaunchKernelGGL(k_excl_scan, dim3(1), dim3(1), 0, st, L.bc2, L.nb);
   hipLaunchKernelGGL(k_sel_flags, dim3(L.nb), dim3(256), 0, st, (const float*)L.logits, n,
-                     (const SelState*)L.sst, (const unsigned*)L.bc2, L.sel, L.bc);
+                     (const SelState*)L.sst, (const unsigned*)L.bc2, stride, L.sel, L.bc);
+  hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1), 0, st, L.sst, (const unsigned*)L.bc, L.nb);
   hipLaunchKernelGGL(k_excl_scan, dim3(1), dim3(1), 0, st, L.bc, L.nb);
   hipLaunchKernelGGL(k_scatter_sel, dim3(L.nb), dim3(256), 0, st, (const unsigned char*)L.sel, n,
                      (const unsigned*)L.bc, L.cand);
   XTC_CHECK_LAUNCH();
+  SelState fin{};
+  XTC_HIP(hipMemcpyAsync(&fin, L.sst, sizeof(SelState), hipMemcpyDeviceToHost, st));
+  XTC_HIP(hipStreamSynchronize(st));
+  *count = (long)fin.cnt;
   return XTC_OK;
 }
 
@@ -485,15 +503,22 @@ namespace xtc {
 xtc_status fit_scalar_residual(const double* phi4, const xtc_grid* grid, int n_orb,
                                const int64_t* pivots, int n_mu, Arena& ar, hipStream_t st,
                                double* rel);
-size_t ws_learned(int64_t n_g, int n_orb, int n_mu, double kappa);
+size_t ws_learned(int64_t n_g, int n_orb, int n_mu, double kappa, long stride);
+xtc_status fit_residuals(const double* phi4, const xtc_grid* grid, int n_orb,
+                         const int64_t* pivots, int n_mu, Arena& ar, hipStream_t st, double* rel);
 }
 
-size_t xtc::ws_learned(int64_t n_g, int n_orb, int n_mu, double kappa) {
+// candidates at most: ceil(kappa n_mu) by score plus ceil(n_g / stride) coverage points
+static long max_candidates(int64_t n_g, int n_mu, double kappa, long stride) {
   long K = (long)ceil(kappa * n_mu);
-  if (K > n_g) K = n_g;
   if (K < n_mu) K = n_mu;
+  if (stride > 0) K += (n_g + stride - 1) / stride;
+  return K > n_g ? n_g : K;
+}
+
+size_t xtc::ws_learned(int64_t n_g, int n_orb, int n_mu, double kappa, long stride) {
   Arena ar(nullptr, 0);
-  layout_learn(ar, n_g, n_orb, K);
+  layout_learn(ar, n_g, n_orb, max_candidates(n_g, n_mu, kappa, stride));
   return ar.used;
 }
 
@@ -504,10 +529,11 @@ xtc_status xtc_select_learned(const double* phi4, const xtc_grid* grid, int n_or
   XTC_TRY(check_mlp(mlp));
   XTC_REQUIRE(mlp->n_nuc >= 1 && mlp->n_nuc <= 4096 && mlp->nuc_xyz, "learned selection: nuclei");
   XTC_REQUIRE(mlp->kappa >= 1.0, "learned selection: kappa must be >= 1");
+  XTC_REQUIRE(mlp->stride >= 0, "learned selection: stride must be >= 0");
   const long n_g = grid->n_g;
   long K = (long)ceil(mlp->kappa * n_mu);
   if (K > n_g) K = n_g;
-  LearnLayout L = layout_learn(ar, n_g, n_orb, K);
+  LearnLayout L = layout_learn(ar, n_g, n_orb, max_candidates(n_g, n_mu, mlp->kappa, mlp->stride));
   XTC_TRY(need_ws(ar));
   // features -> logits -> candidates
   XTC_HIP(hipMemcpyAsync(L.nuc, mlp->nuc_xyz, sizeof(double) * 3 * mlp->n_nuc,
@@ -521,29 +547,33 @@ xtc_status xtc_select_learned(const double* phi4, const xtc_grid* grid, int n_or
   hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n_g, 256)), dim3(256), smem, st, m,
                      (const float*)L.feats, n_g, n_g, L.logits);
   XTC_CHECK_LAUNCH();
-  XTC_TRY(top_k(L, n_g, st));
-  hipLaunchKernelGGL(k_gather_sub, dim3(cdiv(4L * n_orb * K, 256)), dim3(256), 0, st, phi4, grid->w,
-                     n_g, 4 * n_orb, (const long*)L.cand, K, L.sub, L.wsub);
+  long nc = 0;
+  XTC_TRY(top_k(L, n_g, K, mlp->stride, st, &nc));
+  hipLaunchKernelGGL(k_gather_sub, dim3(cdiv(4L * n_orb * nc, 256)), dim3(256), 0, st, phi4, grid->w,
+                     n_g, 4 * n_orb, (const long*)L.cand, nc, L.sub, L.wsub);
   XTC_CHECK_LAUNCH();
   // fused pivoting restricted to the candidates
-  xtc_grid sub{K, nullptr, L.wsub};
+  xtc_grid sub{nc, nullptr, L.wsub};
   std::vector<int64_t> local(n_mu);
   int32_t n_loc = 0;
   xtc_status s = xtc_select_qr(L.sub, &sub, n_orb, n_mu, local.data(), &n_loc, info, ar, st);
   if (s < 0) return s;
-  std::vector<long> cand(K);
-  XTC_HIP(hipMemcpyAsync(cand.data(), L.cand, sizeof(long) * K, hipMemcpyDeviceToHost, st));
+  std::vector<long> cand(nc);
+  XTC_HIP(hipMemcpyAsync(cand.data(), L.cand, sizeof(long) * nc, hipMemcpyDeviceToHost, st));
   XTC_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < n_loc; ++i) pivots[i] = cand[local[i]];
   *n_mu_out = n_loc;
   if (info) {
     info[2] = 0.0;
-    info[6] = (double)K;
+    info[6] = (double)nc;
   }
   if (mode != XTC_SELECT_LEARNED_JUDGED) return s;
-  // judge: weighted scalar-channel fit residual of the proposal over the whole grid
-  double r_l = 0.0;
-  XTC_TRY(xtc::fit_scalar_residual(phi4, grid, n_orb, pivots, n_loc, ar, st, &r_l));
+  // judge: the mean of the four relative fit residuals (scalar and the three gradient
+  // components) of the proposal over the whole grid
+  auto mean4 = [](const double* r) { return 0.25 * ((r[0] + r[1]) + (r[2] + r[3])); };
+  double rl4[4] = {0, 0, 0, 0};
+  XTC_TRY(xtc::fit_residuals(phi4, grid, n_orb, pivots, n_loc, ar, st, rl4));
+  const double r_l = mean4(rl4);
   double r_ref;
   std::vector<int64_t> qr(n_mu);
   int32_t n_qr = 0;
@@ -551,7 +581,9 @@ xtc_status xtc_select_learned(const double* phi4, const xtc_grid* grid, int n_or
     double qinfo[8] = {0};
     xtc_status sq = xtc_select_qr(phi4, grid, n_orb, n_mu, qr.data(), &n_qr, qinfo, ar, st);
     if (sq < 0) return sq;
-    XTC_TRY(xtc::fit_scalar_residual(phi4, grid, n_orb, qr.data(), n_qr, ar, st, &r_ref));
+    double rq4[4] = {0, 0, 0, 0};
+    XTC_TRY(xtc::fit_residuals(phi4, grid, n_orb, qr.data(), n_qr, ar, st, rq4));
+    r_ref = mean4(rq4);
   } else {
     r_ref = exp(mlp->ref_a + mlp->ref_b * log((double)n_mu / (double)n_orb));
   }

@@ -54,3 +54,19 @@ def test_top_candidates_ties_and_order():
     s = np.array([0.5, 2.0, 2.0, -1.0, 2.0, 0.7])
     assert mlp.top_candidates(s, 2).tolist() == [1, 2]
     assert mlp.top_candidates(s, 4).tolist() == [1, 2, 4, 5]
+
+
+def test_candidates_are_top_scores_and_coverage_points():
+    """Candidate rule of the learned proposal: the k best scores (ties to the lowest index)
+    united with every stride-th point, sorted; stride 0 is the top-k set alone."""
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    s = rng.normal(size=1000)
+    s[[10, 20, 30]] = 5.0                      # a three-way tie at the top
+    c = mlp.candidates(s, 2, 0)
+    assert c.tolist() == [10, 20]
+    c = mlp.candidates(s, 50, 7)
+    top = set(np.argsort(-s, kind="stable")[:50].tolist())
+    assert set(c.tolist()) == top | set(range(0, 1000, 7))
+    assert np.all(np.diff(c) > 0)
+    assert mlp.judge_residual([1.0, 2.0, 3.0, 6.0]) == 3.0
