@@ -81,6 +81,14 @@ def parse():
     p.add_argument("--vmc-bh", action="store_true",
                    help="with --vmc, also time the step for the 48-term BH correlator on the "
                         "workload's nuclei (c, d and b per type)")
+    p.add_argument("--learned", action="store_true",
+                   help="run only the learned-points protocol of the chain configuration: 64 "
+                        "seeded chains, the network trained on 48 (QR labels at N_mu = 10 N_orb), "
+                        "scored on the 16 held out against QR, the untrained network and random "
+                        "points, with both judges, time-to-points and time-to-V")
+    p.add_argument("--learned-epochs", type=int, default=6)
+    p.add_argument("--learned-stride", type=int, default=32)
+    p.add_argument("--learned-kappa", type=float, default=3.0)
     p.add_argument("--walkers", type=int, default=16384)
     p.add_argument("--vmc-sweeps", type=int, default=20)
     p.add_argument("--copy-probe", action="store_true",
@@ -98,6 +106,9 @@ def main():
         print(f"bench.py runs on one GPU only (the path is single-GPU in this build); got --gpus {a.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if a.learned:
+        learned_protocol(a)
+        return
     import numpy as np
     import torch
 
@@ -807,6 +818,167 @@ def field_oracle_sample(wl, rho_dev, field_dev, log, n_blk=4, width=256, seed=9)
              "sample": f"exact field of {n_blk} x {width} bra points (starts {starts.tolist()}) x "
                        f"{wl.n_g} ket points from the oracle's density; {dt:.1f} s",
              "density_max_rel_err": max(erho)}, max(errs))
+
+
+def _chain_workload(i):
+    from workloads import make_config
+    return make_config("chain", i)
+
+
+def learned_protocol(a):
+    """The chain configuration's protocol for the learned proposer. The 64 workloads are
+    built on the host by a small pool of worker processes (started before the GPU is
+    touched; they do no GPU work). Training: QR labels, features and the four-system QR
+    residual of chains 0..47; Adam on the pooled points (the library's kernels); judge 0's
+    reference log R_ref = a + b log(N_mu / N_orb) fitted on those residuals (every chain has
+    N_mu = 10 N_orb, so b = 0 and a is the mean of log R_QR). Held out, chains 48..63:
+    QR, the trained and untrained proposals (candidates: the kappa N_mu best scores and
+    every stride-th point), random points, judge 0 (production) and judge 1 (validation),
+    time-to-points, and time-to-V (orbitals, points, fit, split contraction) with and
+    without the network, with the ISDF error of the energy-scale scalar E3 against its
+    exact counterpart."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    os.environ["OMP_NUM_THREADS"] = "2"
+    pool = ProcessPoolExecutor(8, mp_context=mp.get_context("spawn"))
+    jobs = [pool.submit(_chain_workload, i) for i in range(64)]   # workers start here
+    import numpy as np
+    import torch
+
+    from oracle import mlp as omlp   # only the network's seeded initial parameters
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def judge_resid(phi4, grid, piv):
+        _, _, info, _ = api.fit(phi4, grid, piv)
+        return float(np.mean(info[4:8]))
+
+    t_start = time.perf_counter()
+    feats, labels, logr = [], [], []
+    for i in range(48):
+        wl = jobs[i].result()
+        grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+        phi4, _ = api.eval_orbitals(wl.basis, grid, wl.C_mo, wl.n_occ)
+        qr, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_QR)
+        feats.append(api.features(phi4, grid, wl.n_occ, wl.atom_xyz))
+        y = torch.zeros(wl.n_g, dtype=torch.float32, device="cuda")
+        y[torch.as_tensor(qr).cuda()] = 1.0
+        labels.append(y)
+        r = judge_resid(phi4, grid, qr)
+        logr.append((np.log(wl.n_mu / wl.n_orb), np.log(r)))
+        del phi4, grid
+        torch.cuda.empty_cache()
+        log(f"train chain {i}: H{wl.atom_xyz.shape[0]}, {wl.n_g} points, N_mu {wl.n_mu}, R_QR {r:.3e}")
+    F = torch.cat(feats, dim=1)
+    Y = torch.cat(labels)
+    del feats, labels
+    Fn = F.cpu().numpy().astype(np.float64)
+    sh, sc = Fn.mean(1).astype(np.float32), (Fn.std(1) + 1e-3).astype(np.float32)
+    del Fn
+    p0 = omlp.init_params(64, 0).astype(np.float32)
+    x = np.array([v[0] for v in logr]); lr_ = np.array([v[1] for v in logr])
+    if np.ptp(x) < 1e-12:
+        ref_a, ref_b = float(lr_.mean()), 0.0
+    else:
+        ref_b, ref_a = (float(v) for v in np.polyfit(x, lr_, 1))
+    kw = dict(hidden=64, kappa=a.learned_kappa, stride=a.learned_stride)
+    model = api.MlpModel(p0, sh, sc, ref_a=ref_a, ref_b=ref_b, **kw)
+    untrained = api.MlpModel(p0, sh, sc, **kw)
+    sync()
+    t0 = time.perf_counter()
+    hist = api.train_mlp(model, F, Y, epochs=a.learned_epochs, batch=4096, lr=2e-3, log=log)
+    sync()
+    t_train = time.perf_counter() - t0
+    n_train_points, n_pos = int(Y.numel()), int(Y.sum())
+    del F, Y
+    torch.cuda.empty_cache()
+    rows = []
+    for i in range(48, 64):
+        wl = jobs[i].result()
+        grid = api.DeviceGrid.from_host(wl.grid_xyz, wl.grid_w)
+        phi4, rho = api.eval_orbitals(wl.basis, grid, wl.C_mo, wl.n_occ)
+        sync()
+        t0 = time.perf_counter()
+        qr, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_QR)
+        sync()
+        t_qr = time.perf_counter() - t0
+        m0 = model.with_nuclei(wl.atom_xyz)
+        t0 = time.perf_counter()
+        p0_, i0, s0 = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_LEARNED_JUDGED, m0, 1.25)
+        sync()
+        t_l0 = time.perf_counter() - t0
+        m1 = model.with_nuclei(wl.atom_xyz)
+        m1.judge = 1
+        _, i1, s1 = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_LEARNED_JUDGED, m1, 1.25)
+        t0 = time.perf_counter()
+        pl, il, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_LEARNED, m0)
+        sync()
+        t_l = time.perf_counter() - t0
+        pu, _, _ = api.select_points(phi4, grid, wl.n_mu, wl.n_occ, L.XTC_SELECT_LEARNED,
+                                     untrained.with_nuclei(wl.atom_xyz))
+        rand = np.random.default_rng(i).choice(wl.n_g, wl.n_mu, replace=False)
+        r_qr, r_l, r_u, r_r = (judge_resid(phi4, grid, p) for p in (qr, pl, pu, rand))
+
+        def to_v(piv):
+            sync()
+            t = time.perf_counter()
+            xi, xig, _, _ = api.fit(phi4, grid, piv)
+            out = api.kernel_contract(grid, wl.corr, xi, xig, rho, piv, api.ALL_CHANNELS,
+                                      L.XTC_SPLIT_F16)
+            sync()
+            e = out["escale"]
+            return time.perf_counter() - t, abs(e[0] - e[3]) / abs(e[3])
+
+        t_fc_qr, e3_qr = to_v(qr)
+        t_fc_l, e3_l = to_v(p0_)
+        row = {"chain": i, "atoms": int(wl.atom_xyz.shape[0]), "n_g": wl.n_g, "n_mu": wl.n_mu,
+               "R_qr": r_qr, "R_trained": r_l, "R_untrained": r_u, "R_random": r_r,
+               "ratio_trained": r_l / r_qr, "candidates": int(il[6]),
+               "judge0_accept": s0 == 0, "judge1_accept": s1 == 0,
+               "t_points_qr_s": t_qr, "t_points_learned_s": t_l, "t_points_judged0_s": t_l0,
+               "time_to_V_qr_s": t_qr + t_fc_qr, "time_to_V_learned_s": t_l0 + t_fc_l,
+               "E3_isdf_err_qr": e3_qr, "E3_isdf_err_learned": e3_l}
+        rows.append(row)
+        del phi4, rho, grid
+        torch.cuda.empty_cache()
+        log(f"held-out chain {i}: H{row['atoms']}, R_L/R_QR {row['ratio_trained']:.3f} (untrained "
+            f"{r_u / r_qr:.1f}, random {r_r / r_qr:.1f}), judges {int(row['judge0_accept'])}"
+            f"{int(row['judge1_accept'])}, points {t_qr * 1e3:.0f} -> {t_l * 1e3:.0f} ms "
+            f"(judged {t_l0 * 1e3:.0f} ms)")
+    pool.shutdown()
+    ratios = np.array([r["ratio_trained"] for r in rows])
+    agree = np.mean([r["judge0_accept"] == r["judge1_accept"] for r in rows])
+    summ = {
+        "protocol": "64 seeded chains H10-H30; trained on chains 0-47, scored on 48-63; "
+                    f"candidates = {a.learned_kappa} N_mu best scores + every "
+                    f"{a.learned_stride}th point; judge f = 1.25 on the mean of the four relative "
+                    "fit residuals",
+        "train_points": n_train_points, "train_positives": n_pos, "epochs": a.learned_epochs,
+        "train_s": round(t_train, 2), "loss_history": [round(h, 4) for h in hist],
+        "judge0_reference": {"a": ref_a, "b": ref_b},
+        "ratio_trained_median": float(np.median(ratios)), "ratio_trained_max": float(ratios.max()),
+        "ratio_untrained_median": float(np.median([r["R_untrained"] / r["R_qr"] for r in rows])),
+        "ratio_random_median": float(np.median([r["R_random"] / r["R_qr"] for r in rows])),
+        "judge1_accept_rate": float(np.mean([r["judge1_accept"] for r in rows])),
+        "judge0_accept_rate": float(np.mean([r["judge0_accept"] for r in rows])),
+        "judge_agreement_rate": float(agree),
+        "t_points_qr_s": float(np.sum([r["t_points_qr_s"] for r in rows])),
+        "t_points_learned_s": float(np.sum([r["t_points_learned_s"] for r in rows])),
+        "t_points_judged0_s": float(np.sum([r["t_points_judged0_s"] for r in rows])),
+        "time_to_V_qr_s": float(np.sum([r["time_to_V_qr_s"] for r in rows])),
+        "time_to_V_learned_s": float(np.sum([r["time_to_V_learned_s"] for r in rows])),
+        "E3_isdf_err_ratio_median": float(np.median([r["E3_isdf_err_learned"] / r["E3_isdf_err_qr"]
+                                                     for r in rows])),
+        "wall_s": round(time.perf_counter() - t_start, 1),
+    }
+    print(json.dumps({"learned": summ, "held_out": rows}), flush=True)
 
 
 def read_pivots(config):
