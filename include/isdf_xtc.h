@@ -153,6 +153,8 @@ typedef struct {
                               selection and use its residual (validation) */
   double ref_a, ref_b;     /* judge 0: log R_ref = ref_a + ref_b log(n_mu / n_orb) */
   int32_t stride;          /* coverage: every stride-th grid point is a candidate too (0: none) */
+  int32_t bf16;            /* scoring: 0 FP32 on the vector units; 1 BF16 matrix cores (MFMA,
+                              FP32 accumulation; hidden must be 64) */
 } xtc_mlp;
 
 /* Exchange intermediates requested from xtc_kernel_contract (xTC Terms 2 and 3,
@@ -520,7 +522,9 @@ xtc_status xtc_mlp_features(const double* phi4, const xtc_grid* grid, int32_t n_
                             int32_t n_nuc, const double* nuc_xyz, float* feats, void* ws,
                             size_t ws_bytes, void* stream);
 
-/* MLP logits of n points: logits[i] = s(feats[:, i]) with the z-scoring of mlp. FP32. */
+/* MLP logits of n points: logits[i] = s(feats[:, i]) with the z-scoring of mlp; FP32, or
+ * with mlp->bf16 the weights and activations rounded to BF16 on the matrix cores (FP32
+ * accumulation, biases and SiLU in FP32). */
 xtc_status xtc_mlp_forward(const xtc_mlp* mlp, const float* feats, int64_t ld, int64_t n,
                            float* logits, void* stream);
 

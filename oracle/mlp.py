@@ -83,6 +83,26 @@ def forward(p, h, x):
     return s, (z1, a1, z2, a2)
 
 
+def to_bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned in float64: BF16 keeps the
+    upper 16 bits of the FP32 word (8 exponent bits, 7 stored significand bits)."""
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, h, x):
+    """The scores with the weights and the inputs of each product rounded to BF16 (the
+    z-scored features, W1, SiLU(z1), W2; FP32 values in, products and sums exact in FP64),
+    biases, SiLU and the last layer in full precision: the arithmetic of the BF16
+    matrix-core scoring, up to the order and precision of its FP32 sums."""
+    W1, b1, W2, b2, W3, b3 = unpack(p, h)
+    z1 = to_bf16(W1) @ to_bf16(x) + b1[:, None]
+    a1 = to_bf16(silu(z1))
+    z2 = to_bf16(W2) @ a1 + b2[:, None]
+    return W3 @ silu(z2) + b3
+
+
 def softplus(x):
     return np.logaddexp(0.0, x)
 

@@ -75,7 +75,7 @@ class Mlp(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("params", P), ("feat_shift", P),
                 ("feat_scale", P), ("kappa", C.c_double), ("n_nuc", C.c_int32), ("nuc_xyz", D),
                 ("judge", C.c_int32), ("ref_a", C.c_double), ("ref_b", C.c_double),
-                ("stride", C.c_int32)]
+                ("stride", C.c_int32), ("bf16", C.c_int32)]
 
 
 _lib = None

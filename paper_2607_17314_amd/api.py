@@ -446,7 +446,7 @@ class MlpModel:
     statistics, the nuclei for the distance features and the judge settings."""
 
     def __init__(self, params, shift, scale, hidden=64, kappa=3.0, nuclei=None, judge=0,
-                 ref_a=0.0, ref_b=0.0, stride=0):
+                 ref_a=0.0, ref_b=0.0, stride=0, bf16=False):
         self.params = _dev(params, torch.float32)
         self.shift = _dev(shift, torch.float32)
         self.scale = _dev(scale, torch.float32)
@@ -457,11 +457,12 @@ class MlpModel:
         self.judge = int(judge)
         self.ref_a, self.ref_b = float(ref_a), float(ref_b)
         self.stride = int(stride)
+        self.bf16 = bool(bf16)
 
     def c(self):
         return L.Mlp(8, self.hidden, self.params.data_ptr(), self.shift.data_ptr(),
                      self.scale.data_ptr(), self.kappa, self.nuc.shape[0], _dptr(self.nuc),
-                     self.judge, self.ref_a, self.ref_b, self.stride)
+                     self.judge, self.ref_a, self.ref_b, self.stride, int(self.bf16))
 
     def with_nuclei(self, nuclei):
         m = MlpModel.__new__(MlpModel)

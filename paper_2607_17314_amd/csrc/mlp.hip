@@ -119,6 +119,111 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev m, const float* __re
   logits[i] = point_forward(sw, m.h, x, a1, z1);
 }
 
+// BF16 MFMA inference of the 8 -> 64 -> 64 -> 1 network (v_mfma_f32_32x32x16_bf16, FP32
+// accumulation; biases and SiLU in FP32). Each wave takes tiles of 32 points. Every layer
+// is a product of the weights (A operand: rows = output units, k = input units) with the
+// activations (B operand: k = input units, columns = points), so layer 1's accumulator
+// feeds layer 2 without a transpose: lane l (point l % 32, half h = l / 32) holds the
+// units 32 mb + 8 q + 4 h + t (q, t = 0..3) of row block mb, and layer 2 takes input unit
+// u(s) = 32 (j / 2) + 16 (j % 2) + 8 (e / 4) + 4 h + e % 4 as its k slot s = 16 j + 8 h + e
+// (a permutation of the summation index, applied to W2's columns).
+// MFMA 32x32x16 layouts (as measured for the FP16 form on gfx950), lane l, element e,
+// register r: A[l % 32][8 (l / 32) + e], B[8 (l / 32) + e][l % 32],
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float mf16 __attribute__((ext_vector_type(16)));
+constexpr int BF_H = 64;   // the hidden width the BF16 kernel serves
+
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(MlpDev m, const float* __restrict__ f,
+                                                          long ld, long n,
+                                                          float* __restrict__ logits) {
+  extern __shared__ float sw[];
+  load_weights(m, sw);
+  const int np = mlp_nparams(BF_H);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const float* W1 = sw;
+  const float* b1 = W1 + NF * BF_H;
+  const float* W2 = b1 + BF_H;
+  const float* b2 = W2 + BF_H * BF_H;
+  const float* W3 = b2 + BF_H;
+  const float b3 = W3[BF_H];
+  bf8 a1f[2], a2f[2][4];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      a1f[mb][e] = (__bf16)(half == 0 ? W1[(32 * mb + col) * NF + e] : 0.0f);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int u = 32 * (j / 2) + 16 * (j % 2) + 8 * (e / 4) + 4 * half + (e % 4);
+        a2f[mb][j][e] = (__bf16)W2[(32 * mb + col) * BF_H + u];
+      }
+  const mf16 zero = {};
+  const long ntile = (n + 31) / 32;
+  for (long t = (long)blockIdx.x * 4 + wave; t < ntile; t += (long)gridDim.x * 4) {
+    const long p = t * 32 + col;
+    bf8 xb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float v = 0.0f;
+      if (half == 0 && p < n) v = (f[e * ld + p] - sw[np + e]) / sw[np + NF + e];
+      xb[e] = (__bf16)v;
+    }
+    mf16 z1[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) z1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1f[mb], xb, zero, 0, 0, 0);
+    bf8 hb[4];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int unit = 32 * mb + 8 * (r / 4) + 4 * half + r % 4;
+        hb[2 * mb + r / 8][r % 8] = (__bf16)silu(z1[mb][r] + b1[unit]);
+      }
+    mf16 z2[2] = {zero, zero};
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        z2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2f[mb][j], hb[j], z2[mb], 0, 0, 0);
+    float s = 0.0f;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int v = 32 * mb + 8 * (r / 4) + 4 * half + r % 4;
+        s += W3[v] * silu(z2[mb][r] + b2[v]);
+      }
+    s += __shfl_xor(s, 32, 64);
+    if (half == 0 && p < n) logits[p] = s + b3;
+  }
+}
+
+static xtc_status launch_forward(const xtc_mlp* mlp, const float* feats, long ld, long n,
+                                 float* logits, hipStream_t st) {
+  MlpDev m{mlp->params, mlp->feat_shift, mlp->feat_scale, mlp->hidden};
+  const size_t smem = sizeof(float) * (mlp_nparams(mlp->hidden) + 2 * NF);
+  if (mlp->bf16) {
+    XTC_REQUIRE(mlp->hidden == BF_H, "mlp: BF16 inference is built for 64 hidden units");
+    const long tiles = (n + 31) / 32;
+    long blocks = (tiles + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_mlp_forward_bf16, dim3((unsigned)blocks), dim3(256), smem, st, m, feats,
+                       ld, n, logits);
+  } else {
+    hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n, 256)), dim3(256), smem, st, m, feats, ld, n,
+                       logits);
+  }
+  XTC_CHECK_LAUNCH();
+  return XTC_OK;
+}
+
 // per-point backward quantities, point-major: rec[i] = {x[8], a1[h], d1[h], a2[h], d2[h], ds, loss}
 __global__ __launch_bounds__(256) void k_mlp_point_grad(MlpDev m, const float* __restrict__ f,
                                                         long ld, long n,
@@ -369,6 +474,11 @@ extern "C" xtc_status xtc_mlp_features(const double* phi4, const xtc_grid* grid,
 static xtc_status check_mlp(const xtc_mlp* m) {
   XTC_REQUIRE(m && m->params && m->feat_shift && m->feat_scale, "mlp: null argument");
   XTC_REQUIRE(m->in_dim == NF && m->hidden >= 1 && m->hidden <= HMAX, "mlp: bad shape");
+  XTC_REQUIRE(m->bf16 == 0 || m->bf16 == 1, "mlp: bf16 must be 0 or 1");
+  if (m->bf16 && m->hidden != BF_H) {
+    set_error("mlp: BF16 inference is built for 64 hidden units");
+    return XTC_ERR_UNSUPPORTED;
+  }
   return XTC_OK;
 }
 
@@ -376,12 +486,7 @@ extern "C" xtc_status xtc_mlp_forward(const xtc_mlp* mlp, const float* feats, in
                                       float* logits, void* stream) {
   XTC_TRY(check_mlp(mlp));
   XTC_REQUIRE(feats && logits && n > 0 && ld >= n, "xtc_mlp_forward: bad arguments");
-  MlpDev m{mlp->params, mlp->feat_shift, mlp->feat_scale, mlp->hidden};
-  const size_t smem = sizeof(float) * (mlp_nparams(mlp->hidden) + 2 * NF);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n, 256)), dim3(256), smem, as_stream(stream), m, feats,
-                     (long)ld, (long)n, logits);
-  XTC_CHECK_LAUNCH();
-  return XTC_OK;
+  return launch_forward(mlp, feats, (long)ld, (long)n, logits, as_stream(stream));
 }
 
 static inline int rec_stride(int h) { return NF + 4 * h + 2; }
@@ -542,11 +647,7 @@ xtc_status xtc_select_learned(const double* phi4, const xtc_grid* grid, int n_or
   hipLaunchKernelGGL(k_features, dim3(cdiv(n_g, 256)), dim3(256), 0, st, phi4, grid->xyz, grid->w,
                      n_g, n_orb, n_occ, (const double*)L.nuc, mlp->n_nuc, L.feats, n_g);
   XTC_CHECK_LAUNCH();
-  MlpDev m{mlp->params, mlp->feat_shift, mlp->feat_scale, mlp->hidden};
-  const size_t smem = sizeof(float) * (mlp_nparams(mlp->hidden) + 2 * NF);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n_g, 256)), dim3(256), smem, st, m,
-                     (const float*)L.feats, n_g, n_g, L.logits);
-  XTC_CHECK_LAUNCH();
+  XTC_TRY(launch_forward(mlp, L.feats, n_g, n_g, L.logits, st));
   long nc = 0;
   XTC_TRY(top_k(L, n_g, K, mlp->stride, st, &nc));
   hipLaunchKernelGGL(k_gather_sub, dim3(cdiv(4L * n_orb * nc, 256)), dim3(256), 0, st, phi4, grid->w,

@@ -96,6 +96,48 @@ def test_learned_selection_matches_oracle_pivoting_on_the_same_candidates(case, 
     assert np.array_equal(piv, ref)
 
 
+def test_bf16_forward_matches_the_oracle_emulation(case):
+    """The BF16 matrix-core scoring against the oracle's forward with the same operands
+    rounded to BF16 (the two differ only in the order and precision of the FP32 sums),
+    and the learned selection scored in BF16 against the oracle's on its own BF16
+    candidates."""
+    import torch
+    from oracle import mlp, pivots
+    from paper_2607_17314_amd import XTC_SELECT_LEARNED, api
+    wl, phi4, grid, phi4_d = case
+    f = api.features(phi4_d, grid, wl.n_occ, wl.atom_xyz)
+    fn = f.cpu().numpy()
+    model, *_ = _model(api, fn.astype(np.float64), seed=3, nuclei=wl.atom_xyz, stride=7, kappa=2.5)
+    model.bf16 = True
+    s_bf = api.mlp_forward(model, f).cpu().numpy().astype(np.float64)
+    pf = model.params.cpu().numpy().astype(np.float64)
+    sh, sc = model.shift.cpu().numpy(), model.scale.cpu().numpy()
+    x = ((fn - sh[:, None]) / sc[:, None]).astype(np.float32)      # z-scoring in FP32, as the device
+    ref = mlp.forward_bf16(pf, 64, x)
+    s32, _ = mlp.forward(pf, 64, x.astype(np.float64))
+    e = np.abs(s_bf - ref).max() / np.abs(ref).max()
+    e32 = np.abs(s_bf - s32).max() / np.abs(s32).max()
+    note(f"BF16 scoring: vs the oracle's BF16 emulation {e:.2e}, vs the FP32 network {e32:.2e}")
+    # sum order only, unless a hidden activation lands on the other side of a BF16 rounding
+    # boundary (one such flip moves a score by ~1e-5 of the largest)
+    assert e < 2e-4
+    n_mu = 150
+    piv, info, st = api.select_points(phi4_d, grid, n_mu, wl.n_occ, XTC_SELECT_LEARNED, model)
+    K = int(np.ceil(2.5 * n_mu))
+    cand_dev = mlp.candidates(s_bf, K, 7)
+    cand_ref = mlp.candidates(ref, K, 7)
+    diff = np.array(sorted(set(cand_dev.tolist()) ^ set(cand_ref.tolist())), np.int64)
+    note(f"BF16 candidates: {len(cand_dev)} from the device scores, {len(diff)} differ from the "
+         f"oracle emulation's")
+    assert int(info[6]) == len(cand_dev)
+    # a candidate may differ only where the two score sets cross the K-th score within the bound
+    kth = np.sort(ref)[::-1][K - 1]
+    assert np.all(np.abs(ref[diff] - kth) <= 4e-3 * np.abs(ref).max())
+    fp = pivots.select_fused(np.ascontiguousarray(phi4[:, :, cand_dev]), wl.grid_w[cand_dev], n_mu)
+    assert np.array_equal(piv, cand_dev[fp.pivots])
+    torch.cuda.synchronize()
+
+
 def test_corrupted_network_falls_back_to_qr(case):
     from paper_2607_17314_amd import XTC_SELECT_LEARNED_JUDGED, XTC_SELECT_QR, api
     wl, phi4, grid, phi4_d = case

@@ -70,3 +70,29 @@ def test_candidates_are_top_scores_and_coverage_points():
     assert set(c.tolist()) == top | set(range(0, 1000, 7))
     assert np.all(np.diff(c) > 0)
     assert mlp.judge_residual([1.0, 2.0, 3.0, 6.0]) == 3.0
+
+
+def test_bf16_rounding_matches_torch_and_ties_to_even():
+    """to_bf16 against torch's float32 -> bfloat16 conversion (round to nearest even), on
+    random values and on exact halfway cases."""
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-8, 8, size=5000),
+                        1.0 + np.array([1, 3, 5, 7]) * 2.0 ** -8]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.to_bf16(x), ref)
+    # halfway between 1 and 1 + 2^-7 goes down (even), between 1 + 2^-7 and 1 + 2^-6 up
+    assert mlp.to_bf16(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    assert mlp.to_bf16(np.float32(1.0 + 3 * 2.0 ** -8)) == 1.0 + 2.0 ** -6
+
+
+def test_bf16_forward_is_the_fp32_forward_to_bf16_precision():
+    from oracle import mlp
+    rng = np.random.default_rng(8)
+    p = mlp.init_params(64, 3)
+    x = rng.normal(size=(8, 2000))
+    s, _ = mlp.forward(p, 64, x)
+    sb = mlp.forward_bf16(p, 64, x)
+    e = np.abs(sb - s).max() / np.abs(s).max()
+    assert 1e-4 < e < 5e-2
