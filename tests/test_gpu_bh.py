@@ -111,30 +111,45 @@ def test_bh_adjoint_matches_oracle(bh_small, types):
     assert err < 1e-10
 
 
-def test_bh_adjoint_matches_central_differences(bh_small):
-    """Every output is a polynomial of degree <= 2 in c, so central differences are
-    exact up to rounding."""
+@pytest.mark.parametrize("types", [1, 2])
+def test_bh_autograd_matches_central_differences_on_every_coefficient(bh_small, types):
+    """Through XtcContract (torch.autograd, backward = xtc_grad): the gradient of a random
+    linear functional of every output with respect to all 48 (one nucleus type) or 96 (two
+    types) linear coefficients, against central differences of the device forward. Every
+    output is a polynomial of degree <= 2 in c, so central differences are exact up to
+    rounding."""
     import torch
     from paper_2607_17314_amd import api
     wl, xyz, w, piv, fr, rho, corr, cot = bh_small
+    if types == 2:
+        corr = _two_type(corr)
     grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
     dc = {k: t(v) for k, v in cot.items()}
-    g = api.grad(grid, corr, xi, xig, rh, piv, dc).cpu().numpy()
+    ch = CH & ~64
+    theta = torch.tensor(corr.c.ravel(), dtype=torch.float64, requires_grad=True)
+    outs = api.contract_autograd(theta, grid, corr, xi, xig, rh, piv, ch)
+    assert set(outs) == set(dc)
+    loss = sum((outs[k] * dc[k]).sum() for k in outs)
+    loss.backward()
+    g = theta.grad.numpy().copy()
 
     def L(c):
-        out = api.kernel_contract(grid, corr, xi, xig, rh, piv, CH & ~64, c=c)
-        return sum(float(torch.sum(dc[k] * out[k])) for k in ("u1", "u3", "D1", "D4", "field"))
+        out = api.kernel_contract(grid, corr, xi, xig, rh, piv, ch, c=c)
+        return sum(float(torch.sum(dc[k] * out[k])) for k in dc)
 
     c0 = corr.c.ravel().copy()
     h = 1e-4
-    for j in (0, 17, 40):
+    fd = np.zeros_like(g)
+    for j in range(c0.size):
         cp, cm = c0.copy(), c0.copy()
         cp[j] += h
         cm[j] -= h
-        fd = (L(cp) - L(cm)) / (2 * h)
-        note(f"  dL/dc[{j}]: adjoint {g[j]:.12e}, central difference {fd:.12e}")
-        assert abs(g[j] - fd) <= 1e-7 * max(1.0, np.abs(g).max())
+        fd[j] = (L(cp) - L(cm)) / (2 * h)
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    note(f"BH autograd, {types} type(s), {g.size} coefficients vs central differences: rel err {err:.2e}")
+    assert g.size == 48 * types
+    assert err < 1e-7
 
 
 @pytest.mark.parametrize("types", [1, 2])
