@@ -35,7 +35,7 @@ typedef float f16x __attribute__((ext_vector_type(16)));
 constexpr int SR = 256;        // rows per workgroup
 constexpr int SB = 32;         // bra points per workgroup
 constexpr int SKC = 128;       // ket points per chunk (8 k-steps of 16)
-constexpr int SMED = 64;       // chunks per launch: FP32 medium sum, then FP64
+constexpr int SMED = 128;      // chunks per launch: FP32 medium sum, then FP64
 #ifndef SPLIT_WAVES
 #define SPLIT_WAVES 8          // waves per workgroup (4 or 8)
 #endif
@@ -461,6 +461,11 @@ void k_stage1_split(const h8* __restrict__ At, const int* __restrict__ sA,
       for (int x = 0; x < NX; ++x) pair_stage_a(p[x], bxh, bxl, byh, byl, bzh, bzl, cn[x]);
       XTC_INTERLEAVE(4 * NB, 3);
       XTC_FENCE();
+      // the next k-step's pair coordinates, as soon as stage A has used this one's: LDS
+      // reads return in order, so issued ahead of the next K_hi and K_lo they never hold
+      // up a wait for those
+      if (j < 7) read_coords(kcb, j + 1, cn);
+      XTC_FENCE();
       // group 2: A_hi K_hi beside stage B
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -491,11 +496,10 @@ void k_stage1_split(const h8* __restrict__ At, const int* __restrict__ sA,
       }
       XTC_INTERLEAVE(4 * NB, 4);
       XTC_FENCE();
-      // the next k-step's K_lo and pair coordinates
+      // the next k-step's K_lo
       if (j < 7) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) bl[ch] = Bb[(((j + 1) * 4 + ch) * 2 + 1) * 64];
-        read_coords(kcb, j + 1, cn);
       }
       if (j == 3) store_half(buf ^ 1, fr, 0);
       XTC_FENCE();
