@@ -41,6 +41,8 @@ xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch
                             size_t scratch_bytes, hipStream_t st);
 size_t split_scratch_bytes(long n_g, int n_mu);
 size_t rho_row_scratch_bytes(long bp);
+// rows n_mu and n_mu + 1 of the panel in FP64 (split path); part: rho_row_scratch_bytes
+xtc_status rho_row_f64(const Stage1Args& a, const EECoef& cf, double* part, hipStream_t st);
 xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st);
 
 }  // namespace xtc

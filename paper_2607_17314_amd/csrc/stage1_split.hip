@@ -81,8 +81,6 @@ size_t split_scratch_bytes(long n_g, int n_mu) {
   return ar.used + 256;
 }
 
-size_t rho_row_scratch_bytes(long bp);
-
 // --- preparation --------------------------------------------------------------
 
 // w xi in FP64 from xi stored in FP64 or FP32 (T)
@@ -529,89 +527,6 @@ void k_stage1_split(const h8* __restrict__ At, const int* __restrict__ sA,
 }
 
 // Every power even (and no o = 1 term): Q1 has odd powers of rbar only, Q2 even ones.
-// The two density rows of the panel in FP64 on the vector units: row n_mu with
-// rho_gamma (field A_gamma and T3rho) and row n_mu + 1 with the ISDF density
-// rhot (H_{g,c}, which as a sum over N_mu split-precision rows would cancel):
-// one thread per bra point and ket segment; the segments' partial sums are added
-// in a fixed order by k_rho_row_sum.
-constexpr int RHO_SEG = 16;
-
-__global__ __launch_bounds__(256) void k_rho_row(const double* __restrict__ xyz,
-                                                 const double* __restrict__ w,
-                                                 const double* __restrict__ rho,
-                                                 const double* __restrict__ rhot, long n_g,
-                                                 long b0, long bn, EECoef cf,
-                                                 double* __restrict__ part) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  const long seg = blockIdx.y;
-  const long per = (n_g + RHO_SEG - 1) / RHO_SEG;
-  const long k0 = seg * per, k1 = k0 + per < n_g ? k0 + per : n_g;
-  long b = b0 + t;
-  if (b > b0 + bn - 1) b = b0 + bn - 1;
-  const double bx = xyz[b], by = xyz[n_g + b], bz = xyz[2 * n_g + b];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-  for (long g = k0; g < k1; ++g) {
-    const double dx = bx - xyz[g], dy = by - xyz[n_g + g], dz = bz - xyz[2 * n_g + g];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double tt = 1.0 / (1.0 + cf.d * r);
-    const double e = cf.d * r * tt;
-    const double t2 = tt * tt;
-    double p1 = 0.0, p2 = 0.0;
-    for (int j = cf.n1 - 1; j >= 0; --j) p1 = p1 * e + cf.q1[j];
-    for (int j = cf.n2 - 1; j >= 0; --j) p2 = p2 * e + cf.q2[j];
-    const double up = cf.d * t2 * p1;
-    double f = cf.d * cf.d * t2 * tt * p2;
-    if (cf.c1 != 0.0 && r > 0.0) f += cf.c1 * cf.d * t2 / r;
-    const double a = w[g] * rho[g];
-    const double at = w[g] * rhot[g];
-    const double fx = f * dx, fy = f * dy, fz = f * dz, sq = up * up;
-    s0 += a * fx;
-    s1 += a * fy;
-    s2 += a * fz;
-    s3 += a * sq;
-    h0 += at * fx;
-    h1 += at * fy;
-    h2 += at * fz;
-    h3 += at * sq;
-  }
-  if (t < bn) {
-    double* p = part + (seg * 8) * bn + t;
-    p[0] = s0;
-    p[bn] = s1;
-    p[2 * bn] = s2;
-    p[3 * bn] = s3;
-    p[4 * bn] = h0;
-    p[5 * bn] = h1;
-    p[6 * bn] = h2;
-    p[7 * bn] = h3;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rho_row_sum(const double* __restrict__ part, long bn,
-                                                     int n_mu, double* __restrict__ panel,
-                                                     long rows_pad, long bp) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= bn) return;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    double v = 0.0;
-    for (int sgm = 0; sgm < RHO_SEG; ++sgm) v += part[(sgm * 8 + q) * bn + t];
-    panel[((long)(q & 3) * rows_pad + n_mu + (q >> 2)) * bp + t] = v;
-  }
-}
-
-size_t rho_row_scratch_bytes(long bp) { return sizeof(double) * RHO_SEG * 8 * (size_t)bp + 256; }
-
-xtc_status rho_row_f64(const Stage1Args& a, const EECoef& cf, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho_row, dim3(cdiv(a.bn, 256), RHO_SEG), dim3(256), 0, st, a.xyz, a.w, a.rho,
-                     a.rhot, a.n_g, a.b0, a.bn, cf, part);
-  XTC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_rho_row_sum, dim3(cdiv(a.bn, 256)), dim3(256), 0, st, (const double*)part,
-                     a.bn, a.n_mu, a.panel, a.rows_pad, a.bp);
-  XTC_CHECK_LAUNCH();
-  return XTC_OK;
-}
-
 static bool even_powers(const EECoef& cf) {
   if (cf.c1 != 0.0) return false;
   for (int j = 0; j < MAXQ; ++j) {

@@ -47,6 +47,33 @@ def test_split_matches_oracle(api, cases, which):
     assert er.max() < TOL
 
 
+def test_split_odd_powers_match_oracle(api, cases):
+    """A correlator with odd powers of rbar (an o = 1 term, so u'/r carries a 1/r part, and
+    no even-power compaction) on the ragged case: the split stage 1 takes its general
+    polynomial form and the FP64 density rows their o = 1 branch."""
+    import torch
+    from oracle import contract
+    from paper_2607_17314_amd import XTC_SPLIT_F16
+    from workloads import FORM_EE, Correlator
+    case = cases["ragged"]
+    corr = Correlator(FORM_EE, np.array([[0, 0, 1], [0, 0, 2], [0, 0, 3], [0, 0, 5]], np.int32),
+                      np.array([[0.3, -0.4, 0.25, -0.1]]), 0.8)
+    ref = contract.contract(case.xyz, case.w, corr, case.fit.xi, case.fit.xigrad,
+                            case.rho[case.piv], case.rho, CH)
+    grid = api.DeviceGrid.from_host(case.xyz, case.w)
+    out = api.kernel_contract(grid, corr, torch.as_tensor(case.fit.xi).cuda(),
+                              torch.as_tensor(case.fit.xigrad).cuda(), torch.as_tensor(case.rho).cuda(),
+                              case.piv, CH, XTC_SPLIT_F16)
+    torch.cuda.synchronize()
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        e = rel_err(out[k].cpu().numpy(), ref[k])
+        note(f"  odd powers {k}: rel err {e:.2e}")
+        assert e < (1e-12 if k == "field" else TOL), k
+    er = np.abs(out["escale"] - ref["escale"]) / np.abs(ref["escale"])
+    note(f"  odd powers escale rel err {er.max():.2e}")
+    assert er.max() < TOL
+
+
 @pytest.fixture(scope="module")
 def h20_device(api):
     import torch
