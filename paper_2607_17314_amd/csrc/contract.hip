@@ -119,6 +119,7 @@ struct ConLayout {
   long* piv; double* G; double* rhot; double* panel; double* V; double* wt; double* H; double* e3x;
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
   void* gsplit; size_t gsplit_bytes; BHTable* bh;
+  void* gsplit2;   // second operand scratch: the u1/u3 products on the auxiliary stream
   // xi~ per bra super-block: the orbitals at the pivots, xi~ of the block, solve scratch
   double* phimu; double* xigb; double* fitP; double* fitR;
   long bp; long rows_pad; int nsb; int nch;
@@ -134,7 +135,7 @@ static long default_bp(int64_t n_g) {
 // super-block covers at most bp bra points, so any such width gives the same sums up to
 // their order).
 static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision,
-                            int n_orb, int n_q, long bp, bool xig_blocks) {
+                            int n_orb, int n_q, long bp, bool xig_blocks, bool dual) {
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = bp;
@@ -159,6 +160,7 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   // stage-2 GEMMs in split precision: the split operand tiles of one product
   C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
   C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
+  C.gsplit2 = (dual && C.gsplit_bytes) ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   C.bh = ar.take<BHTable>(1);
   C.phimu = C.xigb = C.fitP = C.fitR = nullptr;
   if (xig_blocks && (channels & XTC_U1)) {
@@ -175,7 +177,7 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
 size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q) {
   Arena ar(nullptr, 0);
   layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q,
-             default_bp(n_g), (flags & XTC_WS_XIGRAD_BLOCKS) != 0);
+             default_bp(n_g), (flags & XTC_WS_XIGRAD_BLOCKS) != 0, true);
   return ar.used;
 }
 
@@ -193,6 +195,32 @@ __global__ __launch_bounds__(256) void k_rhot_f32(const double* __restrict__ G,
 }  // namespace xtc
 
 using namespace xtc;
+
+// The auxiliary stream of the current device (created once, default priority, not
+// synchronised with the legacy default stream; ordered by events only), and two events
+// owned by one call.
+namespace {
+std::mutex g_aux_mu;
+hipStream_t g_aux_stream[64] = {};
+
+struct CallEvents {
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~CallEvents() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+};
+}  // namespace
+
+static xtc_status aux_stream(hipStream_t* out) {
+  int dev = -1;
+  XTC_HIP(hipGetDevice(&dev));
+  XTC_REQUIRE(dev >= 0 && dev < 64, "contract: device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  if (!g_aux_stream[dev]) XTC_HIP(hipStreamCreateWithFlags(&g_aux_stream[dev], hipStreamNonBlocking));
+  *out = g_aux_stream[dev];
+  return XTC_OK;
+}
 
 static bool xig_on_the_fly(uint32_t channels, const double* xigrad) {
   return (channels & XTC_U1) && !xigrad;
@@ -247,7 +275,7 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
                                 int64_t bra_begin, int64_t bra_end, double* u1, double* u3,
                                 double* ulap, double* D1, double* D4, double* field,
                                 double* escale, const xtc_exchange* ex, const xtc_xi_source* src,
-                                void* ws, size_t ws_bytes, long bp, void* stream) {
+                                void* ws, size_t ws_bytes, long bp, bool dual, void* stream) {
   XTC_TRY(check_contract_args(grid, corr, n_mu, xi_any, xigrad, rho, pivots, channels, precision,
                               ex, src));
   // xi in FP64 (xi) or FP32 (xi32, split path only); xi~ stored or formed per block
@@ -273,9 +301,18 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   const long n_g = grid->n_g;
   Arena ar(ws, ws_bytes);
   const int n_orb_l = ex ? ex->n_orb : (fly ? src->n_orb : 0);
-  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, n_orb_l, ex ? ex->n_q : 0, bp, fly);
+  ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, n_orb_l, ex ? ex->n_q : 0, bp, fly,
+                           dual);
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_kernel_contract"));
+  hipStream_t st2 = nullptr;
+  CallEvents evs;
+  if (C.gsplit2) {
+    XTC_TRY(aux_stream(&st2));
+    XTC_HIP(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
+    XTC_HIP(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
+  }
+  hipEvent_t ev_fork = evs.fork, ev_join = evs.join;
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   if (ex) XTC_TRY(ex_prepare(C.ex, ex->phi_piv, ex->lq, grid->xyz, grid->w, xi, n_g, st));
@@ -326,8 +363,17 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
     timing_end(tk, st);
     size_t tk2 = timing_begin(TM_STAGE2, st);
     const double beta = sb == 0 ? 0.0 : 1.0;
+    // split precision with the second operand scratch: the u1 and u3 products run on the
+    // auxiliary stream beside the D4 and D1 products, so that each product's last partial
+    // round of workgroups overlaps the next product instead of leaving the chip part idle
+    const bool two = C.gsplit2 != nullptr;
+    hipStream_t su = two ? st2 : st;
+    if (two) {
+      XTC_HIP(hipEventRecord(ev_fork, st));
+      XTC_HIP(hipStreamWaitEvent(st2, ev_fork, 0));
+    }
     auto nt = [&](const double* A, long a_sm, const double* s, const double* B, double* out,
-                  double bet, const float* A32 = nullptr) {
+                  double bet, hipStream_t ss, void* gs, const float* A32 = nullptr) {
       GemmArgs g{};
       g.M = n_mu; g.N = n_mu; g.K = bn;
       g.A = A; g.a_sm = a_sm; g.a_sk = 1;
@@ -336,14 +382,15 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
       g.B = B; g.b_sk = 1; g.b_sn = C.bp;
       g.C = out; g.c_sm = n_mu; g.c_sn = 1;
       g.beta = bet;
-      return precision == XTC_SPLIT_F16 ? gemm_split_nt(g, C.gsplit, C.gsplit_bytes, st)
-                                        : gemm_f64(g, st);
+      return precision == XTC_SPLIT_F16 ? gemm_split_nt(g, gs, C.gsplit_bytes, ss)
+                                        : gemm_f64(g, ss);
     };
     // (w xi) T^T for a panel channel, xi in FP64 or FP32
-    auto nt_xi = [&](const double* B, double* out, double bet) {
-      return xi32 ? nt(nullptr, n_g, grid->w + b0, B, out, bet, xi32 + b0)
-                  : nt(xi + b0, n_g, grid->w + b0, B, out, bet);
+    auto nt_xi = [&](const double* B, double* out, double bet, hipStream_t ss, void* gs) {
+      return xi32 ? nt(nullptr, n_g, grid->w + b0, B, out, bet, ss, gs, xi32 + b0)
+                  : nt(xi + b0, n_g, grid->w + b0, B, out, bet, ss, gs);
     };
+    void* gsu = two ? C.gsplit2 : C.gsplit;
     const double* wb = grid->w + b0;
     if (channels & XTC_U1)
       for (int c = 0; c < 3; ++c) {
@@ -354,15 +401,15 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
           double* out = C.xigb + (long)c * n_mu * C.bp;
           XTC_TRY(fit_columns(src->phi4, n_g, src->n_orb, C.phimu, n_mu, 1 + c,
                               src->chol + (1 + c) * sysd, b0, bn, out, C.bp, C.fitP, C.fitR, C.bp,
-                              st));
+                              su));
           xg = out;
           ld = C.bp;
         }
         XTC_TRY(nt(xg, ld, wb, C.panel + (long)c * C.rows_pad * C.bp, u1 + (long)c * n_mu * n_mu,
-                   beta));
+                   beta, su, gsu));
       }
-    if (channels & XTC_U3) XTC_TRY(nt_xi(C.panel + 3L * C.rows_pad * C.bp, u3, beta));
-    if (channels & XTC_ULAP) XTC_TRY(nt_xi(C.panel + 4L * C.rows_pad * C.bp, ulap, beta));
+    if (channels & XTC_U3) XTC_TRY(nt_xi(C.panel + 3L * C.rows_pad * C.bp, u3, beta, su, gsu));
+    if (channels & XTC_ULAP) XTC_TRY(nt_xi(C.panel + 4L * C.rows_pad * C.bp, ulap, beta, su, gsu));
     hipLaunchKernelGGL(k_point_vectors, dim3(cdiv(bn, 256)), dim3(256), 0, st,
                        (const double*)C.rhot, grid->w, rho, n_g, n_mu, b0, bn,
                        (const double*)C.panel, C.rows_pad, C.bp, need_h ? 1 : 0, C.wt, C.H, C.e3x,
@@ -371,19 +418,23 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
     if (channels & XTC_D4)
       for (int c = 0; c < 3; ++c) {
         const double* Pc = C.panel + (long)c * C.rows_pad * C.bp;
-        XTC_TRY(nt(Pc, C.bp, C.wt, Pc, D4, (sb == 0 && c == 0) ? 0.0 : 1.0));
+        XTC_TRY(nt(Pc, C.bp, C.wt, Pc, D4, (sb == 0 && c == 0) ? 0.0 : 1.0, st, C.gsplit));
       }
     if (channels & XTC_D1) {
       hipLaunchKernelGGL(k_form_V, dim3(cdiv((long)n_mu * bn, 256)), dim3(256), 0, st,
                          (const double*)C.panel, C.rows_pad, C.bp, n_mu, bn, (const double*)C.H,
                          C.V);
       XTC_CHECK_LAUNCH();
-      XTC_TRY(nt_xi(C.V, D1, beta));
+      XTC_TRY(nt_xi(C.V, D1, beta, st, C.gsplit));
     }
     XTC_TRY(reduce_sum_f64(C.e3x, bn, C.sums + 4 * sb, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e4x, bn, C.sums + 4 * sb + 1, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e3, bn, C.sums + 4 * sb + 2, C.red, st));
     XTC_TRY(reduce_sum_f64(C.e4, bn, C.sums + 4 * sb + 3, C.red, st));
+    if (two) {
+      XTC_HIP(hipEventRecord(ev_join, st2));
+      XTC_HIP(hipStreamWaitEvent(st, ev_join, 0));
+    }
     timing_end(tk2, st);
     // xTC Terms 2 and 3 from the same calG panel
     if (ex)
@@ -427,7 +478,7 @@ extern "C" xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correl
   XTC_REQUIRE(grid, "contract: null argument");
   return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
                        bra_end, u1, u3, ulap, D1, D4, field, escale, ex, src, ws, ws_bytes,
-                       default_bp(grid->n_g), stream);
+                       default_bp(grid->n_g), true, stream);
 }
 
 // ---- the variant without a workspace: scratch in a file-scope device array ----------
@@ -473,7 +524,7 @@ extern "C" xtc_status xtc_kernel_contract_noalloc(
   const int n_orb = ex ? ex->n_orb : (fly ? src->n_orb : 0), n_q = ex ? ex->n_q : 0;
   auto need = [&](long bp) {
     Arena ar(nullptr, 0);
-    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp, fly);
+    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp, fly, false);
     return ar.used;
   };
   long bp = default_bp(grid->n_g);
@@ -489,5 +540,5 @@ extern "C" xtc_status xtc_kernel_contract_noalloc(
   XTC_TRY(scratch_address(&ptr));
   return contract_impl(grid, corr, n_mu, xi, xigrad, rho, pivots, channels, precision, bra_begin,
                        bra_end, u1, u3, ulap, D1, D4, field, escale, ex, src, ptr,
-                       (size_t)XTC_NOALLOC_SCRATCH_BYTES, bp, stream);
+                       (size_t)XTC_NOALLOC_SCRATCH_BYTES, bp, false, stream);
 }
