@@ -315,7 +315,11 @@ typedef struct {
  * src: NULL (xi FP64; XTC_U1 needs xigrad), or the xi storage type and, for xigrad = NULL,
  *   the orbitals and kept factors (see xtc_xi_source); then the workspace query takes
  *   n_orb = src->n_orb and flags bit 24 (XTC_WS_XIGRAD_BLOCKS).
- * Asynchronous after the weight check; synchronising if escale != NULL. */
+ * Asynchronous after the weight check; synchronising if escale != NULL. In split precision
+ *   part of stage 2 runs on an internal stream of the library (one per device, created on
+ *   first use, default priority), forked from and joined back into `stream` with events
+ *   in each bra super-block: the call's work is complete when the work enqueued on
+ *   `stream` is. */
 xtc_status xtc_kernel_contract(const xtc_grid* grid, const xtc_correlator* corr, int32_t n_mu,
                                const void* xi, const double* xigrad, const double* rho,
                                const int64_t* pivots, uint32_t channels, int32_t precision,
