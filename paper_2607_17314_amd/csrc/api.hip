@@ -1,4 +1,5 @@
 // Library-wide entry points: error reporting, version, workspace queries.
+#include <mutex>
 #include "common.hpp"
 #include "plans.hpp"
 
@@ -46,6 +47,36 @@ xtc_status check_weights(const xtc_grid* grid, void* ws, size_t ws_bytes, hipStr
 }  // namespace xtc
 
 extern "C" const char* xtc_last_error(void) { return xtc::g_last_error.c_str(); }
+
+namespace xtc {
+namespace {
+std::mutex g_aux_mu;
+hipStream_t g_aux[64][AUX_STREAMS] = {};
+}  // namespace
+
+xtc_status aux_stream(int idx, hipStream_t* out) {
+  int dev = -1;
+  XTC_HIP(hipGetDevice(&dev));
+  XTC_REQUIRE(dev >= 0 && dev < 64 && idx >= 0 && idx < AUX_STREAMS,
+              "auxiliary stream: device ordinal or index out of range");
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  if (!g_aux[dev][idx]) XTC_HIP(hipStreamCreateWithFlags(&g_aux[dev][idx], hipStreamNonBlocking));
+  *out = g_aux[dev][idx];
+  return XTC_OK;
+}
+
+xtc_status CallEvents::create(int n) {
+  XTC_REQUIRE(n >= 0 && n <= 1 + AUX_STREAMS, "events: too many");
+  for (int i = 0; i < n; ++i)
+    if (!ev[i]) XTC_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  return XTC_OK;
+}
+
+CallEvents::~CallEvents() {
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+}  // namespace xtc
 
 extern "C" const char* xtc_version(void) { return "libisdfxtc 0.1.0 (gfx950)"; }
 

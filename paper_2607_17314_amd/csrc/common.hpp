@@ -104,4 +104,18 @@ xtc_status check_weights(const xtc_grid* grid, void* ws, size_t ws_bytes, hipStr
 // Deterministic FP64 sum of x[0..n) (fixed two-level tree); result to *out (device).
 xtc_status reduce_sum_f64(const double* x, long n, double* out, double* scratch, hipStream_t st);
 
+// Auxiliary stream idx (0 .. AUX_STREAMS - 1) of the current device: created on first use
+// with default priority and hipStreamNonBlocking (not synchronised with the legacy
+// default stream), kept until the process ends; work on it is ordered with the caller's
+// stream by events only.
+constexpr int AUX_STREAMS = 2;
+xtc_status aux_stream(int idx, hipStream_t* out);
+
+// Events owned by one call (fork and joins), destroyed when it returns.
+struct CallEvents {
+  hipEvent_t ev[1 + AUX_STREAMS] = {};
+  xtc_status create(int n);
+  ~CallEvents();
+};
+
 }  // namespace xtc

@@ -196,32 +196,6 @@ __global__ __launch_bounds__(256) void k_rhot_f32(const double* __restrict__ G,
 
 using namespace xtc;
 
-// The auxiliary stream of the current device (created once, default priority, not
-// synchronised with the legacy default stream; ordered by events only), and two events
-// owned by one call.
-namespace {
-std::mutex g_aux_mu;
-hipStream_t g_aux_stream[64] = {};
-
-struct CallEvents {
-  hipEvent_t fork = nullptr, join = nullptr;
-  ~CallEvents() {
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
-  }
-};
-}  // namespace
-
-static xtc_status aux_stream(hipStream_t* out) {
-  int dev = -1;
-  XTC_HIP(hipGetDevice(&dev));
-  XTC_REQUIRE(dev >= 0 && dev < 64, "contract: device ordinal out of range");
-  std::lock_guard<std::mutex> lock(g_aux_mu);
-  if (!g_aux_stream[dev]) XTC_HIP(hipStreamCreateWithFlags(&g_aux_stream[dev], hipStreamNonBlocking));
-  *out = g_aux_stream[dev];
-  return XTC_OK;
-}
-
 static bool xig_on_the_fly(uint32_t channels, const double* xigrad) {
   return (channels & XTC_U1) && !xigrad;
 }
@@ -308,11 +282,10 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   hipStream_t st2 = nullptr;
   CallEvents evs;
   if (C.gsplit2) {
-    XTC_TRY(aux_stream(&st2));
-    XTC_HIP(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
-    XTC_HIP(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
+    XTC_TRY(aux_stream(0, &st2));
+    XTC_TRY(evs.create(2));
   }
-  hipEvent_t ev_fork = evs.fork, ev_join = evs.join;
+  hipEvent_t ev_fork = evs.ev[0], ev_join = evs.ev[1];
   if (bh) XTC_HIP(hipMemcpyAsync(C.bh, &bt, sizeof(BHTable), hipMemcpyHostToDevice, st));
   XTC_HIP(hipMemcpyAsync(C.piv, pivots, sizeof(long) * n_mu, hipMemcpyHostToDevice, st));
   if (ex) XTC_TRY(ex_prepare(C.ex, ex->phi_piv, ex->lq, grid->xyz, grid->w, xi, n_g, st));

@@ -146,17 +146,25 @@ __global__ void k_resid(const double* __restrict__ phi4, const double* __restric
   m_out[t] = ww * m2;
 }
 
+// Chunks of grid columns are independent in the right-hand sides and the solves, so
+// isdf_fit runs them in up to FIT_LANES lanes (the caller's stream and auxiliary ones),
+// each with its own scratch: P, R, rtmp, mtmp and red below are lane 0's, Px[l], ... lane l's.
+constexpr int FIT_LANES = 1 + AUX_STREAMS;
+
 struct FitLayout {
   long* piv; double* phimu; double* G; double* A; double* Asave; double* linv; double* P;
   double* R; double* rtmp; double* mtmp; double* red; double* sums; int* fail; double* dg;
-  long chunk; int nblk; int nchunks;
+  double* Px[FIT_LANES]; double* Rx[FIT_LANES]; double* rtx[FIT_LANES]; double* mtx[FIT_LANES];
+  double* redx[FIT_LANES];
+  long chunk; int nblk; int nchunks; int lanes;
 };
 
-static FitLayout layout_fit(Arena& ar, int64_t n_g, int n_orb, int n_mu) {
+static FitLayout layout_fit(Arena& ar, int64_t n_g, int n_orb, int n_mu, bool lanes = false) {
   FitLayout F;
   F.chunk = n_g < FIT_CHUNK ? n_g : FIT_CHUNK;
   F.nblk = (int)cdiv(n_mu, NB);
   F.nchunks = (int)cdiv(n_g, F.chunk);
+  F.lanes = lanes ? (F.nchunks < FIT_LANES ? F.nchunks : FIT_LANES) : 1;
   F.piv = ar.take<long>(n_mu);
   F.phimu = ar.take<double>(4 * (size_t)n_orb * n_mu);
   F.G = ar.take<double>((size_t)n_mu * n_mu);
@@ -171,13 +179,21 @@ static FitLayout layout_fit(Arena& ar, int64_t n_g, int n_orb, int n_mu) {
   F.sums = ar.take<double>(2 * (size_t)F.nchunks + 2);
   F.fail = ar.take<int>(1);
   F.dg = ar.take<double>(n_mu);
+  F.Px[0] = F.P; F.Rx[0] = F.R; F.rtx[0] = F.rtmp; F.mtx[0] = F.mtmp; F.redx[0] = F.red;
+  for (int l = 1; l < F.lanes; ++l) {
+    F.Px[l] = ar.take<double>((size_t)n_mu * F.chunk);
+    F.Rx[l] = ar.take<double>((size_t)n_mu * F.chunk);
+    F.rtx[l] = ar.take<double>(F.chunk);
+    F.mtx[l] = ar.take<double>(F.chunk);
+    F.redx[l] = ar.take<double>(1024);
+  }
   return F;
 }
 
 size_t ws_fit(int64_t n_g, int n_orb, int n_mu, uint32_t what) {
   (void)what;
   Arena ar(nullptr, 0);
-  layout_fit(ar, n_g, n_orb, n_mu);
+  layout_fit(ar, n_g, n_orb, n_mu, true);
   ar.take<double>(n_mu);   // rho at the pivots, when rhot is asked for
   return ar.used;
 }
@@ -474,7 +490,9 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < n_g, "isdf_fit: pivot index out of range");
   hipStream_t st = as_stream(stream);
   Arena ar(ws, ws_bytes);
-  FitLayout F = layout_fit(ar, n_g, n_orb, n_mu);
+  FitLayout F = layout_fit(ar, n_g, n_orb, n_mu, true);
+  CallEvents evs;
+  if (F.lanes > 1) XTC_TRY(evs.create(F.lanes));
   double* Grho = rhot ? ar.take<double>(n_mu) : nullptr;   // rho at the pivots
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "isdf_fit"));
@@ -525,34 +543,50 @@ extern "C" xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t
     }
     if (keep) XTC_TRY(keep_factor(F, n, chol + sys * sys_doubles, st));
     if (!solve) continue;
-    // the FP64 solution of a chunk goes straight into the output, or (FP32 xi) into P first
+    // the FP64 solution of a chunk goes straight into the output, or (FP32 xi) into P first;
+    // chunk c runs in lane c % lanes (lane 0 on the caller's stream), forked from and
+    // joined back into it with events
     const bool f32 = sys == 0 && xi_prec == XTC_FP32;
+    hipStream_t ls[FIT_LANES] = {st};
+    if (F.lanes > 1) {
+      XTC_HIP(hipEventRecord(evs.ev[0], st));
+      for (int l = 1; l < F.lanes; ++l) {
+        XTC_TRY(aux_stream(l - 1, &ls[l]));
+        XTC_HIP(hipStreamWaitEvent(ls[l], evs.ev[0], 0));
+      }
+    }
     for (int c = 0; c < F.nchunks; ++c) {
+      const int l = c % F.lanes;
+      hipStream_t sl = ls[l];
       long g0 = (long)c * F.chunk;
       long cn = (n_g - g0) < F.chunk ? (n_g - g0) : F.chunk;
-      double* out = f32 ? F.P : (sys == 0 ? (double*)xi : xigrad + (long)comp * n * n_g) + g0;
+      double* out = f32 ? F.Px[l] : (sys == 0 ? (double*)xi : xigrad + (long)comp * n * n_g) + g0;
       const long ldo = f32 ? F.chunk : n_g;
-      XTC_TRY(rhs_chunk(phi4, n_g, n_orb, F.phimu, n, comp, g0, cn, F.P, F.R, F.chunk, st));
-      XTC_TRY(solve_chunk(factor_of(F, n), cn, F.R, F.chunk, out, ldo, st));
-      hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, st, phi4, grid->w, n_g,
-                         n_orb, comp, g0, cn, (const double*)out, ldo, n_mu, F.rtmp, F.mtmp);
+      XTC_TRY(rhs_chunk(phi4, n_g, n_orb, F.phimu, n, comp, g0, cn, F.Px[l], F.Rx[l], F.chunk, sl));
+      XTC_TRY(solve_chunk(factor_of(F, n), cn, F.Rx[l], F.chunk, out, ldo, sl));
+      hipLaunchKernelGGL(k_resid, dim3(cdiv(cn, 256)), dim3(256), 0, sl, phi4, grid->w, n_g,
+                         n_orb, comp, g0, cn, (const double*)out, ldo, n_mu, F.rtx[l], F.mtx[l]);
       XTC_CHECK_LAUNCH();
-      XTC_TRY(reduce_sum_f64(F.rtmp, cn, F.sums + 2 * c, F.red, st));
-      XTC_TRY(reduce_sum_f64(F.mtmp, cn, F.sums + 2 * c + 1, F.red, st));
-      XTC_TRY(back_chunk(factor_of(F, n), cn, F.R, F.chunk, out, ldo, st));
+      XTC_TRY(reduce_sum_f64(F.rtx[l], cn, F.sums + 2 * c, F.redx[l], sl));
+      XTC_TRY(reduce_sum_f64(F.mtx[l], cn, F.sums + 2 * c + 1, F.redx[l], sl));
+      XTC_TRY(back_chunk(factor_of(F, n), cn, F.Rx[l], F.chunk, out, ldo, sl));
       if (sys == 0 && rhot) {   // ISDF density from the FP64 solution (the product the
         GemmArgs g{};           // contraction forms from FP64 xi, element for element)
         g.M = 1; g.N = cn; g.K = n;
         g.A = Grho; g.a_sm = 1; g.a_sk = 1;
         g.B = out; g.b_sk = ldo; g.b_sn = 1;
         g.C = rhot + g0; g.c_sm = n_g; g.c_sn = 1;
-        XTC_TRY(gemm_f64(g, st));
+        XTC_TRY(gemm_f64(g, sl));
       }
       if (f32) {
-        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n * cn, 256)), dim3(256), 0, st, (const double*)out,
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n * cn, 256)), dim3(256), 0, sl, (const double*)out,
                            ldo, (float*)xi + g0, n_g, n, cn);
         XTC_CHECK_LAUNCH();
       }
+    }
+    for (int l = 1; l < F.lanes; ++l) {
+      XTC_HIP(hipEventRecord(evs.ev[l], ls[l]));
+      XTC_HIP(hipStreamWaitEvent(st, evs.ev[l], 0));
     }
     std::vector<double> hs(2 * F.nchunks);
     XTC_HIP(hipMemcpyAsync(hs.data(), F.sums, sizeof(double) * 2 * F.nchunks,
