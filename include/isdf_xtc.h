@@ -269,7 +269,9 @@ xtc_status isdf_select_points(const double* phi4, const xtc_grid* grid, int32_t 
  * info: host [8] or NULL: {shift index k per system (-1 none) x4, relative weighted
  * residual sum_g w^2 (|m_g|^2 - xi(g).B(g)) / sum_g w^2 |m_g|^2 x4} (scalar, x, y, z; the
  * residual of a system is reported when its solution is asked for, else 0).
- * Returns XTC_WARN_JITTER if any shift was used. Synchronising. */
+ * Returns XTC_WARN_JITTER if any shift was used. Synchronising. Grids of more than 65,536
+ * points run their column chunks on `stream` and up to two internal streams of the
+ * library (per device, default priority), joined back into `stream` before it returns. */
 xtc_status isdf_fit(const double* phi4, const xtc_grid* grid, int32_t n_orb,
                     const int64_t* pivots, int32_t n_mu, uint32_t what, int32_t xi_prec,
                     void* xi, double* xigrad, double* chol, const double* rho, double* rhot,
