@@ -33,19 +33,32 @@ __global__ void k_gather_piv(const double* __restrict__ phi4, long n_g, int rows
 // Factor the NB x NB diagonal block at (j0, j0) of the n x n matrix a (row-major,
 // lower triangle used) in LDS, write L_jj back (upper part zeroed) and its
 // inverse to linv [NB][NB]; a non-positive or non-finite pivot sets *fail.
+// One workgroup of 256 threads as 16 x 16. The factorisation runs column by column
+// (right-looking, the trailing update spread over the 16 x 16 threads); the inverse
+// goes by 16 x 16 blocks: the four diagonal blocks first (one column per thread),
+// then the blocks below the diagonal by block diagonals,
+//   X_IJ = -inv(L_II) sum_{J <= K < I} L_IK X_KJ,
+// so that its longest dependent chain is ~300 products instead of ~NB^2 / 2.
+constexpr int PB = 16;   // inverse block
+
 __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ a, long n, long j0,
                                                     int nb, double* __restrict__ linv,
                                                     int* __restrict__ fail) {
+  static_assert(NB == 4 * PB, "the inverse works on 4 x 4 blocks of 16");
   __shared__ double s[NB][NB + 1];
   __shared__ double sinv[NB][NB + 1];
+  __shared__ double tmp[NB][NB + 1];
+  __shared__ double rdiag[NB];
   __shared__ int bad;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   if (t == 0) bad = 0;
   for (int e = t; e < NB * NB; e += 256) {
-    int i = e / NB, k = e % NB;
+    const int i = e / NB, k = e % NB;
     s[i][k] = (i < nb && k < nb && k <= i) ? a[(j0 + i) * n + j0 + k] : 0.0;
     sinv[i][k] = 0.0;
   }
+  // padding rows and columns past nb: unit diagonal, so the blocked inverse stays regular
+  if (t < NB && t >= nb) s[t][t] = 1.0;
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     if (t == 0) {
@@ -54,32 +67,56 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ a, long
         bad = 1;
         v = 1.0;
       }
-      s[j][j] = sqrt(v);
+      const double d = sqrt(v);
+      s[j][j] = d;
+      rdiag[j] = 1.0 / d;
     }
     __syncthreads();
-    const double dj = s[j][j];
-    for (int i = j + 1 + t; i < nb; i += 256) s[i][j] /= dj;
+    const double rj = rdiag[j];
+    for (int i = j + 1 + t; i < nb; i += 256) s[i][j] *= rj;
     __syncthreads();
-    const int m = nb - j - 1;   // trailing (i, k), j < k <= i < nb
-    for (int e = t; e < m * m; e += 256) {
-      int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) s[i][k] -= s[i][j] * s[k][j];
+    // trailing update of (i, k), j < k <= i < nb
+    for (int i = j + 1 + ty; i < nb; i += 16) {
+      const double sij = s[i][j];
+      for (int k = j + 1 + tx; k <= i; k += 16) s[i][k] -= sij * s[k][j];
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular block, one column per thread
-  if (t < nb) {
-    const int c = t;
-    for (int i = 0; i < nb; ++i) {
-      if (i < c) continue;
+  for (int i = t; i < NB; i += 256)
+    if (i >= nb) rdiag[i] = 1.0;
+  __syncthreads();
+  // diagonal blocks: thread (block b = ty / 4 .. , column) -- 64 threads, one column each
+  if (t < NB) {
+    const int b = t / PB, c = t;
+    const int r0 = b * PB;
+    for (int i = c; i < r0 + PB; ++i) {
       double v = (i == c) ? 1.0 : 0.0;
       for (int k = c; k < i; ++k) v -= s[i][k] * sinv[k][c];
-      sinv[i][c] = v / s[i][i];
+      sinv[i][c] = v * rdiag[i];
     }
   }
   __syncthreads();
+  // block diagonals d = 1, 2, 3: T_IJ = sum_{J <= K < I} L_IK X_KJ, then X_IJ = -inv(L_II) T_IJ
+  for (int d = 1; d < 4; ++d) {
+    for (int J = 0; J + d < 4; ++J) {
+      const int I = J + d;
+      const int r = I * PB + ty, c = J * PB + tx;
+      double v = 0.0;
+      for (int k = J * PB; k < I * PB; ++k) v += s[r][k] * sinv[k][c];
+      tmp[r][c] = v;
+    }
+    __syncthreads();
+    for (int J = 0; J + d < 4; ++J) {
+      const int I = J + d;
+      const int r = I * PB + ty, c = J * PB + tx;
+      double v = 0.0;
+      for (int k = I * PB; k <= r; ++k) v += sinv[r][k] * tmp[k][c];
+      sinv[r][c] = -v;
+    }
+    __syncthreads();
+  }
   for (int e = t; e < NB * NB; e += 256) {
-    int i = e / NB, k = e % NB;
+    const int i = e / NB, k = e % NB;
     linv[e] = (i < nb && k < nb) ? sinv[i][k] : 0.0;
     if (i < nb && k < nb) a[(j0 + i) * n + j0 + k] = (k <= i) ? s[i][k] : 0.0;
   }
