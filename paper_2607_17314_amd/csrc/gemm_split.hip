@@ -136,6 +136,80 @@ __global__ __launch_bounds__(256) void k_split_tiles(SegOperand o, long rows,
   T[base + 64] = lo;
 }
 
+// The same split for a k-contiguous operand (sk 1), whose eight values per thread are one
+// contiguous run of a row: loaded as 16-byte vectors where the run is aligned and whole.
+__device__ __forceinline__ void load8(const double* p, double (&v)[8]) {
+  const double2* q = (const double2*)p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 t = q[i];
+    v[2 * i] = t.x;
+    v[2 * i + 1] = t.y;
+  }
+}
+__device__ __forceinline__ void load8(const float* p, double (&v)[8]) {
+  const float4* q = (const float4*)p;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float4 t = q[i];
+    v[4 * i] = t.x;
+    v[4 * i + 1] = t.y;
+    v[4 * i + 2] = t.z;
+    v[4 * i + 3] = t.w;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_split_tiles_k1(SegOperand o, long rows,
+                                                        const int* __restrict__ e, long nrb,
+                                                        long nks, long nks_seg,
+                                                        g8* __restrict__ T) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nrb * nks * 64) return;
+  const int lane = (int)(t % 64);
+  const long ks = (t / 64) % nks;
+  const long rb = t / (64 * nks);
+  const long r = rb * 32 + (lane % 32);
+  const int sg = (int)(ks / nks_seg);
+  const long k0 = (ks % nks_seg) * 16 + 8 * (lane / 32);
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (r < rows && sg < o.nseg && k0 < o.K) {
+    const long off = r * o.sm + k0;
+    const bool whole = k0 + 8 <= o.K;
+    if (o.Xf[sg]) {
+      const float* p = o.Xf[sg] + off;
+      if (whole && ((uintptr_t)p & 15) == 0) load8(p, v);
+      else
+        for (int q = 0; q < 8; ++q) v[q] = k0 + q < o.K ? (double)p[q] : 0.0;
+    } else {
+      const double* p = o.X[sg] + off;
+      if (whole && ((uintptr_t)p & 15) == 0) load8(p, v);
+      else
+        for (int q = 0; q < 8; ++q) v[q] = k0 + q < o.K ? p[q] : 0.0;
+    }
+    if (o.s[sg]) {
+      double sv[8];
+      const double* ps = o.s[sg] + k0;
+      if (whole && ((uintptr_t)ps & 15) == 0) load8(ps, sv);
+      else
+        for (int q = 0; q < 8; ++q) sv[q] = k0 + q < o.K ? ps[q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] *= sv[q];
+    }
+  }
+  const double sc = ldexp(1.0, e[r]);
+  g8 hi, lo;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double x = v[q] * sc;
+    const _Float16 h = (_Float16)(float)x;
+    hi[q] = h;
+    lo[q] = (_Float16)(float)(x - (double)(float)h);
+  }
+  const long base = ((rb * nks + ks) * 2) * 64 + lane;
+  T[base] = hi;
+  T[base + 64] = lo;
+}
+
 #define XTC_GFENCE() __builtin_amdgcn_sched_barrier(0)
 
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
@@ -248,6 +322,12 @@ static xtc_status split_operand(const SegOperand& o, long rows, long rows_pad, l
                        e);
   }
   XTC_CHECK_LAUNCH();
+  if (o.sk == 1) {
+    hipLaunchKernelGGL(k_split_tiles_k1, dim3(cdiv((rows_pad / 32) * nks * 64, 256)), dim3(256), 0,
+                       st, o, rows, (const int*)e, rows_pad / 32, nks, nks_seg, T);
+    XTC_CHECK_LAUNCH();
+    return XTC_OK;
+  }
   hipLaunchKernelGGL(k_split_tiles, dim3(cdiv((rows_pad / 32) * nks * 64, 256)), dim3(256), 0, st,
                      o, rows, (const int*)e, rows_pad / 32, nks, nks_seg, T);
   XTC_CHECK_LAUNCH();
