@@ -83,8 +83,27 @@ __global__ __launch_bounds__(256) void k_row_exp(SegOperand o, long rows, int* _
   const long r = blockIdx.x;
   double m = 0.0;
   if (r < rows)
-    for (int sg = 0; sg < o.nseg; ++sg)
-      for (long k = threadIdx.x; k < o.K; k += 256) m = fmax(m, fabs(seg_value(o, sg, r, k)));
+    for (int sg = 0; sg < o.nseg; ++sg) {
+      const double* X = o.X[sg] ? o.X[sg] + r * o.sm : nullptr;
+      const double* sc = o.s[sg];
+      // FP64 rows that start on a 16-byte boundary: two values per load (the maximum does
+      // not depend on the order it is taken in)
+      if (X && !o.Xf[sg] && ((uintptr_t)X & 15) == 0 && (!sc || ((uintptr_t)sc & 15) == 0)) {
+        const long K2 = o.K / 2;
+        for (long k = threadIdx.x; k < K2; k += 256) {
+          double2 v = ((const double2*)X)[k];
+          if (sc) {
+            const double2 t = ((const double2*)sc)[k];
+            v.x *= t.x;
+            v.y *= t.y;
+          }
+          m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+        }
+        if ((o.K & 1) && threadIdx.x == 0) m = fmax(m, fabs(seg_value(o, sg, r, o.K - 1)));
+      } else {
+        for (long k = threadIdx.x; k < o.K; k += 256) m = fmax(m, fabs(seg_value(o, sg, r, k)));
+      }
+    }
   red[threadIdx.x] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
