@@ -237,8 +237,8 @@ def main():
                    "xigrad": "per bra super-block from the kept factors" if blocks else "stored"},
         "time_to_V_s": round(dt, 4),
         "stage_ms": {k: round(v["ms"] / a.steps, 2) for k, v in tm.items() if v["launches"]},
-        "roofline": {"bound": "mfma", "kernel": "stage-1 pair kernel (k_stage1_split)"
-                     if prec == L.XTC_SPLIT_F16 else "stage-1 pair kernel (k_stage1_f64)",
+        "roofline": {"bound": "mfma", "kernel": s1_kernel_name(prec == L.XTC_SPLIT_F16,
+                                                              wl.corr.form != 0),
                      "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4),
                      "traffic": (recorded_traffic("stage1_split_h20_hbm_traffic.md")
@@ -387,6 +387,15 @@ def main():
 
 
 GATE = 1e-6   # the mixed path's bound per output block (max |got - ref| / max |ref|)
+
+
+def s1_kernel_name(split, bh):
+    if not split:
+        return "stage-1 pair kernel (k_stage1_f64_bh)" if bh else "stage-1 pair kernel (k_stage1_f64)"
+    if bh:
+        return ("stage-1 split products (k_stage1_split_pv; the FP64 pair values of k_bh_pairs "
+                "are timed under stage_ms.bh_pairs)")
+    return "stage-1 pair kernel (k_stage1_split)"
 
 
 def block_errors(out, ref, cols=None):

@@ -199,9 +199,13 @@ enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
 
 /* Flag of the contraction's workspace query: xi~ formed per bra super-block. */
 #define XTC_WS_XIGRAD_BLOCKS (1u << 24)
+/* Flag of the contraction's workspace query: the correlator is of the BH form (in split
+ * precision its pair values are generated into a buffer of the workspace). */
+#define XTC_WS_BH (1u << 25)
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
- * precision in bits 16..23 and, for CONTRACT, XTC_WS_XIGRAD_BLOCKS) or the select mode
+ * precision in bits 16..23 and, for CONTRACT, XTC_WS_XIGRAD_BLOCKS and XTC_WS_BH) or the
+ * select mode
  * (SELECT) or the fit mask (FIT) or
  * the precision (EXCHANGE) or the output mask (ASSEMBLY; ONE_BODY takes none); for
  * SELECT in a learned mode, flags = mode | (mlp->stride << 8) and n_aux = ceil(100 kappa).
@@ -305,7 +309,12 @@ typedef struct {
  * escale: host [6] or NULL: {E3, E4, E1, E3x, E4x, E1x} with E3 = G^T u3 G,
  *   E4 = G^T D4 G, E1 = 2 G^T D1 G and their ISDF-free counterparts
  *   E3x = sum_{g,g'} w w' rho rho' |grad_1 u|^2, E4x = sum_g w rho |A_gamma|^2, E1x = 2 E4x.
- * precision: XTC_FP64 or XTC_SPLIT_F16.
+ * precision: XTC_FP64 or XTC_SPLIT_F16. The BH form runs on both (without XTC_ULAP); in
+ *   split precision the four channels of every grid pair are generated in FP64 and stored
+ *   split into FP16 pairs, one ket range of 16,384 points at a time, for the same split
+ *   products (workspace query with XTC_WS_BH: about bp x 256 KiB more, bp the super-block
+ *   width of at most 16,384 points), and its exchange outputs (ex) need XTC_FP64
+ *   (XTC_ERR_UNSUPPORTED otherwise).
  * [bra_begin, bra_end): the bra points g summed over (non-empty, inside the grid; the ket
  *   sums always cover the whole grid). (0, n_g) gives the outputs above; disjoint ranges
  *   give partial sums that add up to them (the bra sharding across devices); field is
@@ -515,9 +524,10 @@ xtc_status xtc_vmc_gn_step(int64_t n_walkers, int32_t n_params, const double* E,
  * products (operand splitting included), 11 the exchange's stage 1 on the projected
  * rows (split path), 12 the exchange's split X-product kernel alone (one entry per
  * launch), 13 the assembly panel kernel (one entry per launch), 14 VMC sampling,
- * 15 VMC local energies, 16 the Gauss-Newton step.
+ * 15 VMC local energies, 16 the Gauss-Newton step, 17 the pair-value generation of the BH
+ * form in split precision (one entry per launch; its split products count under 8).
  * out: host [2 * XTC_TIMING_CATEGORIES]. Not thread-safe. */
-#define XTC_TIMING_CATEGORIES 17
+#define XTC_TIMING_CATEGORIES 18
 xtc_status xtc_timing(int32_t mode, double* out);
 
 /* Learned-point features (see xtc_mlp): feats[k][g], k = 0..7 = log of w, sum phi^2,

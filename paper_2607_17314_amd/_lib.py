@@ -15,6 +15,7 @@ XTC_U1, XTC_U3, XTC_ULAP, XTC_D1, XTC_D4, XTC_FIELD, XTC_ESCALE = 1, 2, 4, 8, 16
 XTC_SELECT_QR, XTC_SELECT_LEARNED, XTC_SELECT_LEARNED_JUDGED = 0, 1, 2
 XTC_FIT_XI, XTC_FIT_XIGRAD, XTC_FIT_KEEP_CHOL = 1, 2, 4
 XTC_WS_XIGRAD_BLOCKS = 1 << 24
+XTC_WS_BH = 1 << 25
 
 
 def chol_system_doubles(n_mu: int) -> int:
@@ -165,4 +166,4 @@ EXPORTED = ["xtc_last_error", "xtc_version", "xtc_workspace_bytes", "xtc_eval_or
             "xtc_vmc_sample", "xtc_vmc_local_energy", "xtc_vmc_gn_step"]
 TIMING_CATEGORIES = ["stage1", "stage2", "select", "fit", "orbitals", "grad", "mlp", "split_prep",
                      "stage1_kernel", "x_pairs", "x_gemm", "x_stage1", "x_mfma", "asm_panel",
-                     "vmc_sample", "vmc_energy", "vmc_gn"]
+                     "vmc_sample", "vmc_energy", "vmc_gn", "bh_pairs"]

@@ -276,6 +276,8 @@ def kernel_contract(grid: DeviceGrid, corr, xi, xigrad, rho, pivots, channels: i
         _check("xtc_kernel_contract_noalloc", L.lib().xtc_kernel_contract_noalloc(*args, _stream()))
     else:
         flags = channels | (precision << 16)
+        if int(corr.form) == L.XTC_U_BH:
+            flags |= L.XTC_WS_BH
         if src is not None and xigrad is None and channels & L.XTC_U1:
             flags |= L.XTC_WS_XIGRAD_BLOCKS
             n_orb = int(src.phi4.shape[1])

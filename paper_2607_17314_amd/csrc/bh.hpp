@@ -56,4 +56,69 @@ __device__ __forceinline__ double bh_a(const BHTable* __restrict__ T, int I, dou
   return b * r / (1.0 + b * r);
 }
 
+// grad_1 u at one pair from the regrouped sums above: TB[I][(a, da/dx, da/dy, da/dz)][slot]
+// holds the bra point's nuclear values in slot gb of NBR, TK[I][o][m] = gamma_{I,o,m} of the
+// ket point, (dx, dy, dz) = r_bra - r_ket. out: d_x u, d_y u, d_z u, |grad_1 u|^2.
+template <int NBR>
+__device__ __forceinline__ void bh_pair_channels(const EECoef& cf, int nn,
+                                                 const double (*TB)[4][NBR], int gb,
+                                                 const double (*TK)[BH_NO][BH_NP], double dx,
+                                                 double dy, double dz, double* out) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double t = 1.0 / (1.0 + cf.d * r);
+  const double e = cf.d * r * t;
+  const double t2 = t * t;
+  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
+  double GF[BH_NO][3] = {};
+  for (int I = 0; I < nn; ++I) {
+    const double a1 = TB[I][0][gb], ax = TB[I][1][gb], ay = TB[I][2][gb], az = TB[I][3][gb];
+    const double a2 = a1 * a1, a3 = a2 * a1;
+#pragma unroll
+    for (int o = 0; o < BH_NO; ++o) {
+      const double* g = TK[I][o];
+      F[o] += g[0] + a1 * g[1] + a2 * g[2] + a3 * g[3];
+      const double Dv = g[1] + 2.0 * a1 * g[2] + 3.0 * a2 * g[3];
+      GF[o][0] += Dv * ax;
+      GF[o][1] += Dv * ay;
+      GF[o][2] += Dv * az;
+    }
+  }
+  const double E[BH_NO] = {1.0, e, e * e, e * e * e};
+  double N[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) N[c] = GF[0][c] + E[1] * GF[1][c] + E[2] * GF[2][c] + E[3] * GF[3][c];
+  double q = 0.0;   // U'_ee(rbar), the pure electron-electron part
+  for (int j = cf.n1 - 1; j >= 0; --j) q = q * e + cf.q1[j];
+  double S = cf.d * t2 * (F[1] + 2.0 * E[1] * F[2] + 3.0 * E[2] * F[3] + q);
+  if (r > 0.0) {
+    const double sr = S / r;
+    out[0] = N[0] + sr * dx;
+    out[1] = N[1] + sr * dy;
+    out[2] = N[2] + sr * dz;
+    out[3] = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
+  } else {
+    out[0] = N[0];
+    out[1] = N[1];
+    out[2] = N[2];
+    out[3] = N[0] * N[0] + N[1] * N[1] + N[2] * N[2] + S * S;
+  }
+}
+
+// gamma_{I,o,m}(g) = sum_n csym[type(I)][m][n][o] a_I(g)^n into out[o][m]
+__device__ __forceinline__ void bh_ket_gamma(const BHTable* __restrict__ T, int I, double x,
+                                             double y, double z, double (*out)[BH_NP]) {
+  const double a = bh_a(T, I, x, y, z);
+  const double A2[BH_NP] = {1.0, a, a * a, a * a * a};
+  const int ty = T->type[I];
+#pragma unroll
+  for (int o = 0; o < BH_NO; ++o)
+#pragma unroll
+    for (int m = 0; m < BH_NP; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int n = 0; n < BH_NP; ++n) s += T->csym[ty][m][n][o] * A2[n];
+      out[o][m] = s;
+    }
+}
+
 }  // namespace xtc

@@ -135,7 +135,7 @@ static long default_bp(int64_t n_g) {
 // super-block covers at most bp bra points, so any such width gives the same sums up to
 // their order).
 static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels, int precision,
-                            int n_orb, int n_q, long bp, bool xig_blocks, bool dual) {
+                            int n_orb, int n_q, long bp, bool xig_blocks, bool dual, bool bh) {
   ConLayout C;
   C.nch = (channels & XTC_ULAP) ? 5 : 4;
   C.bp = bp;
@@ -155,7 +155,9 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   C.sums = ar.take<double>(4 * (size_t)C.nsb + 4);
   C.red = ar.take<double>(1024);
   C.split_bytes = precision == XTC_SPLIT_F16
-                      ? split_scratch_bytes(n_g, n_mu) + rho_row_scratch_bytes(C.bp) : 0;
+                      ? split_scratch_bytes(n_g, n_mu) + rho_row_scratch_bytes(C.bp) +
+                            (bh ? bh_split_scratch_bytes(C.bp) : 0)
+                      : 0;
   C.split = C.split_bytes ? (void*)ar.take<char>(C.split_bytes) : nullptr;
   // stage-2 GEMMs in split precision: the split operand tiles of one product
   C.gsplit_bytes = precision == XTC_SPLIT_F16 ? gemm_split_scratch_bytes(n_mu, n_mu, C.bp) : 0;
@@ -177,7 +179,8 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
 size_t ws_contract(int64_t n_g, int n_mu, uint32_t flags, int n_orb, int n_q) {
   Arena ar(nullptr, 0);
   layout_con(ar, n_g, n_mu, flags & 0xffff, (int)((flags >> 16) & 0xff), n_orb, n_q,
-             default_bp(n_g), (flags & XTC_WS_XIGRAD_BLOCKS) != 0, true);
+             default_bp(n_g), (flags & XTC_WS_XIGRAD_BLOCKS) != 0, true,
+             (flags & XTC_WS_BH) != 0);
   return ar.used;
 }
 
@@ -225,8 +228,8 @@ static xtc_status check_contract_args(const xtc_grid* grid, const xtc_correlator
   for (int m = 0; m < n_mu; ++m)
     XTC_REQUIRE(pivots[m] >= 0 && pivots[m] < grid->n_g, "contract: pivot index out of range");
   XTC_REQUIRE(corr->form == XTC_U_EE || corr->form == XTC_U_BH, "contract: unknown correlator form");
-  if (corr->form == XTC_U_BH && precision != XTC_FP64) {
-    set_error("contract: the BH correlator is evaluated on the FP64 path only");
+  if (corr->form == XTC_U_BH && precision != XTC_FP64 && ex) {
+    set_error("contract: the exchange outputs of the BH correlator are formed on the FP64 path only");
     return XTC_ERR_UNSUPPORTED;
   }
   if (corr->form == XTC_U_BH && (channels & XTC_ULAP)) {
@@ -276,7 +279,7 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   Arena ar(ws, ws_bytes);
   const int n_orb_l = ex ? ex->n_orb : (fly ? src->n_orb : 0);
   ConLayout C = layout_con(ar, n_g, n_mu, channels, precision, n_orb_l, ex ? ex->n_q : 0, bp, fly,
-                           dual);
+                           dual, bh);
   XTC_TRY(need_ws(ar));
   XTC_TRY(check_weights(grid, ws, ws_bytes, st, "xtc_kernel_contract"));
   hipStream_t st2 = nullptr;
@@ -312,7 +315,10 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   Stage1Args s1{grid->xyz, grid->w, xi, rho, C.rhot, n_g, n_mu, 0, 0, C.panel, C.rows_pad, C.bp,
                 C.nch};
   s1.xi32 = xi32;
-  if (bh) s1.bh = C.bh;
+  if (bh) {
+    s1.bh = C.bh;
+    s1.bh_host = &bt;
+  }
   if (precision == XTC_SPLIT_F16) {
     size_t tk = timing_begin(TM_SPLIT_PREP, st);
     XTC_TRY(split_prepare(s1, C.split, st));
@@ -497,7 +503,8 @@ extern "C" xtc_status xtc_kernel_contract_noalloc(
   const int n_orb = ex ? ex->n_orb : (fly ? src->n_orb : 0), n_q = ex ? ex->n_q : 0;
   auto need = [&](long bp) {
     Arena ar(nullptr, 0);
-    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp, fly, false);
+    layout_con(ar, grid->n_g, n_mu, channels, precision, n_orb, n_q, bp, fly, false,
+               corr->form == XTC_U_BH);
     return ar.used;
   };
   long bp = default_bp(grid->n_g);

@@ -34,6 +34,7 @@ struct Stage1Args {
   const BHTable* bh = nullptr;   // device table of a BH correlator (FP64 path), or nullptr for EE
   bool rho_rows = true;          // false: the density rows n_mu, n_mu + 1 may be left unset
   const float* xi32 = nullptr;   // split path: xi in FP32 (then xi is nullptr)
+  const BHTable* bh_host = nullptr;   // the host copy of *bh (split path: channel scales)
 };
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);
@@ -44,5 +45,11 @@ size_t rho_row_scratch_bytes(long bp);
 // rows n_mu and n_mu + 1 of the panel in FP64 (split path); part: rho_row_scratch_bytes
 xtc_status rho_row_f64(const Stage1Args& a, const EECoef& cf, double* part, hipStream_t st);
 xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st);
+// BH form in split precision: the pair values of one launch's ket range, generated in FP64
+// and stored pre-split, then the same split products. Its scratch follows the split
+// operand and the density-row partials: bh_split_scratch_bytes(bp) more bytes.
+size_t bh_split_scratch_bytes(long bp);
+xtc_status stage1_split_bh(const Stage1Args& a, const EECoef& cf, void* scratch,
+                           size_t scratch_bytes, hipStream_t st);
 
 }  // namespace xtc

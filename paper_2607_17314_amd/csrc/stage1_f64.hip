@@ -141,49 +141,8 @@ __global__ __launch_bounds__(256) void k_stage1_f64(const double* __restrict__ x
 
 // BH form (four channels): per pair, from the workgroup's LDS tables of
 //   TB[I][a, grad a][bra]  (the 64 bra points, filled once) and
-//   TK[ket][I][o][m] = gamma_{I,o,m}(ket) = sum_n csym[m][n][o] a_I(ket)^n  (per ket chunk),
-// the nuclear sums F_o and grad F_o, then N, S and the channels (see bh.hpp).
-__device__ __forceinline__ void bh_channels(const EECoef& cf, const BHTable* __restrict__ T,
-                                            int nn, const double (*TB)[4][64], int gb,
-                                            const double (*TK)[BH_NO][BH_NP], double dx,
-                                            double dy, double dz, double* out) {
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  const double t = 1.0 / (1.0 + cf.d * r);
-  const double e = cf.d * r * t;
-  const double t2 = t * t;
-  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
-  double GF[BH_NO][3] = {};
-  for (int I = 0; I < nn; ++I) {
-    const double a1 = TB[I][0][gb], ax = TB[I][1][gb], ay = TB[I][2][gb], az = TB[I][3][gb];
-    const double a2 = a1 * a1, a3 = a2 * a1;
-#pragma unroll
-    for (int o = 0; o < BH_NO; ++o) {
-      const double* g = TK[I][o];
-      F[o] += g[0] + a1 * g[1] + a2 * g[2] + a3 * g[3];
-      const double Dv = g[1] + 2.0 * a1 * g[2] + 3.0 * a2 * g[3];
-      GF[o][0] += Dv * ax;
-      GF[o][1] += Dv * ay;
-      GF[o][2] += Dv * az;
-    }
-  }
-  const double E[BH_NO] = {1.0, e, e * e, e * e * e};
-  double N[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) N[c] = GF[0][c] + E[1] * GF[1][c] + E[2] * GF[2][c] + E[3] * GF[3][c];
-  double S = cf.d * t2 * (F[1] + 2.0 * E[1] * F[2] + 3.0 * E[2] * F[3] + horner(cf.q1, cf.n1, e));
-  if (r > 0.0) {
-    const double sr = S / r;
-    out[0] = N[0] + sr * dx;
-    out[1] = N[1] + sr * dy;
-    out[2] = N[2] + sr * dz;
-    out[3] = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
-  } else {
-    out[0] = N[0];
-    out[1] = N[1];
-    out[2] = N[2];
-    out[3] = N[0] * N[0] + N[1] * N[1] + N[2] * N[2] + S * S;
-  }
-}
+//   TK[ket][I][o][m] = gamma_{I,o,m}(ket)  (per ket chunk),
+// the nuclear sums F_o and grad F_o, then N, S and the channels (bh_pair_channels).
 
 // Same MFMA structure as k_stage1_f64 (four channels), with the BH tables in LDS and RT
 // rows per workgroup (64 or 128): the generated pair channels, whose nuclear sums dominate
@@ -251,18 +210,7 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
       const int kk = e / nn, I = e % nn;
       long g = k0 + kk;
       if (g > n_g - 1) g = n_g - 1;
-      const double a = bh_a(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g]);
-      const double A2[BH_NP] = {1.0, a, a * a, a * a * a};
-      const int ty = T->type[I];
-#pragma unroll
-      for (int o = 0; o < BH_NO; ++o)
-#pragma unroll
-        for (int m = 0; m < BH_NP; ++m) {
-          double s = 0.0;
-#pragma unroll
-          for (int n = 0; n < BH_NP; ++n) s += T->csym[ty][m][n][o] * A2[n];
-          TK[kk][I][o][m] = s;
-        }
+      bh_ket_gamma(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g], TK[kk][I]);
     }
     __syncthreads();
     double ch[4][NCH];
@@ -271,8 +219,8 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
       const int kk = 4 * gk + q;
       long g = k0 + kk;
       if (g > n_g - 1) g = n_g - 1;
-      bh_channels(cf, T, nn, TB, gb, TK[kk], xb - xyz[g], yb - xyz[n_g + g], zb - xyz[2 * n_g + g],
-                  ch[q]);
+      bh_pair_channels<64>(cf, nn, TB, gb, TK[kk], xb - xyz[g], yb - xyz[n_g + g],
+                           zb - xyz[2 * n_g + g], ch[q]);
     }
     __syncthreads();
 #pragma unroll

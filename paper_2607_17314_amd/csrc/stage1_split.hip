@@ -24,18 +24,11 @@
 //   A[l % 32][8 (l / 32) + e]   B[8 (l / 32) + e][l % 32]
 //   D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
 #include <type_traits>
-#include "contract.hpp"
+#include "stage1_split.hpp"
 #include "timing.hpp"
 
 namespace xtc {
 
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef float f16x __attribute__((ext_vector_type(16)));
-
-constexpr int SR = 256;        // rows per workgroup
-constexpr int SB = 32;         // bra points per workgroup
-constexpr int SKC = 128;       // ket points per chunk (8 k-steps of 16)
-constexpr int SMED = 128;      // chunks per launch: FP32 medium sum, then FP64
 #ifndef SPLIT_WAVES
 #define SPLIT_WAVES 8          // waves per workgroup (4 or 8)
 #endif
@@ -49,27 +42,6 @@ struct SplitCoef {
   float q2[MAXQ];   // q2 d^2 2^eg
   int eg, es;       // channel exponents; es is even
 };
-
-struct SplitLayout {
-  h8* A;            // [rows_pad / 32][nks][2][64]
-  int* sA;          // [rows_pad] per-row exponent
-  float* kc;        // [6][n_g_pad]: x_hi, y_hi, z_hi, x_lo, y_lo, z_lo
-  long rows_pad;    // multiple of SR
-  long n_g_pad;     // multiple of SKC
-  long nks;         // n_g_pad / 16
-};
-
-static SplitLayout split_layout(void* base, long n_g, int n_mu) {
-  SplitLayout S;
-  S.rows_pad = ((n_mu + SR - 1) / SR) * SR;
-  S.n_g_pad = ((n_g + 2 * SKC - 1) / (2 * SKC)) * (2 * SKC);   // an even number of chunks
-  S.nks = S.n_g_pad / 16;
-  Arena ar(base, (size_t)-1);
-  S.A = ar.take<h8>((size_t)(S.rows_pad / 32) * S.nks * 2 * 64);
-  S.sA = ar.take<int>(S.rows_pad);
-  S.kc = ar.take<float>(6 * (size_t)S.n_g_pad);
-  return S;
-}
 
 size_t split_scratch_bytes(long n_g, int n_mu) {
   Arena ar(nullptr, 0);
@@ -568,11 +540,11 @@ static void split_coef(const EECoef& cf, SplitCoef* k, bool even) {
 
 xtc_status stage1_split_f16(const Stage1Args& a, const EECoef& cf, void* scratch, size_t bytes,
                             hipStream_t st) {
-  (void)bytes;
   if (a.nch != 4) {
     set_error("split precision: the Laplacian channel is evaluated by the FP64 path only");
     return XTC_ERR_UNSUPPORTED;
   }
+  if (a.bh) return stage1_split_bh(a, cf, scratch, bytes, st);
   SplitLayout S = split_layout(scratch, a.n_g, a.n_mu);
   // the kernel writes whole 256-row tiles and whole 32-column bra tiles
   XTC_REQUIRE(a.rows_pad >= S.rows_pad && a.bp >= ((a.bn + SB - 1) / SB) * SB,

@@ -1,6 +1,6 @@
-"""The multi-centre Boys-Handy correlator (eq. bh-u, 48 terms) on the GPU FP64
-path: the contraction against the oracle on a ragged H6 grid subset, and the
-split path's explicit refusal."""
+"""The multi-centre Boys-Handy correlator (eq. bh-u, 48 terms) on the GPU: the FP64 and
+split-precision contractions against the oracle on a ragged H6 grid subset, the adjoint,
+and the combinations the split path refuses."""
 import numpy as np
 import pytest
 
@@ -53,13 +53,54 @@ def test_bh_contract_matches_oracle(bh_problem):
     assert e < TOL
 
 
-def test_bh_split_path_is_refused(bh_problem):
+@pytest.mark.parametrize("types", [1, 2])
+def test_bh_split_matches_oracle(bh_problem, types):
+    """Split precision (pair values generated in FP64, stored as FP16 pairs, split MFMA
+    products) on the ragged 1,100-point grid: 35 bra tiles (the last of 12 points), ten ket
+    chunks in two generation groups. Within the mixed path's 1e-6 of the oracle per block;
+    the density rows come from the FP64 pair values, so the field stays within 1e-10; the
+    split result is also within 1e-6 of the device's FP64 form."""
+    import torch
+    from oracle import contract
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    wl, xyz, w, piv, fr, rho, corr = bh_problem
+    if types == 2:
+        corr = _two_type(corr)
+    ref = contract.contract(xyz, w, corr, fr.xi, fr.xigrad, rho[piv], rho, CH)
+    grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    out = api.kernel_contract(grid, corr, xi, xig, rh, piv, CH, precision=L.XTC_SPLIT_F16)
+    f64 = api.kernel_contract(grid, corr, xi, xig, rh, piv, CH)
+    torch.cuda.synchronize()
+    note(f"BH split contract, {types} type(s): n_g={w.shape[0]} n_mu={len(piv)}")
+    for k in ("u1", "u3", "D1", "D4", "field"):
+        e = rel_err(out[k].cpu().numpy(), ref[k])
+        ed = float((out[k] - f64[k]).abs().max() / f64[k].abs().max())
+        note(f"  {k}: vs oracle {e:.2e}, vs FP64 device {ed:.2e}")
+        assert e < (1e-10 if k == "field" else 1e-6), k
+        assert ed < (1e-10 if k == "field" else 1e-6), k
+    e = np.max(np.abs(out["escale"] - ref["escale"]) / np.abs(ref["escale"]))
+    note(f"  escale rel err {e:.2e}")
+    assert e < 1e-6
+
+
+def test_bh_split_exchange_outputs_are_refused(bh_problem):
+    """The BH form's exchange intermediates are formed on the FP64 path only."""
+    import torch
     from paper_2607_17314_amd import _lib as L
     from paper_2607_17314_amd import api
     wl, xyz, w, piv, fr, rho, corr = bh_problem
     grid, xi, xig, rh = _device(api, xyz, w, fr, rho)
+    n_orb, n_mu = wl.n_orb, len(piv)
+    ex = {"phi_piv": torch.zeros((n_orb, n_mu), dtype=torch.float64, device="cuda"),
+          "lq": torch.eye(n_orb, wl.n_occ, dtype=torch.float64, device="cuda")}
     with pytest.raises(api.XtcError) as ei:
-        api.kernel_contract(grid, corr, xi, xig, rh, piv, CH, precision=L.XTC_SPLIT_F16)
+        api.kernel_contract(grid, corr, xi, xig, rh, piv, CH, precision=L.XTC_SPLIT_F16,
+                            exchange=ex)
+    assert ei.value.status == L.XTC_ERR_UNSUPPORTED
+    with pytest.raises(api.XtcError) as ei:
+        api.kernel_contract(grid, corr, xi, xig, rh, piv, CH | L.XTC_ULAP,
+                            precision=L.XTC_SPLIT_F16)
     assert ei.value.status == L.XTC_ERR_UNSUPPORTED
 
 

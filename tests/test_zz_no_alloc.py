@@ -84,6 +84,28 @@ def test_noalloc_narrows_super_blocks_to_fit(h6_small):
     _compare(got, ref, False, 1e-12, "narrowed")
 
 
+def test_noalloc_bh_split_narrows_to_fit(cases):
+    """The BH form in split precision on H4 (17,200 points): its pair-value buffer (256 KiB
+    per bra point of a super-block, 4.3 GB at the regular width) makes the no-alloc call
+    narrow the super-blocks; stage 1 is the same per bra point at any width, so only the
+    stage-2 sums are reordered."""
+    import torch
+    from paper_2607_17314_amd import _lib as L
+    from paper_2607_17314_amd import api
+    from workloads import bh_correlator
+    case = cases[0]
+    corr = bh_correlator(case.wl.atom_xyz)
+    grid, xi, xig, rho, piv = _inputs(case)
+    need = api.workspace_bytes(L.XTC_CALL_CONTRACT, case.w.shape[0], 0, len(piv), 0,
+                               CH | (L.XTC_SPLIT_F16 << 16) | L.XTC_WS_BH)
+    note(f"BH split no-alloc: regular workspace {need / 2**20:.0f} MiB")
+    assert need > (256 << 20)
+    got = api.kernel_contract(grid, corr, xi, xig, rho, piv, CH, L.XTC_SPLIT_F16, noalloc=True)
+    ref = api.kernel_contract(grid, corr, xi, xig, rho, piv, CH, L.XTC_SPLIT_F16)
+    torch.cuda.synchronize()
+    _compare(got, ref, False, 1e-6, "BH split narrowed")
+
+
 def test_noalloc_rejects_a_problem_beyond_the_scratch():
     """The split operand of 3072 rows x 194,048 points (2.4 GB) cannot fit: the call returns
     XTC_ERR_NO_WORKSPACE before launching anything."""
