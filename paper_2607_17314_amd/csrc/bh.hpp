@@ -56,33 +56,30 @@ __device__ __forceinline__ double bh_a(const BHTable* __restrict__ T, int I, dou
   return b * r / (1.0 + b * r);
 }
 
-// grad_1 u at one pair from the regrouped sums above: TB[I][(a, da/dx, da/dy, da/dz)][slot]
-// holds the bra point's nuclear values in slot gb of NBR, TK[I][o][m] = gamma_{I,o,m} of the
-// ket point, (dx, dy, dz) = r_bra - r_ket. out: d_x u, d_y u, d_z u, |grad_1 u|^2.
-template <int NBR>
-__device__ __forceinline__ void bh_pair_channels(const EECoef& cf, int nn,
-                                                 const double (*TB)[4][NBR], int gb,
-                                                 const double (*TK)[BH_NO][BH_NP], double dx,
-                                                 double dy, double dz, double* out) {
+// Nuclear sums of one pair, added into F[o] and GF[o][c] (see the regrouping above), from
+// the bra point's values a_I, grad a_I (a1, ax, ay, az) and the ket point's gamma_{I,o,m} (g)
+__device__ __forceinline__ void bh_nuclear_terms(double a1, double ax, double ay, double az,
+                                                 const double (*g)[BH_NP], double* F,
+                                                 double (*GF)[3]) {
+  const double a2 = a1 * a1, a3 = a2 * a1;
+#pragma unroll
+  for (int o = 0; o < BH_NO; ++o) {
+    F[o] += g[o][0] + a1 * g[o][1] + a2 * g[o][2] + a3 * g[o][3];
+    const double Dv = g[o][1] + 2.0 * a1 * g[o][2] + 3.0 * a2 * g[o][3];
+    GF[o][0] += Dv * ax;
+    GF[o][1] += Dv * ay;
+    GF[o][2] += Dv * az;
+  }
+}
+
+// grad_1 u = N + S rhat from the nuclear sums and the pair difference (dx, dy, dz) =
+// r_bra - r_ket. out: d_x u, d_y u, d_z u, |grad_1 u|^2.
+__device__ __forceinline__ void bh_finish(const EECoef& cf, const double* F, const double (*GF)[3],
+                                          double dx, double dy, double dz, double* out) {
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
   const double t = 1.0 / (1.0 + cf.d * r);
   const double e = cf.d * r * t;
   const double t2 = t * t;
-  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
-  double GF[BH_NO][3] = {};
-  for (int I = 0; I < nn; ++I) {
-    const double a1 = TB[I][0][gb], ax = TB[I][1][gb], ay = TB[I][2][gb], az = TB[I][3][gb];
-    const double a2 = a1 * a1, a3 = a2 * a1;
-#pragma unroll
-    for (int o = 0; o < BH_NO; ++o) {
-      const double* g = TK[I][o];
-      F[o] += g[0] + a1 * g[1] + a2 * g[2] + a3 * g[3];
-      const double Dv = g[1] + 2.0 * a1 * g[2] + 3.0 * a2 * g[3];
-      GF[o][0] += Dv * ax;
-      GF[o][1] += Dv * ay;
-      GF[o][2] += Dv * az;
-    }
-  }
   const double E[BH_NO] = {1.0, e, e * e, e * e * e};
   double N[3];
 #pragma unroll
@@ -102,6 +99,21 @@ __device__ __forceinline__ void bh_pair_channels(const EECoef& cf, int nn,
     out[2] = N[2];
     out[3] = N[0] * N[0] + N[1] * N[1] + N[2] * N[2] + S * S;
   }
+}
+
+// grad_1 u at one pair: TB[I][(a, da/dx, da/dy, da/dz)][slot] holds the bra point's nuclear
+// values in slot gb of NBR, TK[I][o][m] = gamma_{I,o,m} of the ket point, (dx, dy, dz) =
+// r_bra - r_ket.
+template <int NBR>
+__device__ __forceinline__ void bh_pair_channels(const EECoef& cf, int nn,
+                                                 const double (*TB)[4][NBR], int gb,
+                                                 const double (*TK)[BH_NO][BH_NP], double dx,
+                                                 double dy, double dz, double* out) {
+  double F[BH_NO] = {0.0, 0.0, 0.0, 0.0};
+  double GF[BH_NO][3] = {};
+  for (int I = 0; I < nn; ++I)
+    bh_nuclear_terms(TB[I][0][gb], TB[I][1][gb], TB[I][2][gb], TB[I][3][gb], TK[I], F, GF);
+  bh_finish(cf, F, GF, dx, dy, dz, out);
 }
 
 // gamma_{I,o,m}(g) = sum_n csym[type(I)][m][n][o] a_I(g)^n into out[o][m]

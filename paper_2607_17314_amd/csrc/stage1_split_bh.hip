@@ -22,7 +22,10 @@
 
 namespace xtc {
 
-typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+// The kernel's own LDS writes completed (lgkmcnt(0)) before a barrier: the barrier alone is
+// not relied on to order them with other waves' reads that follow it.
+#define XTC_LDS_DONE() __builtin_amdgcn_s_waitcnt(0xc07f)
+#define XTC_FENCE() __builtin_amdgcn_sched_barrier(0)
 
 constexpr int GCH = 8;                // ket chunks per generation workgroup
 constexpr int PV_CHUNK = 8 * 4 * 2 * 64;   // h8 per (bra tile, ket chunk): [ks][ch][hl][lane]
@@ -60,12 +63,46 @@ static void bh_split_exponents(const BHTable& T, const EECoef& cf, int* eg, int*
   *es = 14 - 2 * ex;
 }
 
+// gamma_{I,o,m} of one ket point (see bh.hpp) from the workgroup's LDS copies of the
+// nuclei (x, y, z, b) and of csym
+__device__ __forceinline__ void ket_gamma_lds(const double (*NU)[4], const int* __restrict__ ty,
+                                              const double* CS, int I, double x, double y,
+                                              double z, double* out) {
+  const double dx = x - NU[I][0], dy = y - NU[I][1], dz = z - NU[I][2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double a = NU[I][3] * r / (1.0 + NU[I][3] * r);
+  const double A2[BH_NP] = {1.0, a, a * a, a * a * a};
+  const double* c = CS + ty[I] * (BH_NP * BH_NP * BH_NO);   // [m][n][o]
+#pragma unroll
+  for (int o = 0; o < BH_NO; ++o)
+#pragma unroll
+    for (int m = 0; m < BH_NP; ++m) {
+      double v = 0.0;
+#pragma unroll
+      for (int n = 0; n < BH_NP; ++n) v += c[(m * BH_NP + n) * BH_NO + o] * A2[n];
+      out[o * BH_NP + m] = v;
+    }
+}
+
+// Doubles per ket in the LDS ket tables: the 16 kets of a wave read at once sit 2 doubles
+// (4 banks) apart modulo the 64 banks, instead of all in one bank.
+__host__ __device__ constexpr int bh_ket_stride(int nn) { return nn * BH_NO * BH_NP + 2; }
+
+// LDS of k_bh_pairs, in doubles: bra tables, ket tables, csym, nuclei, then the staged
+// half-precision fragments (two k-steps' worth, 2 x 4096 halves)
+__host__ __device__ constexpr long bh_pairs_lds_doubles(int nn) {
+  return (long)nn * 4 * SB + 16L * bh_ket_stride(nn) + BH_MAXTYPE * BH_NP * BH_NP * BH_NO +
+         4L * BH_MAXNUC + 2 * 4096 / 4;
+}
+
 // One workgroup: bra tile blockIdx.x (32 points) x the GCH ket chunks of group blockIdx.y
 // of the launch. Per k-step (16 kets) the ket tables gamma_{I,o,m} go to LDS, then thread
-// (slot L = tid % 64, wave v) makes the pairs of slot L's bra and kets 8 (L / 32) + 2 v + u,
-// u = 0, 1: elements 2 v, 2 v + 1 of slot L's B fragments, stored as (hi, hi) and (lo, lo)
-// half pairs. The density-row sums of each bra slot are added over the workgroup in a
-// fixed order and written (first launch) or added (later launches) to part[group][8][bp].
+// (ket kk = tid % 16, bra pair q = tid / 16) makes the pairs (bra 2 q + v, ket kk), v = 0, 1:
+// each ket table read from LDS serves two pairs. The split values are staged in LDS in the
+// B-fragment order (slot L = bra + 32 (kk / 8), element kk % 8) and copied out, 16 bytes per
+// lane, during the next k-step. The density-row sums of each bra are added over the
+// workgroup in a fixed order and written (first launch) or added (later launches) to
+// part[group][8][bp].
 __global__ __launch_bounds__(256) void k_bh_pairs(
     const double* __restrict__ xyz, const double* __restrict__ w, const double* __restrict__ rho,
     const double* __restrict__ rhot, long n_g, long b0, long bn, long c0, long nloc, EECoef cf,
@@ -73,11 +110,19 @@ __global__ __launch_bounds__(256) void k_bh_pairs(
     double* __restrict__ part, long bp, int first) {
   extern __shared__ double sm[];
   const int nn = T->n_nuc;
-  double(*TB)[4][SB] = (double(*)[4][SB])sm;   // [nn][a, grad a][bra slot]
-  double* TK = sm + nn * 4 * SB;                // [16 kets][nn][BH_NO][BH_NP]
-  const int tid = threadIdx.x, L = tid & 63, wv = tid >> 6, gb = L & 31;
+  double(*TB)[4][SB] = (double(*)[4][SB])sm;                  // [nn][a, grad a][bra]
+  const int ks = bh_ket_stride(nn);
+  double* TK = sm + nn * 4 * SB;                               // [16 kets][ks]: [nn][BH_NO][BH_NP]
+  double* CS = TK + 16 * ks;                                   // csym [t][m][n][o]
+  double(*NU)[4] = (double(*)[4])(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO);   // nuclei
+  h8* ST = (h8*)(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO + 4 * BH_MAXNUC);   // [2][512] h8
+  _Float16* STh = (_Float16*)ST;
+  const int tid = threadIdx.x, kk = tid & 15, q2 = tid >> 4;
   const long bt = blockIdx.x;
   const long blast = b0 + bn - 1;
+  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
+    CS[e] = (&T->csym[0][0][0][0])[e];
+  for (int e = tid; e < 4 * nn; e += 256) NU[e / 4][e % 4] = T->nuc[e / 4][e % 4];
   for (int e = tid; e < nn * SB; e += 256) {
     const int I = e / SB, bb = e % SB;
     long b = b0 + bt * SB + bb;
@@ -87,72 +132,115 @@ __global__ __launch_bounds__(256) void k_bh_pairs(
 #pragma unroll
     for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
   }
-  long b = b0 + bt * SB + gb;
-  if (b > blast) b = blast;
-  const double xb = xyz[b], yb = xyz[n_g + b], zb = xyz[2 * n_g + b];
+  XTC_LDS_DONE();
+  double xb[2], yb[2], zb[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    long b = b0 + bt * SB + 2 * q2 + v;
+    if (b > blast) b = blast;
+    xb[v] = xyz[b];
+    yb[v] = xyz[n_g + b];
+    zb[v] = xyz[2 * n_g + b];
+  }
   const double sg = ldexp(1.0, eg), ss = ldexp(1.0, es);
-  double s[4] = {0.0, 0.0, 0.0, 0.0}, h[4] = {0.0, 0.0, 0.0, 0.0};
+  double s[2][4] = {}, h[2][4] = {};
   const long cl0 = (long)blockIdx.y * GCH;
   const long cl1 = cl0 + GCH < nloc ? cl0 + GCH : nloc;
-  const int kq = 8 * (L >> 5) + 2 * wv;
+  long prev = -1;   // pv index of the staged k-step's first fragment
   for (long cl = cl0; cl < cl1; ++cl) {
-    h8* dst = pv + (bt * nloc + cl) * PV_CHUNK + L;
     for (int j = 0; j < 8; ++j) {
       const long k0 = (c0 + cl) * SKC + 16 * j;
-      __syncthreads();   // the previous k-step's readers of TK are done (and TB is written)
+      __syncthreads();   // TK free again; the previous k-step's staging complete
+      if (prev >= 0) {
+        const h8* src = ST + ((j + 7) & 1) * 512;   // the buffer of the previous k-step
+        pv[prev + tid] = src[tid];
+        pv[prev + 256 + tid] = src[256 + tid];
+      }
       for (int e = tid; e < 16 * nn; e += 256) {
         long g = k0 + e / nn;
         if (g > n_g - 1) g = n_g - 1;
-        bh_ket_gamma(T, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
-                     (double(*)[BH_NP])(TK + (long)e * BH_NO * BH_NP));
+        ket_gamma_lds(NU, T->type, CS, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
+                      TK + (e / nn) * ks + (e % nn) * BH_NO * BH_NP);
       }
+      XTC_LDS_DONE();
       __syncthreads();
-      double o[2][4];
+      const long g = k0 + kk;
+      const long gc = g < n_g ? g : n_g - 1;   // padding kets: finite values, zero weight
+      const double kx = xyz[gc], ky = xyz[n_g + gc], kz = xyz[2 * n_g + gc];
+      const double(*tk)[BH_NO][BH_NP] =
+          (const double(*)[BH_NO][BH_NP])(TK + kk * ks);
+      const double a = g < n_g ? w[g] * rho[g] : 0.0, at = g < n_g ? w[g] * rhot[g] : 0.0;
+      unsigned pk[2][4];   // per bra and channel: (hi, lo) halves of the scaled value
+      // the nuclear sums of both pairs in one pass over the nuclei: each ket table entry is
+      // read from LDS once for the two bras
+      double F[2][BH_NO] = {}, GF[2][BH_NO][3] = {};
+#pragma unroll 2
+      for (int I = 0; I < nn; ++I) {
+        double gk[BH_NO][BH_NP];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int kk = kq + u;
-        const long g = k0 + kk;
-        const long gc = g < n_g ? g : n_g - 1;   // padding kets: finite values, zero weight
-        bh_pair_channels<SB>(cf, nn, TB, gb,
-                             (const double(*)[BH_NO][BH_NP])(TK + (long)kk * nn * BH_NO * BH_NP),
-                             xb - xyz[gc], yb - xyz[n_g + gc], zb - xyz[2 * n_g + gc], o[u]);
-        if (g < n_g) {
-          const double a = w[g] * rho[g], at = w[g] * rhot[g];
+        for (int o = 0; o < BH_NO; ++o)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            s[q] = fma(a, o[u][q], s[q]);
-            h[q] = fma(at, o[u][q], h[q]);
-          }
+          for (int m = 0; m < BH_NP; ++m) gk[o][m] = tk[I][o][m];
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          bh_nuclear_terms(TB[I][0][2 * q2 + v], TB[I][1][2 * q2 + v], TB[I][2][2 * q2 + v],
+                           TB[I][3][2 * q2 + v], gk, F[v], GF[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        double o[4];
+        bh_finish(cf, F[v], GF[v], xb[v] - kx, yb[v] - ky, zb[v] - kz, o);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          s[v][c] = fma(a, o[c], s[v][c]);
+          h[v][c] = fma(at, o[c], h[v][c]);
+          const double x = o[c] * (c < 3 ? sg : ss);
+          const _Float16 hi = (_Float16)(float)x;
+          const _Float16 lo = (_Float16)(float)(x - (double)hi);
+          pk[v][c] = (unsigned)__builtin_bit_cast(unsigned short, hi) |
+                     ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
         }
       }
+      // lanes kk = 2p and 2p + 1 (adjacent lanes) trade values so that each writes whole
+      // 32-bit words: the even lane elements (2p, 2p + 1) of bra 2 q, the odd lane those of
+      // bra 2 q + 1
+      const bool odd = kk & 1;
+      unsigned* dw = (unsigned*)(STh + (j & 1) * 4096);
+      const int bw = 2 * q2 + (odd ? 1 : 0);
+      const int slot = bw + 32 * (kk >> 3);
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const double sc = ch < 3 ? sg : ss;
-        const double v0 = o[0][ch] * sc, v1 = o[1][ch] * sc;
-        const _Float16 h0 = (_Float16)(float)v0, h1 = (_Float16)(float)v1;
-        const _Float16 l0 = (_Float16)(float)(v0 - (double)h0);
-        const _Float16 l1 = (_Float16)(float)(v1 - (double)h1);
-        ((h2*)(dst + ((j * 4 + ch) * 2 + 0) * 64))[wv] = (h2){h0, h1};
-        ((h2*)(dst + ((j * 4 + ch) * 2 + 1) * 64))[wv] = (h2){l0, l1};
+      for (int c = 0; c < 4; ++c) {
+        const unsigned mine = odd ? pk[1][c] : pk[0][c];
+        const unsigned other = (unsigned)__shfl_xor((int)(odd ? pk[0][c] : pk[1][c]), 1);
+        const unsigned e0 = odd ? other : mine, e1 = odd ? mine : other;   // kets 2p, 2p + 1
+        dw[(((c * 2 + 0) * 64 + slot) * 8 + (kk & 6)) / 2] = (e0 & 0xffffu) | (e1 << 16);
+        dw[(((c * 2 + 1) * 64 + slot) * 8 + (kk & 6)) / 2] = (e0 >> 16) | (e1 & 0xffff0000u);
       }
+      XTC_LDS_DONE();
+      prev = (bt * nloc + cl) * PV_CHUNK + j * 512;
     }
   }
   __syncthreads();
-  double* red = sm;   // [8 sums][8 contributors][SB]
-  const int ctb = 2 * wv + (L >> 5);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    red[(q * 8 + ctb) * SB + gb] = s[q];
-    red[((4 + q) * 8 + ctb) * SB + gb] = h[q];
-  }
+  pv[prev + tid] = ST[512 + tid];   // the last k-step (j = 7) staged in buffer 1
+  pv[prev + 256 + tid] = ST[512 + 256 + tid];
   __syncthreads();
-  const int q = tid >> 5, bb = tid & 31;
+  double* red = sm;   // [8 sums][32 bras][16 kets], over the tables and the staging
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      red[(c * SB + 2 * q2 + v) * 16 + kk] = s[v][c];
+      red[((4 + c) * SB + 2 * q2 + v) * 16 + kk] = h[v][c];
+    }
+  XTC_LDS_DONE();
+  __syncthreads();
+  const int qq = tid >> 5, bb = tid & 31;
   double v = 0.0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) v += red[(q * 8 + c) * SB + bb];
+  for (int c = 0; c < 16; ++c) v += red[(qq * SB + bb) * 16 + c];
   const long tb = bt * SB + bb;
   if (tb < bn) {
-    double* p = part + ((long)blockIdx.y * 8 + q) * bp + tb;
+    double* p = part + ((long)blockIdx.y * 8 + qq) * bp + tb;
     *p = first ? v : *p + v;
   }
 }
@@ -171,32 +259,56 @@ __global__ __launch_bounds__(256) void k_bh_rho_rows(const double* __restrict__ 
   }
 }
 
+// Tile groups of the split-product launch: PV_GR row tiles x PV_GB bra tiles per XCD at a
+// time (32 workgroups, one per CU of the XCD), which share PV_GR row tiles of A and PV_GB
+// bra tiles of pair values in its L2. A is read two k-steps ahead of its use and the pair
+// values a whole chunk ahead, so the groups favour sharing A.
+constexpr int PV_GR = 2, PV_GB = 16;
+
 // The split products over ket chunks [c0, c1) with the pair values from pv. 8 waves over a
-// tile of 256 rows (wave v: rows 32 v .. 32 v + 31) x 32 bra points; workgroup ids are
-// mapped so that the row tiles of one bra tile, which read the same pair values, run on
-// one XCD (ids are dealt to the 8 XCDs in turn).
+// tile of 256 rows (wave v: rows 32 v .. 32 v + 31) x 32 bra points. grouped: the grid has
+// nrt x nbt_grid workgroups (nrt a multiple of PV_GR, nbt_grid of PV_GB, nrt nbt_grid of
+// 8 PV_GR PV_GB; tiles past nbt exit at once), and XCD x (ids are dealt to the 8 XCDs in
+// turn) takes the consecutive tile groups [x, x + 1) nwg / 8 in order; otherwise the row
+// tiles of one bra tile are consecutive.
 __global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
 void k_stage1_split_pv(const h8* __restrict__ At, const int* __restrict__ sA, long nks,
-                       const h8* __restrict__ pv, int nrt, int nbt, long nloc, int eg, int es,
-                       double* __restrict__ panel, long rows_pad_panel, long bp, long c0, long c1,
-                       int first_flush) {
+                       const h8* __restrict__ pv, int nrt, int nbt, int nbt_grid, int grouped,
+                       long nloc, int eg, int es, double* __restrict__ panel, long rows_pad_panel,
+                       long bp, long c0, long c1, int first_flush) {
   extern __shared__ h8 Bs[];   // [2 buf][8 ksteps][4 ch][2 hl][64 lanes]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long nwg = (long)nrt * nbt, id = blockIdx.x;
-  const long lid = (nwg % 8 == 0) ? (id % 8) * (nwg / 8) + id / 8 : id;
-  const long row0 = (lid % nrt) * SR, bt = lid / nrt, nb0 = bt * SB;
+  const long nwg = (long)nrt * nbt_grid, id = blockIdx.x;
+  long rt, bt;
+  if (grouped) {
+    const long lid = (id % 8) * (nwg / 8) + id / 8;
+    const long blk = lid / (PV_GR * PV_GB), wq = lid % (PV_GR * PV_GB);
+    const long nrb = nrt / PV_GR;
+    rt = (blk % nrb) * PV_GR + wq % PV_GR;
+    bt = (blk / nrb) * PV_GB + wq / PV_GR;
+  } else {
+    const long lid = (nwg % 8 == 0) ? (id % 8) * (nwg / 8) + id / 8 : id;
+    rt = lid % nrt;
+    bt = lid / nrt;
+  }
+  if (bt >= nbt) return;   // padding of the grouped grid (whole workgroup, before any barrier)
+  const long row0 = rt * SR, nb0 = bt * SB;
   const h8* Aw = At + (row0 / 32 + wave) * nks * 128 + lane;
   const h8* Bt = pv + bt * nloc * PV_CHUNK + tid;
   const long last_ks = nks - 1;
 #pragma unroll
   for (int i = 0; i < 8; ++i) Bs[i * 512 + tid] = Bt[i * 512];
-  h8 a0[2], a1[2];
+  // A operand pipeline: k-steps ks + 1 and ks + 2 in flight while ks is used
+  h8 a0[2], a1[2], a2[2];
   {
     const long s0 = c0 * 8, s1 = c0 * 8 + 1 < last_ks ? c0 * 8 + 1 : last_ks;
+    const long s2 = c0 * 8 + 2 < last_ks ? c0 * 8 + 2 : last_ks;
     a0[0] = Aw[s0 * 128];
     a0[1] = Aw[s0 * 128 + 64];
     a1[0] = Aw[s1 * 128];
     a1[1] = Aw[s1 * 128 + 64];
+    a2[0] = Aw[s2 * 128];
+    a2[1] = Aw[s2 * 128 + 64];
   }
   f16x med[4], acc[4];
 #pragma unroll
@@ -209,9 +321,15 @@ void k_stage1_split_pv(const h8* __restrict__ At, const int* __restrict__ sA, lo
     constexpr bool ZERO = decltype(zero_tag)::value;
     const int buf = (int)((c - c0) & 1);
     const h8* Bb = Bs + buf * PV_CHUNK + lane;
-    const bool more = c + 1 < c1;
-    const h8* Bn = Bt + (c + 1 - c0) * PV_CHUNK;
+    // the next chunk's pair values (this chunk's again after the launch's last chunk, into
+    // the buffer nobody reads any more), issued before this chunk's A loads without a
+    // branch, so that the waits for A count exactly and the wait for them at the chunk's end
+    // leaves the A loads in flight
+    const long cn = c + 1 < c1 ? c + 1 - c0 : c - c0;
+    const h8* Bn = Bt + cn * PV_CHUNK;
     h8 nx[8], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) nx[i] = Bn[i * 512];
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
       bh[ch] = Bb[(ch * 2 + 0) * 64];
@@ -219,12 +337,14 @@ void k_stage1_split_pv(const h8* __restrict__ At, const int* __restrict__ sA, lo
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      long ks2 = c * 8 + j + 2;
-      if (ks2 > last_ks) ks2 = last_ks;
-      h8 a2[2];
-      a2[0] = Aw[ks2 * 128];
-      a2[1] = Aw[ks2 * 128 + 64];
-      if (more) nx[j] = Bn[j * 512];
+      long ks3 = c * 8 + j + 3;
+      if (ks3 > last_ks) ks3 = last_ks;
+      h8 a3[2];
+      a3[0] = Aw[ks3 * 128];
+      a3[1] = Aw[ks3 * 128 + 64];
+      // scheduling fences keep the loads issued ahead of their uses (unfenced, the
+      // scheduler sinks them towards the MFMAs and every k-step waits on memory)
+      XTC_FENCE();
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch)
         acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[1], bh[ch],
@@ -232,27 +352,31 @@ void k_stage1_split_pv(const h8* __restrict__ At, const int* __restrict__ sA, lo
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch)
         acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[0], bh[ch], acc[ch], 0, 0, 0);
+      XTC_FENCE();
       if (j < 7) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) bh[ch] = Bb[(((j + 1) * 4 + ch) * 2 + 0) * 64];
       }
+      XTC_FENCE();
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch)
         acc[ch] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[0], bl[ch], acc[ch], 0, 0, 0);
+      XTC_FENCE();
       if (j < 7) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) bl[ch] = Bb[(((j + 1) * 4 + ch) * 2 + 1) * 64];
       }
+      XTC_FENCE();
       a0[0] = a1[0];
       a0[1] = a1[1];
       a1[0] = a2[0];
       a1[1] = a2[1];
+      a2[0] = a3[0];
+      a2[1] = a3[1];
     }
-    if (more) {
-      h8* Bo = Bs + (buf ^ 1) * PV_CHUNK + tid;
+    h8* Bo = Bs + (buf ^ 1) * PV_CHUNK + tid;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bo[i * 512] = nx[i];
-    }
+    for (int i = 0; i < 8; ++i) Bo[i * 512] = nx[i];
     __syncthreads();
   };
   // chunks in pairs (every launch covers an even number): the MFMA accumulator sums
@@ -302,11 +426,16 @@ xtc_status stage1_split_bh(const Stage1Args& a, const EECoef& cf, void* scratch,
   int eg = 0, es = 0;
   bh_split_exponents(*a.bh_host, cf, &eg, &es);
   const int nn = a.bh_host->n_nuc;
-  const size_t lds_gen = sizeof(double) * (size_t)std::max(nn * (4 * SB + 16 * BH_NO * BH_NP),
-                                                           8 * 8 * SB);
+  const size_t lds_gen = sizeof(double) * (size_t)std::max(bh_pairs_lds_doubles(nn), 8L * SB * 16);
   const size_t lds_pv = sizeof(h8) * 2 * PV_CHUNK;
   const int nrt = (int)(S.rows_pad / SR);
   const long nchunks = S.n_g_pad / SKC;
+  const int grouped = nrt % PV_GR == 0 ? 1 : 0;
+  int nbt_grid = nbt;
+  if (grouped) {   // whole tile groups, and as many workgroups on each of the 8 XCDs
+    nbt_grid = (int)cdiv(nbt, PV_GB) * PV_GB;
+    while (((long)nrt * nbt_grid) % (8 * PV_GR * PV_GB) != 0) nbt_grid += PV_GB;
+  }
   for (long c0 = 0; c0 < nchunks; c0 += SMED) {
     const long nloc = SMED < nchunks - c0 ? SMED : nchunks - c0;
     size_t tk = timing_begin(TM_S1_PAIRS, st);
@@ -316,9 +445,10 @@ xtc_status stage1_split_bh(const Stage1Args& a, const EECoef& cf, void* scratch,
     timing_end(tk, st);
     XTC_CHECK_LAUNCH();
     tk = timing_begin(TM_S1_KERNEL, st);
-    hipLaunchKernelGGL(k_stage1_split_pv, dim3((unsigned)nrt * nbt), dim3(512), lds_pv, st,
-                       (const h8*)S.A, (const int*)S.sA, S.nks, (const h8*)pv, nrt, nbt, nloc, eg,
-                       es, a.panel, a.rows_pad, a.bp, c0, c0 + nloc, c0 == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_stage1_split_pv, dim3((unsigned)nrt * nbt_grid), dim3(512), lds_pv, st,
+                       (const h8*)S.A, (const int*)S.sA, S.nks, (const h8*)pv, nrt, nbt, nbt_grid,
+                       grouped, nloc, eg, es, a.panel, a.rows_pad, a.bp, c0, c0 + nloc,
+                       c0 == 0 ? 1 : 0);
     timing_end(tk, st);
     XTC_CHECK_LAUNCH();
   }
