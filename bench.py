@@ -519,8 +519,9 @@ def assembly_bench(wl, inter, width, log):
 
 def recorded_traffic(summary: str):
     """Calibrated HBM bytes per launch from a committed counter summary under profiles/,
-    or None when the summary is missing or the kernel source has changed since (its
-    SHA-1 differs from the one recorded with the counters)."""
+    or None when the summary is missing or the kernel source has changed since (the SHA-1
+    of its source files, concatenated in the order listed, differs from the one recorded
+    with the counters)."""
     import hashlib
     import re
     root = os.path.dirname(os.path.abspath(__file__))
@@ -529,12 +530,15 @@ def recorded_traffic(summary: str):
     except OSError:
         return None
     t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
-    src = re.search(r"^source: (\S+)$", text, re.M)
+    src = re.search(r"^source: (.+)$", text, re.M)
     sha = re.search(r"^source_sha1: ([0-9a-f]{40})$", text, re.M)
     if not (t and src and sha):
         return None
     try:
-        now = hashlib.sha1(open(os.path.join(root, src.group(1)), "rb").read()).hexdigest()
+        h = hashlib.sha1()
+        for f in src.group(1).split(", "):
+            h.update(open(os.path.join(root, f.strip()), "rb").read())
+        now = h.hexdigest()
     except OSError:
         return None
     return int(t.group(1)) if now == sha.group(1) else None
