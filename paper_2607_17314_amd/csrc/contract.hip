@@ -120,6 +120,7 @@ struct ConLayout {
   double* e4x; double* e3; double* e4; double* sums; double* red; void* split; size_t split_bytes;
   void* gsplit; size_t gsplit_bytes; BHTable* bh;
   void* gsplit2;   // second operand scratch: the u1/u3 products on the auxiliary stream
+  double* pv64;    // FP64 path, BH form: the pair values of one ket launch
   // xi~ per bra super-block: the orbitals at the pivots, xi~ of the block, solve scratch
   double* phimu; double* xigb; double* fitP; double* fitR;
   long bp; long rows_pad; int nsb; int nch;
@@ -164,6 +165,8 @@ static ConLayout layout_con(Arena& ar, int64_t n_g, int n_mu, uint32_t channels,
   C.gsplit = C.gsplit_bytes ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   C.gsplit2 = (dual && C.gsplit_bytes) ? (void*)ar.take<char>(C.gsplit_bytes) : nullptr;
   C.bh = ar.take<BHTable>(1);
+  C.pv64 = (bh && precision == XTC_FP64) ? ar.take<double>(bh_f64_pv_bytes(C.bp) / sizeof(double))
+                                         : nullptr;
   C.phimu = C.xigb = C.fitP = C.fitR = nullptr;
   if (xig_blocks && (channels & XTC_U1)) {
     C.phimu = ar.take<double>(4 * (size_t)n_orb * n_mu);
@@ -318,6 +321,7 @@ static xtc_status contract_impl(const xtc_grid* grid, const xtc_correlator* corr
   if (bh) {
     s1.bh = C.bh;
     s1.bh_host = &bt;
+    s1.pv64 = C.pv64;
   }
   if (precision == XTC_SPLIT_F16) {
     size_t tk = timing_begin(TM_SPLIT_PREP, st);

@@ -35,6 +35,8 @@ struct Stage1Args {
   bool rho_rows = true;          // false: the density rows n_mu, n_mu + 1 may be left unset
   const float* xi32 = nullptr;   // split path: xi in FP32 (then xi is nullptr)
   const BHTable* bh_host = nullptr;   // the host copy of *bh (split path: channel scales)
+  double* pv64 = nullptr;   // FP64 path, BH form: pair-value buffer of bh_f64_pv_bytes(bp), or
+                            // nullptr for the pair values made beside the products
 };
 
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st);
@@ -51,5 +53,10 @@ xtc_status split_prepare(const Stage1Args& a, void* scratch, hipStream_t st);
 size_t bh_split_scratch_bytes(long bp);
 xtc_status stage1_split_bh(const Stage1Args& a, const EECoef& cf, void* scratch,
                            size_t scratch_bytes, hipStream_t st);
+// BH form on the FP64 path with a pair-value buffer: the four channels of the pairs of ket
+// chunks [c0, c0 + nloc) (chunks of 128 kets, nloc <= 128) in FP64 into a.pv64
+size_t bh_f64_pv_bytes(long bp);
+xtc_status bh_pair_values_f64(const Stage1Args& a, const EECoef& cf, long c0, long nloc,
+                              hipStream_t st);
 
 }  // namespace xtc

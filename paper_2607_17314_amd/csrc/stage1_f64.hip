@@ -13,7 +13,7 @@
 //     v_mfma_f64_16x16x4f64 per channel and sub-tile.
 // The kernel tile is generated once per workgroup and reused by all 64 rows.
 #include "bh.hpp"
-#include "contract.hpp"
+#include "stage1_split.hpp"
 #include "timing.hpp"
 
 namespace xtc {
@@ -264,7 +264,122 @@ __global__ __launch_bounds__(256) void k_stage1_f64_bh(
         }
 }
 
+// BH form with its pair values made beforehand (k_bh_pairs_f64, FP64, once per pair and
+// ket launch instead of once per row tile): the FP64 products of k_stage1_f64 over the
+// 16-ket steps of one launch, kets [kbeg, kbeg + 16 nsteps), the B tile read from the buffer
+// (pv64[tile][step][q][c][gk][gb], the pair (bra gb, ket 4 gk + q)) and the next step's A
+// and B loaded into registers while the current step's MFMAs run. first: the panel is
+// written, else added to.
+__global__ __launch_bounds__(256) void k_stage1_f64_pv(const double* __restrict__ w,
+                                                       const double* __restrict__ xi,
+                                                       const double* __restrict__ rho,
+                                                       const double* __restrict__ rhot, long n_g,
+                                                       int n_mu, long bn,
+                                                       const double* __restrict__ pv64,
+                                                       long nsteps, long kbeg,
+                                                       double* __restrict__ panel, long rows_pad,
+                                                       long bp, int first) {
+  constexpr int KC = 16, NCH = 4;
+  __shared__ double As[64][KC + 1];
+  __shared__ double Bs[NCH][KC][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)blockIdx.y * 64;
+  const long nb0 = (long)blockIdx.x * 64;
+  const int gb = tid & 63, gk = tid >> 6;
+  const double* pb = pv64 + (long)blockIdx.x * nsteps * 4096 + gk * 64 + gb;
+  d4 acc[NCH][2][2];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[c][i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+  double ra[4], ch[4][NCH];
+  auto load = [&](long sidx) {
+    const long k0 = kbeg + 16 * sidx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      const int row = e >> 4, kk = e & 15;
+      const long g = k0 + kk, rr = m0 + row;
+      double v = 0.0;
+      if (g < n_g && rr <= n_mu + 1)
+        v = w[g] * (rr < n_mu ? xi[rr * n_g + g] : (rr == n_mu ? rho[g] : rhot[g]));
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) ch[q][c] = pb[sidx * 4096 + (q * 4 + c) * 256];
+  };
+  load(0);
+  const int li = lane & 15, lk = lane >> 4;
+  for (long sidx = 0; sidx < nsteps; ++sidx) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      As[e >> 4][e & 15] = ra[j];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) Bs[c][4 * gk + q][gb] = ch[q][c];
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile's LDS stores done before the barrier
+    __syncthreads();
+    if (sidx + 1 < nsteps) load(sidx + 1);
+    __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the MFMAs
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const double a0 = As[32 * wm + li][4 * s + lk];
+      const double a1 = As[32 * wm + 16 + li][4 * s + lk];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double bb0 = Bs[c][4 * s + lk][32 * wn + li];
+        const double bb1 = Bs[c][4 * s + lk][32 * wn + 16 + li];
+        acc[c][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb0, acc[c][0][0], 0, 0, 0);
+        acc[c][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb1, acc[c][0][1], 0, 0, 0);
+        acc[c][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb0, acc[c][1][0], 0, 0, 0);
+        acc[c][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb1, acc[c][1][1], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long row = m0 + 32 * wm + 16 * i + lk + 4 * r;   // D[(l/16) + 4r][l%16]
+          const long col = nb0 + 32 * wn + 16 * j + li;
+          if (row <= n_mu + 1 && col < bn) {
+            double* p = panel + ((long)c * rows_pad + row) * bp + col;
+            *p = first ? acc[c][i][j][r] : *p + acc[c][i][j][r];
+          }
+        }
+}
+
 xtc_status stage1_f64(const Stage1Args& a, const EECoef& cf, hipStream_t st) {
+  if (a.bh && a.pv64) {
+    XTC_REQUIRE(a.nch == 4, "BH correlator: the Laplacian channel is defined for the EE form only");
+    const long nch = (a.n_g + SKC - 1) / SKC;
+    for (long c0 = 0; c0 < nch; c0 += SMED) {
+      const long nloc = SMED < nch - c0 ? SMED : nch - c0;
+      size_t tk = timing_begin(TM_S1_PAIRS, st);
+      XTC_TRY(bh_pair_values_f64(a, cf, c0, nloc, st));
+      timing_end(tk, st);
+      tk = timing_begin(TM_S1_KERNEL, st);
+      hipLaunchKernelGGL(k_stage1_f64_pv, dim3(cdiv(a.bn, 64), cdiv(a.n_mu + 2, 64)), dim3(256), 0,
+                         st, a.w, a.xi, a.rho, a.rhot, a.n_g, a.n_mu, a.bn, (const double*)a.pv64,
+                         nloc * 8, c0 * SKC, a.panel, a.rows_pad, a.bp, c0 == 0 ? 1 : 0);
+      timing_end(tk, st);
+      XTC_CHECK_LAUNCH();
+    }
+    return XTC_OK;
+  }
   dim3 grid(cdiv(a.bn, 64), cdiv(a.n_mu + 2, 64));
   const size_t tk = timing_begin(TM_S1_KERNEL, st);
   if (a.bh) {

@@ -245,6 +245,110 @@ __global__ __launch_bounds__(256) void k_bh_pairs(
   }
 }
 
+// The FP64 path's pair values (the BH form): the same tables and nuclear sums as k_bh_pairs,
+// the four channels stored unscaled in FP64 for k_stage1_f64_pv, per 16-ket step s of the
+// launch and 64-bra tile t: pv64[t][s][q][c][gk][gb] for the pair (bra gb, ket 4 gk + q).
+// The grid covers whole 64-bra tiles (two 32-bra halves; bras past the range repeat its
+// last point).
+__global__ __launch_bounds__(256) void k_bh_pairs_f64(const double* __restrict__ xyz, long n_g,
+                                                      long b0, long bn, long c0, long nloc,
+                                                      EECoef cf, const BHTable* __restrict__ T,
+                                                      double* __restrict__ pv64) {
+  extern __shared__ double sm[];
+  const int nn = T->n_nuc;
+  double(*TB)[4][SB] = (double(*)[4][SB])sm;
+  const int ks = bh_ket_stride(nn);
+  double* TK = sm + nn * 4 * SB;
+  double* CS = TK + 16 * ks;
+  double(*NU)[4] = (double(*)[4])(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO);
+  const int tid = threadIdx.x, kk = tid & 15, q2 = tid >> 4;
+  const long bt = blockIdx.x;
+  const long blast = b0 + bn - 1;
+  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
+    CS[e] = (&T->csym[0][0][0][0])[e];
+  for (int e = tid; e < 4 * nn; e += 256) NU[e / 4][e % 4] = T->nuc[e / 4][e % 4];
+  for (int e = tid; e < nn * SB; e += 256) {
+    const int I = e / SB, bb = e % SB;
+    long b = b0 + bt * SB + bb;
+    if (b > blast) b = blast;
+    double v[4];
+    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
+  }
+  XTC_LDS_DONE();
+  double xb[2], yb[2], zb[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    long b = b0 + bt * SB + 2 * q2 + v;
+    if (b > blast) b = blast;
+    xb[v] = xyz[b];
+    yb[v] = xyz[n_g + b];
+    zb[v] = xyz[2 * n_g + b];
+  }
+  const long nsteps = nloc * 8;
+  const long cl0 = (long)blockIdx.y * GCH;
+  const long cl1 = cl0 + GCH < nloc ? cl0 + GCH : nloc;
+  // this thread's slot in a step: bra 64 (bt % 2) + 2 q2 + v of tile bt / 2, ket 4 gk + q
+  double* dst = pv64 + (bt >> 1) * nsteps * 4096 + (kk & 3) * 1024 + (kk >> 2) * 64 +
+                (bt & 1) * 32 + 2 * q2;
+  for (long cl = cl0; cl < cl1; ++cl) {
+    for (int j = 0; j < 8; ++j) {
+      const long k0 = (c0 + cl) * SKC + 16 * j;
+      __syncthreads();
+      for (int e = tid; e < 16 * nn; e += 256) {
+        long g = k0 + e / nn;
+        if (g > n_g - 1) g = n_g - 1;
+        ket_gamma_lds(NU, T->type, CS, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
+                      TK + (e / nn) * ks + (e % nn) * BH_NO * BH_NP);
+      }
+      XTC_LDS_DONE();
+      __syncthreads();
+      long g = k0 + kk;
+      if (g > n_g - 1) g = n_g - 1;   // padding kets: finite values; their A is zero
+      const double kx = xyz[g], ky = xyz[n_g + g], kz = xyz[2 * n_g + g];
+      const double(*tk)[BH_NO][BH_NP] = (const double(*)[BH_NO][BH_NP])(TK + kk * ks);
+      double F[2][BH_NO] = {}, GF[2][BH_NO][3] = {};
+      for (int I = 0; I < nn; ++I) {
+        double gk[BH_NO][BH_NP];
+#pragma unroll
+        for (int o = 0; o < BH_NO; ++o)
+#pragma unroll
+          for (int m = 0; m < BH_NP; ++m) gk[o][m] = tk[I][o][m];
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          bh_nuclear_terms(TB[I][0][2 * q2 + v], TB[I][1][2 * q2 + v], TB[I][2][2 * q2 + v],
+                           TB[I][3][2 * q2 + v], gk, F[v], GF[v]);
+      }
+      double* d = dst + (cl * 8 + j) * 4096;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        double o[4];
+        bh_finish(cf, F[v], GF[v], xb[v] - kx, yb[v] - ky, zb[v] - kz, o);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) d[c * 256 + v] = o[c];
+      }
+    }
+  }
+}
+
+size_t bh_f64_pv_bytes(long bp) {
+  return (size_t)cdiv(bp, 64) * SMED * 8 * 4096 * sizeof(double) + 256;
+}
+
+xtc_status bh_pair_values_f64(const Stage1Args& a, const EECoef& cf, long c0, long nloc,
+                              hipStream_t st) {
+  XTC_REQUIRE(a.bh && a.bh_host && a.pv64, "FP64 BH stage 1: no correlator table or buffer");
+  XTC_REQUIRE(nloc >= 1 && nloc <= SMED && a.bn <= a.bp, "FP64 BH stage 1: bad launch range");
+  const int nn = a.bh_host->n_nuc;
+  const size_t lds = sizeof(double) * ((size_t)nn * 4 * SB + 16 * (size_t)bh_ket_stride(nn) +
+                                       BH_MAXTYPE * BH_NP * BH_NP * BH_NO + 4 * BH_MAXNUC);
+  hipLaunchKernelGGL(k_bh_pairs_f64, dim3(2 * cdiv(a.bn, 64), cdiv(nloc, GCH)), dim3(256), lds, st,
+                     a.xyz, a.n_g, a.b0, a.bn, c0, nloc, cf, a.bh, a.pv64);
+  XTC_CHECK_LAUNCH();
+  return XTC_OK;
+}
+
 // rows n_mu (rho_gamma) and n_mu + 1 (ISDF density) of the panel from the group sums
 __global__ __launch_bounds__(256) void k_bh_rho_rows(const double* __restrict__ part, int ngrp,
                                                      long bn, int n_mu, double* __restrict__ panel,
