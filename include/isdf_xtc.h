@@ -199,8 +199,8 @@ enum { XTC_CALL_EVAL_ORBITALS = 1, XTC_CALL_SELECT = 2, XTC_CALL_FIT = 3,
 
 /* Flag of the contraction's workspace query: xi~ formed per bra super-block. */
 #define XTC_WS_XIGRAD_BLOCKS (1u << 24)
-/* Flag of the contraction's workspace query: the correlator is of the BH form (in split
- * precision its pair values are generated into a buffer of the workspace). */
+/* Flag of the contraction's workspace query: the correlator is of the BH form (its pair
+ * values are generated into a buffer of the workspace, in either precision). */
 #define XTC_WS_BH (1u << 25)
 
 /* Workspace bytes a call needs. flags: channels (CONTRACT/GRAD, with the
@@ -309,12 +309,12 @@ typedef struct {
  * escale: host [6] or NULL: {E3, E4, E1, E3x, E4x, E1x} with E3 = G^T u3 G,
  *   E4 = G^T D4 G, E1 = 2 G^T D1 G and their ISDF-free counterparts
  *   E3x = sum_{g,g'} w w' rho rho' |grad_1 u|^2, E4x = sum_g w rho |A_gamma|^2, E1x = 2 E4x.
- * precision: XTC_FP64 or XTC_SPLIT_F16. The BH form runs on both (without XTC_ULAP); in
- *   split precision the four channels of every grid pair are generated in FP64 and stored
- *   split into FP16 pairs, one ket range of 16,384 points at a time, for the same split
- *   products (workspace query with XTC_WS_BH: about bp x 256 KiB more, bp the super-block
- *   width of at most 16,384 points), and its exchange outputs (ex) need XTC_FP64
- *   (XTC_ERR_UNSUPPORTED otherwise).
+ * precision: XTC_FP64 or XTC_SPLIT_F16. The BH form runs on both (without XTC_ULAP): the
+ *   four channels of every grid pair are generated in FP64, one ket range of 16,384 points
+ *   at a time, and stored for the products, split into FP16 pairs in split precision
+ *   (workspace query with XTC_WS_BH: about bp x 256 KiB more, bp the super-block width of
+ *   at most 16,384 points) or in FP64 (bp x 512 KiB more); its exchange outputs (ex) need
+ *   XTC_FP64 (XTC_ERR_UNSUPPORTED otherwise).
  * [bra_begin, bra_end): the bra points g summed over (non-empty, inside the grid; the ket
  *   sums always cover the whole grid). (0, n_g) gives the outputs above; disjoint ranges
  *   give partial sums that add up to them (the bra sharding across devices); field is
