@@ -402,7 +402,7 @@ void k_stage1_split_pv(const h8* __restrict__ At, const int* __restrict__ sA, lo
   const long last_ks = nks - 1;
 #pragma unroll
   for (int i = 0; i < 8; ++i) Bs[i * 512 + tid] = Bt[i * 512];
-  // A operand pipeline: k-steps ks + 1 and ks + 2 in flight while ks is used
+  // A operand pipeline: loaded three k-steps ahead (ks + 1 .. ks + 3 in flight while ks is used)
   h8 a0[2], a1[2], a2[2];
   {
     const long s0 = c0 * 8, s1 = c0 * 8 + 1 < last_ks ? c0 * 8 + 1 : last_ks;
