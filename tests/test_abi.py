@@ -40,6 +40,22 @@ def test_version_and_workspace_sizes():
     assert api.workspace_bytes(L.XTC_CALL_FIT, 194000, 300, 3000) < 4 * 3000 * 194000 * 8
 
 
+def test_bh_workspace_holds_the_pair_value_buffer():
+    """With XTC_WS_BH the contraction's workspace grows by the BH pair-value buffer of one
+    ket launch (16,384 kets) for a super-block (at most 16,384 bra points): 16 bytes per
+    pair in split precision (four channels, two FP16 halves), 32 in FP64 (four doubles),
+    bra points counted in whole tiles (32 and 64 points); alignment adds < 1 KiB."""
+    from paper_2607_17314_amd import api, _lib as L
+    ch = 1 | 2 | 8 | 16 | 32 | 64
+    for n_g, bp in ((194000, 16384), (1100, 1152)):
+        for prec, per_pair, tile in ((L.XTC_SPLIT_F16, 16, 32), (L.XTC_FP64, 32, 64)):
+            flags = ch | (prec << 16)
+            base = api.workspace_bytes(L.XTC_CALL_CONTRACT, n_g, 0, 300, 0, flags)
+            bh = api.workspace_bytes(L.XTC_CALL_CONTRACT, n_g, 0, 300, 0, flags | L.XTC_WS_BH)
+            want = -(-bp // tile) * tile * 16384 * per_pair
+            assert 0 <= (bh - base) - want < 1024, (n_g, prec, bh - base, want)
+
+
 def test_host_argument_checks_return_invalid_arg():
     from paper_2607_17314_amd import _lib as L
     lib = L.lib()
