@@ -88,11 +88,95 @@ __device__ __forceinline__ void ket_gamma_lds(const double (*NU)[4], const int* 
 // (4 banks) apart modulo the 64 banks, instead of all in one bank.
 __host__ __device__ constexpr int bh_ket_stride(int nn) { return nn * BH_NO * BH_NP + 2; }
 
-// LDS of k_bh_pairs, in doubles: bra tables, ket tables, csym, nuclei, then the staged
-// half-precision fragments (two k-steps' worth, 2 x 4096 halves)
-__host__ __device__ constexpr long bh_pairs_lds_doubles(int nn) {
+// LDS tables of the pair-value kernels, in doubles: bra tables [nn][a, grad a][32 bras],
+// ket tables [16 kets][bh_ket_stride(nn)], csym [t][m][n][o], nuclei [BH_MAXNUC][x, y, z, b]
+__host__ __device__ constexpr long bh_tables_lds_doubles(int nn) {
   return (long)nn * 4 * SB + 16L * bh_ket_stride(nn) + BH_MAXTYPE * BH_NP * BH_NP * BH_NO +
-         4L * BH_MAXNUC + 2 * 4096 / 4;
+         4L * BH_MAXNUC;
+}
+
+// LDS of k_bh_pairs: the tables, then the staged half-precision fragments (two k-steps'
+// worth, 2 x 4096 halves)
+__host__ __device__ constexpr long bh_pairs_lds_doubles(int nn) {
+  return bh_tables_lds_doubles(nn) + 2 * 4096 / 4;
+}
+
+struct BHLds {
+  double (*TB)[4][SB];   // bra tables of the 32-bra tile
+  double* TK;            // ket tables of the current 16-ket step
+  double* CS;            // csym
+  double (*NU)[4];       // nuclei
+  int ks;                // doubles per ket in TK
+};
+
+__device__ __forceinline__ BHLds bh_lds(double* sm, int nn) {
+  BHLds L;
+  L.TB = (double(*)[4][SB])sm;
+  L.ks = bh_ket_stride(nn);
+  L.TK = sm + nn * 4 * SB;
+  L.CS = L.TK + 16 * L.ks;
+  L.NU = (double(*)[4])(L.CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO);
+  return L;
+}
+
+// csym, the nuclei and the bra tables of bra tile bt (bras past the range repeat its last
+// point); followed by a barrier before any use
+__device__ __forceinline__ void bh_fill_bra_tables(const BHLds& L, const BHTable* __restrict__ T,
+                                                   const double* __restrict__ xyz, long n_g,
+                                                   long b0, long bn, long bt, int nn, int tid) {
+  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
+    L.CS[e] = (&T->csym[0][0][0][0])[e];
+  for (int e = tid; e < 4 * nn; e += 256) L.NU[e / 4][e % 4] = T->nuc[e / 4][e % 4];
+  const long blast = b0 + bn - 1;
+  for (int e = tid; e < nn * SB; e += 256) {
+    const int I = e / SB, bb = e % SB;
+    long b = b0 + bt * SB + bb;
+    if (b > blast) b = blast;
+    double v[4];
+    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.TB[I][q][bb] = v[q];
+  }
+  XTC_LDS_DONE();
+}
+
+// the ket tables of kets k0 .. k0 + 15 (kets past the grid repeat its last point); between
+// barriers
+__device__ __forceinline__ void bh_fill_ket_tables(const BHLds& L, const BHTable* __restrict__ T,
+                                                   const double* __restrict__ xyz, long n_g,
+                                                   long k0, int nn, int tid) {
+  for (int e = tid; e < 16 * nn; e += 256) {
+    long g = k0 + e / nn;
+    if (g > n_g - 1) g = n_g - 1;
+    ket_gamma_lds(L.NU, T->type, L.CS, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
+                  L.TK + (e / nn) * L.ks + (e % nn) * BH_NO * BH_NP);
+  }
+  XTC_LDS_DONE();
+}
+
+// the nuclear sums of the pairs (bra 2 q2 + v, ket kk), v = 0, 1, in one pass over the
+// nuclei: each ket-table entry is read from LDS once for the two bras
+__device__ __forceinline__ void bh_two_pairs(const BHLds& L, int nn, int q2, int kk,
+                                             double (&F)[2][BH_NO], double (&GF)[2][BH_NO][3]) {
+  const double(*tk)[BH_NO][BH_NP] = (const double(*)[BH_NO][BH_NP])(L.TK + kk * L.ks);
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int o = 0; o < BH_NO; ++o) {
+      F[v][o] = 0.0;
+      GF[v][o][0] = GF[v][o][1] = GF[v][o][2] = 0.0;
+    }
+  for (int I = 0; I < nn; ++I) {
+    double gk[BH_NO][BH_NP];
+#pragma unroll
+    for (int o = 0; o < BH_NO; ++o)
+#pragma unroll
+      for (int m = 0; m < BH_NP; ++m) gk[o][m] = tk[I][o][m];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      bh_nuclear_terms(L.TB[I][0][2 * q2 + v], L.TB[I][1][2 * q2 + v], L.TB[I][2][2 * q2 + v],
+                       L.TB[I][3][2 * q2 + v], gk, F[v], GF[v]);
+  }
 }
 
 // One workgroup: bra tile blockIdx.x (32 points) x the GCH ket chunks of group blockIdx.y
@@ -110,29 +194,13 @@ __global__ __launch_bounds__(256) void k_bh_pairs(
     double* __restrict__ part, long bp, int first) {
   extern __shared__ double sm[];
   const int nn = T->n_nuc;
-  double(*TB)[4][SB] = (double(*)[4][SB])sm;                  // [nn][a, grad a][bra]
-  const int ks = bh_ket_stride(nn);
-  double* TK = sm + nn * 4 * SB;                               // [16 kets][ks]: [nn][BH_NO][BH_NP]
-  double* CS = TK + 16 * ks;                                   // csym [t][m][n][o]
-  double(*NU)[4] = (double(*)[4])(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO);   // nuclei
-  h8* ST = (h8*)(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO + 4 * BH_MAXNUC);   // [2][512] h8
+  const BHLds L = bh_lds(sm, nn);
+  h8* ST = (h8*)(sm + bh_tables_lds_doubles(nn));   // [2][512] h8
   _Float16* STh = (_Float16*)ST;
   const int tid = threadIdx.x, kk = tid & 15, q2 = tid >> 4;
   const long bt = blockIdx.x;
   const long blast = b0 + bn - 1;
-  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
-    CS[e] = (&T->csym[0][0][0][0])[e];
-  for (int e = tid; e < 4 * nn; e += 256) NU[e / 4][e % 4] = T->nuc[e / 4][e % 4];
-  for (int e = tid; e < nn * SB; e += 256) {
-    const int I = e / SB, bb = e % SB;
-    long b = b0 + bt * SB + bb;
-    if (b > blast) b = blast;
-    double v[4];
-    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
-  }
-  XTC_LDS_DONE();
+  bh_fill_bra_tables(L, T, xyz, n_g, b0, bn, bt, nn, tid);
   double xb[2], yb[2], zb[2];
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
@@ -156,36 +224,15 @@ __global__ __launch_bounds__(256) void k_bh_pairs(
         pv[prev + tid] = src[tid];
         pv[prev + 256 + tid] = src[256 + tid];
       }
-      for (int e = tid; e < 16 * nn; e += 256) {
-        long g = k0 + e / nn;
-        if (g > n_g - 1) g = n_g - 1;
-        ket_gamma_lds(NU, T->type, CS, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
-                      TK + (e / nn) * ks + (e % nn) * BH_NO * BH_NP);
-      }
-      XTC_LDS_DONE();
+      bh_fill_ket_tables(L, T, xyz, n_g, k0, nn, tid);
       __syncthreads();
       const long g = k0 + kk;
       const long gc = g < n_g ? g : n_g - 1;   // padding kets: finite values, zero weight
       const double kx = xyz[gc], ky = xyz[n_g + gc], kz = xyz[2 * n_g + gc];
-      const double(*tk)[BH_NO][BH_NP] =
-          (const double(*)[BH_NO][BH_NP])(TK + kk * ks);
       const double a = g < n_g ? w[g] * rho[g] : 0.0, at = g < n_g ? w[g] * rhot[g] : 0.0;
       unsigned pk[2][4];   // per bra and channel: (hi, lo) halves of the scaled value
-      // the nuclear sums of both pairs in one pass over the nuclei: each ket table entry is
-      // read from LDS once for the two bras
-      double F[2][BH_NO] = {}, GF[2][BH_NO][3] = {};
-#pragma unroll 2
-      for (int I = 0; I < nn; ++I) {
-        double gk[BH_NO][BH_NP];
-#pragma unroll
-        for (int o = 0; o < BH_NO; ++o)
-#pragma unroll
-          for (int m = 0; m < BH_NP; ++m) gk[o][m] = tk[I][o][m];
-#pragma unroll
-        for (int v = 0; v < 2; ++v)
-          bh_nuclear_terms(TB[I][0][2 * q2 + v], TB[I][1][2 * q2 + v], TB[I][2][2 * q2 + v],
-                           TB[I][3][2 * q2 + v], gk, F[v], GF[v]);
-      }
+      double F[2][BH_NO], GF[2][BH_NO][3];
+      bh_two_pairs(L, nn, q2, kk, F, GF);
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         double o[4];
@@ -256,27 +303,11 @@ __global__ __launch_bounds__(256) void k_bh_pairs_f64(const double* __restrict__
                                                       double* __restrict__ pv64) {
   extern __shared__ double sm[];
   const int nn = T->n_nuc;
-  double(*TB)[4][SB] = (double(*)[4][SB])sm;
-  const int ks = bh_ket_stride(nn);
-  double* TK = sm + nn * 4 * SB;
-  double* CS = TK + 16 * ks;
-  double(*NU)[4] = (double(*)[4])(CS + BH_MAXTYPE * BH_NP * BH_NP * BH_NO);
+  const BHLds L = bh_lds(sm, nn);
   const int tid = threadIdx.x, kk = tid & 15, q2 = tid >> 4;
   const long bt = blockIdx.x;
   const long blast = b0 + bn - 1;
-  for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
-    CS[e] = (&T->csym[0][0][0][0])[e];
-  for (int e = tid; e < 4 * nn; e += 256) NU[e / 4][e % 4] = T->nuc[e / 4][e % 4];
-  for (int e = tid; e < nn * SB; e += 256) {
-    const int I = e / SB, bb = e % SB;
-    long b = b0 + bt * SB + bb;
-    if (b > blast) b = blast;
-    double v[4];
-    bh_nuc_point(T, I, xyz[b], xyz[n_g + b], xyz[2 * n_g + b], v);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) TB[I][q][bb] = v[q];
-  }
-  XTC_LDS_DONE();
+  bh_fill_bra_tables(L, T, xyz, n_g, b0, bn, bt, nn, tid);
   double xb[2], yb[2], zb[2];
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
@@ -296,30 +327,13 @@ __global__ __launch_bounds__(256) void k_bh_pairs_f64(const double* __restrict__
     for (int j = 0; j < 8; ++j) {
       const long k0 = (c0 + cl) * SKC + 16 * j;
       __syncthreads();
-      for (int e = tid; e < 16 * nn; e += 256) {
-        long g = k0 + e / nn;
-        if (g > n_g - 1) g = n_g - 1;
-        ket_gamma_lds(NU, T->type, CS, e % nn, xyz[g], xyz[n_g + g], xyz[2 * n_g + g],
-                      TK + (e / nn) * ks + (e % nn) * BH_NO * BH_NP);
-      }
-      XTC_LDS_DONE();
+      bh_fill_ket_tables(L, T, xyz, n_g, k0, nn, tid);
       __syncthreads();
       long g = k0 + kk;
       if (g > n_g - 1) g = n_g - 1;   // padding kets: finite values; their A is zero
       const double kx = xyz[g], ky = xyz[n_g + g], kz = xyz[2 * n_g + g];
-      const double(*tk)[BH_NO][BH_NP] = (const double(*)[BH_NO][BH_NP])(TK + kk * ks);
-      double F[2][BH_NO] = {}, GF[2][BH_NO][3] = {};
-      for (int I = 0; I < nn; ++I) {
-        double gk[BH_NO][BH_NP];
-#pragma unroll
-        for (int o = 0; o < BH_NO; ++o)
-#pragma unroll
-          for (int m = 0; m < BH_NP; ++m) gk[o][m] = tk[I][o][m];
-#pragma unroll
-        for (int v = 0; v < 2; ++v)
-          bh_nuclear_terms(TB[I][0][2 * q2 + v], TB[I][1][2 * q2 + v], TB[I][2][2 * q2 + v],
-                           TB[I][3][2 * q2 + v], gk, F[v], GF[v]);
-      }
+      double F[2][BH_NO], GF[2][BH_NO][3];
+      bh_two_pairs(L, nn, q2, kk, F, GF);
       double* d = dst + (cl * 8 + j) * 4096;
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
@@ -341,8 +355,7 @@ xtc_status bh_pair_values_f64(const Stage1Args& a, const EECoef& cf, long c0, lo
   XTC_REQUIRE(a.bh && a.bh_host && a.pv64, "FP64 BH stage 1: no correlator table or buffer");
   XTC_REQUIRE(nloc >= 1 && nloc <= SMED && a.bn <= a.bp, "FP64 BH stage 1: bad launch range");
   const int nn = a.bh_host->n_nuc;
-  const size_t lds = sizeof(double) * ((size_t)nn * 4 * SB + 16 * (size_t)bh_ket_stride(nn) +
-                                       BH_MAXTYPE * BH_NP * BH_NP * BH_NO + 4 * BH_MAXNUC);
+  const size_t lds = sizeof(double) * (size_t)bh_tables_lds_doubles(nn);
   hipLaunchKernelGGL(k_bh_pairs_f64, dim3(2 * cdiv(a.bn, 64), cdiv(nloc, GCH)), dim3(256), lds, st,
                      a.xyz, a.n_g, a.b0, a.bn, c0, nloc, cf, a.bh, a.pv64);
   XTC_CHECK_LAUNCH();
