@@ -13,7 +13,9 @@
 //      v_mfma_f32_32x32x16_f16, the pair values streamed from the buffer through LDS
 //      (double-buffered, one ket chunk ahead), FP32 accumulation over a pair of chunks,
 //      an FP32 medium sum over the launch, FP64 in the panel, scales removed exactly.
-// The A operand and its per-row exponents are the split operand of the EE path.
+// The A operand and its per-row exponents are the split operand of the EE path. The FP64
+// path of the BH form takes its pair values from k_bh_pairs_f64 below (the same tables and
+// sums, the values stored unscaled in FP64 for k_stage1_f64_pv).
 #include <algorithm>
 #include <type_traits>
 #include "bh.hpp"
