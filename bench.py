@@ -391,7 +391,10 @@ GATE = 1e-6   # the mixed path's bound per output block (max |got - ref| / max |
 
 def s1_kernel_name(split, bh):
     if not split:
-        return "stage-1 pair kernel (k_stage1_f64_bh)" if bh else "stage-1 pair kernel (k_stage1_f64)"
+        if bh:
+            return ("stage-1 FP64 products (k_stage1_f64_pv; the FP64 pair values of "
+                    "k_bh_pairs_f64 are timed under stage_ms.bh_pairs)")
+        return "stage-1 pair kernel (k_stage1_f64)"
     if bh:
         return ("stage-1 split products (k_stage1_split_pv; the FP64 pair values of k_bh_pairs "
                 "are timed under stage_ms.bh_pairs)")
