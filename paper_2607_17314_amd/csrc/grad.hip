@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_grad_pairs(
 // BH partial stride: [types x 64 Z][MAXQ + 1 Zee][dL/dd, dL/db_t per type]
 constexpr int ZS = BH_MAXTYPE * 64 + MAXQ + 1 + 1 + BH_MAXTYPE;
 
-template <int NT, bool NL>
+template <int NT, bool LIN, bool NL>
 __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __restrict__ T,
                                              const double (*Cs)[BH_NP][BH_NP][BH_NO],
                                              int nn, const double (*TB)[4][GT], int bi,
@@ -343,7 +343,7 @@ __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __
     znl[0] += vdn + W * dS;
   }
   // electron-electron (0, 0, o) terms: W o e^{o-1} d t^2
-  {
+  if (LIN) {
     double ep = 1.0;   // e^{o-1}
     for (int o = 1; o <= omax_ee; ++o) {
       zee[o] += o * ep * wd;
@@ -361,14 +361,16 @@ __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       if (tt != ty) continue;
+      if (LIN) {
 #pragma unroll
-      for (int mm = 0; mm < BH_NP; ++mm)
+        for (int mm = 0; mm < BH_NP; ++mm)
 #pragma unroll
-        for (int o = 0; o < BH_NO; ++o) {
-          const double u = q * dA1[mm] * E[o] + A1[mm] * ES[o];
+          for (int o = 0; o < BH_NO; ++o) {
+            const double u = q * dA1[mm] * E[o] + A1[mm] * ES[o];
 #pragma unroll
-          for (int n = 0; n < BH_NP; ++n) z[tt * 64 + mm * 16 + n * 4 + o] += u * A2[n];
-        }
+            for (int n = 0; n < BH_NP; ++n) z[tt * 64 + mm * 16 + n * 4 + o] += u * A2[n];
+          }
+      }
       if (NL) {
         // b of this nucleus' type: a' = a (1 - a) / b, (grad a)' = (1 - 2 a) / b grad a;
         // dL/db += q sum_o rbar^o (grad F_o)'/grad a + W d t^2 sum_o o rbar^{o-1} F_o'
@@ -401,9 +403,13 @@ __device__ __forceinline__ void pair_grad_bh(const EECoef& cf, const BHTable* __
   }
 }
 
-// M tiles exactly as k_grad_pairs (four channels), then the BH per-pair adjoint; NL adds
-// the derivatives with respect to d and the b of each nucleus type.
-template <int NT, bool NL>
+// M tiles exactly as k_grad_pairs (four channels), then the BH per-pair adjoint: LIN the
+// linear coefficients (Z and Zee), NL the derivatives with respect to d and the b of each
+// nucleus type. For one nucleus type the NL part runs as a launch of its own after the LIN
+// one (beside the 64 Z accumulators it spilled ~1 KB per lane; alone it spills 20 bytes)
+// and writes only its entries of the partials; for two types the combined form is kept
+// (the separate two-type form crashes the device compiler).
+template <int NT, bool LIN, bool NL>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int n_rows,
                      const double* __restrict__ xi, const double* __restrict__ rho,
@@ -446,15 +452,16 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
   }
   for (int e = tid; e < BH_MAXTYPE * BH_NP * BH_NP * BH_NO; e += 256)
     (&Cs[0][0][0][0])[e] = (&T->csym[0][0][0][0])[e];
-  double z[NT * 64];
+  constexpr int NZ = LIN ? NT * 64 : 1, NZE = LIN ? MAXQ + 1 : 1, NZN = NL ? 1 + NT : 1;
+  double z[NZ];
 #pragma unroll
-  for (int k = 0; k < NT * 64; ++k) z[k] = 0.0;
-  double zee[MAXQ + 1];
+  for (int k = 0; k < NZ; ++k) z[k] = 0.0;
+  double zee[NZE];
 #pragma unroll
-  for (int k = 0; k <= MAXQ; ++k) zee[k] = 0.0;
-  double znl[1 + NT];
+  for (int k = 0; k < NZE; ++k) zee[k] = 0.0;
+  double znl[NZN];
 #pragma unroll
-  for (int k = 0; k <= NT; ++k) znl[k] = 0.0;
+  for (int k = 0; k < NZN; ++k) znl[k] = 0.0;
 
   for (long kc = k_lo; kc < k_hi; kc += GT) {
     __syncthreads();
@@ -472,7 +479,7 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
       TA[I][kk] = bh_a(T, I, xyz[g], xyz[n_g + g], xyz[2 * n_g + g]);
     }
     d4 acc[NCH][2][2];
-    m_tiles<NCH, NT == 1 && !NL>(Pb, rows_pad, bp, n_rows, xi, rho, rhot, w, n_g, n_mu, bt0, bn,
+    m_tiles<NCH, NT == 1 && LIN && !NL>(Pb, rows_pad, bp, n_rows, xi, rho, rhot, w, n_g, n_mu, bt0, bn,
                                  kc, k_hi, Gs, As, acc);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -486,26 +493,29 @@ void k_grad_pairs_bh(const double* __restrict__ Pb, long rows_pad, long bp, int 
           double mv[NCH];
 #pragma unroll
           for (int c = 0; c < NCH; ++c) mv[c] = acc[c][i][j][r];
-          pair_grad_bh<NT, NL>(cf, T, Cs, nn, TB, bi, TA, kj, bxyz[0][bi] - kxyz[0][kj],
+          pair_grad_bh<NT, LIN, NL>(cf, T, Cs, nn, TB, bi, TA, kj, bxyz[0][bi] - kxyz[0][kj],
                            bxyz[1][bi] - kxyz[1][kj], bxyz[2][bi] - kxyz[2][kj], mv, z, zee,
                            omax_ee, znl);
         }
   }
   // deterministic block reduction: [NT * 64 Z entries][MAXQ + 1 Zee entries][1 + NT nonlinear]
   __syncthreads();
-  constexpr int NRED = NT * 64 + MAXQ + 1 + (NL ? 1 + NT : 0);
+  constexpr int K0 = LIN ? 0 : NT * 64 + MAXQ + 1;
+  constexpr int K1 = NL ? NT * 64 + MAXQ + 1 + 1 + NT : NT * 64 + MAXQ + 1;
 #pragma unroll
-  for (int k = 0; k < NRED; ++k) {
-    double v = k < NT * 64 ? z[k] : (k < NT * 64 + MAXQ + 1 ? zee[k - NT * 64]
-                                                            : znl[k - NT * 64 - MAXQ - 1]);
+  for (int k = K0; k < K1; ++k) {
+    double v = k < NT * 64 ? z[LIN ? k : 0]
+                           : (k < NT * 64 + MAXQ + 1 ? zee[LIN ? k - NT * 64 : 0]
+                                                     : znl[NL ? k - NT * 64 - MAXQ - 1 : 0]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) red[wave][k] = v;
   }
   __syncthreads();
   const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
-  for (int k = tid; k < ZS; k += 256) {
-    const double v = k < NRED ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
+  // LIN writes every entry (those past its range as 0); NL alone writes only its own
+  for (int k = (LIN ? 0 : K0) + tid; k < (LIN ? ZS : K1); k += 256) {
+    const double v = k < K1 ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
     partials[blk * ZS + k] = v;
   }
 }
@@ -779,14 +789,22 @@ extern "C" xtc_status xtc_grad(const xtc_grid* grid, const xtc_correlator* corr,
     const int stride = bh ? ZS : MAXQ + 1;
     double* part = L.partials + (long)sb * L.nblk * stride;
     if (bh) {
-#define XTC_LAUNCH_BH(NTV, NLV)                                                                  \
-  hipLaunchKernelGGL((k_grad_pairs_bh<NTV, NLV>), gridp, dim3(256), 0, st, (const double*)L.Pb,    \
-                     L.rows_pad, L.bp, n_mu + 2, xi, rho, (const double*)L.rhot, grid->w,        \
-                     grid->xyz, n_g, n_mu, b0, bn, cf, (const BHTable*)L.bh, omax_ee, part)
-      if (bt.n_types == 1 && !dd) XTC_LAUNCH_BH(1, false);
-      else if (bt.n_types == 1) XTC_LAUNCH_BH(1, true);
-      else if (!dd) XTC_LAUNCH_BH(2, false);
-      else XTC_LAUNCH_BH(2, true);
+#define XTC_LAUNCH_BH(NTV, LINV, NLV)                                                           \
+  hipLaunchKernelGGL((k_grad_pairs_bh<NTV, LINV, NLV>), gridp, dim3(256), 0, st,                 \
+                     (const double*)L.Pb, L.rows_pad, L.bp, n_mu + 2, xi, rho,                   \
+                     (const double*)L.rhot, grid->w, grid->xyz, n_g, n_mu, b0, bn, cf,           \
+                     (const BHTable*)L.bh, omax_ee, part)
+      if (bt.n_types == 1) {
+        XTC_LAUNCH_BH(1, true, false);
+        if (dd) {   // the nonlinear parameters in a launch of their own (after the linear one)
+          XTC_CHECK_LAUNCH();
+          XTC_LAUNCH_BH(1, false, true);
+        }
+      } else if (!dd) {
+        XTC_LAUNCH_BH(2, true, false);
+      } else {
+        XTC_LAUNCH_BH(2, true, true);
+      }
 #undef XTC_LAUNCH_BH
     }
     else if (L.nch == 4)
